@@ -1,0 +1,660 @@
+/*
+ * capart_oracle.c -- plain, slow, obviously-correct CPU oracle for
+ * contention-aware GPU partitioning and task-to-partition allocation
+ * (Zahaf et al., arXiv 2105.10312).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the HIP engine; it is written directly
+ * from the paper's definitions, in the paper's order, with no blocking,
+ * fusion or reordering.  All arithmetic is integer; intermediate products
+ * are carried in 128 bits so that no overflow argument is needed here.
+ *
+ * What is computed, per task set (n tasks, M compute units, at most K parts):
+ *   1. execution times (Section "Modeling kernel execution times" and the
+ *      scaling function of Section "Task set generation"):
+ *        Cn(m) = C_seq + ceil(C_par / m)          no conflict
+ *        Cc(m) = ceil(k * Cn(m) / 1000)            conflict (k per-mille)
+ *   2. conflict (Section "Task Model"): a task is in conflict iff at least one
+ *      OTHER task of the same type (memory / compute) shares its partition;
+ *      its execution time is Cc then, Cn otherwise;
+ *   3. per-partition test (Section "Schedulability test": any policy with an
+ *      exact test; interference folded into the execution times): each
+ *      partition is one server running its tasks one at a time on all its
+ *      compute units, preemptive fixed priority, deadline-monotonic order by
+ *      (D, T, index), exact response-time fixed point
+ *        R = C_i + sum_{j in hp(i)} ceil(R / T_j) * C_j ,  R <= D_i;
+ *   4. Lemma 1 (necessary test): sum_i Cn_i(1)/T_i > M => unschedulable,
+ *      evaluated as floor-Q32 utilisations so the rejection is sound;
+ *   5. Lemma 2: smallest partition for one task, m_min = min{m : Cn(m) <= D};
+ *   6. partitionings: integer partitions of M into at most K positive parts,
+ *      non-increasing, listed in descending lexicographic order;
+ *   7. allocation: exhaustive (all k^n maps, index = base-k digits with task
+ *      0 most significant) or the heuristic H(pi) below;
+ *   8. partition utilisation U(P) = sum ceil(C_i * 2^32 / T_i) (Q32, the
+ *      order relation ">" of Definition 5); the best feasible triple minimises
+ *      (max_p U_p, sum_p U_p, partitioning index, allocation index);
+ *   9. the whole-GPU baseline ("1G"): every task on one partition of M.
+ *
+ * H(pi), the paper's heuristic ingredients applied to fixed partition sizes:
+ * tasks in decreasing one-unit utilisation (Algorithm 1's ordered list),
+ * each placed on the candidate partition that stays schedulable and ranks
+ * best, by ">" (lower merged utilisation, Definition 5, "BF") or by ">>"
+ * (fewer compute units needed by the merged partition, Definition 4 with the
+ * search of Algorithm 2, "SMS"); with ACT, task pairs whose two-task merge is
+ * invalid (Definition 3 / Algorithm 2) are forbidden to share a partition
+ * (Section "Forbidden list").  Ties fall to the lower partition index.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+enum { OR_EXH = 0, OR_BF_INA = 1, OR_BF_ACT = 2, OR_SMS_INA = 3, OR_SMS_ACT = 4 };
+enum { OR_OK = 0, OR_E_INVAL = -1, OR_E_RANGE = -2 };
+#define OR_FLAG_NO_LEMMA1 1
+#define OR_MAXN 64
+#define OR_MINF 1000000 /* "no such m" for Lemma 2 */
+
+typedef struct {
+    int64_t terms;   /* response-time terms: seed + each ceil(R/T_j)*C_j */
+    int64_t tests;   /* partition schedulability tests                   */
+    int64_t combines;/* exhaustive allocations examined                  */
+} or_counters;
+
+typedef struct {
+    int n, M;
+    const int64_t *T, *D, *Cs, *Cp;
+    const int32_t *k;
+    const uint8_t *type;
+    or_counters *cnt;
+} or_set;
+
+/* ---- 1. execution times ------------------------------------------------ */
+static int64_t or_cn(const or_set *s, int i, int m)
+{
+    return s->Cs[i] + (s->Cp[i] + m - 1) / m;
+}
+
+static int64_t or_cc(const or_set *s, int i, int m)
+{
+    i128 x = (i128)s->k[i] * (i128)or_cn(s, i, m);
+    return (int64_t)((x + 999) / 1000);
+}
+
+int64_t or_time(const int64_t *Cs, const int64_t *Cp, const int32_t *k, int i, int m, int conflict)
+{
+    or_set s = {0};
+    s.Cs = Cs; s.Cp = Cp; s.k = k;
+    return conflict ? or_cc(&s, i, m) : or_cn(&s, i, m);
+}
+
+/* ---- 2+3. one partition: conflicts, DM order, exact RTA --------------- */
+/* mem[0..cnt) are task indices.  R_out (indexed by task) gets the response
+ * time or -1; with early_exit the test stops at the first miss (the rest of
+ * R_out is left untouched).  Returns 1 iff every task meets its deadline and
+ * then *U = sum ceil(C_i 2^32 / T_i). */
+static int or_eval_part(const or_set *s, const int *mem, int cnt, int m, int early_exit,
+                        int64_t *R_out, uint64_t *U)
+{
+    int order[OR_MAXN];
+    int64_t C[OR_MAXN];
+    int a, b, t, u;
+    int feasible = 1;
+    if (s->cnt) s->cnt->tests++;
+    for (a = 0; a < cnt; a++) {
+        int same = 0;
+        for (b = 0; b < cnt; b++)
+            if (s->type[mem[b]] == s->type[mem[a]]) same++;
+        /* "same" counts the task itself: a conflict needs one other task */
+        C[a] = (same >= 2) ? or_cc(s, mem[a], m) : or_cn(s, mem[a], m);
+        order[a] = a;
+    }
+    /* deadline-monotonic priority: (D, T, index) ascending; insertion sort */
+    for (a = 1; a < cnt; a++) {
+        int x = order[a];
+        b = a - 1;
+        while (b >= 0) {
+            int y = order[b];
+            int64_t dx = s->D[mem[x]], dy = s->D[mem[y]];
+            int64_t tx = s->T[mem[x]], ty = s->T[mem[y]];
+            int later = (dy > dx) || (dy == dx && (ty > tx || (ty == tx && mem[y] > mem[x])));
+            if (!later) break;
+            order[b + 1] = y;
+            b--;
+        }
+        order[b + 1] = x;
+    }
+    for (t = 0; t < cnt; t++) {
+        int pi = order[t], i = mem[pi];
+        i128 R = C[pi], W;
+        int ok = 0;
+        for (;;) {
+            W = C[pi];
+            if (s->cnt) s->cnt->terms++;
+            for (u = 0; u < t; u++) {
+                int pj = order[u], j = mem[pj];
+                i128 q = (R + s->T[j] - 1) / s->T[j];
+                W += q * C[pj];
+                if (s->cnt) s->cnt->terms++;
+            }
+            if (W > s->D[i]) { ok = 0; break; }
+            if (W == R) { ok = 1; break; }
+            R = W;
+        }
+        if (R_out) R_out[i] = ok ? (int64_t)R : -1;
+        if (!ok) {
+            feasible = 0;
+            if (early_exit) return 0;
+        }
+    }
+    if (feasible && U) {
+        u128 acc = 0;
+        for (a = 0; a < cnt; a++) {
+            u128 num = ((u128)C[a]) << 32;
+            u128 den = (u128)s->T[mem[a]];
+            acc += (num + den - 1) / den;
+        }
+        *U = (uint64_t)acc;
+    }
+    return feasible;
+}
+
+/* ---- a whole triple (partitioning, allocation) -------------------------- */
+static int or_eval_triple(const or_set *s, const int *sizes, int k, const int8_t *alloc,
+                          int early_exit, int64_t *R_out, uint64_t *maxU, uint64_t *sumU)
+{
+    int mem[OR_MAXN];
+    int p, i, feasible = 1;
+    uint64_t mx = 0, sm = 0;
+    for (p = 0; p < k; p++) {
+        int cnt = 0;
+        uint64_t U = 0;
+        for (i = 0; i < s->n; i++)
+            if (alloc[i] == p) mem[cnt++] = i;
+        if (cnt == 0) continue; /* an empty partition is trivially schedulable, U = 0 */
+        if (!or_eval_part(s, mem, cnt, sizes[p], early_exit, R_out, &U)) {
+            feasible = 0;
+            if (early_exit) return 0;
+            continue;
+        }
+        if (U > mx) mx = U;
+        sm += U;
+    }
+    if (feasible) {
+        if (maxU) *maxU = mx;
+        if (sumU) *sumU = sm;
+    }
+    return feasible;
+}
+
+/* ---- 4. Lemma 1 ---------------------------------------------------------- */
+static int or_lemma1_reject(const or_set *s)
+{
+    u128 acc = 0;
+    int i;
+    for (i = 0; i < s->n; i++)
+        acc += (((u128)or_cn(s, i, 1)) << 32) / (u128)s->T[i];
+    return acc > (((u128)s->M) << 32);
+}
+
+/* ---- 5. Lemma 2 (linear scan, as stated) ------------------------------- */
+static int or_m_min(const or_set *s, int i)
+{
+    int m;
+    for (m = 1; m <= s->M; m++)
+        if (or_cn(s, i, m) - s->D[i] <= 0) return m;
+    return OR_MINF;
+}
+
+/* ---- 6. integer partitions of M into <= K parts, descending lex ------- */
+typedef struct {
+    int64_t count, want;
+    int *out;      /* if non-NULL: write K sizes per partitioning (0-padded) */
+    int64_t cap;
+    int K;
+    int cur[16];
+} or_enum_ctx;
+
+static void or_enum_rec(or_enum_ctx *c, int rem, int maxpart, int depth)
+{
+    int x, j;
+    if (rem == 0) {
+        if (c->out && c->count < c->cap) {
+            for (j = 0; j < c->K; j++) c->out[c->count * c->K + j] = j < depth ? c->cur[j] : 0;
+        }
+        c->count++;
+        return;
+    }
+    if (depth == c->K) return;
+    for (x = (rem < maxpart ? rem : maxpart); x >= 1; x--) {
+        if ((int64_t)x * (c->K - depth) < rem) break; /* cannot fill with parts <= x */
+        c->cur[depth] = x;
+        or_enum_rec(c, rem - x, x, depth + 1);
+    }
+}
+
+int64_t or_count_partitionings(int M, int K)
+{
+    or_enum_ctx c;
+    memset(&c, 0, sizeof c);
+    if (M < 1 || K < 1 || K > 16) return 0;
+    c.K = K;
+    or_enum_rec(&c, M, M, 0);
+    return c.count;
+}
+
+int64_t or_enumerate_partitionings(int M, int K, int *out, int64_t cap)
+{
+    or_enum_ctx c;
+    memset(&c, 0, sizeof c);
+    if (M < 1 || K < 1 || K > 16) return 0;
+    c.K = K; c.out = out; c.cap = cap;
+    or_enum_rec(&c, M, M, 0);
+    return c.count;
+}
+
+/* ---- 7b. the heuristic H(pi) -------------------------------------------- */
+static uint64_t or_u1(const or_set *s, int i)
+{
+    u128 num = ((u128)or_cn(s, i, 1)) << 32, den = (u128)s->T[i];
+    return (uint64_t)((num + den - 1) / den);
+}
+
+/* forbidden pair (ACT): no valid two-task merge (Definition 3, Algorithm 2) */
+static int or_forbidden(const or_set *s, int i, int j, const int *mm)
+{
+    int mem[2], m, lo, hi;
+    if (mm[i] >= OR_MINF || mm[j] >= OR_MINF) return 1;
+    mem[0] = i; mem[1] = j;
+    lo = mm[i] > mm[j] ? mm[i] : mm[j];
+    hi = mm[i] + mm[j] - 1;
+    if (hi > s->M) hi = s->M;
+    for (m = lo; m <= hi; m++)
+        if (or_eval_part(s, mem, 2, m, 1, NULL, NULL)) return 0;
+    return 1;
+}
+
+static int or_heuristic(const or_set *s, const int *sizes, int k, int variant, int8_t *alloc)
+{
+    int n = s->n, i, t, p, a, b;
+    int mm[OR_MAXN], sigma[OR_MAXN];
+    uint64_t u1[OR_MAXN];
+    int members[8][OR_MAXN];
+    int nmem[8];
+    int act = (variant == OR_BF_ACT || variant == OR_SMS_ACT);
+    int sms = (variant == OR_SMS_INA || variant == OR_SMS_ACT);
+    static const int none = -1;
+    (void)none;
+
+    for (i = 0; i < n; i++) {
+        mm[i] = or_m_min(s, i);
+        u1[i] = or_u1(s, i);
+        sigma[i] = i;
+        alloc[i] = -1;
+    }
+    /* decreasing one-unit utilisation, ties by index */
+    for (a = 1; a < n; a++) {
+        int x = sigma[a];
+        b = a - 1;
+        while (b >= 0 && (u1[sigma[b]] < u1[x] || (u1[sigma[b]] == u1[x] && sigma[b] > x))) {
+            sigma[b + 1] = sigma[b];
+            b--;
+        }
+        sigma[b + 1] = x;
+    }
+    for (p = 0; p < k; p++) nmem[p] = 0;
+    for (t = 0; t < n; t++) {
+        int tau = sigma[t];
+        int best_p = -1;
+        uint64_t best_U = 0;
+        int best_req = 0;
+        for (p = 0; p < k; p++) {
+            int cand[OR_MAXN], c = nmem[p], q, feas, req = 0;
+            uint64_t U = 0;
+            if (mm[tau] > sizes[p]) continue;
+            if (act) {
+                int bad = 0;
+                for (q = 0; q < nmem[p]; q++)
+                    if (or_forbidden(s, tau, members[p][q], mm)) { bad = 1; break; }
+                if (bad) continue;
+            }
+            memcpy(cand, members[p], sizeof(int) * (size_t)c);
+            cand[c++] = tau;
+            feas = or_eval_part(s, cand, c, sizes[p], 1, NULL, &U);
+            if (!feas) continue;
+            if (sms) {
+                int m;
+                for (m = 1; m <= sizes[p]; m++)
+                    if (or_eval_part(s, cand, c, m, 1, NULL, NULL)) { req = m; break; }
+            }
+            if (best_p < 0) {
+                best_p = p; best_U = U; best_req = req;
+            } else if (sms) {
+                if (req < best_req || (req == best_req && U < best_U)) {
+                    best_p = p; best_U = U; best_req = req;
+                }
+            } else if (U < best_U) {
+                best_p = p; best_U = U;
+            }
+        }
+        if (best_p < 0) {
+            for (i = 0; i < n; i++) alloc[i] = -1;
+            return 0;
+        }
+        members[best_p][nmem[best_p]++] = tau;
+        alloc[tau] = (int8_t)best_p;
+    }
+    return 1;
+}
+
+/* ---- validation (the boundary's input contract) ------------------------- */
+static int or_validate(const or_set *s, int K, int mode)
+{
+    int i;
+    if (s->n < 1 || s->n > OR_MAXN || s->M < 1 || s->M > 255) return OR_E_INVAL;
+    for (i = 0; i < s->n; i++) {
+        int64_t T = s->T[i], D = s->D[i], a = s->Cs[i], b = s->Cp[i];
+        if (T < 1 || T >= ((int64_t)1 << 31)) return OR_E_RANGE;
+        if (D < 1 || D > T) return OR_E_RANGE;
+        if (a < 0 || b < 0 || a >= ((int64_t)1 << 31) || b >= ((int64_t)1 << 31)) return OR_E_RANGE;
+        if (a + b < 1 || a + b >= ((int64_t)1 << 31)) return OR_E_RANGE;
+        if (s->k[i] < 1000 || s->k[i] > 1000000) return OR_E_RANGE;
+        if (s->type[i] > 1) return OR_E_RANGE;
+    }
+    if (mode == OR_EXH) {
+        int kk = K < s->M ? K : s->M;
+        u128 pw = 1;
+        for (i = 0; i < s->n; i++) {
+            pw *= (u128)kk;
+            if (pw >= ((u128)1 << 62)) return OR_E_INVAL;
+        }
+    }
+    return OR_OK;
+}
+
+/* ---- one set ----------------------------------------------------------- */
+typedef struct {
+    int32_t status;
+    uint8_t verdict, verdict_1g;
+    int32_t pidx;
+    int64_t aidx;
+    uint64_t maxU, sumU;
+    int64_t n_evals;
+} or_set_result;
+
+/* solve one set; sizes_out[K], alloc_out[n], R_out[n], R1g_out[n] */
+static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_result *res,
+                         int32_t *sizes_out, int8_t *alloc_out, int64_t *R_out, int64_t *R1g_out)
+{
+    int n = s->n, i, p, k;
+    int64_t P, pi;
+    int *table;
+    int8_t cur[OR_MAXN], best_alloc[OR_MAXN];
+    int best_found = 0;
+    int64_t best_pidx = -1, best_aidx = -1;
+    uint64_t best_max = 0, best_sum = 0;
+    int reject;
+    int one[1];
+    int8_t zeros[OR_MAXN];
+
+    memset(res, 0, sizeof *res);
+    res->pidx = -1; res->aidx = -1;
+    for (p = 0; p < K; p++) sizes_out[p] = 0;
+    for (i = 0; i < n && i < OR_MAXN; i++) { alloc_out[i] = -1; R_out[i] = -1; R1g_out[i] = -1; }
+    res->status = or_validate(s, K, mode);
+    if (res->status != OR_OK) {
+        if (n > 0 && n <= OR_MAXN) for (i = 0; i < n; i++) { alloc_out[i] = -1; R_out[i] = -1; R1g_out[i] = -1; }
+        return;
+    }
+    P = or_count_partitionings(s->M, K);
+    res->n_evals = P;
+    table = (int *)malloc(sizeof(int) * (size_t)(P * K));
+    or_enumerate_partitionings(s->M, K, table, P);
+    reject = (flags & OR_FLAG_NO_LEMMA1) ? 0 : or_lemma1_reject(s);
+    if (!reject) {
+        for (pi = 0; pi < P; pi++) {
+            const int *sz = table + pi * K;
+            for (k = 0; k < K && sz[k] > 0; k++) {}
+            if (mode == OR_EXH) {
+                int64_t a, A = 1;
+                for (i = 0; i < n; i++) A *= k;
+                for (a = 0; a < A; a++) {
+                    int64_t x = a;
+                    uint64_t mx, sm;
+                    for (i = n - 1; i >= 0; i--) { cur[i] = (int8_t)(x % k); x /= k; }
+                    if (s->cnt) s->cnt->combines++;
+                    if (!or_eval_triple(s, sz, k, cur, 1, NULL, &mx, &sm)) continue;
+                    if (!best_found || mx < best_max || (mx == best_max && sm < best_sum)) {
+                        best_found = 1; best_max = mx; best_sum = sm;
+                        best_pidx = pi; best_aidx = a;
+                        memcpy(best_alloc, cur, (size_t)n);
+                    }
+                }
+            } else {
+                uint64_t mx, sm;
+                if (!or_heuristic(s, sz, k, mode, cur)) continue;
+                if (!or_eval_triple(s, sz, k, cur, 1, NULL, &mx, &sm)) abort(); /* H builds feasible maps */
+                if (!best_found || mx < best_max || (mx == best_max && sm < best_sum)) {
+                    best_found = 1; best_max = mx; best_sum = sm;
+                    best_pidx = pi; best_aidx = 0;
+                    memcpy(best_alloc, cur, (size_t)n);
+                }
+            }
+        }
+    }
+    if (best_found) {
+        const int *sz = table + best_pidx * K;
+        for (k = 0; k < K && sz[k] > 0; k++) sizes_out[k] = sz[k];
+        res->verdict = 1;
+        res->pidx = (int32_t)best_pidx;
+        res->aidx = best_aidx;
+        res->maxU = best_max;
+        res->sumU = best_sum;
+        memcpy(alloc_out, best_alloc, (size_t)n);
+        or_eval_triple(s, sz, k, best_alloc, 0, R_out, NULL, NULL);
+    }
+    /* whole-GPU baseline: one partition of M units, every task evaluated */
+    one[0] = s->M;
+    memset(zeros, 0, sizeof zeros);
+    res->verdict_1g = (uint8_t)or_eval_triple(s, one, 1, zeros, 0, R1g_out, NULL, NULL);
+    free(table);
+}
+
+/* ---- exported entry points ----------------------------------------------- */
+static void or_make_set(or_set *s, int64_t off0, int64_t off1, int32_t M, const int64_t *T, const int64_t *D,
+                        const int64_t *Cs, const int64_t *Cp, const int32_t *k, const uint8_t *type,
+                        or_counters *cnt)
+{
+    s->n = (int)(off1 - off0);
+    s->M = M;
+    s->T = T + off0; s->D = D + off0; s->Cs = Cs + off0; s->Cp = Cp + off0;
+    s->k = k + off0; s->type = type + off0;
+    s->cnt = cnt;
+}
+
+typedef struct {
+    int64_t n_sets;
+    const int64_t *off; const int32_t *M;
+    const int64_t *T, *D, *Cs, *Cp; const int32_t *k; const uint8_t *type;
+    int K, mode, flags;
+    int32_t *status; uint8_t *verdict, *verdict_1g; int32_t *pidx, *sizes;
+    int64_t *aidx; uint64_t *maxU, *sumU; int64_t *n_evals;
+    int8_t *alloc; int64_t *R, *R1g; int64_t *counters;
+    int64_t next;
+    pthread_mutex_t lock;
+} or_batch;
+
+static void or_batch_set(or_batch *b, int64_t si)
+{
+    or_set s;
+    or_counters cnt = {0, 0, 0};
+    or_set_result r;
+    int64_t o0 = b->off[si], o1 = b->off[si + 1];
+    int n = (int)(o1 - o0), i;
+    int8_t al[OR_MAXN]; int64_t R[OR_MAXN], R1[OR_MAXN];
+    or_make_set(&s, o0, o1, b->M[si], b->T, b->D, b->Cs, b->Cp, b->k, b->type, &cnt);
+    if (n < 0) n = 0;
+    or_solve_one(&s, b->K, b->mode, b->flags, &r, b->sizes + si * b->K, al, R, R1);
+    b->status[si] = r.status; b->verdict[si] = r.verdict; b->verdict_1g[si] = r.verdict_1g;
+    b->pidx[si] = r.pidx; b->aidx[si] = r.aidx; b->maxU[si] = r.maxU; b->sumU[si] = r.sumU;
+    b->n_evals[si] = r.n_evals;
+    for (i = 0; i < n; i++) {
+        if (i < OR_MAXN && r.status == OR_OK) {
+            b->alloc[o0 + i] = al[i]; b->R[o0 + i] = R[i]; b->R1g[o0 + i] = R1[i];
+        } else {
+            b->alloc[o0 + i] = -1; b->R[o0 + i] = -1; b->R1g[o0 + i] = -1;
+        }
+    }
+    if (b->counters) {
+        b->counters[si * 3 + 0] = cnt.terms;
+        b->counters[si * 3 + 1] = cnt.tests;
+        b->counters[si * 3 + 2] = cnt.combines;
+    }
+}
+
+static void *or_worker(void *arg)
+{
+    or_batch *b = (or_batch *)arg;
+    for (;;) {
+        int64_t si;
+        pthread_mutex_lock(&b->lock);
+        si = b->next++;
+        pthread_mutex_unlock(&b->lock);
+        if (si >= b->n_sets) break;
+        or_batch_set(b, si);
+    }
+    return NULL;
+}
+
+/* Solve a batch of task sets (SoA, offsets[n_sets+1]) with nthreads workers.
+ * Outputs: per set status, verdict, verdict_1g, pidx, sizes[K], aidx, maxU,
+ * sumU, n_evals; per task alloc, R, R1g; counters[3] per set (optional). */
+int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
+                   const int64_t *T, const int64_t *D, const int64_t *Cs, const int64_t *Cp,
+                   const int32_t *k, const uint8_t *type, int K, int mode, int flags, int nthreads,
+                   int32_t *status, uint8_t *verdict, uint8_t *verdict_1g, int32_t *pidx, int32_t *sizes,
+                   int64_t *aidx, uint64_t *maxU, uint64_t *sumU, int64_t *n_evals,
+                   int8_t *alloc, int64_t *R, int64_t *R1g, int64_t *counters)
+{
+    or_batch b;
+    pthread_t th[256];
+    int t;
+    if (K < 1 || K > 8 || mode < OR_EXH || mode > OR_SMS_ACT) return OR_E_INVAL;
+    b.n_sets = n_sets; b.off = off; b.M = M; b.T = T; b.D = D; b.Cs = Cs; b.Cp = Cp; b.k = k;
+    b.type = type; b.K = K; b.mode = mode; b.flags = flags; b.status = status; b.verdict = verdict;
+    b.verdict_1g = verdict_1g; b.pidx = pidx; b.sizes = sizes; b.aidx = aidx; b.maxU = maxU;
+    b.sumU = sumU; b.n_evals = n_evals; b.alloc = alloc; b.R = R; b.R1g = R1g; b.counters = counters;
+    b.next = 0;
+    pthread_mutex_init(&b.lock, NULL);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads == 1) {
+        or_worker(&b);
+    } else {
+        for (t = 0; t < nthreads; t++) pthread_create(&th[t], NULL, or_worker, &b);
+        for (t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    }
+    pthread_mutex_destroy(&b.lock);
+    return OR_OK;
+}
+
+/* ---- single-function entry points used by the pins ---------------------- */
+#define OR_SET_ARGS int n, int M, const int64_t *T, const int64_t *D, const int64_t *Cs, \
+                    const int64_t *Cp, const int32_t *k, const uint8_t *type
+#define OR_SET_INIT(s) do { (s).n = n; (s).M = M; (s).T = T; (s).D = D; (s).Cs = Cs; (s).Cp = Cp; \
+                            (s).k = k; (s).type = type; (s).cnt = NULL; } while (0)
+
+/* evaluate one triple; returns feasible; R_out[n] (-1 for misses or, with
+ * early_exit, for tasks never reached) */
+int or_eval_triple_ex(OR_SET_ARGS, const int32_t *sizes, int nparts, const int8_t *alloc,
+                      int early_exit, int64_t *R_out, uint64_t *maxU, uint64_t *sumU, int64_t *counters)
+{
+    or_set s;
+    or_counters cnt = {0, 0, 0};
+    int sz[16], i, f;
+    OR_SET_INIT(s);
+    s.cnt = &cnt;
+    for (i = 0; i < nparts && i < 16; i++) sz[i] = sizes[i];
+    for (i = 0; i < n; i++) R_out[i] = -1;
+    *maxU = 0; *sumU = 0;
+    f = or_eval_triple(&s, sz, nparts, alloc, early_exit, R_out, maxU, sumU);
+    if (counters) { counters[0] = cnt.terms; counters[1] = cnt.tests; counters[2] = cnt.combines; }
+    return f;
+}
+
+int or_heuristic_ex(OR_SET_ARGS, const int32_t *sizes, int nparts, int variant, int8_t *alloc)
+{
+    or_set s;
+    int sz[16], i;
+    OR_SET_INIT(s);
+    for (i = 0; i < nparts && i < 16; i++) sz[i] = sizes[i];
+    return or_heuristic(&s, sz, nparts, variant, alloc);
+}
+
+/* best allocation on one fixed partitioning (exhaustive or heuristic):
+ * returns found; writes alloc[n], maxU, sumU, aidx */
+int or_best_on_partitioning(OR_SET_ARGS, const int32_t *sizes, int nparts, int mode,
+                            int8_t *alloc, uint64_t *maxU, uint64_t *sumU, int64_t *aidx)
+{
+    or_set s;
+    int sz[16], i, found = 0;
+    int8_t cur[OR_MAXN];
+    OR_SET_INIT(s);
+    for (i = 0; i < nparts && i < 16; i++) sz[i] = sizes[i];
+    if (mode == OR_EXH) {
+        int64_t a, A = 1;
+        for (i = 0; i < n; i++) A *= nparts;
+        for (a = 0; a < A; a++) {
+            int64_t x = a;
+            uint64_t mx, sm;
+            for (i = n - 1; i >= 0; i--) { cur[i] = (int8_t)(x % nparts); x /= nparts; }
+            if (!or_eval_triple(&s, sz, nparts, cur, 1, NULL, &mx, &sm)) continue;
+            if (!found || mx < *maxU || (mx == *maxU && sm < *sumU)) {
+                found = 1; *maxU = mx; *sumU = sm; *aidx = a;
+                memcpy(alloc, cur, (size_t)n);
+            }
+        }
+    } else {
+        if (or_heuristic(&s, sz, nparts, mode, cur)) {
+            found = or_eval_triple(&s, sz, nparts, cur, 1, NULL, maxU, sumU);
+            *aidx = 0;
+            memcpy(alloc, cur, (size_t)n);
+        }
+    }
+    if (!found) for (i = 0; i < n; i++) alloc[i] = -1;
+    return found;
+}
+
+int or_m_min_ex(OR_SET_ARGS, int i)
+{
+    or_set s;
+    OR_SET_INIT(s);
+    return or_m_min(&s, i);
+}
+
+int or_forbidden_ex(OR_SET_ARGS, int i, int j)
+{
+    or_set s;
+    int mm[OR_MAXN], t;
+    OR_SET_INIT(s);
+    for (t = 0; t < n; t++) mm[t] = or_m_min(&s, t);
+    return or_forbidden(&s, i, j, mm);
+}
+
+int or_lemma1_reject_ex(OR_SET_ARGS)
+{
+    or_set s;
+    OR_SET_INIT(s);
+    return or_lemma1_reject(&s);
+}
+
+uint64_t or_u1_ex(OR_SET_ARGS, int i)
+{
+    or_set s;
+    OR_SET_INIT(s);
+    return or_u1(&s, i);
+}
