@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark: schedulability evaluations per second on one MI355X.
+
+A step is one pass of the whole hot path over one batch resident in HBM:
+validation and per-set precompute (prep kernel), evaluation of every
+(task set, partitioning) pair with heuristic allocation and per-partition
+response-time tests (eval kernel), selection of the best triple, response
+times of the chosen triple and of the whole-GPU baseline (final kernel).
+Default workload: 100,000 seeded synthetic task sets, n = 10 tasks, M = 80
+compute units, at most K = 4 partitions (4263 partitionings per set), BF-INA
+heuristic allocation; 426,300,000 evaluations per step.
+
+Prints one JSON line (metric, value in evals/s, ms_per_step, roofline of the
+dominant kernel measured with HIP events on its launch stream, and the CPU
+oracle timed on a bounded sample of the same workload on the host's cores).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "schedulability evals/sec (taskset×partitioning); p99 admission latency"
+# Per-term and per-test VALU issue slots (lane-operations at full rate) of the
+# response-time test; a term is 3 integer multiplies (v_mul_hi_u32 and two
+# v_mad_u64_u32), each issued at quarter rate on CDNA.
+C_TERM = 12
+C_TEST = 8
+PEAK_INT_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit VALU)
+PMC_FILE = os.path.join(ROOT, "profiles", "eval_heur_c2_bf_ina_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2105_10312_amd", "csrc", "capart_kernels.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_bytes():
+    """HBM bytes per eval launch from the committed rocprofv3 counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(ts, K, mode, sample_sets, threads):
+    import numpy as np
+
+    import oracle
+    from paper_2105_10312_amd import workload
+    sub = workload.subset(ts, np.arange(min(sample_sets, ts.n_sets)))
+    P = int(sum(oracle.count_partitionings(int(m), K) for m in sub["M"]))
+    t0 = time.perf_counter()
+    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True)
+    dt = time.perf_counter() - t0
+    c = r["counters"].sum(axis=0)
+    return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "sets": sub.n_sets}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+    ap.add_argument("--n-sets", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=6000, help="task sets timed on the CPU oracle")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0 = all host cores (at most 16)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (counts from 200 sets)")
+    ap.add_argument("--per-set-launch", action="store_true", help="plain path: one launch sequence per set")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the engine shards task sets independently and this build "
+              "runs no multi-GPU configuration (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2105_10312_amd import capart, workload
+
+    K = 4
+    log(f"[bench] generating workload: {args.n_sets} sets, n=10, M=80, K={K}")
+    ts = workload.config_c2(n_sets=args.n_sets)
+    P = capart.capart_count_partitionings(80, K)
+    evals_per_step = P * ts.n_sets
+    dev = capart.device_tasksets(ts)
+    out = capart.device_results(ts.n_sets, ts.n_tasks, K)
+    eng = capart.Engine(0)
+    flags = capart.CAPART_FLAG_PER_SET_LAUNCH if args.per_set_launch else 0
+    stream = torch.cuda.current_stream()
+
+    def step():
+        capart.capart_solve_async(eng.ctx, dev, K, args.mode, out, stream=stream, flags=flags, max_tasks=10,
+                                  max_M=80)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    st = out["status"][: ts.n_sets].cpu().numpy()
+    if not (st == 0).all():
+        raise SystemExit(f"bench: {int((st != 0).sum())} sets reported errors")
+    capart.capart_timing_enable(eng.ctx, True)
+    capart.capart_timing_read(eng.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_k, n_k = capart.capart_timing_read(eng.ctx)
+    capart.capart_timing_enable(eng.ctx, False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = evals_per_step / (ms_per_step / 1000.0)
+    verdicts = int(out["verdict"][: ts.n_sets].sum().item())
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} evals/s; kernels ms {ms_k}")
+
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    if args.no_cpu:
+        cb = cpu_baseline(ts, K, args.mode, 200, threads)
+        cpu = None
+    else:
+        log(f"[bench] CPU oracle on {args.cpu_sample} sets with {threads} threads")
+        cb = cpu_baseline(ts, K, args.mode, args.cpu_sample, threads)
+        cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {cb['sets']} of the {ts.n_sets} sets ({cb['evals']} evals), "
+                         f"{cb['seconds']:.2f} s wall"}
+        log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s")
+    terms_per_eval = cb["terms"] / cb["evals"]
+    tests_per_eval = cb["tests"] / cb["evals"]
+    eval_ms = ms_k["eval"] / max(1, n_k["eval"])
+    ops = evals_per_step * (terms_per_eval * C_TERM + tests_per_eval * C_TEST)
+    achieved = ops / (eval_ms / 1000.0)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved / PEAK_INT_LANE_OPS, "traffic": traffic_bytes(),
+            "kernel": "eval_heur_kernel", "kernel_ms": eval_ms,
+            "ops_per_launch": ops, "terms_per_eval": terms_per_eval, "tests_per_eval": tests_per_eval,
+            "ops_per_term": C_TERM, "ops_per_test": C_TEST,
+            "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
+                                 "final": ms_k["final"] / max(1, n_k["final"])}}
+    res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"batched plain: {ts.n_sets} task sets, n=10, M=80, K=4, {args.mode} "
+                                  f"heuristic allocation" + (", one launch per set" if args.per_set_launch else ""),
+                      "n_sets": ts.n_sets, "n": 10, "M": 80, "K": K, "alloc_mode": args.mode,
+                      "evals_per_step": evals_per_step, "schedulable_sets": verdicts},
+           "roofline": roof, "cpu_baseline": cpu}
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * capart.h -- C ABI of the contention-aware GPU partitioning engine for
+ * MI355X (gfx950).  Method: Zahaf et al., "Contention-Aware GPU Partitioning
+ * and Task-to-Partition Allocation for Real-Time Workloads", arXiv 2105.10312.
+ *
+ * Problem (paper, Section "Heuristics", problem statement and Algorithm 1's
+ * inputs/outputs): given a set of real-time GPU kernels (tasks) and an integer
+ * number M of compute units, choose partition sizes and a task-to-partition
+ * allocation so that every task meets its deadline, and say whether the set is
+ * schedulable.  This library evaluates, for many task sets at once, every
+ * partitioning of M compute units into at most K partitions, allocates tasks to
+ * the partitions of each partitioning (exhaustively, or with the paper's greedy
+ * heuristic ingredients), tests each partition and keeps the best feasible
+ * (partitioning, allocation); the whole-GPU baseline ("1G", every task on one
+ * partition of M units) is evaluated alongside.
+ *
+ * Model (all integers; times in microseconds):
+ *   Cn_i(m) = C_seq_i + ceil(C_par_i / m)          time on m units, no conflict
+ *   Cc_i(m) = ceil(k_i * Cn_i(m) / 1000)            time on m units, in conflict
+ *     (Section "Modeling kernel execution times": a/m + b per interference
+ *      state; Section "Task set generation": conflict inflation factor k)
+ *   task i is in conflict iff another task of the same type (memory/compute)
+ *   shares its partition (Section "Task Model");
+ *   each partition runs its tasks one at a time on all its units, preemptive
+ *   fixed priority in deadline-monotonic order (D, T, index), exact
+ *   response-time test R_i = C_i + sum_{hp} ceil(R_i/T_j) C_j <= D_i
+ *   (Section "Schedulability test": any policy with an exact test, interference
+ *   folded into the execution times);
+ *   U(P) = sum_{i in P} ceil(C_i * 2^32 / T_i)  (Q32 utilisation, Definition 5);
+ *   best triple = min over feasible triples of (max_p U_p, sum_p U_p,
+ *   partitioning index, allocation index).
+ *   Lemma 1 (sum Cn_i(1)/T_i > M => unschedulable) prunes sets; Lemma 2 gives
+ *   the smallest partition for one task.
+ *
+ * Partitionings of M into at most K parts are integer partitions (parts >= 1,
+ * sum M) written non-increasing and numbered in descending lexicographic order
+ * from 0: M=8, K=3 gives (8),(7,1),(6,2),(6,1,1),(5,3),(5,2,1),(4,4),(4,3,1),
+ * (4,2,2),(3,3,2).  An allocation maps task i to part a_i in [0, k); the
+ * exhaustive mode numbers allocations by the base-k digits of (a_0 .. a_{n-1}),
+ * task 0 most significant; a part may stay empty.
+ *
+ * Heuristic allocation on a fixed partitioning (modes HEUR_*): tasks are taken
+ * in decreasing Cn_i(1)/T_i (ties: lower index); each is placed on the part
+ * that stays schedulable with it and ranks best: BF ranks by (U of the merged
+ * part, part index) -- the order ">" of Definition 5; SMS ranks by (fewest units
+ * the merged part needs, U, part index) -- the order ">>" of Definition 4 with
+ * the search of Algorithm 2; ACT additionally never co-locates a task pair whose
+ * two-task merge is invalid (Definition 3, Section "Forbidden list"); INA does
+ * not.  A task with no candidate part makes the partitioning fail.
+ *
+ * Ownership: callers own every input and output buffer.  Host-pointer calls are
+ * synchronous and borrow buffers for the call only.  *_async calls take device
+ * pointers and are ordered on the given HIP stream; the caller keeps buffers
+ * alive until the stream has passed the operation.  A context owns only its
+ * device workspace and is not thread-safe; use one context per host thread.
+ * No C++ exception crosses this interface.
+ *
+ * Errors: every call returns a capart_status.  Problems with one task set
+ * (invalid sizes or values) are reported in results.status[s] and the batch
+ * continues; an infeasible set is not an error (verdict 0, pidx -1, alloc -1,
+ * R -1).  capart_last_error() gives a message for the last failing call.
+ */
+#ifndef CAPART_H
+#define CAPART_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t capart_status;
+#define CAPART_OK        0
+#define CAPART_E_INVAL  (-1) /* null/inconsistent arguments, sizes out of the supported range */
+#define CAPART_E_RANGE  (-2) /* a task value outside its domain (see capart_tasksets)         */
+#define CAPART_E_NOMEM  (-3) /* device or host allocation failed                              */
+#define CAPART_E_DEVICE (-4) /* HIP runtime error                                             */
+#define CAPART_E_AGAIN  (-5) /* serving back-pressure: no slot or memory free, retry later    */
+#define CAPART_E_STATE  (-6) /* call not valid in the object's current state                  */
+
+/* allocation modes */
+#define CAPART_EXHAUSTIVE    0
+#define CAPART_HEUR_BF_INA   1
+#define CAPART_HEUR_BF_ACT   2
+#define CAPART_HEUR_SMS_INA  3
+#define CAPART_HEUR_SMS_ACT  4
+
+/* per-partition scheduling policy */
+#define CAPART_POLICY_FP_DM  0 /* preemptive fixed priority, deadline monotonic, exact RTA */
+
+/* option flags */
+#define CAPART_FLAG_SKIP_1G         1u /* do not evaluate the whole-GPU baseline (R_1g = -1)    */
+#define CAPART_FLAG_NO_LEMMA1       2u /* disable the Lemma 1 pre-filter (results identical)     */
+#define CAPART_FLAG_PER_SET_LAUNCH  4u /* plain path: one launch sequence per task set           */
+
+/* limits */
+#define CAPART_MAX_TASKS   64   /* tasks per set                                          */
+#define CAPART_MAX_M       255  /* compute units per set                                  */
+#define CAPART_MAX_K       8    /* parts per partitioning                                  */
+#define CAPART_MAX_NM      8192 /* n * M per set (the per-set time table lives in LDS)    */
+
+/*
+ * Task sets, structure of arrays.  Set s holds tasks set_offset[s] ..
+ * set_offset[s+1]-1 and has M[s] compute units.  Domains (else per-set status
+ * E_RANGE): 1 <= T < 2^31; 1 <= D <= T; C_seq >= 0, C_par >= 0,
+ * 1 <= C_seq + C_par < 2^31; 1000 <= k_permille <= 1000000; type in {0, 1}
+ * (0 = compute-intensive, 1 = memory-intensive).  Sizes (else per-set status
+ * E_INVAL): 1 <= n <= min(max_tasks, 64); 1 <= M <= min(max_M, 255);
+ * n * M <= 8192; exhaustive mode needs min(K, M)^n < 2^62.  max_tasks and
+ * max_M are caller-declared bounds over the batch (the launch is sized from
+ * them without reading device memory).
+ */
+typedef struct capart_tasksets {
+    int64_t n_sets;
+    int64_t n_tasks_total;       /* = set_offset[n_sets]                    */
+    int32_t max_tasks;           /* bound on tasks per set, 1..64           */
+    int32_t max_M;               /* bound on M, 1..255                      */
+    const int64_t *set_offset;   /* [n_sets + 1], non-decreasing, from 0    */
+    const int32_t *M;            /* [n_sets]                                */
+    const int64_t *T;            /* [n_tasks_total] period                  */
+    const int64_t *D;            /* [n_tasks_total] relative deadline       */
+    const int64_t *C_seq;        /* [n_tasks_total] part not sped up by m   */
+    const int64_t *C_par;        /* [n_tasks_total] part divided over m     */
+    const int32_t *k_permille;   /* [n_tasks_total] conflict inflation      */
+    const uint8_t *type;         /* [n_tasks_total] 0 compute, 1 memory     */
+} capart_tasksets;
+
+typedef struct capart_options {
+    int32_t K;           /* maximum number of parts, 1..8      */
+    int32_t policy;      /* CAPART_POLICY_FP_DM                */
+    int32_t alloc_mode;  /* CAPART_EXHAUSTIVE or CAPART_HEUR_* */
+    uint32_t flags;      /* CAPART_FLAG_*                      */
+} capart_options;
+
+/*
+ * Results.  Per set: status (CAPART_OK or the set's error), verdict (1 iff a
+ * feasible triple exists), verdict_1g, pidx (index of the chosen partitioning
+ * of M[s] into <= K parts, -1 if none), sizes[s*K .. s*K+K) (its parts,
+ * 0-padded), aidx (allocation index: base-k digits in exhaustive mode, 0 for the
+ * heuristic, -1 if none), maxU and sumU (Q32 utilisation key of the chosen
+ * triple), n_evals (number of partitionings resolved: P(M, K), including sets
+ * rejected by Lemma 1; 0 for invalid sets).  Per task: alloc (part index or -1),
+ * R (response time in the chosen triple or -1), R_1g (response time on the
+ * whole GPU, -1 on a miss or with CAPART_FLAG_SKIP_1G).
+ * Optional debug output, per (set, partitioning): if dbg_key is non-NULL,
+ * dbg_key[3*(dbg_offset[s] + p) + {0,1,2}] = {maxU, sumU, found ? aidx : ~0}
+ * for partitioning p of set s (maxU = sumU = ~0 when nothing is feasible);
+ * dbg_offset[s] is supplied by the caller (e.g. prefix sums of P(M_s, K)).
+ */
+typedef struct capart_results {
+    int32_t *status;
+    uint8_t *verdict;
+    uint8_t *verdict_1g;
+    int32_t *pidx;
+    int32_t *sizes;
+    int64_t *aidx;
+    uint64_t *maxU;
+    uint64_t *sumU;
+    int64_t *n_evals;
+    int8_t *alloc;
+    int64_t *R;
+    int64_t *R_1g;
+    uint64_t *dbg_key;           /* optional, may be NULL */
+    const int64_t *dbg_offset;   /* required iff dbg_key  */
+} capart_results;
+
+typedef struct capart_ctx capart_ctx;
+
+/* Create a context on HIP device `device` (uploads the partition-count table).
+ * E_DEVICE if the device cannot be used, E_NOMEM on allocation failure. */
+capart_status capart_create(int device, capart_ctx **out);
+capart_status capart_destroy(capart_ctx *ctx);
+/* Message for the last failing call on ctx (or for capart_create when ctx is
+ * NULL); never NULL; valid until the next call on ctx. */
+const char *capart_last_error(const capart_ctx *ctx);
+
+/* Number of partitionings of M into at most K positive parts (host only). */
+capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count);
+/* Write them in canonical order into sizes[count*K] (0-padded); at most
+ * `capacity` partitionings are written; *count gets the total (host only). */
+capart_status capart_enumerate_partitionings(int32_t M, int32_t K, int32_t *sizes, int64_t capacity,
+                                             int64_t *count);
+/* Host-side validation of a host-pointer batch: status_out[n_sets] gets each
+ * set's status (the same rules the device applies).  Returns E_INVAL for
+ * batch-level problems (NULL pointers, bad offsets, K or mode out of range). */
+capart_status capart_validate(const capart_tasksets *host_in, const capart_options *opt, int32_t *status_out);
+
+/* Evaluate one triple of one set (host pointers, set_offset = {0, n}):
+ * sizes[k] (parts, any order), alloc[n] in [0, k).  Every task is tested (no
+ * early exit): R[n] gets response times or -1; *feasible = all met; *maxU and
+ * *sumU are valid when feasible.  Runs on the device. */
+capart_status capart_test_triple(capart_ctx *ctx, const capart_tasksets *one_set, const int32_t *sizes, int32_t k,
+                                 const int8_t *alloc, uint8_t *feasible, int64_t *R, uint64_t *maxU,
+                                 uint64_t *sumU);
+/* Best allocation of one set on one fixed partitioning sizes[k] (non-increasing,
+ * sum M, k <= opt->K) under opt->alloc_mode: *found, alloc_out[n] (-1 if not
+ * found), *maxU, *sumU, *aidx.  Runs on the device. */
+capart_status capart_allocate(capart_ctx *ctx, const capart_tasksets *one_set, const int32_t *sizes, int32_t k,
+                              const capart_options *opt, int8_t *alloc_out, uint8_t *found, uint64_t *maxU,
+                              uint64_t *sumU, int64_t *aidx);
+
+/* Solve a batch held in host memory; results in host memory (synchronous). */
+capart_status capart_solve(capart_ctx *ctx, const capart_tasksets *host_in, const capart_options *opt,
+                           capart_results *host_out);
+/* Solve a batch held in device memory; results written to device memory,
+ * ordered on hip_stream (a hipStream_t, NULL = default stream).  This is the
+ * plain GPU path: one launch sequence over the whole batch, or one per set
+ * with CAPART_FLAG_PER_SET_LAUNCH. */
+capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                 capart_results *dev_out, void *hip_stream);
+
+/* Kernel timing.  While enabled on a context, every launch sequence of
+ * capart_solve / capart_solve_async records HIP events on its own stream
+ * before and after the prep, eval and final kernels (one sequence per batch,
+ * or per set with CAPART_FLAG_PER_SET_LAUNCH).  capart_timing_read waits for
+ * the recorded events, returns the summed durations in milliseconds
+ * (ms[0] prep, ms[1] eval, ms[2] final) and the number of launches of each
+ * (launches[3]), and clears them.  Disabling drops unread records. */
+capart_status capart_timing_enable(capart_ctx *ctx, int enable);
+capart_status capart_timing_read(capart_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAPART_H */

@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build()
         lib = C.CDLL(LIB)
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C")

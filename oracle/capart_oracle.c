@@ -356,6 +356,7 @@ static int or_validate(const or_set *s, int K, int mode)
 {
     int i;
     if (s->n < 1 || s->n > OR_MAXN || s->M < 1 || s->M > 255) return OR_E_INVAL;
+    if (s->n * s->M > 8192) return OR_E_INVAL; /* the boundary's per-set size limit */
     for (i = 0; i < s->n; i++) {
         int64_t T = s->T[i], D = s->D[i], a = s->Cs[i], b = s->Cp[i];
         if (T < 1 || T >= ((int64_t)1 << 31)) return OR_E_RANGE;

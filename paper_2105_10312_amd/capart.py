@@ -1,0 +1,338 @@
+"""Thin ctypes binding of libcapart (the gfx950 engine's C ABI).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind ``include/capart.h``.  Functions keep the C names.  Host-pointer calls
+take numpy arrays; ``capart_solve_async`` takes torch tensors that live on the
+GPU (torch is used for device memory and streams, nothing else).  There is no
+CPU fallback: if ``libcapart.so`` is missing the import of the library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcapart.so")
+
+CAPART_OK, CAPART_E_INVAL, CAPART_E_RANGE, CAPART_E_NOMEM = 0, -1, -2, -3
+CAPART_E_DEVICE, CAPART_E_AGAIN, CAPART_E_STATE = -4, -5, -6
+CAPART_EXHAUSTIVE, CAPART_HEUR_BF_INA, CAPART_HEUR_BF_ACT = 0, 1, 2
+CAPART_HEUR_SMS_INA, CAPART_HEUR_SMS_ACT = 3, 4
+CAPART_POLICY_FP_DM = 0
+CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
+MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
+         "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
+EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count_partitionings",
+           "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
+           "capart_solve", "capart_solve_async", "capart_timing_enable", "capart_timing_read"]
+
+_vp = C.c_void_p
+
+
+class capart_tasksets(C.Structure):
+    _fields_ = [("n_sets", C.c_int64), ("n_tasks_total", C.c_int64), ("max_tasks", C.c_int32),
+                ("max_M", C.c_int32), ("set_offset", _vp), ("M", _vp), ("T", _vp), ("D", _vp),
+                ("C_seq", _vp), ("C_par", _vp), ("k_permille", _vp), ("type", _vp)]
+
+
+class capart_options(C.Structure):
+    _fields_ = [("K", C.c_int32), ("policy", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32)]
+
+
+class capart_results(C.Structure):
+    _fields_ = [("status", _vp), ("verdict", _vp), ("verdict_1g", _vp), ("pidx", _vp), ("sizes", _vp),
+                ("aidx", _vp), ("maxU", _vp), ("sumU", _vp), ("n_evals", _vp), ("alloc", _vp), ("R", _vp),
+                ("R_1g", _vp), ("dbg_key", _vp), ("dbg_offset", _vp)]
+
+
+class CapartError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"capart error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libcapart.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes libcapart bind to that one copy, so that torch's device
+        # memory and streams belong to the runtime that launches the kernels
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        lib.capart_create.argtypes = [C.c_int, P(_vp)]
+        lib.capart_destroy.argtypes = [_vp]
+        lib.capart_last_error.argtypes = [_vp]
+        lib.capart_last_error.restype = C.c_char_p
+        lib.capart_count_partitionings.argtypes = [C.c_int32, C.c_int32, P(C.c_int64)]
+        lib.capart_enumerate_partitionings.argtypes = [C.c_int32, C.c_int32, _vp, C.c_int64, P(C.c_int64)]
+        lib.capart_validate.argtypes = [P(capart_tasksets), P(capart_options), _vp]
+        lib.capart_test_triple.argtypes = [_vp, P(capart_tasksets), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
+        lib.capart_allocate.argtypes = [_vp, P(capart_tasksets), _vp, C.c_int32, P(capart_options), _vp, _vp,
+                                        _vp, _vp, _vp]
+        lib.capart_solve.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results)]
+        lib.capart_solve_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp]
+        lib.capart_timing_enable.argtypes = [_vp, C.c_int]
+        lib.capart_timing_read.argtypes = [_vp, _vp, _vp]
+        for name in EXPORTS:
+            if name != "capart_last_error":
+                getattr(lib, name).restype = C.c_int32
+        _lib = lib
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != CAPART_OK:
+        msg = load_library().capart_last_error(ctx)
+        raise CapartError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def make_options(K: int, mode="BF_INA", flags: int = 0) -> capart_options:
+    return capart_options(int(K), CAPART_POLICY_FP_DM, _mode(mode), int(flags))
+
+
+def make_tasksets(ts: dict, max_tasks: int | None = None, max_M: int | None = None) -> tuple:
+    """capart_tasksets over numpy (host) or torch (device) arrays; returns (struct, keep-alive)."""
+    off = ts["set_offset"]
+    S = int(ts["M"].shape[0])
+    if max_tasks is None:
+        sizes = np.diff(np.asarray(off.cpu() if hasattr(off, "cpu") else off))
+        max_tasks = int(min(64, max(1, sizes.max() if S else 1)))
+    if max_M is None:
+        Mh = ts["M"].cpu().numpy() if hasattr(ts["M"], "cpu") else ts["M"]
+        max_M = int(min(255, max(1, Mh.max() if S else 1)))
+    N = int(ts["T"].shape[0])
+    st = capart_tasksets(S, N, int(max_tasks), int(max_M), _ptr(off), _ptr(ts["M"]), _ptr(ts["T"]),
+                         _ptr(ts["D"]), _ptr(ts["C_seq"]), _ptr(ts["C_par"]), _ptr(ts["k_permille"]),
+                         _ptr(ts["type"]))
+    return st, ts
+
+
+def _host_ts(ts: dict) -> dict:
+    return {"set_offset": np.ascontiguousarray(ts["set_offset"], np.int64),
+            "M": np.ascontiguousarray(ts["M"], np.int32),
+            "T": np.ascontiguousarray(ts["T"], np.int64), "D": np.ascontiguousarray(ts["D"], np.int64),
+            "C_seq": np.ascontiguousarray(ts["C_seq"], np.int64),
+            "C_par": np.ascontiguousarray(ts["C_par"], np.int64),
+            "k_permille": np.ascontiguousarray(ts["k_permille"], np.int32),
+            "type": np.ascontiguousarray(ts["type"], np.uint8)}
+
+
+# ---- C-ABI mirrors ---------------------------------------------------------------
+
+def capart_create(device: int = 0):
+    lib = load_library()
+    h = _vp()
+    _check(lib.capart_create(int(device), C.byref(h)), None)
+    return h
+
+
+def capart_destroy(ctx) -> None:
+    _check(load_library().capart_destroy(ctx))
+
+
+def capart_last_error(ctx=None) -> str:
+    return load_library().capart_last_error(ctx).decode()
+
+
+def capart_count_partitionings(M: int, K: int) -> int:
+    c = C.c_int64(0)
+    _check(load_library().capart_count_partitionings(int(M), int(K), C.byref(c)))
+    return int(c.value)
+
+
+def capart_enumerate_partitionings(M: int, K: int) -> np.ndarray:
+    P = capart_count_partitionings(M, K)
+    buf = np.zeros((max(P, 1), K), np.int32)
+    c = C.c_int64(0)
+    _check(load_library().capart_enumerate_partitionings(int(M), int(K), buf.ctypes.data, P, C.byref(c)))
+    return buf[:P]
+
+
+def capart_validate(ts: dict, K: int, mode="BF_INA", flags: int = 0, max_tasks=None, max_M=None) -> np.ndarray:
+    h = _host_ts(ts)
+    st, _keep = make_tasksets(h, max_tasks, max_M)
+    opt = make_options(K, mode, flags)
+    out = np.zeros(st.n_sets, np.int32)
+    _check(load_library().capart_validate(C.byref(st), C.byref(opt), out.ctypes.data))
+    return out
+
+
+def _one_set(task: dict) -> dict:
+    n = len(task["T"])
+    return _host_ts({"set_offset": np.array([0, n]), "M": np.array([int(task["M"])]), "T": task["T"],
+                     "D": task["D"], "C_seq": task["C_seq"], "C_par": task["C_par"],
+                     "k_permille": task["k_permille"], "type": task["type"]})
+
+
+def capart_test_triple(ctx, task: dict, sizes, alloc):
+    """One triple of one set on the device: (feasible, R[n], maxU, sumU)."""
+    h = _one_set(task)
+    st, _keep = make_tasksets(h)
+    sz = np.ascontiguousarray(sizes, np.int32)
+    al = np.ascontiguousarray(alloc, np.int8)
+    n = len(al)
+    feas = np.zeros(1, np.uint8)
+    R = np.zeros(n, np.int64)
+    mx = np.zeros(1, np.uint64)
+    sm = np.zeros(1, np.uint64)
+    _check(load_library().capart_test_triple(ctx, C.byref(st), sz.ctypes.data, len(sz), al.ctypes.data,
+                                             feas.ctypes.data, R.ctypes.data, mx.ctypes.data, sm.ctypes.data), ctx)
+    return bool(feas[0]), R, int(mx[0]), int(sm[0])
+
+
+def capart_allocate(ctx, task: dict, sizes, K: int, mode="BF_INA"):
+    """Best allocation on one partitioning: (found, alloc[n], maxU, sumU, aidx)."""
+    h = _one_set(task)
+    st, _keep = make_tasksets(h)
+    sz = np.ascontiguousarray(sizes, np.int32)
+    opt = make_options(K, mode)
+    n = len(task["T"])
+    al = np.zeros(n, np.int8)
+    found = np.zeros(1, np.uint8)
+    mx = np.zeros(1, np.uint64)
+    sm = np.zeros(1, np.uint64)
+    ai = np.zeros(1, np.int64)
+    _check(load_library().capart_allocate(ctx, C.byref(st), sz.ctypes.data, len(sz), C.byref(opt), al.ctypes.data,
+                                          found.ctypes.data, mx.ctypes.data, sm.ctypes.data, ai.ctypes.data), ctx)
+    return bool(found[0]), al, int(mx[0]), int(sm[0]), int(ai[0])
+
+
+RESULT_FIELDS = (("status", np.int32, "S"), ("verdict", np.uint8, "S"), ("verdict_1g", np.uint8, "S"),
+                 ("pidx", np.int32, "S"), ("sizes", np.int32, "SK"), ("aidx", np.int64, "S"),
+                 ("maxU", np.uint64, "S"), ("sumU", np.uint64, "S"), ("n_evals", np.int64, "S"),
+                 ("alloc", np.int8, "N"), ("R", np.int64, "N"), ("R_1g", np.int64, "N"))
+
+
+def dbg_offsets(M, K: int) -> np.ndarray:
+    """Prefix sums of P(M_s, K): start of each set's per-partitioning debug keys."""
+    M = np.asarray(M)
+    cnt = np.array([capart_count_partitionings(int(m), K) if 1 <= m <= 255 else 0 for m in M], np.int64)
+    off = np.zeros(len(M) + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    return off
+
+
+def capart_solve(ctx, ts: dict, K: int, mode="BF_INA", flags: int = 0, debug: bool = False, max_tasks=None,
+                 max_M=None) -> dict:
+    """Solve a host batch (synchronous); returns a dict of numpy result arrays."""
+    h = _host_ts(ts)
+    st, _keep = make_tasksets(h, max_tasks, max_M)
+    opt = make_options(K, mode, flags)
+    S, N = st.n_sets, st.n_tasks_total
+    out = {}
+    for name, dt, shape in RESULT_FIELDS:
+        size = S if shape == "S" else (S * K if shape == "SK" else N)
+        out[name] = np.zeros(max(size, 1), dt)
+    dbg = dboff = None
+    if debug:
+        dboff = dbg_offsets(h["M"], K)
+        dbg = np.zeros(max(3 * int(dboff[-1]), 3), np.uint64)
+    res = capart_results(*[_ptr(out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg), _ptr(dboff))
+    _check(load_library().capart_solve(ctx, C.byref(st), C.byref(opt), C.byref(res)), ctx)
+    for name, dt, shape in RESULT_FIELDS:
+        size = S if shape == "S" else (S * K if shape == "SK" else N)
+        out[name] = out[name][:size]
+    out["sizes"] = out["sizes"].reshape(S, K)
+    if debug:
+        out["dbg_key"] = dbg[:3 * int(dboff[-1])].reshape(-1, 3)
+        out["dbg_offset"] = dboff
+    return out
+
+
+def device_results(S: int, N: int, K: int, device="cuda"):
+    """Allocate result tensors on the GPU for capart_solve_async."""
+    import torch
+    tmap = {np.int32: torch.int32, np.uint8: torch.uint8, np.int64: torch.int64, np.uint64: torch.uint64,
+            np.int8: torch.int8}
+    out = {}
+    for name, dt, shape in RESULT_FIELDS:
+        size = S if shape == "S" else (S * K if shape == "SK" else N)
+        out[name] = torch.empty(max(size, 1), dtype=tmap[dt], device=device)
+    return out
+
+
+def device_tasksets(ts: dict, device="cuda") -> dict:
+    """Copy a host batch to GPU tensors (SoA, same dtypes)."""
+    import torch
+    h = _host_ts(ts)
+    return {k: torch.from_numpy(v).to(device) for k, v in h.items()}
+
+
+def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=None, flags: int = 0,
+                       max_tasks=None, max_M=None, dbg_key=None, dbg_offset=None) -> None:
+    """Solve a batch resident in GPU memory; results land in dev_out (torch tensors) on `stream`."""
+    import torch
+    if max_tasks is None or max_M is None:
+        raise ValueError("device batches need declared max_tasks and max_M bounds")
+    st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
+    opt = make_options(K, mode, flags)
+    res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load_library().capart_solve_async(ctx, C.byref(st), C.byref(opt), C.byref(res),
+                                             C.c_void_p(stream.cuda_stream)), ctx)
+
+
+def capart_timing_enable(ctx, enable: bool = True) -> None:
+    _check(load_library().capart_timing_enable(ctx, int(bool(enable))), ctx)
+
+
+def capart_timing_read(ctx):
+    """Summed kernel milliseconds since the last read: ({prep, eval, final}, {launch counts})."""
+    ms = np.zeros(3, np.float64)
+    n = np.zeros(3, np.int64)
+    _check(load_library().capart_timing_read(ctx, ms.ctypes.data, n.ctypes.data), ctx)
+    names = ("prep", "eval", "final")
+    return dict(zip(names, ms.tolist())), dict(zip(names, n.tolist()))
+
+
+class Engine:
+    """Owns one context on one device."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = capart_create(device)
+
+    def close(self):
+        if self.ctx is not None:
+            capart_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, ts, K, mode="BF_INA", flags=0, debug=False):
+        return capart_solve(self.ctx, ts, K, mode, flags, debug)
+
+    def test_triple(self, task, sizes, alloc):
+        return capart_test_triple(self.ctx, task, sizes, alloc)
+
+    def allocate(self, task, sizes, K, mode="BF_INA"):
+        return capart_allocate(self.ctx, task, sizes, K, mode)

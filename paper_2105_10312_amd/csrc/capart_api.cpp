@@ -1,0 +1,735 @@
+// C ABI of the engine: context, workspace, host-side validation, partition
+// enumeration and launch orchestration.  Every step of the method runs in the
+// gfx950 kernels; this file only sizes, checks and sequences them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "capart.h"
+#include "capart_internal.h"
+
+using namespace capart;
+
+struct capart_ctx {
+    int device = 0;
+    std::string err;
+    std::vector<uint32_t> np_host;
+    uint32_t *np_dev = nullptr;
+    hipStream_t stream = nullptr;  // for host-pointer calls
+    void *ws = nullptr;            // workspace
+    size_t ws_bytes = 0;
+    void *stage = nullptr;         // staging buffer for host-pointer calls
+    size_t stage_bytes = 0;
+    bool timing = false;           // record kernel events
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::array<hipEvent_t, 4>> ev_pending;
+};
+
+namespace {
+
+std::string g_create_err = "no error";
+
+capart_status fail(capart_ctx *c, capart_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+capart_status hip_fail(capart_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, CAPART_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// NP(r, j, x): partitions of r into at most j parts, each part <= x.
+void build_np(std::vector<uint32_t> &np)
+{
+    np.assign((size_t)NP_J * NP_R * NP_X, 0u);
+    for (int x = 0; x < NP_X; x++) np[np_index(0, 0, x)] = 1u;
+    for (int j = 1; j < NP_J; j++) {
+        for (int r = 0; r < NP_R; r++) {
+            for (int x = 0; x < NP_X; x++) {
+                uint64_t c = 0;
+                if (r == 0) {
+                    c = 1;
+                } else {
+                    // first (largest) part y in [1, min(x, r)], rest <= y in j-1 parts
+                    const int top = std::min(x, r);
+                    for (int y = 1; y <= top; y++) c += np[np_index(j - 1, r - y, y)];
+                }
+                np[np_index(j, r, x)] = (uint32_t)c;
+            }
+        }
+    }
+}
+
+const std::vector<uint32_t> &host_np()
+{
+    static std::vector<uint32_t> tab;
+    if (tab.empty()) build_np(tab);
+    return tab;
+}
+
+uint32_t count_parts(int M, int K) { return host_np()[np_index(K, M, M)]; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t rec, forbid, sigma, setflags, memmask, partial, total;
+};
+
+WsLayout ws_layout(int64_t S, int64_t N, int chunks)
+{
+    WsLayout l;
+    size_t o = 0;
+    l.rec = o; o = align256(o + sizeof(TaskRec) * (size_t)std::max<int64_t>(N, 1));
+    l.forbid = o; o = align256(o + 8 * (size_t)std::max<int64_t>(N, 1));
+    l.sigma = o; o = align256(o + (size_t)std::max<int64_t>(N, 1));
+    l.setflags = o; o = align256(o + 4 * (size_t)std::max<int64_t>(S, 1));
+    l.memmask = o; o = align256(o + 8 * (size_t)std::max<int64_t>(S, 1));
+    l.partial = o; o = align256(o + 32 * (size_t)std::max<int64_t>(S, 1) * (size_t)chunks);
+    l.total = o;
+    return l;
+}
+
+capart_status ensure_ws(capart_ctx *c, size_t bytes)
+{
+    if (bytes <= c->ws_bytes) return CAPART_OK;
+    hipError_t e = hipDeviceSynchronize();  // earlier calls may still use the old workspace
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    if (c->ws) hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    e = hipMalloc(&c->ws, bytes);
+    if (e != hipSuccess) {
+        c->ws = nullptr;
+        return fail(c, CAPART_E_NOMEM, "workspace allocation failed");
+    }
+    c->ws_bytes = bytes;
+    return CAPART_OK;
+}
+
+capart_status ensure_stage(capart_ctx *c, size_t bytes)
+{
+    if (bytes <= c->stage_bytes) return CAPART_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    if (c->stage) hipFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    e = hipMalloc(&c->stage, bytes);
+    if (e != hipSuccess) {
+        c->stage = nullptr;
+        return fail(c, CAPART_E_NOMEM, "staging allocation failed");
+    }
+    c->stage_bytes = bytes;
+    return CAPART_OK;
+}
+
+bool valid_mode(int m) { return m >= CAPART_EXHAUSTIVE && m <= CAPART_HEUR_SMS_ACT; }
+
+capart_status check_options(capart_ctx *c, const capart_options *opt)
+{
+    if (!opt) return fail(c, CAPART_E_INVAL, "options is NULL");
+    if (opt->K < 1 || opt->K > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "K must be in [1, 8]");
+    if (opt->policy != CAPART_POLICY_FP_DM) return fail(c, CAPART_E_INVAL, "unsupported policy");
+    if (!valid_mode(opt->alloc_mode)) return fail(c, CAPART_E_INVAL, "unknown allocation mode");
+    if (opt->flags & ~(CAPART_FLAG_SKIP_1G | CAPART_FLAG_NO_LEMMA1 | CAPART_FLAG_PER_SET_LAUNCH))
+        return fail(c, CAPART_E_INVAL, "unknown flag");
+    return CAPART_OK;
+}
+
+capart_status check_batch_shape(capart_ctx *c, const capart_tasksets *in)
+{
+    if (!in) return fail(c, CAPART_E_INVAL, "task sets is NULL");
+    if (in->n_sets < 0 || in->n_tasks_total < 0) return fail(c, CAPART_E_INVAL, "negative size");
+    if (in->n_sets > ((int64_t)1 << 31) - 1) return fail(c, CAPART_E_INVAL, "too many sets for one launch");
+    if (in->max_tasks < 1 || in->max_tasks > CAPART_MAX_TASKS) return fail(c, CAPART_E_INVAL, "max_tasks out of [1,64]");
+    if (in->max_M < 1 || in->max_M > CAPART_MAX_M) return fail(c, CAPART_E_INVAL, "max_M out of [1,255]");
+    if (in->n_sets > 0 && (!in->set_offset || !in->M))
+        return fail(c, CAPART_E_INVAL, "NULL set arrays");
+    if (in->n_tasks_total > 0 && (!in->T || !in->D || !in->C_seq || !in->C_par || !in->k_permille || !in->type))
+        return fail(c, CAPART_E_INVAL, "NULL task arrays");
+    return CAPART_OK;
+}
+
+bool results_ok(const capart_results *r)
+{
+    return r && r->status && r->verdict && r->verdict_1g && r->pidx && r->sizes && r->aidx && r->maxU && r->sumU &&
+           r->n_evals && r->alloc && r->R && r->R_1g && (!r->dbg_key || r->dbg_offset);
+}
+
+// Per-set validation on the host (same rules as the device).
+int32_t validate_set(const capart_tasksets *in, int64_t s, int K, int mode)
+{
+    const int64_t o0 = in->set_offset[s], o1 = in->set_offset[s + 1];
+    if (o0 < 0 || o1 < o0 || o1 > in->n_tasks_total) return CAPART_E_INVAL;
+    const int64_t n = o1 - o0;
+    const int32_t M = in->M[s];
+    if (n < 1 || n > std::min(in->max_tasks, CAPART_MAX_TASKS) || M < 1 || M > std::min(in->max_M, CAPART_MAX_M) ||
+        n * M > CAPART_MAX_NM)
+        return CAPART_E_INVAL;
+    const int64_t L31 = (int64_t)1 << 31;
+    for (int64_t i = o0; i < o1; i++) {
+        const int64_t T = in->T[i], D = in->D[i], a = in->C_seq[i], b = in->C_par[i];
+        const int32_t k = in->k_permille[i];
+        if (T < 1 || T >= L31 || D < 1 || D > T || a < 0 || b < 0 || a >= L31 || b >= L31 || a + b < 1 ||
+            a + b >= L31 || k < 1000 || k > 1000000 || in->type[i] > 1)
+            return CAPART_E_RANGE;
+    }
+    if (mode == CAPART_EXHAUSTIVE) {
+        const uint64_t kk = (uint64_t)std::min(K, M);
+        const uint64_t lim = ((1ull << 62) - 1ull) / kk;
+        uint64_t pw = 1;
+        for (int64_t i = 0; i < n; i++) {
+            if (pw > lim) return CAPART_E_INVAL;
+            pw *= kk;
+        }
+    }
+    return CAPART_OK;
+}
+
+struct Plan {
+    Launch L;
+    int64_t S, N;
+};
+
+Plan make_plan(const capart_tasksets *in, const capart_options *opt)
+{
+    Plan p;
+    p.S = in->n_sets;
+    p.N = in->n_tasks_total;
+    Launch &L = p.L;
+    L.s0 = 0;
+    L.S = p.S;
+    L.K = opt->K;
+    L.mode = opt->alloc_mode;
+    L.flags = opt->flags;
+    L.threads = 256;
+    const uint32_t Pmax = count_parts(in->max_M, opt->K);
+    if (opt->alloc_mode == CAPART_EXHAUSTIVE) {
+        L.chunks = (int)Pmax;
+        L.chunk = 1;
+    } else {
+        // enough blocks to fill the chip (~8 per CU) while keeping one table
+        // build per block amortised over many partitionings
+        const int64_t per_set_launch = (opt->flags & CAPART_FLAG_PER_SET_LAUNCH) ? 1 : p.S;
+        const int64_t want_blocks = 2048;
+        int64_t ch = (want_blocks + std::max<int64_t>(per_set_launch, 1) - 1) / std::max<int64_t>(per_set_launch, 1);
+        const int64_t chmax = std::max<int64_t>(1, (Pmax + 255) / 256);
+        ch = std::max<int64_t>(1, std::min(ch, chmax));
+        L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
+        L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
+    }
+    return p;
+}
+
+hipEvent_t take_event(capart_ctx *c)
+{
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch prep, eval and final for one launch range, with timing events when enabled.
+capart_status launch_three(capart_ctx *c, const Batch &b, const Work &w, const Out &o, const Launch &L,
+                           hipStream_t st, uint32_t p_lo, uint32_t p_hi)
+{
+    std::array<hipEvent_t, 4> ev{};
+    const bool tm = c->timing;
+    if (tm)
+        for (auto &e : ev)
+            if (!(e = take_event(c))) return fail(c, CAPART_E_DEVICE, "hipEventCreate failed");
+    hipError_t e;
+    if (tm) hipEventRecord(ev[0], st);
+    if ((e = launch_prep(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if (tm) hipEventRecord(ev[1], st);
+    if ((e = launch_eval_range(b, w, o, L, st, p_lo, p_hi)) != hipSuccess) return hip_fail(c, e, "eval launch");
+    if (tm) hipEventRecord(ev[2], st);
+    if ((e = launch_final(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
+    if (tm) {
+        hipEventRecord(ev[3], st);
+        c->ev_pending.push_back(ev);
+    }
+    return CAPART_OK;
+}
+
+capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &p, hipStream_t st,
+                       uint32_t p_lo = 0u, uint32_t p_hi = 0xFFFFFFFFu)
+{
+    const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
+    capart_status rc = ensure_ws(c, l.total);
+    if (rc != CAPART_OK) return rc;
+    char *base = (char *)c->ws;
+    Work w;
+    w.rec = (TaskRec *)(base + l.rec);
+    w.forbid = (uint64_t *)(base + l.forbid);
+    w.sigma = (uint8_t *)(base + l.sigma);
+    w.setflags = (uint32_t *)(base + l.setflags);
+    w.memmask = (uint64_t *)(base + l.memmask);
+    w.partial = (uint64_t *)(base + l.partial);
+    w.np = c->np_dev;
+    if (p.L.flags & CAPART_FLAG_PER_SET_LAUNCH) {
+        for (int64_t s = 0; s < p.S; s++) {
+            Launch L1 = p.L;
+            L1.s0 = s;
+            L1.S = 1;
+            if ((rc = launch_three(c, b, w, o, L1, st, p_lo, p_hi)) != CAPART_OK) return rc;
+        }
+        return CAPART_OK;
+    }
+    return launch_three(c, b, w, o, p.L, st, p_lo, p_hi);
+}
+
+Batch make_batch(const capart_tasksets *in)
+{
+    Batch b;
+    b.off = in->set_offset;
+    b.M = in->M;
+    b.T = in->T;
+    b.D = in->D;
+    b.Cs = in->C_seq;
+    b.Cp = in->C_par;
+    b.k = in->k_permille;
+    b.type = in->type;
+    b.n_tasks_total = in->n_tasks_total;
+    b.max_tasks = in->max_tasks;
+    b.max_M = in->max_M;
+    return b;
+}
+
+Out make_out(const capart_results *r)
+{
+    Out o;
+    o.status = r->status;
+    o.verdict = r->verdict;
+    o.verdict_1g = r->verdict_1g;
+    o.pidx = r->pidx;
+    o.sizes = r->sizes;
+    o.aidx = r->aidx;
+    o.maxU = r->maxU;
+    o.sumU = r->sumU;
+    o.n_evals = r->n_evals;
+    o.alloc = r->alloc;
+    o.R = r->R;
+    o.R_1g = r->R_1g;
+    o.dbg_key = r->dbg_key;
+    o.dbg_offset = r->dbg_offset;
+    return o;
+}
+
+// Bump allocator over the staging buffer.
+struct Bump {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n)
+    {
+        T *p = (T *)(base + off);
+        off = align256(off + sizeof(T) * std::max<size_t>(n, 1));
+        return p;
+    }
+};
+
+size_t stage_need(int64_t S, int64_t N, int K, int64_t ndbg)
+{
+    size_t t = 0;
+    auto add = [&](size_t bytes) { t = align256(t + std::max<size_t>(bytes, 1)); };
+    add(8 * (S + 1)); add(4 * S);                                          // offsets, M
+    add(8 * N); add(8 * N); add(8 * N); add(8 * N); add(4 * N); add(N);    // task arrays
+    add(4 * S); add(S); add(S); add(4 * S); add(4 * S * K); add(8 * S);  // status .. aidx
+    add(8 * S); add(8 * S); add(8 * S);                                    // maxU sumU n_evals
+    add(N); add(8 * N); add(8 * N);                                        // alloc R R_1g
+    add(24 * ndbg); add(8 * S);                                            // dbg
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+capart_status capart_create(int device, capart_ctx **out)
+{
+    if (!out) return CAPART_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        g_create_err = std::string("no HIP device: ") + hipGetErrorString(e);
+        return CAPART_E_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        g_create_err = "device index out of range";
+        return CAPART_E_INVAL;
+    }
+    capart_ctx *c = new (std::nothrow) capart_ctx;
+    if (!c) return CAPART_E_NOMEM;
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        delete c;
+        return CAPART_E_DEVICE;
+    }
+    const std::vector<uint32_t> &np = host_np();
+    if ((e = hipMalloc(&c->np_dev, np.size() * sizeof(uint32_t))) != hipSuccess) {
+        g_create_err = "count table allocation failed";
+        delete c;
+        return CAPART_E_NOMEM;
+    }
+    if ((e = hipMemcpy(c->np_dev, np.data(), np.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipStreamCreate(&c->stream)) != hipSuccess) {
+        g_create_err = std::string("context setup: ") + hipGetErrorString(e);
+        hipFree(c->np_dev);
+        if (c->stream) hipStreamDestroy(c->stream);
+        delete c;
+        return CAPART_E_DEVICE;
+    }
+    // raise the dynamic-LDS limit for the largest per-set tables; if the
+    // runtime refuses, launches needing more than the default report E_DEVICE
+    e = configure_kernels();
+    c->err = (e == hipSuccess) ? "no error" : std::string("LDS limit not raised: ") + hipGetErrorString(e);
+    *out = c;
+    return CAPART_OK;
+}
+
+capart_status capart_destroy(capart_ctx *c)
+{
+    if (!c) return CAPART_E_INVAL;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &a : c->ev_pending)
+        for (auto e : a) hipEventDestroy(e);
+    for (auto e : c->ev_free) hipEventDestroy(e);
+    if (c->ws) hipFree(c->ws);
+    if (c->stage) hipFree(c->stage);
+    if (c->np_dev) hipFree(c->np_dev);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+    return CAPART_OK;
+}
+
+const char *capart_last_error(const capart_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count)
+{
+    if (!count || M < 1 || M > CAPART_MAX_M || K < 1 || K > CAPART_MAX_K) return CAPART_E_INVAL;
+    *count = count_parts(M, K);
+    return CAPART_OK;
+}
+
+capart_status capart_enumerate_partitionings(int32_t M, int32_t K, int32_t *sizes, int64_t capacity, int64_t *count)
+{
+    if (!count || M < 1 || M > CAPART_MAX_M || K < 1 || K > CAPART_MAX_K || capacity < 0 || (capacity > 0 && !sizes))
+        return CAPART_E_INVAL;
+    const int64_t P = count_parts(M, K);
+    *count = P;
+    if (capacity == 0) return CAPART_OK;
+    // first partitioning (M), then successors in descending lexicographic order
+    std::vector<int32_t> a(K, 0);
+    a[0] = M;
+    for (int64_t q = 0; q < P && q < capacity; q++) {
+        std::copy(a.begin(), a.end(), sizes + q * K);
+        // successor: rightmost part that can shrink by one with the remainder
+        // refilled greedily into the parts to its right
+        int tail = 0, sel = -1;
+        for (int i = K - 1; i >= 0; i--) {
+            if (a[i] > 1 && tail + 1 <= (K - i - 1) * (a[i] - 1)) { sel = i; break; }
+            tail += a[i];
+        }
+        if (sel < 0) break;
+        const int v = a[sel] - 1;
+        int rest = tail + 1;
+        a[sel] = v;
+        for (int i = sel + 1; i < K; i++) {
+            const int x = std::min(v, rest);
+            a[i] = x;
+            rest -= x;
+        }
+    }
+    return CAPART_OK;
+}
+
+capart_status capart_validate(const capart_tasksets *in, const capart_options *opt, int32_t *status_out)
+{
+    capart_status rc;
+    if ((rc = check_options(nullptr, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(nullptr, in)) != CAPART_OK) return rc;
+    if (in->n_sets > 0 && !status_out) return CAPART_E_INVAL;
+    for (int64_t s = 0; s < in->n_sets; s++) status_out[s] = validate_set(in, s, opt->K, opt->alloc_mode);
+    return CAPART_OK;
+}
+
+capart_status capart_solve_async(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                 capart_results *out, void *hip_stream)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const Plan p = make_plan(in, opt);
+    return run_plan(c, make_batch(in), make_out(out), p, (hipStream_t)hip_stream);
+}
+
+static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                capart_results *out, uint32_t p_lo, uint32_t p_hi)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
+    if (in->set_offset[0] != 0 || in->set_offset[in->n_sets] != in->n_tasks_total)
+        return fail(c, CAPART_E_INVAL, "set_offset must run from 0 to n_tasks_total");
+    const int64_t S = in->n_sets, N = in->n_tasks_total;
+    const int K = opt->K;
+    int64_t ndbg = 0;
+    if (out->dbg_key) {
+        for (int64_t s = 0; s < S; s++) {
+            const int32_t M = in->M[s];
+            if (M >= 1 && M <= CAPART_MAX_M) ndbg = std::max<int64_t>(ndbg, out->dbg_offset[s] + count_parts(M, K));
+        }
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if ((rc = ensure_stage(c, stage_need(S, N, K, ndbg))) != CAPART_OK) return rc;
+    Bump bp{(char *)c->stage};
+    capart_tasksets d = *in;
+    int64_t *d_off = bp.take<int64_t>(S + 1);
+    int32_t *d_M = bp.take<int32_t>(S);
+    int64_t *d_T = bp.take<int64_t>(N), *d_D = bp.take<int64_t>(N), *d_Cs = bp.take<int64_t>(N),
+            *d_Cp = bp.take<int64_t>(N);
+    int32_t *d_k = bp.take<int32_t>(N);
+    uint8_t *d_ty = bp.take<uint8_t>(N);
+    capart_results r;
+    r.status = bp.take<int32_t>(S);
+    r.verdict = bp.take<uint8_t>(S);
+    r.verdict_1g = bp.take<uint8_t>(S);
+    r.pidx = bp.take<int32_t>(S);
+    r.sizes = bp.take<int32_t>(S * K);
+    r.aidx = bp.take<int64_t>(S);
+    r.maxU = bp.take<uint64_t>(S);
+    r.sumU = bp.take<uint64_t>(S);
+    r.n_evals = bp.take<int64_t>(S);
+    r.alloc = bp.take<int8_t>(N);
+    r.R = bp.take<int64_t>(N);
+    r.R_1g = bp.take<int64_t>(N);
+    r.dbg_key = out->dbg_key ? bp.take<uint64_t>(3 * ndbg) : nullptr;
+    int64_t *d_dbgoff = bp.take<int64_t>(S);
+    r.dbg_offset = out->dbg_key ? d_dbgoff : nullptr;
+    hipStream_t st = c->stream;
+    struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
+        {d_off, in->set_offset, 8 * (size_t)(S + 1)}, {d_M, in->M, 4 * (size_t)S},
+        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, 8 * (size_t)N},
+        {d_Cp, in->C_par, 8 * (size_t)N}, {d_k, in->k_permille, 4 * (size_t)N}, {d_ty, in->type, (size_t)N},
+        {d_dbgoff, out->dbg_key ? (const void *)out->dbg_offset : nullptr, out->dbg_key ? 8 * (size_t)S : 0}};
+    for (const auto &x : h2d)
+        if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync H2D");
+    d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
+    d.type = d_ty;
+    const Plan p = make_plan(in, opt);
+    if ((rc = run_plan(c, make_batch(&d), make_out(&r), p, st, p_lo, p_hi)) != CAPART_OK) return rc;
+    Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
+                {out->verdict_1g, r.verdict_1g, (size_t)S}, {out->pidx, r.pidx, 4 * (size_t)S},
+                {out->sizes, r.sizes, 4 * (size_t)S * K}, {out->aidx, r.aidx, 8 * (size_t)S},
+                {out->maxU, r.maxU, 8 * (size_t)S}, {out->sumU, r.sumU, 8 * (size_t)S},
+                {out->n_evals, r.n_evals, 8 * (size_t)S}, {out->alloc, r.alloc, (size_t)N},
+                {out->R, r.R, 8 * (size_t)N}, {out->R_1g, r.R_1g, 8 * (size_t)N},
+                {out->dbg_key, r.dbg_key, out->dbg_key ? 24 * (size_t)ndbg : 0}};
+    for (const auto &x : d2h)
+        if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync D2H");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    return CAPART_OK;
+}
+
+capart_status capart_solve(capart_ctx *c, const capart_tasksets *in, const capart_options *opt, capart_results *out)
+{
+    return solve_host(c, in, opt, out, 0u, 0xFFFFFFFFu);
+}
+
+static capart_status one_set_check(capart_ctx *c, const capart_tasksets *one, const int32_t *sizes, int32_t k)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc = check_batch_shape(c, one);
+    if (rc != CAPART_OK) return rc;
+    if (one->n_sets != 1 || one->set_offset[0] != 0 || one->set_offset[1] != one->n_tasks_total)
+        return fail(c, CAPART_E_INVAL, "expected exactly one set with offsets {0, n}");
+    if (!sizes || k < 1 || k > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "k must be in [1, 8]");
+    int64_t sum = 0;
+    for (int p = 0; p < k; p++) {
+        if (sizes[p] < 1) return fail(c, CAPART_E_INVAL, "part sizes must be >= 1");
+        sum += sizes[p];
+    }
+    if (sum > one->M[0]) return fail(c, CAPART_E_INVAL, "parts exceed M");
+    return CAPART_OK;
+}
+
+capart_status capart_test_triple(capart_ctx *c, const capart_tasksets *one, const int32_t *sizes, int32_t k,
+                                 const int8_t *alloc, uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU)
+{
+    capart_status rc = one_set_check(c, one, sizes, k);
+    if (rc != CAPART_OK) return rc;
+    const int64_t n = one->n_tasks_total;
+    if (!alloc || !feasible || !R || !maxU || !sumU) return fail(c, CAPART_E_INVAL, "NULL argument");
+    for (int64_t i = 0; i < n; i++)
+        if (alloc[i] < 0 || alloc[i] >= k) return fail(c, CAPART_E_INVAL, "allocation index out of [0, k)");
+    int32_t st_host = validate_set(one, 0, CAPART_MAX_K, CAPART_HEUR_BF_INA);
+    if (st_host != CAPART_OK) return fail(c, st_host, "invalid task set");
+    // solve infrastructure: upload the set, run prep, then the triple kernel
+    capart_options opt{CAPART_MAX_K, CAPART_POLICY_FP_DM, CAPART_HEUR_BF_INA, 0u};
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if ((rc = ensure_stage(c, stage_need(1, n, CAPART_MAX_K, 0) + 4096)) != CAPART_OK) return rc;
+    Bump bp{(char *)c->stage};
+    int64_t *d_off = bp.take<int64_t>(2);
+    int32_t *d_M = bp.take<int32_t>(1);
+    int64_t *d_T = bp.take<int64_t>(n), *d_D = bp.take<int64_t>(n), *d_Cs = bp.take<int64_t>(n),
+            *d_Cp = bp.take<int64_t>(n);
+    int32_t *d_k = bp.take<int32_t>(n);
+    uint8_t *d_ty = bp.take<uint8_t>(n);
+    int32_t *d_sizes = bp.take<int32_t>(8);
+    int8_t *d_alloc = bp.take<int8_t>(n);
+    uint8_t *d_feas = bp.take<uint8_t>(1);
+    int64_t *d_R = bp.take<int64_t>(n);
+    uint64_t *d_mx = bp.take<uint64_t>(1), *d_sm = bp.take<uint64_t>(1);
+    int32_t *d_status = bp.take<int32_t>(1);
+    hipStream_t st = c->stream;
+    const int64_t offs[2] = {0, n};
+    struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
+        {d_off, offs, 16}, {d_M, one->M, 4}, {d_T, one->T, 8 * (size_t)n}, {d_D, one->D, 8 * (size_t)n},
+        {d_Cs, one->C_seq, 8 * (size_t)n}, {d_Cp, one->C_par, 8 * (size_t)n}, {d_k, one->k_permille, 4 * (size_t)n},
+        {d_ty, one->type, (size_t)n}, {d_sizes, sizes, 4 * (size_t)k}, {d_alloc, alloc, (size_t)n}};
+    for (const auto &x : h2d)
+        if ((e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync H2D");
+    capart_tasksets d = *one;
+    d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
+    d.type = d_ty;
+    const Plan p = make_plan(&d, &opt);
+    const WsLayout l = ws_layout(1, n, p.L.chunks);
+    if ((rc = ensure_ws(c, l.total)) != CAPART_OK) return rc;
+    char *base = (char *)c->ws;
+    Work w;
+    w.rec = (TaskRec *)(base + l.rec);
+    w.forbid = (uint64_t *)(base + l.forbid);
+    w.sigma = (uint8_t *)(base + l.sigma);
+    w.setflags = (uint32_t *)(base + l.setflags);
+    w.memmask = (uint64_t *)(base + l.memmask);
+    w.partial = (uint64_t *)(base + l.partial);
+    w.np = c->np_dev;
+    Out o{};
+    o.status = d_status;
+    const Batch b = make_batch(&d);
+    if ((e = launch_prep(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if ((e = launch_triple(b, w, d_sizes, k, d_alloc, d_feas, d_R, d_mx, d_sm, st)) != hipSuccess)
+        return hip_fail(c, e, "triple launch");
+    Cp d2h[] = {{feasible, d_feas, 1}, {R, d_R, 8 * (size_t)n}, {maxU, d_mx, 8}, {sumU, d_sm, 8}};
+    for (const auto &x : d2h)
+        if ((e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync D2H");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    return CAPART_OK;
+}
+
+capart_status capart_allocate(capart_ctx *c, const capart_tasksets *one, const int32_t *sizes, int32_t k,
+                              const capart_options *opt, int8_t *alloc_out, uint8_t *found, uint64_t *maxU,
+                              uint64_t *sumU, int64_t *aidx)
+{
+    capart_status rc = one_set_check(c, one, sizes, k);
+    if (rc != CAPART_OK) return rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if (!alloc_out || !found || !maxU || !sumU || !aidx) return fail(c, CAPART_E_INVAL, "NULL argument");
+    const int32_t M = one->M[0];
+    if (k > opt->K) return fail(c, CAPART_E_INVAL, "k exceeds K");
+    int64_t sum = 0;
+    for (int p = 0; p < k; p++) {
+        if (p > 0 && sizes[p] > sizes[p - 1]) return fail(c, CAPART_E_INVAL, "sizes must be non-increasing");
+        sum += sizes[p];
+    }
+    if (sum != M) return fail(c, CAPART_E_INVAL, "sizes must sum to M");
+    // index of this partitioning in canonical order
+    const int64_t P = count_parts(M, opt->K);
+    std::vector<int32_t> tab((size_t)P * opt->K);
+    int64_t cnt = 0;
+    capart_enumerate_partitionings(M, opt->K, tab.data(), P, &cnt);
+    int64_t pidx = -1;
+    for (int64_t q = 0; q < P && pidx < 0; q++) {
+        bool eq = true;
+        for (int p = 0; p < opt->K; p++)
+            if (tab[q * opt->K + p] != (p < k ? sizes[p] : 0)) { eq = false; break; }
+        if (eq) pidx = q;
+    }
+    if (pidx < 0) return fail(c, CAPART_E_INVAL, "not a partitioning of M");
+    // solve the set on this partitioning alone
+    const int64_t n = one->n_tasks_total;
+    std::vector<int32_t> status(1), pid(1), szs(opt->K);
+    std::vector<uint8_t> verdict(1), v1g(1);
+    std::vector<int64_t> ai(1), ne(1), R(n), R1(n);
+    std::vector<uint64_t> mx(1), sm(1);
+    std::vector<int8_t> al(n);
+    capart_results r{status.data(), verdict.data(), v1g.data(), pid.data(), szs.data(), ai.data(), mx.data(),
+                     sm.data(), ne.data(), al.data(), R.data(), R1.data(), nullptr, nullptr};
+    capart_options o1 = *opt;
+    o1.flags |= CAPART_FLAG_SKIP_1G;
+    if ((rc = solve_host(c, one, &o1, &r, (uint32_t)pidx, (uint32_t)pidx + 1u)) != CAPART_OK) return rc;
+    if (status[0] != CAPART_OK) return fail(c, status[0], "invalid task set");
+    *found = verdict[0];
+    *maxU = mx[0];
+    *sumU = sm[0];
+    *aidx = ai[0];
+    for (int64_t i = 0; i < n; i++) alloc_out[i] = *found ? al[i] : (int8_t)-1;
+    return CAPART_OK;
+}
+
+capart_status capart_timing_enable(capart_ctx *c, int enable)
+{
+    if (!c) return CAPART_E_INVAL;
+    c->timing = enable != 0;
+    if (!c->timing) {
+        for (auto &a : c->ev_pending)
+            for (auto e : a) c->ev_free.push_back(e);
+        c->ev_pending.clear();
+    }
+    return CAPART_OK;
+}
+
+capart_status capart_timing_read(capart_ctx *c, double *ms, int64_t *launches)
+{
+    if (!c || !ms || !launches) return CAPART_E_INVAL;
+    double acc[3] = {0, 0, 0};
+    for (auto &a : c->ev_pending) {
+        hipError_t e = hipEventSynchronize(a[3]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        for (int k = 0; k < 3; k++) {
+            float t = 0.f;
+            if ((e = hipEventElapsedTime(&t, a[k], a[k + 1])) != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+            acc[k] += t;
+        }
+    }
+    for (int k = 0; k < 3; k++) {
+        ms[k] = acc[k];
+        launches[k] = (int64_t)c->ev_pending.size();
+    }
+    for (auto &a : c->ev_pending)
+        for (auto e : a) c->ev_free.push_back(e);
+    c->ev_pending.clear();
+    return CAPART_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Integer arithmetic of the engine's kernels, written so that it also compiles
+// as plain host C++ (define CAPART_HD empty) for exhaustive CPU checks.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef CAPART_HD
+#define CAPART_HD __host__ __device__
+#endif
+
+namespace capart {
+
+// Saturation value for execution times: larger than every admissible deadline
+// (D < 2^31), so a saturated time compares exactly like the true one against
+// D and T.
+constexpr uint32_t C_SAT = 0x80000000u;
+constexpr uint16_t MMIN_NONE = 0xFFFFu;
+
+// c = ceil(2^64 / T) split in 32-bit halves, for T >= 2.
+CAPART_HD inline void magic_u32(uint32_t T, uint32_t *clo, uint32_t *chi)
+{
+    uint64_t c = (T >= 2) ? (~0ull / T) + 1ull : 0ull;  // ceil(2^64/T) = floor((2^64-1)/T) + 1
+    *clo = (uint32_t)c;
+    *chi = (uint32_t)(c >> 32);
+}
+
+// floor(x / T) for any 32-bit x, from c = ceil(2^64/T): the high 64 bits of
+// the 96-bit product c*x (the error term c*x/2^64 - x/T < x/2^64 <= 1/T keeps
+// the floor exact).  Two 32-bit multiplies: mul_hi then a 64-bit mad.
+CAPART_HD inline uint32_t floordiv_magic(uint32_t x, uint32_t clo, uint32_t chi)
+{
+    uint32_t lo_hi = (uint32_t)(((uint64_t)clo * x) >> 32);
+    return (uint32_t)(((uint64_t)chi * x + lo_hi) >> 32);
+}
+
+// Execution time on m units without conflict: C_seq + ceil(C_par / m).
+// With C_seq + C_par < 2^31 the result is < 2^31.
+CAPART_HD inline uint32_t time_n(uint32_t Cs, uint32_t Cp, uint32_t m)
+{
+    return Cs + (Cp + m - 1u) / m;
+}
+
+// Execution time in conflict: ceil(k * Cn / 1000), saturated at C_SAT.
+CAPART_HD inline uint32_t time_c(uint32_t k, uint32_t cn)
+{
+    uint64_t x = (uint64_t)k * cn;  // < 2^20 * 2^31
+    uint64_t c = (x + 999u) / 1000u;
+    return c > C_SAT ? C_SAT : (uint32_t)c;
+}
+
+// ceil(C * 2^32 / T) - 1 for 1 <= C <= T (value in [0, 2^32 - 1]); all ones when
+// C > T (the task cannot be in a feasible partition then).
+CAPART_HD inline uint32_t util_q32_m1(uint32_t C, uint32_t T)
+{
+    if (C > T) return 0xFFFFFFFFu;
+    uint64_t num = (uint64_t)C << 32;
+    uint64_t q = (num + T - 1u) / T;
+    return (uint32_t)(q - 1u);
+}
+
+// Lemma 2 closed form: least m in [1, M] with C_seq + ceil(C_par/m) <= D.
+CAPART_HD inline uint16_t m_min(uint32_t Cs, uint32_t Cp, uint32_t D, uint32_t M)
+{
+    if (Cp == 0u) return Cs <= D ? (uint16_t)1 : MMIN_NONE;
+    if (D <= Cs) return MMIN_NONE;
+    uint32_t slack = D - Cs;
+    uint32_t m = (Cp + slack - 1u) / slack;  // Cp < 2^31, slack < 2^31
+    return m <= M ? (uint16_t)m : MMIN_NONE;
+}
+
+}  // namespace capart

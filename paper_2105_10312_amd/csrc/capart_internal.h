@@ -1,0 +1,86 @@
+// Internal interface between the C-ABI host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "capart.h"
+
+namespace capart {
+
+// Per-task record in deadline-monotonic rank order (32 bytes).  clo/chi hold
+// c = ceil(2^64 / T) so that floor(x / T) = (c * x) >> 64 for every 32-bit x
+// (T >= 2; Lemire, Kaser & Kurz, "Faster remainder by direct computation").
+struct TaskRec {
+    uint32_t T, D, Cs, Cp;
+    uint32_t k, clo, chi;
+    uint16_t mmin;  // Lemma 2: least m with Cn(m) <= D, 0xFFFF if none <= M
+    uint8_t orig;   // index of the task inside its set
+    uint8_t mem;    // 1 = memory-intensive
+};
+static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
+
+constexpr uint32_t SETF_VALID = 1u;
+constexpr uint32_t SETF_LEMMA1 = 2u;  // Lemma 1 rejects the set
+
+// Partition-count table: NP(r, j, x) = number of partitions of r into at most
+// j parts, each part <= x (parts >= 1); r, x in [0, 255], j in [0, 8].
+constexpr int NP_R = 256, NP_J = 9, NP_X = 256;
+__host__ __device__ inline int np_index(int j, int r, int x) { return (j * NP_R + r) * NP_X + x; }
+
+struct Batch {           // device pointers of the caller's batch (set range [s0, s0+S))
+    const int64_t *off;
+    const int32_t *M;
+    const int64_t *T, *D, *Cs, *Cp;
+    const int32_t *k;
+    const uint8_t *type;
+    int64_t n_tasks_total;
+    int32_t max_tasks, max_M;
+};
+
+struct Work {            // device workspace owned by the context
+    TaskRec *rec;        // [N]
+    uint64_t *forbid;    // [N] ACT forbidden-pair masks, by rank
+    uint8_t *sigma;      // [N] ranks in decreasing one-unit utilisation
+    uint32_t *setflags;  // [S]
+    uint64_t *memmask;   // [S] memory-intensive ranks
+    uint64_t *partial;   // [S * CH * 4] best key per (set, chunk)
+    const uint32_t *np;  // partition-count table
+};
+
+struct Out {             // device pointers of the caller's results
+    int32_t *status;
+    uint8_t *verdict, *verdict_1g;
+    int32_t *pidx, *sizes;
+    int64_t *aidx;
+    uint64_t *maxU, *sumU;
+    int64_t *n_evals;
+    int8_t *alloc;
+    int64_t *R, *R_1g;
+    uint64_t *dbg_key;
+    const int64_t *dbg_offset;
+};
+
+struct Launch {
+    int64_t s0, S;       // set range
+    int K, mode;
+    uint32_t flags;
+    int chunks;          // CH: chunks per set
+    uint32_t chunk;      // partitionings per chunk (heuristic) / 1 (exhaustive)
+    int threads;         // threads per evaluation block
+};
+
+// Host-side sizing helpers shared by the launchers.
+size_t table_lds_bytes(int max_tasks, int max_M);
+
+hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+// evaluation restricted to partitioning indices [p_lo, p_hi)
+hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                             uint32_t p_lo, uint32_t p_hi);
+hipError_t launch_final(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
+                         uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st);
+hipError_t configure_kernels();
+
+}  // namespace capart

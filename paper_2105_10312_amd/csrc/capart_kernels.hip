@@ -1,0 +1,852 @@
+// gfx950 kernels of the contention-aware partitioning engine.
+//
+// Work decomposition (one HIP stream, three launches per batch):
+//   prep  : one wave per task set -- validation, deadline-monotonic ranks,
+//           Lemma 1 and Lemma 2, heuristic order, exact-division constants,
+//           ACT forbidden pairs; writes a packed per-task record.
+//   eval  : one block per (set, chunk of partitionings).  The block stages the
+//           set's records and a per-(m, conflict, task) table of execution
+//           times and Q32 utilisations in LDS, then every lane walks a
+//           contiguous run of partitionings (unranked once, then stepped in
+//           descending lexicographic order), allocates tasks (heuristic) or
+//           scans allocations (exhaustive), and keeps its best key; the block
+//           reduces keys with cross-lane shuffles and writes one partial.
+//   final : one wave per set -- reduces the partials, rebuilds the chosen
+//           allocation, computes response times of the chosen triple and of
+//           the whole-GPU baseline (one lane per task) and writes the results.
+//
+// All arithmetic is integer.  Response-time iterations use 32-bit operands
+// with 64-bit accumulation: every hp task that has passed satisfies
+// C_j <= D_j <= T_j, so each term ceil(R/T_j)*C_j < 2^32 and the sum of at
+// most 64 terms stays far below 2^64; a task whose time reaches its period
+// (utilisation >= 1) makes every lower-priority task miss, which is decided
+// without iterating.
+#include "capart_internal.h"
+#include "capart_arith.h"
+
+namespace capart {
+
+constexpr int MAXN = CAPART_MAX_TASKS;
+
+struct Key {
+    uint64_t a, b, c, d;  // (maxU, sumU, pidx, aidx); "none" = all ones
+};
+
+__device__ __forceinline__ Key key_none() { return Key{~0ull, ~0ull, ~0ull, ~0ull}; }
+
+__device__ __forceinline__ bool key_less(const Key &x, const Key &y)
+{
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.d < y.d;
+}
+
+__device__ __forceinline__ Key key_shfl_xor(const Key &k, int mask)
+{
+    Key o;
+    o.a = __shfl_xor(k.a, mask, 64);
+    o.b = __shfl_xor(k.b, mask, 64);
+    o.c = __shfl_xor(k.c, mask, 64);
+    o.d = __shfl_xor(k.d, mask, 64);
+    return o;
+}
+
+__device__ __forceinline__ Key wave_min(Key k)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        Key t = key_shfl_xor(k, o);
+        if (key_less(t, k)) k = t;
+    }
+    return k;
+}
+
+// Block-wide minimum; result valid in thread 0.  `scratch` holds >= 16 keys.
+__device__ Key block_min(Key k, Key *scratch)
+{
+    k = wave_min(k);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return k;
+    if (lane == 0) scratch[wid] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; i++)
+            if (key_less(scratch[i], k)) k = scratch[i];
+    }
+    return k;
+}
+
+__device__ __forceinline__ int ctz64(uint64_t x) { return __builtin_ctzll(x); }
+
+// ---------------------------------------------------------------------------
+// Per-set data in LDS (ranks are deadline-monotonic priority positions).
+struct SetLDS {
+    uint32_t T[MAXN], D[MAXN], clo[MAXN], chi[MAXN];
+    uint32_t Cs[MAXN], Cp[MAXN], k[MAXN];
+    uint32_t mmin[MAXN];
+    uint64_t forbid[MAXN];
+    uint8_t sigma[MAXN];
+    uint8_t orig[MAXN];
+    uint8_t rank_of[MAXN];
+    uint64_t memmask;
+};
+
+// Execution-time and utilisation tables, [m-1][conflict][rank], u32:
+//   tabC: time on m units; tabU: ceil(C*2^32/T) - 1.
+struct Tables {
+    const uint32_t *C;
+    const uint32_t *U;
+    int n;
+};
+
+extern __shared__ uint32_t capart_dyn_lds[];
+
+__device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act, Tables &tb)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < n; i += nt) {
+        TaskRec t = w.rec[off + i];
+        L.T[i] = t.T; L.D[i] = t.D; L.clo[i] = t.clo; L.chi[i] = t.chi;
+        L.Cs[i] = t.Cs; L.Cp[i] = t.Cp; L.k[i] = t.k;
+        L.mmin[i] = t.mmin;
+        L.orig[i] = t.orig;
+        L.rank_of[t.orig] = (uint8_t)i;
+        L.sigma[i] = w.sigma[off + i];
+        L.forbid[i] = act ? w.forbid[off + i] : 0ull;
+    }
+    if (tid == 0) L.memmask = w.memmask[s];
+    __syncthreads();
+    uint32_t *tc = capart_dyn_lds;
+    uint32_t *tu = capart_dyn_lds + 2 * n * M;
+    for (int e = tid; e < n * M; e += nt) {
+        const int m = e / n + 1, r = e - (m - 1) * n;
+        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+        const uint32_t cc = time_c(L.k[r], cn);
+        const int base = (m - 1) * 2 * n + r;
+        tc[base] = cn;
+        tc[base + n] = cc;
+        tu[base] = util_q32_m1(cn, L.T[r]);
+        tu[base + n] = util_q32_m1(cc, L.T[r]);
+    }
+    __syncthreads();
+    tb.C = tc;
+    tb.U = tu;
+    tb.n = n;
+}
+
+// Conflict mask of a partition holding rank set S: bit r set iff task r has
+// another task of its type in S (Section "Task Model").
+__device__ __forceinline__ uint64_t conflict_mask(uint64_t S, uint64_t memmask)
+{
+    const uint64_t mem = S & memmask, cmp = S & ~memmask;
+    return (__popcll(mem) >= 2 ? memmask : 0ull) | (__popcll(cmp) >= 2 ? ~memmask : 0ull);
+}
+
+// Exact response time of rank r on m units with higher-priority members hp
+// and conflict mask cm; returns 0 on a deadline miss.
+__device__ uint32_t rta(const SetLDS &L, const Tables &tb, int m, int r, uint64_t hp, uint64_t cm)
+{
+    const int n = tb.n;
+    const uint32_t *row = tb.C + (m - 1) * 2 * n;
+    const uint32_t C = row[(int)((cm >> r) & 1ull) * n + r];
+    uint64_t base = C;
+    bool sat = false;
+    for (uint64_t h = hp; h; h &= h - 1) {
+        const int j = ctz64(h);
+        const uint32_t Cj = row[(int)((cm >> j) & 1ull) * n + j];
+        base += Cj;
+        sat |= (Cj >= L.T[j]);
+    }
+    const uint32_t D = L.D[r];
+    if (sat || base > D) return 0u;
+    uint64_t R = base;
+    for (;;) {
+        const uint32_t x = (uint32_t)R - 1u;
+        uint64_t W = base;
+        for (uint64_t h = hp; h; h &= h - 1) {
+            const int j = ctz64(h);
+            const uint32_t Cj = row[(int)((cm >> j) & 1ull) * n + j];
+            const uint32_t q = floordiv_magic(x, L.clo[j], L.chi[j]);
+            W += (uint64_t)q * Cj;
+        }
+        if (W > D) return 0u;
+        if (W == R) return (uint32_t)R;
+        R = W;
+    }
+}
+
+// Schedulability of rank set S on one partition of m units; *U = Q32 sum.
+__device__ bool part_test(const SetLDS &L, const Tables &tb, uint64_t S, int m, uint64_t *U)
+{
+    const int n = tb.n;
+    const uint64_t cm = conflict_mask(S, L.memmask);
+    const uint32_t *urow = tb.U + (m - 1) * 2 * n;
+    uint64_t u = 0;
+    for (uint64_t rem = S; rem; rem &= rem - 1) {
+        const int r = ctz64(rem);
+        const uint64_t hp = S & ((1ull << r) - 1ull);
+        if (!rta(L, tb, m, r, hp, cm)) return false;
+        u += (uint64_t)urow[(int)((cm >> r) & 1ull) * n + r] + 1ull;
+    }
+    *U = u;
+    return true;
+}
+
+// Fewest units (<= mp, where S is known feasible) that schedule S: binary
+// search, valid because feasibility is monotone in m (no timing anomalies).
+__device__ int min_units(const SetLDS &L, const Tables &tb, uint64_t S, int mp)
+{
+    int lo = 1;
+    for (uint64_t h = S; h; h &= h - 1) lo = max(lo, (int)L.mmin[ctz64(h)]);
+    int hi = mp;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        uint64_t u;
+        if (part_test(L, tb, S, mid, &u))
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Heuristic allocation on a fixed partitioning m[0..k) (non-increasing):
+// tasks in decreasing one-unit utilisation, each to the best-ranked part that
+// stays schedulable.  S[p] = rank masks, U[p] = Q32 utilisations.
+template <int KMAX, bool ACT, bool SMS>
+__device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
+                          uint64_t (&S)[KMAX], uint64_t (&U)[KMAX])
+{
+#pragma unroll
+    for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; }
+    for (int t = 0; t < n; t++) {
+        const int r = L.sigma[t];
+        const uint64_t bit = 1ull << r;
+        const int mm = (int)L.mmin[r];
+        const uint64_t fb = ACT ? L.forbid[r] : 0ull;
+        int best = -1, bestReq = 0;
+        uint64_t bestU = 0;
+        // parts are visited with compile-time indices so that S, U and m stay in registers
+#pragma unroll
+        for (int p = 0; p < KMAX; p++) {
+            const int mp = m[p];
+            const uint64_t Sp = S[p];
+            if (p >= k || mm > mp) continue;
+            if (ACT && (fb & Sp)) continue;
+            const uint64_t Sn = Sp | bit;
+            uint64_t Un;
+            if (!part_test(L, tb, Sn, mp, &Un)) continue;
+            int req = 0;
+            if (SMS) req = min_units(L, tb, Sn, mp);
+            const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
+            if (better) { best = p; bestU = Un; bestReq = req; }
+        }
+        if (best < 0) return false;
+#pragma unroll
+        for (int p = 0; p < KMAX; p++)
+            if (p == best) { S[p] |= bit; U[p] = bestU; }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Partitionings of M into at most K parts in descending lexicographic order.
+template <int KMAX>
+__device__ __forceinline__ int unrank(const uint32_t *np, int M, int K, uint32_t rank, int (&a)[KMAX])
+{
+    int rem = M, maxp = M, k = 0;
+#pragma unroll
+    for (int j = 0; j < KMAX; j++) {
+        int y = 0;
+        if (j < K && rem > 0) {
+            const int left = K - j - 1;
+            y = min(rem, maxp);
+            for (; y > 1; y--) {
+                const uint32_t c = np[np_index(left, rem - y, y)];
+                if (rank < c) break;
+                rank -= c;
+            }
+            rem -= y;
+            maxp = y;
+            k++;
+        }
+        a[j] = y;
+    }
+    return k;
+}
+
+// Next partitioning in descending lexicographic order; returns the new number
+// of parts (0 if `a` was the last one).
+template <int KMAX>
+__device__ __forceinline__ int next_partition(int (&a)[KMAX], int K)
+{
+    int tail = 0, sel = -1, v = 0;
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; i--) {
+        if (sel < 0 && i < K) {
+            const int vi = a[i] - 1;
+            if (a[i] > 1 && tail + 1 <= (K - i - 1) * vi) {
+                sel = i;
+                v = vi;
+            } else {
+                tail += a[i];
+            }
+        }
+    }
+    if (sel < 0) return 0;
+    int rest = tail + 1, k = 0;
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) {
+        if (i == sel) {
+            a[i] = v;
+        } else if (i > sel) {
+            const int x = min(v, rest);
+            a[i] = x;
+            rest -= x;
+        }
+        k += (a[i] > 0);
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// prep: one wave per set.
+__global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch Lp)
+{
+    __shared__ uint32_t sD[MAXN], sT[MAXN];
+    __shared__ uint64_t su1[MAXN];
+    __shared__ TaskRec srec[MAXN];
+    __shared__ uint64_t sforbid[MAXN];
+    const int64_t s = Lp.s0 + blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t off0 = b.off[s], off1 = b.off[s + 1];
+    const int M = b.M[s];
+    int status = CAPART_OK;
+    const int nmax = min(b.max_tasks, MAXN), Mmax = min(b.max_M, CAPART_MAX_M);
+    if (off0 < 0 || off1 < off0 || off1 > b.n_tasks_total) status = CAPART_E_INVAL;
+    const int64_t n64 = off1 - off0;
+    if (status == CAPART_OK && (n64 < 1 || n64 > nmax || M < 1 || M > Mmax || n64 * M > CAPART_MAX_NM))
+        status = CAPART_E_INVAL;
+    if (status != CAPART_OK) {
+        if (lane == 0) { o.status[s] = status; w.setflags[s] = 0u; }
+        return;
+    }
+    const int n = (int)n64;
+    int64_t T = 1, D = 1, Cs = 0, Cp = 1;
+    int32_t kk = 1000;
+    int ty = 0;
+    bool bad = false;
+    if (lane < n) {
+        T = b.T[off0 + lane]; D = b.D[off0 + lane];
+        Cs = b.Cs[off0 + lane]; Cp = b.Cp[off0 + lane];
+        kk = b.k[off0 + lane]; ty = b.type[off0 + lane];
+        const int64_t L31 = (int64_t)1 << 31;
+        bad = (T < 1 || T >= L31 || D < 1 || D > T || Cs < 0 || Cp < 0 || Cs >= L31 || Cp >= L31 ||
+               Cs + Cp < 1 || Cs + Cp >= L31 || kk < 1000 || kk > 1000000 || ty > 1);
+    }
+    if (__ballot(bad)) status = CAPART_E_RANGE;
+    if (status == CAPART_OK && Lp.mode == CAPART_EXHAUSTIVE) {
+        // k^n < 2^62 for the largest k = min(K, M)
+        const uint64_t kk2 = (uint64_t)min(Lp.K, M);
+        const uint64_t lim = ((1ull << 62) - 1ull) / kk2;
+        uint64_t pw = 1;
+        for (int i = 0; i < n; i++) {
+            if (pw > lim) { status = CAPART_E_INVAL; break; }
+            pw *= kk2;
+        }
+    }
+    if (lane == 0) o.status[s] = status;
+    if (status != CAPART_OK) {
+        if (lane == 0) w.setflags[s] = 0u;
+        return;
+    }
+    // deadline-monotonic rank and heuristic order
+    const uint32_t c1 = (uint32_t)(Cs + Cp);
+    uint64_t u1 = 0, l1 = 0;
+    if (lane < n) {
+        const uint64_t num = (uint64_t)c1 << 32;
+        u1 = (num + (uint64_t)T - 1) / (uint64_t)T;  // ceil(Cn(1) 2^32 / T)
+        l1 = num / (uint64_t)T;                      // floor, for Lemma 1
+        sD[lane] = (uint32_t)D;
+        sT[lane] = (uint32_t)T;
+        su1[lane] = u1;
+    }
+    __syncthreads();
+    int rank = 0, pos = 0;
+    if (lane < n) {
+        for (int j = 0; j < n; j++) {
+            const bool before = (sD[j] < (uint32_t)D) || (sD[j] == (uint32_t)D && (sT[j] < (uint32_t)T ||
+                                                                                   (sT[j] == (uint32_t)T && j < lane)));
+            rank += before;
+            pos += (su1[j] > u1) || (su1[j] == u1 && j < lane);
+        }
+    }
+    // Lemma 1: saturating wave sum of floor-Q32 utilisations
+    uint64_t acc = (lane < n) ? l1 : 0ull;
+    const uint64_t cap = (uint64_t)M << 32;
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+        const uint64_t t = __shfl_xor(acc, o2, 64);
+        acc = (acc > cap || t > cap) ? cap + 1 : acc + t;
+    }
+    const bool reject = (acc > cap) && !(Lp.flags & CAPART_FLAG_NO_LEMMA1);
+    // memory-intensive ranks
+    uint64_t mm = (lane < n && ty == 1) ? (1ull << rank) : 0ull;
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) mm |= __shfl_xor(mm, o2, 64);
+    if (lane < n) {
+        TaskRec r;
+        r.T = (uint32_t)T; r.D = (uint32_t)D; r.Cs = (uint32_t)Cs; r.Cp = (uint32_t)Cp; r.k = (uint32_t)kk;
+        magic_u32((uint32_t)T, &r.clo, &r.chi);
+        r.mmin = m_min((uint32_t)Cs, (uint32_t)Cp, (uint32_t)D, (uint32_t)M);
+        r.orig = (uint8_t)lane;
+        r.mem = (uint8_t)ty;
+        w.rec[off0 + rank] = r;
+        w.sigma[off0 + pos] = (uint8_t)rank;
+        srec[rank] = r;
+        sforbid[rank] = 0ull;
+    }
+    if (lane == 0) {
+        w.memmask[s] = mm;
+        w.setflags[s] = SETF_VALID | (reject ? SETF_LEMMA1 : 0u);
+    }
+    const bool act = (Lp.mode == CAPART_HEUR_BF_ACT || Lp.mode == CAPART_HEUR_SMS_ACT);
+    if (!act) return;
+    __syncthreads();
+    // ACT: pair (a, b), a < b in rank order, is forbidden iff no size in
+    // [max(mmin), min(mmin_a + mmin_b - 1, M)] schedules both together; by
+    // monotonicity in m it suffices to test the top of that range.
+    if (lane < n) {
+        const int bb = lane;
+        const TaskRec tb = srec[bb];
+        uint64_t fb = 0ull;
+        for (int a = 0; a < bb; a++) {
+            const TaskRec ta = srec[a];
+            bool forb = true;
+            if (ta.mmin != MMIN_NONE && tb.mmin != MMIN_NONE) {
+                const uint32_t m = min((uint32_t)ta.mmin + tb.mmin - 1u, (uint32_t)M);
+                const bool conf = ta.mem == tb.mem;
+                uint32_t Ca = time_n(ta.Cs, ta.Cp, m), Cb = time_n(tb.Cs, tb.Cp, m);
+                if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
+                if (Ca <= ta.D && Ca < ta.T) {
+                    uint64_t R = (uint64_t)Cb + Ca;
+                    for (;;) {
+                        if (R > tb.D) break;
+                        const uint64_t W = (uint64_t)Cb + ((R + ta.T - 1) / ta.T) * (uint64_t)Ca;
+                        if (W > tb.D) break;
+                        if (W == R) { forb = false; break; }
+                        R = W;
+                    }
+                }
+            }
+            if (forb) {
+                fb |= 1ull << a;
+                atomicOr((unsigned long long *)&sforbid[a], (unsigned long long)(1ull << bb));
+            }
+        }
+        atomicOr((unsigned long long *)&sforbid[bb], (unsigned long long)fb);
+    }
+    __syncthreads();
+    if (lane < n) w.forbid[off0 + lane] = sforbid[lane];
+}
+
+// ---------------------------------------------------------------------------
+// eval, heuristic allocation: one block per (set, chunk of partitionings).
+template <int KMAX, bool ACT, bool SMS>
+__global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
+                                                        uint32_t p_hi)
+{
+    __shared__ SetLDS L;
+    __shared__ Key red[16];
+    const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
+    const int c = blockIdx.x % Lp.chunks;
+    const uint32_t f = w.setflags[s];
+    if (!(f & SETF_VALID)) return;
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    const int M = b.M[s];
+    const uint32_t P = w.np[np_index(Lp.K, M, M)];
+    const uint32_t p0 = (uint32_t)c * Lp.chunk;
+    if (p0 >= P) return;
+    const uint32_t p1 = min(P, p0 + Lp.chunk);
+    const bool dbg = o.dbg_key != nullptr;
+    Key best = key_none();
+    if (!(f & SETF_LEMMA1)) {
+        Tables tb;
+        stage_set(L, w, off, n, M, s, ACT, tb);
+        const uint32_t cnt = p1 - p0;
+        const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
+        uint32_t q0 = p0 + threadIdx.x * per, q1 = min(p1, q0 + per);
+        q0 = max(q0, p_lo);
+        q1 = min(q1, p_hi);
+        if (q0 < q1) {
+            int m[KMAX];
+            int k = unrank<KMAX>(w.np, M, Lp.K, q0, m);
+            for (uint32_t q = q0;;) {
+                uint64_t S[KMAX], U[KMAX];
+                const bool ok = heuristic<KMAX, ACT, SMS>(L, tb, n, m, k, S, U);
+                uint64_t mx = 0, sm = 0;
+                if (ok) {
+#pragma unroll
+                    for (int p = 0; p < KMAX; p++) { mx = max(mx, U[p]); sm += U[p]; }
+                    const Key kk{mx, sm, q, 0ull};
+                    if (key_less(kk, best)) best = kk;
+                }
+                if (dbg) {
+                    uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
+                    d[0] = ok ? mx : ~0ull;
+                    d[1] = ok ? sm : ~0ull;
+                    d[2] = ok ? 0ull : ~0ull;
+                }
+                if (++q >= q1) break;
+                k = next_partition<KMAX>(m, Lp.K);
+            }
+        }
+    } else if (dbg) {
+        for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+            if (q < p_lo || q >= p_hi) continue;
+            uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
+            d[0] = d[1] = d[2] = ~0ull;
+        }
+    }
+    best = block_min(best, red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = w.partial + 4 * ((s) * (int64_t)Lp.chunks + c);
+        dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+    }
+}
+
+// eval, exhaustive allocation: one block per (set, partitioning); lanes stride
+// over allocation indices (base-k digits, task 0 most significant).
+template <int KMAX>
+__global__ __launch_bounds__(256) void eval_exh_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
+                                                       uint32_t p_hi)
+{
+    __shared__ SetLDS L;
+    __shared__ Key red[16];
+    const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
+    const uint32_t q = blockIdx.x % Lp.chunks;
+    const uint32_t f = w.setflags[s];
+    if (!(f & SETF_VALID)) return;
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    const int M = b.M[s];
+    const uint32_t P = w.np[np_index(Lp.K, M, M)];
+    if (q >= P) return;
+    Key best = key_none();
+    if (!(f & SETF_LEMMA1) && q >= p_lo && q < p_hi) {
+        Tables tb;
+        stage_set(L, w, off, n, M, s, false, tb);
+        int m[KMAX];
+        const int k = unrank<KMAX>(w.np, M, Lp.K, q, m);
+        uint64_t A = 1;
+        for (int i = 0; i < n; i++) A *= (uint64_t)k;
+        for (uint64_t a = threadIdx.x; a < A; a += blockDim.x) {
+            uint64_t S[KMAX];
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) S[p] = 0ull;
+            uint64_t x = a;
+            for (int i = n - 1; i >= 0; i--) {
+                const int d = (int)(x % (uint64_t)k);
+                x /= (uint64_t)k;
+                const uint64_t bit = 1ull << L.rank_of[i];
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (p == d) S[p] |= bit;
+            }
+            bool ok = true;
+            uint64_t mx = 0, sm = 0;
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                if (ok && p < k && S[p]) {
+                    uint64_t u;
+                    if (!part_test(L, tb, S[p], m[p], &u)) {
+                        ok = false;
+                    } else {
+                        mx = max(mx, u);
+                        sm += u;
+                    }
+                }
+            }
+            if (ok) {
+                const Key kk{mx, sm, q, a};
+                if (key_less(kk, best)) best = kk;
+            }
+        }
+    }
+    best = block_min(best, red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = w.partial + 4 * ((s) * (int64_t)Lp.chunks + q);
+        dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+        if (o.dbg_key != nullptr && q >= p_lo && q < p_hi) {
+            uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
+            d[0] = best.a; d[1] = best.b; d[2] = best.d;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// final: one wave per set.
+template <int KMAX>
+__global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launch Lp)
+{
+    __shared__ SetLDS L;
+    __shared__ uint64_t sS[KMAX];
+    __shared__ int sm_[KMAX];
+    __shared__ int sk;
+    const int64_t s = Lp.s0 + blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t f = w.setflags[s];
+    const int K = Lp.K;
+    if (!(f & SETF_VALID)) {
+        const int64_t off0 = b.off[s], off1 = b.off[s + 1];
+        if (lane == 0) {
+            o.verdict[s] = 0; o.verdict_1g[s] = 0; o.pidx[s] = -1; o.aidx[s] = -1;
+            o.maxU[s] = 0; o.sumU[s] = 0; o.n_evals[s] = 0;
+        }
+        for (int p = lane; p < K; p += 64) o.sizes[s * K + p] = 0;
+        if (off0 >= 0 && off1 >= off0 && off1 <= b.n_tasks_total) {
+            for (int64_t i = off0 + lane; i < off1; i += 64) { o.alloc[i] = -1; o.R[i] = -1; o.R_1g[i] = -1; }
+        }
+        return;
+    }
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    const int M = b.M[s];
+    const uint32_t P = w.np[np_index(K, M, M)];
+    // reduce the partials of this set's live chunks
+    Key best = key_none();
+    const bool exh = (Lp.mode == CAPART_EXHAUSTIVE);
+    for (int c = lane; c < Lp.chunks; c += 64) {
+        const bool live = exh ? ((uint32_t)c < P) : ((uint64_t)c * Lp.chunk < P);
+        if (!live) continue;
+        const uint64_t *src = w.partial + 4 * (s * (int64_t)Lp.chunks + c);
+        const Key kk{src[0], src[1], src[2], src[3]};
+        if (key_less(kk, best)) best = kk;
+    }
+    best = wave_min(best);
+    const bool found = best.a != ~0ull;
+    const bool act = (Lp.mode == CAPART_HEUR_BF_ACT || Lp.mode == CAPART_HEUR_SMS_ACT);
+    Tables tb;
+    stage_set(L, w, off, n, M, s, act, tb);
+    if (found && lane == 0) {
+        int m[KMAX];
+        int k = unrank<KMAX>(w.np, M, K, (uint32_t)best.c, m);
+        uint64_t S[KMAX], U[KMAX];
+#pragma unroll
+        for (int p = 0; p < KMAX; p++) S[p] = 0ull;
+        if (exh) {
+            uint64_t x = best.d;
+            for (int i = n - 1; i >= 0; i--) {
+                const int d = (int)(x % (uint64_t)k);
+                x /= (uint64_t)k;
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (p == d) S[p] |= 1ull << L.rank_of[i];
+            }
+        } else {
+            switch (Lp.mode) {
+            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true>(L, tb, n, m, k, S, U); break;
+            default: heuristic<KMAX, true, true>(L, tb, n, m, k, S, U); break;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < KMAX; p++) { sS[p] = S[p]; sm_[p] = m[p]; }
+        sk = k;
+    }
+    __syncthreads();
+    // response times of the chosen triple
+    if (lane < n) {
+        const int64_t gi = off + L.orig[lane];
+        if (found) {
+            int part = 0, mp = 0;
+            uint64_t Sp = 0;
+            for (int p = 0; p < sk; p++)
+                if ((sS[p] >> lane) & 1ull) { part = p; mp = sm_[p]; Sp = sS[p]; }
+            const uint32_t R = rta(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull), conflict_mask(Sp, L.memmask));
+            o.alloc[gi] = (int8_t)part;
+            o.R[gi] = R ? (int64_t)R : -1;
+        } else {
+            o.alloc[gi] = -1;
+            o.R[gi] = -1;
+        }
+    }
+    // whole-GPU baseline: every task on one partition of M units
+    bool ok1 = true;
+    if (!(Lp.flags & CAPART_FLAG_SKIP_1G)) {
+        const uint64_t all = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+        uint32_t R1 = 0;
+        if (lane < n) {
+            R1 = rta(L, tb, M, lane, all & ((1ull << lane) - 1ull), conflict_mask(all, L.memmask));
+            o.R_1g[off + L.orig[lane]] = R1 ? (int64_t)R1 : -1;
+        }
+        ok1 = !__ballot(lane < n && R1 == 0u);
+    } else {
+        if (lane < n) o.R_1g[off + L.orig[lane]] = -1;
+        ok1 = false;
+    }
+    if (lane == 0) {
+        o.verdict[s] = found ? 1 : 0;
+        o.verdict_1g[s] = ok1 ? 1 : 0;
+        o.pidx[s] = found ? (int32_t)best.c : -1;
+        o.aidx[s] = found ? (int64_t)best.d : -1;
+        o.maxU[s] = found ? best.a : 0ull;
+        o.sumU[s] = found ? best.b : 0ull;
+        o.n_evals[s] = (int64_t)P;
+    }
+    for (int p = lane; p < K; p += 64) o.sizes[s * K + p] = (found && p < KMAX) ? sm_[p] : 0;
+}
+
+// ---------------------------------------------------------------------------
+// One triple of one set (set 0 of the batch): every task tested, one lane each.
+template <int KMAX>
+__global__ __launch_bounds__(64) void triple_kernel(Batch b, Work w, const int32_t *sizes, int k, const int8_t *alloc,
+                                                    uint8_t *feasible, int64_t *Rout, uint64_t *maxU, uint64_t *sumU)
+{
+    __shared__ SetLDS L;
+    __shared__ uint64_t sS[KMAX];
+    __shared__ unsigned long long sU[KMAX];
+    const int lane = threadIdx.x;
+    if (!(w.setflags[0] & SETF_VALID)) return;
+    const int n = (int)(b.off[1] - b.off[0]);
+    const int M = b.M[0];  // every part size is in [1, M] (checked by the host)
+    Tables tb;
+    stage_set(L, w, 0, n, M, 0, false, tb);
+    if (lane < KMAX) { sS[lane] = 0ull; sU[lane] = 0ull; }
+    __syncthreads();
+    if (lane < n) {
+        const int p = alloc[L.orig[lane]];
+        atomicOr((unsigned long long *)&sS[p], (unsigned long long)(1ull << lane));
+    }
+    __syncthreads();
+    uint32_t R = 0;
+    if (lane < n) {
+        const int p = alloc[L.orig[lane]];
+        const uint64_t Sp = sS[p];
+        const uint64_t cm = conflict_mask(Sp, L.memmask);
+        R = rta(L, tb, sizes[p], lane, Sp & ((1ull << lane) - 1ull), cm);
+        Rout[L.orig[lane]] = R ? (int64_t)R : -1;
+        if (R) {
+            const uint32_t u = tb.U[(sizes[p] - 1) * 2 * n + (int)((cm >> lane) & 1ull) * n + lane];
+            atomicAdd(&sU[p], (unsigned long long)u + 1ull);
+        }
+    }
+    const bool ok = !__ballot(lane < n && R == 0u);
+    __syncthreads();
+    if (lane == 0) {
+        uint64_t mx = 0, sm = 0;
+        for (int p = 0; p < k; p++) { mx = max(mx, (uint64_t)sU[p]); sm += sU[p]; }
+        *feasible = ok ? 1 : 0;
+        *maxU = ok ? mx : 0ull;
+        *sumU = ok ? sm : 0ull;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-set tables: 4 u32 per (m, task) pair; every valid set has n * M <= CAPART_MAX_NM.
+size_t table_lds_bytes(int max_tasks, int max_M)
+{
+    const long nm = (long)max_tasks * max_M;
+    return (size_t)16 * (size_t)(nm < CAPART_MAX_NM ? nm : CAPART_MAX_NM);
+}
+
+static size_t dyn_bytes(const Batch &b) { return table_lds_bytes(min(b.max_tasks, MAXN), min(b.max_M, 255)); }
+
+hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    if (L.S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)L.S), dim3(64), 0, st, b, w, o, L);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_eval_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                                uint32_t p_lo, uint32_t p_hi)
+{
+    const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
+    const size_t lds = dyn_bytes(b);
+    switch (L.mode) {
+    case CAPART_EXHAUSTIVE:
+        hipLaunchKernelGGL((eval_exh_kernel<KMAX>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    case CAPART_HEUR_BF_INA:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    case CAPART_HEUR_BF_ACT:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    case CAPART_HEUR_SMS_INA:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    default:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                             uint32_t p_lo, uint32_t p_hi)
+{
+    if (L.S <= 0) return hipSuccess;
+    return L.K <= 4 ? launch_eval_k<4>(b, w, o, L, st, p_lo, p_hi) : launch_eval_k<8>(b, w, o, L, st, p_lo, p_hi);
+}
+
+hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    return launch_eval_range(b, w, o, L, st, 0u, 0xFFFFFFFFu);
+}
+
+hipError_t launch_final(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    if (L.S <= 0) return hipSuccess;
+    const size_t lds = dyn_bytes(b);
+    if (L.K <= 4)
+        hipLaunchKernelGGL((final_kernel<4>), dim3((unsigned)L.S), dim3(64), lds, st, b, w, o, L);
+    else
+        hipLaunchKernelGGL((final_kernel<8>), dim3((unsigned)L.S), dim3(64), lds, st, b, w, o, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
+                         uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st)
+{
+    const size_t lds = dyn_bytes(b);
+    hipLaunchKernelGGL((triple_kernel<8>), dim3(1), dim3(64), lds, st, b, w, sizes, k, alloc, feasible, R, maxU,
+                       sumU);
+    return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t allow_lds(F *fn)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)table_lds_bytes(MAXN, CAPART_MAX_M));
+}
+
+hipError_t configure_kernels()
+{
+    hipError_t e = hipSuccess, t;
+#define CAPART_ALLOW(fn) do { t = allow_lds(fn); if (t != hipSuccess) e = t; } while (0)
+    CAPART_ALLOW((eval_exh_kernel<4>));
+    CAPART_ALLOW((eval_exh_kernel<8>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true>));
+    CAPART_ALLOW((final_kernel<4>));
+    CAPART_ALLOW((final_kernel<8>));
+    CAPART_ALLOW((triple_kernel<8>));
+#undef CAPART_ALLOW
+    return e;
+}
+
+}  // namespace capart

@@ -1,0 +1,84 @@
+// Host-compiled check of the kernels' integer arithmetic (capart_arith.h)
+// against plain 128-bit reference expressions.  Exit status 0 = all passed.
+#define CAPART_HD
+#include "capart_arith.h"
+
+#include <cstdio>
+#include <cstdint>
+#include <random>
+
+using namespace capart;
+typedef unsigned __int128 u128;
+
+static int fails = 0;
+#define CHECK(c) do { if (!(c)) { if (fails++ < 10) std::printf("FAIL %s line %d\n", #c, __LINE__); } } while (0)
+
+int main()
+{
+    std::mt19937_64 rng(12345);
+    // floor division by the 2^64 reciprocal: all 32-bit x for a few divisors,
+    // random pairs over the full range, and edge cases
+    const uint32_t edge_T[] = {2, 3, 5, 7, 10, 1000, 65535, 65536, 65537, 999999, 1u << 30, (1u << 31) - 1,
+                               (1u << 31) - 2, 0x7FFFFFFDu, 3u << 29};
+    const uint32_t edge_x[] = {0, 1, 2, 0x7FFFFFFEu, 0x7FFFFFFFu, 0x80000000u, 0xFFFFFFFEu, 0xFFFFFFFFu};
+    for (uint32_t T : edge_T) {
+        uint32_t lo, hi;
+        magic_u32(T, &lo, &hi);
+        for (uint32_t x : edge_x) CHECK(floordiv_magic(x, lo, hi) == x / T);
+        for (int t = 0; t < 200000; t++) {
+            uint32_t x = (uint32_t)rng();
+            CHECK(floordiv_magic(x, lo, hi) == x / T);
+            uint32_t y = (uint32_t)(rng() % (4ull * T)) + (uint32_t)(rng() % 3) * T;  // near multiples
+            CHECK(floordiv_magic(y, lo, hi) == y / T);
+            uint32_t z = (uint32_t)((rng() % 1000) * (uint64_t)T % 0x100000000ull);
+            if (z) CHECK(floordiv_magic(z - 1, lo, hi) == (z - 1) / T);
+            CHECK(floordiv_magic(z, lo, hi) == z / T);
+        }
+    }
+    for (uint32_t T = 2; T < 3000; T++) {
+        uint32_t lo, hi;
+        magic_u32(T, &lo, &hi);
+        for (uint32_t x = 0; x < 40000; x += 7) CHECK(floordiv_magic(x, lo, hi) == x / T);
+        for (int t = 0; t < 200; t++) { uint32_t x = (uint32_t)rng(); CHECK(floordiv_magic(x, lo, hi) == x / T); }
+    }
+    for (int t = 0; t < 2000000; t++) {
+        uint32_t T = 2 + (uint32_t)(rng() % ((1u << 31) - 3));
+        uint32_t lo, hi;
+        magic_u32(T, &lo, &hi);
+        uint32_t x = (uint32_t)rng();
+        CHECK(floordiv_magic(x, lo, hi) == x / T);
+    }
+    // execution times, utilisation, Lemma 2
+    for (int t = 0; t < 2000000; t++) {
+        uint32_t Cs = (uint32_t)(rng() % (1u << 30)), Cp = (uint32_t)(rng() % (1u << 30));
+        if (t % 3 == 0) { Cs = (uint32_t)(rng() % 1000); Cp = (uint32_t)(rng() % 100000); }
+        if (Cs + Cp == 0) Cp = 1;
+        uint32_t m = 1 + (uint32_t)(rng() % 255);
+        uint32_t k = 1000 + (uint32_t)(rng() % 999001);
+        uint64_t cn_ref = (uint64_t)Cs + ((uint64_t)Cp + m - 1) / m;
+        uint32_t cn = time_n(Cs, Cp, m);
+        CHECK(cn == cn_ref);
+        u128 cc_ref = ((u128)k * cn_ref + 999) / 1000;
+        uint32_t cc = time_c(k, cn);
+        CHECK(cc == (cc_ref > C_SAT ? C_SAT : (uint32_t)cc_ref));
+        uint32_t T = 1 + (uint32_t)(rng() % ((1u << 31) - 1));
+        if (t % 2) T = cn + (uint32_t)(rng() % 1000);
+        if (T >= (1u << 31)) T = (1u << 31) - 1;
+        uint32_t u = util_q32_m1(cn, T);
+        if (cn <= T) {
+            u128 q = (((u128)cn << 32) + T - 1) / T;
+            CHECK((u128)u + 1 == q);
+        } else {
+            CHECK(u == 0xFFFFFFFFu);
+        }
+        uint32_t D = 1 + (uint32_t)(rng() % ((1u << 31) - 1));
+        if (t % 2) D = cn_ref < (1u << 31) ? (uint32_t)cn_ref + (uint32_t)(rng() % 3) : D;
+        uint32_t M = 1 + (uint32_t)(rng() % 255);
+        uint16_t mm = m_min(Cs, Cp, D, M);
+        uint32_t want = MMIN_NONE;
+        for (uint32_t q = 1; q <= M; q++) if ((uint64_t)Cs + ((uint64_t)Cp + q - 1) / q <= D) { want = q; break; }
+        CHECK(mm == want);
+    }
+    std::printf("%s (%d failures)\n", fails ? "FAILED" : "OK", fails);
+    return fails ? 1 : 0;
+}

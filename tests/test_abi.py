@@ -1,0 +1,100 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol that
+include/capart.h declares, and its host-side logic (partition enumeration,
+input validation) agrees with the oracle.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10312_amd import capart, workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "capart.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:capart_status|const char \*)\s*(capart_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = capart.load_library()
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert sorted(syms) == sorted(capart.EXPORTS)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(capart.CapartError) as e:
+        capart.capart_create(0)
+    assert e.value.code in (capart.CAPART_E_DEVICE, capart.CAPART_E_INVAL)
+    assert capart.capart_last_error(None)
+
+
+@pytest.mark.parametrize("M,K", [(1, 1), (8, 3), (16, 4), (48, 4), (80, 4), (108, 4), (30, 8), (255, 2), (60, 6)])
+def test_enumeration_matches_oracle(M, K):
+    assert capart.capart_count_partitionings(M, K) == oracle.count_partitionings(M, K)
+    assert np.array_equal(capart.capart_enumerate_partitionings(M, K), oracle.enumerate_partitionings(M, K))
+
+
+def test_enumeration_argument_errors():
+    lib = capart.load_library()
+    c = ctypes.c_int64(0)
+    assert lib.capart_count_partitionings(0, 3, ctypes.byref(c)) == capart.CAPART_E_INVAL
+    assert lib.capart_count_partitionings(8, 9, ctypes.byref(c)) == capart.CAPART_E_INVAL
+    assert lib.capart_count_partitionings(256, 2, ctypes.byref(c)) == capart.CAPART_E_INVAL
+    assert lib.capart_count_partitionings(8, 3, None) == capart.CAPART_E_INVAL
+
+
+def _bad_batch():
+    good = dict(T=[100], D=[100], C_seq=[1], C_par=[10], k_permille=[1200], type=[0])
+    sets = [
+        (8, good), (0, good), (256, good), (8, dict(good, T=[0], D=[0])), (8, dict(good, D=[101])),
+        (8, dict(good, D=[0])), (8, dict(good, T=[2**31], D=[5])), (8, dict(good, C_seq=[-1])),
+        (8, dict(good, C_seq=[0], C_par=[0])), (8, dict(good, C_par=[2**31])),
+        (8, dict(good, k_permille=[999])), (8, dict(good, k_permille=[1000001])), (8, dict(good, type=[2])),
+        (8, {k: v * 65 for k, v in good.items()}), (200, {k: v * 41 for k, v in good.items()}),
+        (8, {k: v * 40 for k, v in good.items()}),
+    ]
+    tasks = []
+    for M, d in sets:
+        t = {k: np.array(v) for k, v in d.items()}
+        t["M"] = M
+        tasks.append(t)
+    off = np.zeros(len(tasks) + 1, np.int64)
+    off[1:] = np.cumsum([len(t["T"]) for t in tasks])
+    b = {"set_offset": off, "M": np.array([t["M"] for t in tasks], np.int32)}
+    for key, dt in (("T", np.int64), ("D", np.int64), ("C_seq", np.int64), ("C_par", np.int64),
+                    ("k_permille", np.int32), ("type", np.uint8)):
+        b[key] = np.concatenate([np.asarray(t[key], dt) for t in tasks])
+    return b
+
+
+@pytest.mark.parametrize("mode", ["EXH", "BF_INA"])
+def test_validation_matches_oracle(mode):
+    b = _bad_batch()
+    want = oracle.solve(b, 3, mode)["status"]
+    got = capart.capart_validate(b, 3, mode, max_tasks=64, max_M=255)
+    assert want.tolist() == got.tolist()
+    assert set(got.tolist()) == {0, -1, -2}
+
+
+def test_validation_on_generated_workloads_is_clean():
+    for ts in (workload.config_c1(), workload.config_c2(n_sets=500), workload.config_c3(n_sets=500)):
+        assert (capart.capart_validate(ts, 4, "BF_INA") == 0).all()
+
+
+def test_validate_rejects_bad_batch_arguments():
+    b = _bad_batch()
+    with pytest.raises(capart.CapartError):
+        capart.capart_validate(b, 9, "BF_INA")
+    with pytest.raises(capart.CapartError):
+        capart.capart_validate(b, 3, 7)
