@@ -80,11 +80,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
     ap.add_argument("--n-sets", type=int, default=100_000)
-    ap.add_argument("--cpu-sample", type=int, default=6000, help="task sets timed on the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=30000, help="task sets timed on the CPU oracle")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = all host cores (at most 16)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (counts from 200 sets)")
     ap.add_argument("--per-set-launch", action="store_true", help="plain path: one launch sequence per set")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.arange(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the engine shards task sets independently and this build "
               "runs no multi-GPU configuration (use --gpus 1)", file=sys.stderr)
