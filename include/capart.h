@@ -209,6 +209,67 @@ capart_status capart_solve(capart_ctx *ctx, const capart_tasksets *host_in, cons
 capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
                                  capart_results *dev_out, void *hip_stream);
 
+/*
+ * Batched form.  A plan binds one device-resident batch (capart_tasksets with
+ * device pointers) and its device result buffers, and prepares one persistent
+ * launch over all of it: the per-set sizes are read back once (set_offset and
+ * M), every set's partitionings are cut into work items of similar estimated
+ * cost (number of partitionings x (n+1)^2), items are queued largest first,
+ * and a persistent evaluation grid pulls them from a device counter, so sets of
+ * uneven size and budget share one launch without idle blocks.  With
+ * use_graph the prep, evaluation and final kernels are captured into a HIP
+ * graph; capart_run_batch then costs one graph launch.  With autotune the plan
+ * times candidate tunings (threads per block, loop form, item size, blocks per
+ * compute unit) on a prefix of the batch and keeps the fastest; every candidate
+ * computes identical results.  Autotuning runs the path on that prefix and so
+ * writes into the result buffers.  The plan owns its workspace; the caller
+ * keeps the bound buffers alive and unchanged in size while the plan exists.
+ * Results are those of capart_solve_async on the same batch, bit for bit.
+ * Exhaustive mode is not batched this way (E_INVAL).
+ */
+typedef struct capart_plan capart_plan;
+
+typedef struct capart_plan_config {
+    int32_t autotune;       /* 1: time candidates on a prefix of the batch; 0: use the context's tuning */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit, 0 = automatic                        */
+    int32_t item_evals;     /* partitionings per work item for a 10-task set, 0 = automatic             */
+    int32_t use_graph;      /* 1: capture the launch sequence into a HIP graph                          */
+} capart_plan_config;
+
+typedef struct capart_plan_info {
+    int64_t n_sets, n_items, total_evals;
+    int32_t threads, loop_form, blocks, item_evals;
+    int32_t candidates_tried, use_graph;
+    double tune_ms;         /* host wall time spent autotuning */
+} capart_plan_info;
+
+capart_status capart_plan_batch(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                const capart_results *dev_out, const capart_plan_config *cfg, capart_plan **out);
+/* Run the plan on hip_stream (NULL = default stream): one graph launch, or the
+ * three kernels when kernel timing is enabled on the plan's context (same
+ * kernels and arguments, bracketed by timing events). */
+capart_status capart_run_batch(capart_plan *plan, void *hip_stream);
+capart_status capart_plan_get_info(const capart_plan *plan, capart_plan_info *info);
+capart_status capart_plan_destroy(capart_plan *plan);
+
+/* Launch tuning of a context (applies to later calls on it).  Every choice
+ * computes identical results; they trade divergence, occupancy and block
+ * count.  threads: threads per evaluation block, 0 = automatic, else 64, 128,
+ * 192 or 256 (reduced automatically when a set's LDS tables need it); chunk:
+ * partitionings per evaluation block, 0 = automatic (enough blocks to fill the
+ * chip); loop_form: 0 = automatic, 1 = each lane runs the heuristic of one
+ * partitioning per loop step, 2 = each loop step is one candidate test (a lane
+ * that finishes a partitioning continues with its next one at the next step).
+ * NULL restores the automatic choices.  E_INVAL for values out of range. */
+typedef struct capart_tuning {
+    int32_t threads;
+    int32_t chunk;
+    int32_t loop_form;
+    int32_t reserved;  /* must be 0 */
+} capart_tuning;
+capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
+capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);
+
 /* Kernel timing.  While enabled on a context, every launch sequence of
  * capart_solve / capart_solve_async records HIP events on its own stream
  * before and after the prep, eval and final kernels (one sequence per batch,

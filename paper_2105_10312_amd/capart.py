@@ -26,7 +26,9 @@ MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPAR
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
 EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count_partitionings",
            "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
-           "capart_solve", "capart_solve_async", "capart_timing_enable", "capart_timing_read"]
+           "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
+           "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
+           "capart_plan_destroy"]
 
 _vp = C.c_void_p
 
@@ -45,6 +47,21 @@ class capart_results(C.Structure):
     _fields_ = [("status", _vp), ("verdict", _vp), ("verdict_1g", _vp), ("pidx", _vp), ("sizes", _vp),
                 ("aidx", _vp), ("maxU", _vp), ("sumU", _vp), ("n_evals", _vp), ("alloc", _vp), ("R", _vp),
                 ("R_1g", _vp), ("dbg_key", _vp), ("dbg_offset", _vp)]
+
+
+class capart_tuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("reserved", C.c_int32)]
+
+
+class capart_plan_config(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("blocks_per_cu", C.c_int32), ("item_evals", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class capart_plan_info(C.Structure):
+    _fields_ = [("n_sets", C.c_int64), ("n_items", C.c_int64), ("total_evals", C.c_int64), ("threads", C.c_int32),
+                ("loop_form", C.c_int32), ("blocks", C.c_int32), ("item_evals", C.c_int32),
+                ("candidates_tried", C.c_int32), ("use_graph", C.c_int32), ("tune_ms", C.c_double)]
 
 
 class CapartError(RuntimeError):
@@ -83,7 +100,14 @@ def load_library():
                                         _vp, _vp, _vp]
         lib.capart_solve.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results)]
         lib.capart_solve_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp]
+        lib.capart_set_tuning.argtypes = [_vp, P(capart_tuning)]
+        lib.capart_get_tuning.argtypes = [_vp, P(capart_tuning)]
         lib.capart_timing_enable.argtypes = [_vp, C.c_int]
+        lib.capart_plan_batch.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results),
+                                          P(capart_plan_config), P(_vp)]
+        lib.capart_run_batch.argtypes = [_vp, _vp]
+        lib.capart_plan_get_info.argtypes = [_vp, P(capart_plan_info)]
+        lib.capart_plan_destroy.argtypes = [_vp]
         lib.capart_timing_read.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS:
             if name != "capart_last_error":
@@ -298,6 +322,17 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
                                              C.c_void_p(stream.cuda_stream)), ctx)
 
 
+def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0) -> None:
+    t = capart_tuning(int(threads), int(chunk), int(loop_form), 0)
+    _check(load_library().capart_set_tuning(ctx, C.byref(t)), ctx)
+
+
+def capart_get_tuning(ctx) -> dict:
+    t = capart_tuning()
+    _check(load_library().capart_get_tuning(ctx, C.byref(t)), ctx)
+    return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form}
+
+
 def capart_timing_enable(ctx, enable: bool = True) -> None:
     _check(load_library().capart_timing_enable(ctx, int(bool(enable))), ctx)
 
@@ -309,6 +344,48 @@ def capart_timing_read(ctx):
     _check(load_library().capart_timing_read(ctx, ms.ctypes.data, n.ctypes.data), ctx)
     names = ("prep", "eval", "final")
     return dict(zip(names, ms.tolist())), dict(zip(names, n.tolist()))
+
+
+class Plan:
+    """Batched form: a persistent, optionally graph-captured launch bound to one
+    device batch and its device result tensors (keeps them alive)."""
+
+    def __init__(self, ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, flags: int = 0,
+                 autotune: bool = True, blocks_per_cu: int = 0, item_evals: int = 0, use_graph: bool = True,
+                 dbg_key=None, dbg_offset=None):
+        self.ctx = ctx
+        self._st, self._keep = make_tasksets(dev_ts, max_tasks, max_M)
+        self._opt = make_options(K, mode, flags)
+        self._out = dev_out
+        self._res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
+        self._dbg = (dbg_key, dbg_offset)
+        cfg = capart_plan_config(int(bool(autotune)), int(blocks_per_cu), int(item_evals), int(bool(use_graph)))
+        h = _vp()
+        _check(load_library().capart_plan_batch(ctx, C.byref(self._st), C.byref(self._opt), C.byref(self._res),
+                                                C.byref(cfg), C.byref(h)), ctx)
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(load_library().capart_run_batch(self.handle, C.c_void_p(stream.cuda_stream)), self.ctx)
+
+    def info(self) -> dict:
+        i = capart_plan_info()
+        _check(load_library().capart_plan_get_info(self.handle, C.byref(i)), self.ctx)
+        return {f[0]: getattr(i, f[0]) for f in capart_plan_info._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _check(load_library().capart_plan_destroy(self.handle), self.ctx)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Engine:

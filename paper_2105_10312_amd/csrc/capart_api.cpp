@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -26,6 +27,7 @@ struct capart_ctx {
     size_t ws_bytes = 0;
     void *stage = nullptr;         // staging buffer for host-pointer calls
     size_t stage_bytes = 0;
+    capart_tuning tune{0, 0, 0, 0}; // launch tuning (0 = automatic)
     bool timing = false;           // record kernel events
     std::vector<hipEvent_t> ev_free;
     std::vector<std::array<hipEvent_t, 4>> ev_pending;
@@ -199,7 +201,7 @@ struct Plan {
     int64_t S, N;
 };
 
-Plan make_plan(const capart_tasksets *in, const capart_options *opt)
+Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capart_tuning &tu)
 {
     Plan p;
     p.S = in->n_sets;
@@ -210,7 +212,10 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt)
     L.K = opt->K;
     L.mode = opt->alloc_mode;
     L.flags = opt->flags;
-    L.threads = 256;
+    L.threads = eval_threads(in->max_tasks, in->max_M);
+    if (tu.threads > 0) L.threads = std::min(L.threads, tu.threads);
+    L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
+    L.form = tu.loop_form > 0 ? tu.loop_form : 1;
     const uint32_t Pmax = count_parts(in->max_M, opt->K);
     if (opt->alloc_mode == CAPART_EXHAUSTIVE) {
         L.chunks = (int)Pmax;
@@ -221,9 +226,10 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt)
         const int64_t per_set_launch = (opt->flags & CAPART_FLAG_PER_SET_LAUNCH) ? 1 : p.S;
         const int64_t want_blocks = 2048;
         int64_t ch = (want_blocks + std::max<int64_t>(per_set_launch, 1) - 1) / std::max<int64_t>(per_set_launch, 1);
-        const int64_t chmax = std::max<int64_t>(1, (Pmax + 255) / 256);
+        const int64_t chmax = std::max<int64_t>(1, (Pmax + L.threads - 1) / L.threads);
         ch = std::max<int64_t>(1, std::min(ch, chmax));
         L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
+        if (tu.chunk > 0) L.chunk = std::min<uint32_t>((uint32_t)tu.chunk, std::max<uint32_t>(Pmax, 1));
         L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
     }
     return p;
@@ -251,6 +257,7 @@ capart_status launch_three(capart_ctx *c, const Batch &b, const Work &w, const O
         for (auto &e : ev)
             if (!(e = take_event(c))) return fail(c, CAPART_E_DEVICE, "hipEventCreate failed");
     hipError_t e;
+    (void)hipGetLastError();  // launch checks below report this sequence's errors only
     if (tm) hipEventRecord(ev[0], st);
     if ((e = launch_prep(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
     if (tm) hipEventRecord(ev[1], st);
@@ -271,7 +278,7 @@ capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &
     capart_status rc = ensure_ws(c, l.total);
     if (rc != CAPART_OK) return rc;
     char *base = (char *)c->ws;
-    Work w;
+    Work w{};
     w.rec = (TaskRec *)(base + l.rec);
     w.forbid = (uint64_t *)(base + l.forbid);
     w.sigma = (uint8_t *)(base + l.sigma);
@@ -480,7 +487,7 @@ capart_status capart_solve_async(capart_ctx *c, const capart_tasksets *in, const
     if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    const Plan p = make_plan(in, opt);
+    const Plan p = make_plan(in, opt, c->tune);
     return run_plan(c, make_batch(in), make_out(out), p, (hipStream_t)hip_stream);
 }
 
@@ -542,7 +549,7 @@ static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const 
             return hip_fail(c, e, "hipMemcpyAsync H2D");
     d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
     d.type = d_ty;
-    const Plan p = make_plan(in, opt);
+    const Plan p = make_plan(in, opt, c->tune);
     if ((rc = run_plan(c, make_batch(&d), make_out(&r), p, st, p_lo, p_hi)) != CAPART_OK) return rc;
     Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
                 {out->verdict_1g, r.verdict_1g, (size_t)S}, {out->pidx, r.pidx, 4 * (size_t)S},
@@ -621,11 +628,11 @@ capart_status capart_test_triple(capart_ctx *c, const capart_tasksets *one, cons
     capart_tasksets d = *one;
     d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
     d.type = d_ty;
-    const Plan p = make_plan(&d, &opt);
+    const Plan p = make_plan(&d, &opt, c->tune);
     const WsLayout l = ws_layout(1, n, p.L.chunks);
     if ((rc = ensure_ws(c, l.total)) != CAPART_OK) return rc;
     char *base = (char *)c->ws;
-    Work w;
+    Work w{};
     w.rec = (TaskRec *)(base + l.rec);
     w.forbid = (uint64_t *)(base + l.forbid);
     w.sigma = (uint8_t *)(base + l.sigma);
@@ -697,6 +704,29 @@ capart_status capart_allocate(capart_ctx *c, const capart_tasksets *one, const i
     return CAPART_OK;
 }
 
+capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
+{
+    if (!c) return CAPART_E_INVAL;
+    if (!t) {
+        c->tune = capart_tuning{0, 0, 0, 0};
+        return CAPART_OK;
+    }
+    if (t->threads < 0 || t->threads > 256 || (t->threads % 64) != 0)
+        return fail(c, CAPART_E_INVAL, "threads must be 0 or a multiple of 64 up to 256");
+    if (t->chunk < 0) return fail(c, CAPART_E_INVAL, "chunk must be >= 0");
+    if (t->loop_form < 0 || t->loop_form > 2) return fail(c, CAPART_E_INVAL, "loop_form must be 0, 1 or 2");
+    if (t->reserved != 0) return fail(c, CAPART_E_INVAL, "reserved must be 0");
+    c->tune = *t;
+    return CAPART_OK;
+}
+
+capart_status capart_get_tuning(const capart_ctx *c, capart_tuning *t)
+{
+    if (!c || !t) return CAPART_E_INVAL;
+    *t = c->tune;
+    return CAPART_OK;
+}
+
 capart_status capart_timing_enable(capart_ctx *c, int enable)
 {
     if (!c) return CAPART_E_INVAL;
@@ -729,6 +759,340 @@ capart_status capart_timing_read(capart_ctx *c, double *ms, int64_t *launches)
     for (auto &a : c->ev_pending)
         for (auto e : a) c->ev_free.push_back(e);
     c->ev_pending.clear();
+    return CAPART_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form (plan / run).
+struct capart_plan {
+    capart_ctx *ctx = nullptr;
+    capart_tasksets in{};
+    capart_options opt{};
+    capart_results out{};
+    Launch L{};
+    int blocks = 0;
+    bool use_graph = true;
+    void *buf = nullptr;
+    Work w{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    capart_plan_info info{};
+};
+
+namespace {
+
+struct PlanLayout {
+    size_t rec, forbid, sigma, setflags, memmask, partial, items, slot_off, counter, total;
+};
+
+PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
+{
+    PlanLayout l;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + std::max<size_t>(bytes, 1)); return at; };
+    l.rec = take(sizeof(TaskRec) * (size_t)N);
+    l.forbid = take(8 * (size_t)N);
+    l.sigma = take((size_t)N);
+    l.setflags = take(4 * (size_t)S);
+    l.memmask = take(8 * (size_t)S);
+    l.partial = take(32 * (size_t)n_items);
+    l.items = take(sizeof(WorkItem) * (size_t)n_items);
+    l.slot_off = take(4 * (size_t)(S + 1));
+    l.counter = take(4);
+    l.total = o;
+    return l;
+}
+
+// Work items: each set's partitionings cut into ranges of about
+// item_evals * 121 / (n+1)^2 partitionings (the response-time work of a
+// partitioning grows roughly with n^2), queued by decreasing estimated cost.
+void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M, int64_t S, const capart_tasksets *in,
+                 int K, int item_evals, std::vector<WorkItem> &items, std::vector<uint32_t> &slot_off,
+                 int64_t &total_evals)
+{
+    items.clear();
+    slot_off.assign((size_t)S + 1, 0u);
+    total_evals = 0;
+    std::vector<uint64_t> cost;
+    for (int64_t s = 0; s < S; s++) {
+        slot_off[s] = (uint32_t)items.size();
+        const int64_t n = off[s + 1] - off[s];
+        const int32_t m = M[s];
+        if (off[s] < 0 || n < 1 || n > std::min(in->max_tasks, CAPART_MAX_TASKS) || m < 1 ||
+            m > std::min(in->max_M, CAPART_MAX_M) || n * m > CAPART_MAX_NM)
+            continue;
+        const uint32_t P = count_parts(m, K);
+        total_evals += P;
+        const uint64_t w = (uint64_t)(n + 1) * (uint64_t)(n + 1);
+        const uint32_t per = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(1u << 20, (uint64_t)item_evals * 121 / w));
+        for (uint32_t p0 = 0; p0 < P; p0 += per) {
+            const uint32_t p1 = std::min(P, p0 + per);
+            items.push_back(WorkItem{(uint32_t)s, p0, p1, (uint32_t)items.size()});
+            cost.push_back((uint64_t)(p1 - p0) * w);
+        }
+    }
+    slot_off[S] = (uint32_t)items.size();
+    std::vector<uint32_t> order(items.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    std::vector<WorkItem> sorted(items.size());
+    for (size_t i = 0; i < order.size(); i++) sorted[i] = items[order[i]];
+    items.swap(sorted);
+}
+
+struct PlanBuffers {
+    void *buf = nullptr;
+    Work w{};
+};
+
+capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std::vector<WorkItem> &items,
+                                 const std::vector<uint32_t> &slot_off, PlanBuffers &pb)
+{
+    const PlanLayout l = plan_layout(S, N, (int64_t)items.size());
+    hipError_t e = hipMalloc(&pb.buf, l.total);
+    if (e != hipSuccess) {
+        pb.buf = nullptr;
+        return fail(c, CAPART_E_NOMEM, "plan workspace allocation failed");
+    }
+    char *base = (char *)pb.buf;
+    pb.w.rec = (TaskRec *)(base + l.rec);
+    pb.w.forbid = (uint64_t *)(base + l.forbid);
+    pb.w.sigma = (uint8_t *)(base + l.sigma);
+    pb.w.setflags = (uint32_t *)(base + l.setflags);
+    pb.w.memmask = (uint64_t *)(base + l.memmask);
+    pb.w.partial = (uint64_t *)(base + l.partial);
+    pb.w.items = (const WorkItem *)(base + l.items);
+    pb.w.n_items = (uint32_t)items.size();
+    pb.w.counter = (uint32_t *)(base + l.counter);
+    pb.w.slot_off = (const uint32_t *)(base + l.slot_off);
+    pb.w.np = c->np_dev;
+    if (!items.empty() &&
+        (e = hipMemcpy(base + l.items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return hip_fail(c, e, "hipMemcpy items");
+    if ((e = hipMemcpy(base + l.slot_off, slot_off.data(), 4 * slot_off.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "hipMemcpy slot offsets");
+    return CAPART_OK;
+}
+
+capart_status launch_plan_kernels(capart_ctx *c, const Batch &b, const Work &w, const Out &o, const Launch &L,
+                                  int blocks, hipStream_t st, bool timed)
+{
+    std::array<hipEvent_t, 4> ev{};
+    if (timed)
+        for (auto &e : ev)
+            if (!(e = take_event(c))) return fail(c, CAPART_E_DEVICE, "hipEventCreate failed");
+    hipError_t e;
+    (void)hipGetLastError();
+    if (timed) hipEventRecord(ev[0], st);
+    if ((e = launch_prep(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if (timed) hipEventRecord(ev[1], st);
+    if ((e = launch_eval_persistent(b, w, o, L, blocks, st)) != hipSuccess) return hip_fail(c, e, "eval launch");
+    if (timed) hipEventRecord(ev[2], st);
+    if ((e = launch_final(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
+    if (timed) {
+        hipEventRecord(ev[3], st);
+        c->ev_pending.push_back(ev);
+    }
+    return CAPART_OK;
+}
+
+Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int threads, int form)
+{
+    Launch L{};
+    L.s0 = 0;
+    L.S = in->n_sets;
+    L.K = opt->K;
+    L.mode = opt->alloc_mode;
+    L.flags = opt->flags & ~CAPART_FLAG_PER_SET_LAUNCH;
+    L.threads = std::min(threads, eval_threads(in->max_tasks, in->max_M));
+    L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
+    L.form = form;
+    L.chunks = 1;
+    L.chunk = 0;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                const capart_results *out, const capart_plan_config *cfg, capart_plan **plan_out)
+{
+    if (!c || !plan_out) return CAPART_E_INVAL;
+    *plan_out = nullptr;
+    capart_status rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
+    if (opt->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "the batched form runs heuristic modes");
+    if (in->n_sets < 1) return fail(c, CAPART_E_INVAL, "empty batch");
+    if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
+    const capart_plan_config def{1, 0, 0, 1};
+    const capart_plan_config &cf = cfg ? *cfg : def;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const int64_t S = in->n_sets, N = in->n_tasks_total;
+    std::vector<int64_t> off((size_t)S + 1);
+    std::vector<int32_t> M((size_t)S);
+    if ((e = hipMemcpy(off.data(), in->set_offset, 8 * (size_t)(S + 1), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(M.data(), in->M, 4 * (size_t)S, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "reading set sizes");
+    const Batch b = make_batch(in);
+    const Out o = make_out(out);
+    const int cus = device_cu_count();
+    int threads = c->tune.threads > 0 ? c->tune.threads : 256;
+    int form = c->tune.loop_form > 0 ? c->tune.loop_form : 1;
+    int item_evals = cf.item_evals > 0 ? cf.item_evals : 4096;
+    int bpc = cf.blocks_per_cu > 0 ? cf.blocks_per_cu : 4;
+    int tried = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (cf.autotune) {
+        // candidates timed on a prefix of the batch (sets are independent
+        // draws, so a prefix has the batch's mix of sizes)
+        const int64_t St = std::min<int64_t>(S, std::max<int64_t>(4096, S / 16));
+        capart_tasksets sub = *in;
+        sub.n_sets = St;
+        sub.n_tasks_total = off[St];
+        const Batch bs = make_batch(&sub);
+        double best_ms = 1e300;
+        const int th_c[] = {128, 256};
+        const int form_c[] = {1, 2};
+        const int ie_c[] = {1024, 4096, 16384};
+        const int bpc_c[] = {2, 4, 8};
+        for (int th : th_c)
+            for (int fo : form_c)
+                for (int ie : ie_c)
+                    for (int bp : bpc_c) {
+                        if (cf.item_evals > 0 && ie != ie_c[1]) continue;
+                        if (cf.blocks_per_cu > 0 && bp != bpc_c[1]) continue;
+                        const int ie2 = cf.item_evals > 0 ? cf.item_evals : ie;
+                        const int bp2 = cf.blocks_per_cu > 0 ? cf.blocks_per_cu : bp;
+                        std::vector<WorkItem> items;
+                        std::vector<uint32_t> so;
+                        int64_t te = 0;
+                        build_items(off, M, St, in, opt->K, ie2, items, so, te);
+                        PlanBuffers pb;
+                        if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, pb)) != CAPART_OK) {
+                            if (pb.buf) hipFree(pb.buf);
+                            return rc;
+                        }
+                        const Launch L = plan_launch(&sub, opt, th, fo);
+                        hipEvent_t e0 = take_event(c), e1 = take_event(c);
+                        double ms = 0;
+                        for (int rep = 0; rep < 3 && rc == CAPART_OK; rep++) {
+                            if (rep == 1) hipEventRecord(e0, c->stream);
+                            rc = launch_plan_kernels(c, bs, pb.w, o, L, cus * bp2, c->stream, false);
+                        }
+                        hipEventRecord(e1, c->stream);
+                        hipError_t se = hipEventSynchronize(e1);
+                        float f = 0.f;
+                        if (se == hipSuccess) se = hipEventElapsedTime(&f, e0, e1);
+                        ms = f / 2.0;
+                        c->ev_free.push_back(e0);
+                        c->ev_free.push_back(e1);
+                        hipFree(pb.buf);
+                        if (rc != CAPART_OK) return rc;
+                        if (se != hipSuccess) return hip_fail(c, se, "autotune timing");
+                        tried++;
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            threads = th;
+                            form = fo;
+                            item_evals = ie2;
+                            bpc = bp2;
+                        }
+                    }
+    }
+    const double tune_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    capart_plan *pl = new (std::nothrow) capart_plan;
+    if (!pl) return fail(c, CAPART_E_NOMEM, "plan allocation failed");
+    pl->ctx = c;
+    pl->in = *in;
+    pl->opt = *opt;
+    pl->out = *out;
+    pl->use_graph = cf.use_graph != 0;
+    std::vector<WorkItem> items;
+    std::vector<uint32_t> so;
+    int64_t te = 0;
+    build_items(off, M, S, in, opt->K, item_evals, items, so, te);
+    PlanBuffers pb;
+    if ((rc = alloc_plan_buffers(c, S, N, items, so, pb)) != CAPART_OK) {
+        if (pb.buf) hipFree(pb.buf);
+        delete pl;
+        return rc;
+    }
+    pl->buf = pb.buf;
+    pl->w = pb.w;
+    pl->L = plan_launch(in, opt, threads, form);
+    pl->blocks = cus * bpc;
+    pl->info.n_sets = S;
+    pl->info.n_items = (int64_t)items.size();
+    pl->info.total_evals = te;
+    pl->info.threads = pl->L.threads;
+    pl->info.loop_form = form;
+    pl->info.blocks = pl->blocks;
+    pl->info.item_evals = item_evals;
+    pl->info.candidates_tried = tried;
+    pl->info.use_graph = pl->use_graph ? 1 : 0;
+    pl->info.tune_ms = tune_ms;
+    if (pl->use_graph) {
+        if ((e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            capart_plan_destroy(pl);
+            return hip_fail(c, e, "hipStreamBeginCapture");
+        }
+        rc = launch_plan_kernels(c, make_batch(in), pl->w, make_out(out), pl->L, pl->blocks, c->stream, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->stream, &g);
+        if (rc != CAPART_OK || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            capart_plan_destroy(pl);
+            return rc != CAPART_OK ? rc : hip_fail(c, e, "hipStreamEndCapture");
+        }
+        pl->graph = g;
+        if ((e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            pl->exec = nullptr;
+            capart_plan_destroy(pl);
+            return hip_fail(c, e, "hipGraphInstantiate");
+        }
+    }
+    *plan_out = pl;
+    return CAPART_OK;
+}
+
+capart_status capart_run_batch(capart_plan *pl, void *hip_stream)
+{
+    if (!pl) return CAPART_E_INVAL;
+    capart_ctx *c = pl->ctx;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (pl->use_graph && !c->timing) {
+        if ((e = hipGraphLaunch(pl->exec, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        return CAPART_OK;
+    }
+    return launch_plan_kernels(c, make_batch(&pl->in), pl->w, make_out(&pl->out), pl->L, pl->blocks, st, c->timing);
+}
+
+capart_status capart_plan_get_info(const capart_plan *pl, capart_plan_info *info)
+{
+    if (!pl || !info) return CAPART_E_INVAL;
+    *info = pl->info;
+    return CAPART_OK;
+}
+
+capart_status capart_plan_destroy(capart_plan *pl)
+{
+    if (!pl) return CAPART_E_INVAL;
+    hipSetDevice(pl->ctx->device);
+    hipDeviceSynchronize();
+    if (pl->exec) hipGraphExecDestroy(pl->exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    if (pl->buf) hipFree(pl->buf);
+    delete pl;
     return CAPART_OK;
 }
 

@@ -38,14 +38,25 @@ struct Batch {           // device pointers of the caller's batch (set range [s0
     int32_t max_tasks, max_M;
 };
 
+// One unit of batched (persistent-kernel) work: partitionings [p0, p1) of a
+// set; its best key goes to partial slot `slot`.
+struct WorkItem {
+    uint32_t set, p0, p1, slot;
+};
+
 struct Work {            // device workspace owned by the context
     TaskRec *rec;        // [N]
     uint64_t *forbid;    // [N] ACT forbidden-pair masks, by rank
     uint8_t *sigma;      // [N] ranks in decreasing one-unit utilisation
     uint32_t *setflags;  // [S]
     uint64_t *memmask;   // [S] memory-intensive ranks
-    uint64_t *partial;   // [S * CH * 4] best key per (set, chunk)
+    uint64_t *partial;   // [S * CH * 4] best key per (set, chunk), or per item slot
     const uint32_t *np;  // partition-count table
+    // batched form only
+    const WorkItem *items;     // [n_items], largest first
+    uint32_t n_items;
+    uint32_t *counter;         // next item to take (reset by the prep kernel)
+    const uint32_t *slot_off;  // [S + 1] partial slots of each set
 };
 
 struct Out {             // device pointers of the caller's results
@@ -68,10 +79,13 @@ struct Launch {
     int chunks;          // CH: chunks per set
     uint32_t chunk;      // partitionings per chunk (heuristic) / 1 (exhaustive)
     int threads;         // threads per evaluation block
+    int table_words;     // u32 words of dynamic LDS reserved for the per-set tables
+    int form;            // heuristic loop form: 1 = one step per partitioning, 2 = one step per candidate test
 };
 
 // Host-side sizing helpers shared by the launchers.
 size_t table_lds_bytes(int max_tasks, int max_M);
+int eval_threads(int max_tasks, int max_M);
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
@@ -79,6 +93,10 @@ hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
                              uint32_t p_lo, uint32_t p_hi);
 hipError_t launch_final(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+// batched form: persistent evaluation over the work items with `blocks` blocks
+hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                  hipStream_t st);
+int device_cu_count();
 hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
                          uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st);
 hipError_t configure_kernels();

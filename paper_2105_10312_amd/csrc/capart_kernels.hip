@@ -87,6 +87,7 @@ struct SetLDS {
     uint32_t Cs[MAXN], Cp[MAXN], k[MAXN];
     uint32_t mmin[MAXN];
     uint64_t forbid[MAXN];
+    uint64_t intf[MAXN];  // ranks j with T_j < D_r: the only ones that can add a second job
     uint8_t sigma[MAXN];
     uint8_t orig[MAXN];
     uint8_t rank_of[MAXN];
@@ -118,6 +119,11 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
     }
     if (tid == 0) L.memmask = w.memmask[s];
     __syncthreads();
+    for (int r = tid; r < n; r += nt) {
+        uint64_t f = 0ull;
+        for (int j = 0; j < n; j++) f |= (uint64_t)(L.T[j] < L.D[r]) << j;
+        L.intf[r] = f;
+    }
     uint32_t *tc = capart_dyn_lds;
     uint32_t *tu = capart_dyn_lds + 2 * n * M;
     for (int e = tid; e < n * M; e += nt) {
@@ -136,75 +142,135 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
     tb.n = n;
 }
 
+// Rank masks: 32-bit when every set of the launch has at most 32 tasks.
+__device__ __forceinline__ int mctz(uint32_t x) { return __builtin_ctz(x); }
+__device__ __forceinline__ int mctz(uint64_t x) { return __builtin_ctzll(x); }
+__device__ __forceinline__ int mpopc(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ int mpopc(uint64_t x) { return __popcll(x); }
+template <typename MT>
+__device__ __forceinline__ MT below(int r) { return (MT(1) << r) - MT(1); }
+template <typename MT>
+__device__ __forceinline__ uint32_t mbit(MT m, int j) { return (uint32_t)(m >> j) & 1u; }
+
 // Conflict mask of a partition holding rank set S: bit r set iff task r has
 // another task of its type in S (Section "Task Model").
-__device__ __forceinline__ uint64_t conflict_mask(uint64_t S, uint64_t memmask)
+template <typename MT>
+__device__ __forceinline__ MT conflict_mask(MT S, MT memmask)
 {
-    const uint64_t mem = S & memmask, cmp = S & ~memmask;
-    return (__popcll(mem) >= 2 ? memmask : 0ull) | (__popcll(cmp) >= 2 ? ~memmask : 0ull);
+    const MT mem = S & memmask, cmp = S & ~memmask;
+    return (mpopc(mem) >= 2 ? memmask : MT(0)) | (mpopc(cmp) >= 2 ? ~memmask : MT(0));
 }
 
-// Exact response time of rank r on m units with higher-priority members hp
-// and conflict mask cm; returns 0 on a deadline miss.
-__device__ uint32_t rta(const SetLDS &L, const Tables &tb, int m, int r, uint64_t hp, uint64_t cm)
+// Fixed point of R = base + sum_{j in hp} floor((R-1)/T_j) C_j from R = base,
+// where base = C_r + sum_{j in hp} C_j is the demand with one job of every
+// higher-priority task (so the sum equals C_r + sum ceil(R/T_j) C_j), and hp
+// holds only tasks with T_j < D_r (the others never release a second job
+// before D_r).  Returns R, or 0 once R exceeds D.
+template <typename MT>
+__device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row, int n, uint64_t base, uint32_t D,
+                                           MT hp, MT cm)
+{
+    if (base > D) return 0u;
+    uint64_t R = base;
+    while (hp) {
+        const uint32_t x = (uint32_t)R - 1u;
+        uint64_t W = base;
+        for (MT h = hp; h; h &= h - MT(1)) {
+            const int j = mctz(h);
+            const uint32_t Cj = row[(int)mbit(cm, j) * n + j];
+            W += (uint64_t)floordiv_magic(x, L.clo[j], L.chi[j]) * Cj;
+        }
+        if (W > D) return 0u;
+        if (W == R) break;
+        R = W;
+    }
+    return (uint32_t)R;
+}
+
+// Test the members of S with rank >= first on one partition of m units,
+// taking the members below `first` as already schedulable (their response
+// times cannot change).  cm = conflict mask of S.
+template <typename MT>
+__device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, int m, MT cm)
 {
     const int n = tb.n;
     const uint32_t *row = tb.C + (m - 1) * 2 * n;
-    const uint32_t C = row[(int)((cm >> r) & 1ull) * n + r];
-    uint64_t base = C;
-    bool sat = false;
-    for (uint64_t h = hp; h; h &= h - 1) {
-        const int j = ctz64(h);
-        const uint32_t Cj = row[(int)((cm >> j) & 1ull) * n + j];
-        base += Cj;
+    uint64_t sumC = 0;
+    bool sat = false;  // some higher-priority task has utilisation >= 1
+    for (MT h = S & below<MT>(first); h; h &= h - MT(1)) {
+        const int j = mctz(h);
+        const uint32_t Cj = row[(int)mbit(cm, j) * n + j];
+        sumC += Cj;
         sat |= (Cj >= L.T[j]);
     }
-    const uint32_t D = L.D[r];
-    if (sat || base > D) return 0u;
-    uint64_t R = base;
-    for (;;) {
-        const uint32_t x = (uint32_t)R - 1u;
-        uint64_t W = base;
-        for (uint64_t h = hp; h; h &= h - 1) {
-            const int j = ctz64(h);
-            const uint32_t Cj = row[(int)((cm >> j) & 1ull) * n + j];
-            const uint32_t q = floordiv_magic(x, L.clo[j], L.chi[j]);
-            W += (uint64_t)q * Cj;
-        }
-        if (W > D) return 0u;
-        if (W == R) return (uint32_t)R;
-        R = W;
+    for (MT rem = S & ~below<MT>(first); rem; rem &= rem - MT(1)) {
+        const int r = mctz(rem);
+        const uint32_t Cr = row[(int)mbit(cm, r) * n + r];
+        if (sat) return false;
+        const MT hp = S & below<MT>(r) & (MT)L.intf[r];
+        if (!rta_fp<MT>(L, row, n, sumC + Cr, L.D[r], hp, cm)) return false;
+        sumC += Cr;
+        sat |= (Cr >= L.T[r]);
     }
+    return true;
 }
 
-// Schedulability of rank set S on one partition of m units; *U = Q32 sum.
-__device__ bool part_test(const SetLDS &L, const Tables &tb, uint64_t S, int m, uint64_t *U)
+// Whole-partition test with its Q32 utilisation.
+template <typename MT>
+__device__ bool part_test(const SetLDS &L, const Tables &tb, MT S, int m, uint64_t *U)
 {
     const int n = tb.n;
-    const uint64_t cm = conflict_mask(S, L.memmask);
+    const MT cm = conflict_mask<MT>(S, (MT)L.memmask);
+    if (!test_from<MT>(L, tb, S, 0, m, cm)) return false;
     const uint32_t *urow = tb.U + (m - 1) * 2 * n;
     uint64_t u = 0;
-    for (uint64_t rem = S; rem; rem &= rem - 1) {
-        const int r = ctz64(rem);
-        const uint64_t hp = S & ((1ull << r) - 1ull);
-        if (!rta(L, tb, m, r, hp, cm)) return false;
-        u += (uint64_t)urow[(int)((cm >> r) & 1ull) * n + r] + 1ull;
+    for (MT h = S; h; h &= h - MT(1)) {
+        const int r = mctz(h);
+        u += (uint64_t)urow[(int)mbit(cm, r) * n + r] + 1ull;
     }
     *U = u;
     return true;
 }
 
-// Fewest units (<= mp, where S is known feasible) that schedule S: binary
-// search, valid because feasibility is monotone in m (no timing anomalies).
-__device__ int min_units(const SetLDS &L, const Tables &tb, uint64_t S, int mp)
+// Test of S_old + {tau} on m units when S_old is known schedulable there with
+// utilisation U_old.  Only tau, the lower-priority members and (if tau makes
+// the single same-type member conflict) that member and those below it can
+// change; U is updated by the same differences.
+template <typename MT>
+__device__ bool part_test_add(const SetLDS &L, const Tables &tb, MT Sold, int tau, int m, uint64_t Uold,
+                              uint64_t *U)
+{
+    const int n = tb.n;
+    const MT memm = (MT)L.memmask;
+    const MT S = Sold | (MT(1) << tau);
+    const MT same = Sold & (mbit(memm, tau) ? memm : ~memm);
+    const int ns = mpopc(same);
+    const MT cm = conflict_mask<MT>(S, memm);
+    int first = tau, flip = -1;
+    if (ns == 1) {
+        flip = mctz(same);
+        first = min(first, flip);
+    }
+    if (!test_from<MT>(L, tb, S, first, m, cm)) return false;
+    const uint32_t *urow = tb.U + (m - 1) * 2 * n;
+    uint64_t u = Uold + (uint64_t)urow[(ns >= 1 ? n : 0) + tau] + 1ull;
+    if (flip >= 0) u += (uint64_t)urow[n + flip] - (uint64_t)urow[flip];
+    *U = u;
+    return true;
+}
+
+// Fewest units (<= mp, where S is known schedulable) that schedule S: binary
+// search, valid because schedulability is monotone in m (no timing anomalies).
+template <typename MT>
+__device__ int min_units(const SetLDS &L, const Tables &tb, MT S, int mp)
 {
     int lo = 1;
-    for (uint64_t h = S; h; h &= h - 1) lo = max(lo, (int)L.mmin[ctz64(h)]);
+    for (MT h = S; h; h &= h - MT(1)) lo = max(lo, (int)L.mmin[mctz(h)]);
     int hi = mp;
+    const MT cm = conflict_mask<MT>(S, (MT)L.memmask);
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        uint64_t u;
-        if (part_test(L, tb, S, mid, &u))
+        if (test_from<MT>(L, tb, S, 0, mid, cm))
             hi = mid;
         else
             lo = mid + 1;
@@ -212,41 +278,67 @@ __device__ int min_units(const SetLDS &L, const Tables &tb, uint64_t S, int mp)
     return lo;
 }
 
+// Response time of rank r on m units with higher-priority members hp (every
+// task of hp is evaluated whether or not it meets its own deadline); 0 on a miss.
+template <typename MT>
+__device__ uint32_t rta_one(const SetLDS &L, const Tables &tb, int m, int r, MT hp, MT cm)
+{
+    const int n = tb.n;
+    const uint32_t *row = tb.C + (m - 1) * 2 * n;
+    uint64_t base = row[(int)mbit(cm, r) * n + r];
+    bool sat = false;
+    for (MT h = hp; h; h &= h - MT(1)) {
+        const int j = mctz(h);
+        const uint32_t Cj = row[(int)mbit(cm, j) * n + j];
+        base += Cj;
+        sat |= (Cj >= L.T[j]);
+    }
+    if (sat) return 0u;
+    return rta_fp<MT>(L, row, n, base, L.D[r], hp & (MT)L.intf[r], cm);
+}
+
+template <int KMAX, typename V>
+__device__ __forceinline__ V pick(const V (&a)[KMAX], int p)
+{
+    V v = a[0];
+#pragma unroll
+    for (int i = 1; i < KMAX; i++) v = (p == i) ? a[i] : v;
+    return v;
+}
+
 // Heuristic allocation on a fixed partitioning m[0..k) (non-increasing):
 // tasks in decreasing one-unit utilisation, each to the best-ranked part that
 // stays schedulable.  S[p] = rank masks, U[p] = Q32 utilisations.
-template <int KMAX, bool ACT, bool SMS>
+template <int KMAX, bool ACT, bool SMS, typename MT>
 __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
-                          uint64_t (&S)[KMAX], uint64_t (&U)[KMAX])
+                                          MT (&S)[KMAX], uint64_t (&U)[KMAX])
 {
 #pragma unroll
-    for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; }
+    for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
     for (int t = 0; t < n; t++) {
         const int r = L.sigma[t];
-        const uint64_t bit = 1ull << r;
         const int mm = (int)L.mmin[r];
-        const uint64_t fb = ACT ? L.forbid[r] : 0ull;
+        const MT fb = ACT ? (MT)L.forbid[r] : MT(0);
         int best = -1, bestReq = 0;
         uint64_t bestU = 0;
         // parts are visited with compile-time indices so that S, U and m stay in registers
 #pragma unroll
         for (int p = 0; p < KMAX; p++) {
             const int mp = m[p];
-            const uint64_t Sp = S[p];
+            const MT Sp = S[p];
             if (p >= k || mm > mp) continue;
             if (ACT && (fb & Sp)) continue;
-            const uint64_t Sn = Sp | bit;
             uint64_t Un;
-            if (!part_test(L, tb, Sn, mp, &Un)) continue;
+            if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un)) continue;
             int req = 0;
-            if (SMS) req = min_units(L, tb, Sn, mp);
+            if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp);
             const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
             if (better) { best = p; bestU = Un; bestReq = req; }
         }
         if (best < 0) return false;
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
-            if (p == best) { S[p] |= bit; U[p] = bestU; }
+            if (p == best) { S[p] |= MT(1) << r; U[p] = bestU; }
     }
     return true;
 }
@@ -321,6 +413,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     __shared__ uint64_t sforbid[MAXN];
     const int64_t s = Lp.s0 + blockIdx.x;
     const int lane = threadIdx.x;
+    if (w.counter != nullptr && blockIdx.x == 0 && lane == 0) *w.counter = 0u;  // batched form: restart the queue
     const int64_t off0 = b.off[s], off1 = b.off[s + 1];
     const int M = b.M[s];
     int status = CAPART_OK;
@@ -454,12 +547,137 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
 
 // ---------------------------------------------------------------------------
 // eval, heuristic allocation: one block per (set, chunk of partitionings).
-template <int KMAX, bool ACT, bool SMS>
+// Every lane walks a contiguous run of partitionings.  The heuristic is run as
+// a per-lane state machine whose loop step is ONE candidate test (task sigma_t
+// on part p): a lane that finishes a partitioning starts the next one at the
+// next step instead of idling until the slowest lane of its wave has finished.
+template <int KMAX>
+__device__ __forceinline__ uint64_t pack_sizes(const int (&m)[KMAX])
+{
+    uint64_t v = 0;
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) v |= (uint64_t)(uint32_t)m[i] << (8 * i);
+    return v;
+}
+
+__device__ __forceinline__ int size_of(uint64_t mpack, int p) { return (int)((mpack >> (8 * p)) & 0xFFu); }
+
+// Per-lane part state (rank masks and utilisations) lives in LDS, lane-
+// interleaved (entry p of lane l at p * blockDim + l), so that the
+// data-dependent part index costs one conflict-free LDS access.
+template <int KMAX, bool ACT, bool SMS, typename MT>
+__device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K, uint32_t q0,
+                         uint32_t q1, Key &best, uint64_t *dbg, MT *lS, uint64_t *lU)
+{
+    const int stride = blockDim.x;
+    MT *myS = lS + threadIdx.x;
+    uint64_t *myU = lU + threadIdx.x;
+    int m[KMAX];
+    int k = unrank<KMAX>(np, M, K, q0, m);
+    uint64_t mpack = pack_sizes<KMAX>(m);
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
+    uint32_t q = q0;
+    int t = 0, p = 0, bp = -1, breq = 0;
+    uint64_t bu = 0;
+    for (;;) {
+        const int tau = L.sigma[t];
+        const int mm = (int)L.mmin[tau];
+        const MT fb = ACT ? (MT)L.forbid[tau] : MT(0);
+        // next candidate part that can hold tau (Lemma 2 size, ACT pairs)
+        while (p < k && (mm > size_of(mpack, p) || (ACT && (fb & myS[p * stride])))) p++;
+        if (p < k) {
+            const int mp = size_of(mpack, p);
+            const MT Sp = myS[p * stride];
+            uint64_t Un;
+            if (part_test_add<MT>(L, tb, Sp, tau, mp, myU[p * stride], &Un)) {
+                int req = 0;
+                if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << tau), mp);
+                const bool better = (bp < 0) || (SMS ? (req < breq || (req == breq && Un < bu)) : (Un < bu));
+                if (better) { bp = p; bu = Un; breq = req; }
+            }
+            p++;
+        }
+        bool done = false, ok = false;
+        if (p >= k) {
+            if (bp < 0) {
+                done = true;
+            } else {
+                myS[bp * stride] |= MT(1) << tau;
+                myU[bp * stride] = bu;
+                bp = -1;
+                p = 0;
+                if (++t >= n) done = ok = true;
+            }
+        }
+        if (done) {
+            uint64_t mx = 0, sm = 0;
+            if (ok) {
+                for (int i = 0; i < k; i++) {
+                    const uint64_t u = myU[i * stride];
+                    mx = max(mx, u);
+                    sm += u;
+                }
+                const Key kk{mx, sm, q, 0ull};
+                if (key_less(kk, best)) best = kk;
+            }
+            if (dbg) {
+                uint64_t *d = dbg + 3 * (uint64_t)q;
+                d[0] = ok ? mx : ~0ull;
+                d[1] = ok ? sm : ~0ull;
+                d[2] = ok ? 0ull : ~0ull;
+            }
+            if (++q >= q1) break;
+            k = next_partition<KMAX>(m, K);
+            mpack = pack_sizes<KMAX>(m);
+#pragma unroll
+            for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
+            t = 0;
+            p = 0;
+            bp = -1;
+        }
+    }
+}
+
+// Loop form 1: one loop step per partitioning (the heuristic of one
+// partitioning runs to completion, parts unrolled over registers).
+template <int KMAX, bool ACT, bool SMS, typename MT>
+__device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
+                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg)
+{
+    int m[KMAX];
+    int k = unrank<KMAX>(np, M, K, q0, m);
+    for (uint32_t q = q0;;) {
+        MT S[KMAX];
+        uint64_t U[KMAX];
+        const bool ok = heuristic<KMAX, ACT, SMS, MT>(L, tb, n, m, k, S, U);
+        uint64_t mx = 0, sm = 0;
+        if (ok) {
+#pragma unroll
+            for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
+            const Key kk{mx, sm, q, 0ull};
+            if (key_less(kk, best)) best = kk;
+        }
+        if (dbg) {
+            uint64_t *d = dbg + 3 * (uint64_t)q;
+            d[0] = ok ? mx : ~0ull;
+            d[1] = ok ? sm : ~0ull;
+            d[2] = ok ? 0ull : ~0ull;
+        }
+        if (++q >= q1) break;
+        k = next_partition<KMAX>(m, K);
+    }
+}
+
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
 __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
+    // per-lane part state follows the tables in dynamic LDS
+    uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words);
+    MT *lS = (MT *)(lU + KMAX * blockDim.x);
     const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
     const int c = blockIdx.x % Lp.chunks;
     const uint32_t f = w.setflags[s];
@@ -471,7 +689,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     const uint32_t p0 = (uint32_t)c * Lp.chunk;
     if (p0 >= P) return;
     const uint32_t p1 = min(P, p0 + Lp.chunk);
-    const bool dbg = o.dbg_key != nullptr;
+    uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
     Key best = key_none();
     if (!(f & SETF_LEMMA1)) {
         Tables tb;
@@ -482,32 +700,15 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
         q0 = max(q0, p_lo);
         q1 = min(q1, p_hi);
         if (q0 < q1) {
-            int m[KMAX];
-            int k = unrank<KMAX>(w.np, M, Lp.K, q0, m);
-            for (uint32_t q = q0;;) {
-                uint64_t S[KMAX], U[KMAX];
-                const bool ok = heuristic<KMAX, ACT, SMS>(L, tb, n, m, k, S, U);
-                uint64_t mx = 0, sm = 0;
-                if (ok) {
-#pragma unroll
-                    for (int p = 0; p < KMAX; p++) { mx = max(mx, U[p]); sm += U[p]; }
-                    const Key kk{mx, sm, q, 0ull};
-                    if (key_less(kk, best)) best = kk;
-                }
-                if (dbg) {
-                    uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
-                    d[0] = ok ? mx : ~0ull;
-                    d[1] = ok ? sm : ~0ull;
-                    d[2] = ok ? 0ull : ~0ull;
-                }
-                if (++q >= q1) break;
-                k = next_partition<KMAX>(m, Lp.K);
-            }
+            if (FORM == 2)
+                heur_run<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
+            else
+                heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg);
         }
     } else if (dbg) {
         for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
             if (q < p_lo || q >= p_hi) continue;
-            uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
+            uint64_t *d = dbg + 3 * (uint64_t)q;
             d[0] = d[1] = d[2] = ~0ull;
         }
     }
@@ -515,6 +716,65 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (threadIdx.x == 0) {
         uint64_t *dst = w.partial + 4 * ((s) * (int64_t)Lp.chunks + c);
         dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+    }
+}
+
+// eval, batched form: a persistent grid; each block repeatedly takes the next
+// work item (set, partitioning range) from a global counter, restages the
+// set's LDS tables only when the set changes, and writes the item's best key
+// to its partial slot.  Items come largest first, so the tail is short.
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
+__global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, Out o, Launch Lp)
+{
+    __shared__ SetLDS L;
+    __shared__ Key red[16];
+    __shared__ uint32_t s_item;
+    uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words);
+    MT *lS = (MT *)(lU + KMAX * blockDim.x);
+    int64_t staged = -1;
+    Tables tb;
+    tb.C = tb.U = nullptr;
+    tb.n = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(w.counter, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= w.n_items) break;
+        const WorkItem wi = w.items[it];
+        const int64_t s = wi.set;
+        const uint32_t f = w.setflags[s];
+        Key best = key_none();
+        uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
+        if ((f & SETF_VALID) && !(f & SETF_LEMMA1)) {
+            const int64_t off = b.off[s];
+            const int n = (int)(b.off[s + 1] - off);
+            const int M = b.M[s];
+            if (s != staged) {
+                stage_set(L, w, off, n, M, s, ACT, tb);
+                staged = s;
+            }
+            const uint32_t cnt = wi.p1 - wi.p0;
+            const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
+            const uint32_t q0 = wi.p0 + threadIdx.x * per, q1 = min(wi.p1, q0 + per);
+            if (q0 < q1) {
+                if (FORM == 2)
+                    heur_run<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
+                else
+                    heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg);
+            }
+        } else if (dbg && (f & SETF_VALID)) {
+            for (uint32_t q = wi.p0 + threadIdx.x; q < wi.p1; q += blockDim.x) {
+                uint64_t *d = dbg + 3 * (uint64_t)q;
+                d[0] = d[1] = d[2] = ~0ull;
+            }
+        }
+        best = block_min(best, red);
+        if (threadIdx.x == 0) {
+            uint64_t *dst = w.partial + 4 * (uint64_t)wi.slot;
+            dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+        }
+        __syncthreads();
     }
 }
 
@@ -562,7 +822,7 @@ __global__ __launch_bounds__(256) void eval_exh_kernel(Batch b, Work w, Out o, L
             for (int p = 0; p < KMAX; p++) {
                 if (ok && p < k && S[p]) {
                     uint64_t u;
-                    if (!part_test(L, tb, S[p], m[p], &u)) {
+                    if (!part_test<uint64_t>(L, tb, S[p], m[p], &u)) {
                         ok = false;
                     } else {
                         mx = max(mx, u);
@@ -619,12 +879,20 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
     // reduce the partials of this set's live chunks
     Key best = key_none();
     const bool exh = (Lp.mode == CAPART_EXHAUSTIVE);
-    for (int c = lane; c < Lp.chunks; c += 64) {
-        const bool live = exh ? ((uint32_t)c < P) : ((uint64_t)c * Lp.chunk < P);
-        if (!live) continue;
-        const uint64_t *src = w.partial + 4 * (s * (int64_t)Lp.chunks + c);
-        const Key kk{src[0], src[1], src[2], src[3]};
-        if (key_less(kk, best)) best = kk;
+    if (w.slot_off != nullptr) {  // batched form: the set's item slots
+        for (uint32_t c = w.slot_off[s] + lane; c < w.slot_off[s + 1]; c += 64) {
+            const uint64_t *src = w.partial + 4 * (uint64_t)c;
+            const Key kk{src[0], src[1], src[2], src[3]};
+            if (key_less(kk, best)) best = kk;
+        }
+    } else {
+        for (int c = lane; c < Lp.chunks; c += 64) {
+            const bool live = exh ? ((uint32_t)c < P) : ((uint64_t)c * Lp.chunk < P);
+            if (!live) continue;
+            const uint64_t *src = w.partial + 4 * (s * (int64_t)Lp.chunks + c);
+            const Key kk{src[0], src[1], src[2], src[3]};
+            if (key_less(kk, best)) best = kk;
+        }
     }
     best = wave_min(best);
     const bool found = best.a != ~0ull;
@@ -648,10 +916,10 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
             }
         } else {
             switch (Lp.mode) {
-            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false>(L, tb, n, m, k, S, U); break;
-            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false>(L, tb, n, m, k, S, U); break;
-            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true>(L, tb, n, m, k, S, U); break;
-            default: heuristic<KMAX, true, true>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false, uint64_t>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false, uint64_t>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true, uint64_t>(L, tb, n, m, k, S, U); break;
+            default: heuristic<KMAX, true, true, uint64_t>(L, tb, n, m, k, S, U); break;
             }
         }
 #pragma unroll
@@ -667,7 +935,8 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
             uint64_t Sp = 0;
             for (int p = 0; p < sk; p++)
                 if ((sS[p] >> lane) & 1ull) { part = p; mp = sm_[p]; Sp = sS[p]; }
-            const uint32_t R = rta(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull), conflict_mask(Sp, L.memmask));
+            const uint32_t R = rta_one<uint64_t>(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull),
+                                                 conflict_mask<uint64_t>(Sp, L.memmask));
             o.alloc[gi] = (int8_t)part;
             o.R[gi] = R ? (int64_t)R : -1;
         } else {
@@ -681,7 +950,7 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         const uint64_t all = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
         uint32_t R1 = 0;
         if (lane < n) {
-            R1 = rta(L, tb, M, lane, all & ((1ull << lane) - 1ull), conflict_mask(all, L.memmask));
+            R1 = rta_one<uint64_t>(L, tb, M, lane, all & ((1ull << lane) - 1ull), conflict_mask<uint64_t>(all, L.memmask));
             o.R_1g[off + L.orig[lane]] = R1 ? (int64_t)R1 : -1;
         }
         ok1 = !__ballot(lane < n && R1 == 0u);
@@ -727,8 +996,8 @@ __global__ __launch_bounds__(64) void triple_kernel(Batch b, Work w, const int32
     if (lane < n) {
         const int p = alloc[L.orig[lane]];
         const uint64_t Sp = sS[p];
-        const uint64_t cm = conflict_mask(Sp, L.memmask);
-        R = rta(L, tb, sizes[p], lane, Sp & ((1ull << lane) - 1ull), cm);
+        const uint64_t cm = conflict_mask<uint64_t>(Sp, L.memmask);
+        R = rta_one<uint64_t>(L, tb, sizes[p], lane, Sp & ((1ull << lane) - 1ull), cm);
         Rout[L.orig[lane]] = R ? (int64_t)R : -1;
         if (R) {
             const uint32_t u = tb.U[(sizes[p] - 1) * 2 * n + (int)((cm >> lane) & 1ull) * n + lane];
@@ -754,7 +1023,18 @@ size_t table_lds_bytes(int max_tasks, int max_M)
     return (size_t)16 * (size_t)(nm < CAPART_MAX_NM ? nm : CAPART_MAX_NM);
 }
 
+// Blocks of 256 threads, or 128 when the tables are large, so that tables,
+// per-lane part state (at most 8 parts x 16 bytes per lane) and the static
+// per-set arrays fit the 160 KB of LDS.
+int eval_threads(int max_tasks, int max_M) { return table_lds_bytes(max_tasks, max_M) > 96 * 1024 ? 128 : 256; }
+
 static size_t dyn_bytes(const Batch &b) { return table_lds_bytes(min(b.max_tasks, MAXN), min(b.max_M, 255)); }
+
+template <int KMAX, typename MT>
+static size_t heur_dyn_bytes(const Launch &L)
+{
+    return (size_t)4 * L.table_words + (size_t)L.threads * KMAX * (sizeof(MT) + sizeof(uint64_t));
+}
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
@@ -763,37 +1043,105 @@ hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch
     return hipGetLastError();
 }
 
-template <int KMAX>
-static hipError_t launch_eval_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
-                                uint32_t p_lo, uint32_t p_hi)
+template <int KMAX, typename MT, int FORM>
+static hipError_t launch_heur(const Launch &L, const Batch &b, const Work &w, const Out &o, hipStream_t st,
+                              uint32_t p_lo, uint32_t p_hi)
 {
     const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
-    const size_t lds = dyn_bytes(b);
+    const size_t lds = FORM == 2 ? heur_dyn_bytes<KMAX, MT>(L) : (size_t)4 * L.table_words;
     switch (L.mode) {
-    case CAPART_EXHAUSTIVE:
-        hipLaunchKernelGGL((eval_exh_kernel<KMAX>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
-        break;
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+                           p_hi);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+                           p_hi);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+                           p_hi);
         break;
     default:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+                           p_hi);
         break;
     }
     return hipGetLastError();
+}
+
+template <int KMAX, typename MT>
+static hipError_t launch_eval_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                                uint32_t p_lo, uint32_t p_hi)
+{
+    if (L.mode == CAPART_EXHAUSTIVE) {
+        const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
+        hipLaunchKernelGGL((eval_exh_kernel<KMAX>), grid, block, dyn_bytes(b), st, b, w, o, L, p_lo, p_hi);
+        return hipGetLastError();
+    }
+    return L.form == 2 ? launch_heur<KMAX, MT, 2>(L, b, w, o, st, p_lo, p_hi)
+                       : launch_heur<KMAX, MT, 1>(L, b, w, o, st, p_lo, p_hi);
+}
+
+template <int KMAX, typename MT, int FORM>
+static hipError_t launch_persistent_k(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                      hipStream_t st)
+{
+    const dim3 grid((unsigned)blocks), block((unsigned)L.threads);
+    const size_t lds = FORM == 2 ? heur_dyn_bytes<KMAX, MT>(L) : (size_t)4 * L.table_words;
+    switch (L.mode) {
+    case CAPART_HEUR_BF_INA:
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        break;
+    case CAPART_HEUR_BF_ACT:
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, false, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        break;
+    case CAPART_HEUR_SMS_INA:
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, true, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        break;
+    default:
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, true, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int KMAX, typename MT>
+static hipError_t launch_persistent_f(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                      hipStream_t st)
+{
+    return L.form == 2 ? launch_persistent_k<KMAX, MT, 2>(b, w, o, L, blocks, st)
+                       : launch_persistent_k<KMAX, MT, 1>(b, w, o, L, blocks, st);
+}
+
+hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                  hipStream_t st)
+{
+    if (b.max_tasks <= 32)
+        return L.K <= 4 ? launch_persistent_f<4, uint32_t>(b, w, o, L, blocks, st)
+                        : launch_persistent_f<8, uint32_t>(b, w, o, L, blocks, st);
+    return L.K <= 4 ? launch_persistent_f<4, uint64_t>(b, w, o, L, blocks, st)
+                    : launch_persistent_f<8, uint64_t>(b, w, o, L, blocks, st);
+}
+
+int device_cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
 }
 
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
                              uint32_t p_lo, uint32_t p_hi)
 {
     if (L.S <= 0) return hipSuccess;
-    return L.K <= 4 ? launch_eval_k<4>(b, w, o, L, st, p_lo, p_hi) : launch_eval_k<8>(b, w, o, L, st, p_lo, p_hi);
+    // 32-bit rank masks when every set of the launch has at most 32 tasks
+    if (b.max_tasks <= 32)
+        return L.K <= 4 ? launch_eval_k<4, uint32_t>(b, w, o, L, st, p_lo, p_hi)
+                        : launch_eval_k<8, uint32_t>(b, w, o, L, st, p_lo, p_hi);
+    return L.K <= 4 ? launch_eval_k<4, uint64_t>(b, w, o, L, st, p_lo, p_hi)
+                    : launch_eval_k<8, uint64_t>(b, w, o, L, st, p_lo, p_hi);
 }
 
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
@@ -821,11 +1169,15 @@ hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, in
     return hipGetLastError();
 }
 
+// Let a kernel use all of the 160 KB LDS beyond its static arrays.
 template <typename F>
 static hipError_t allow_lds(F *fn)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)table_lds_bytes(MAXN, CAPART_MAX_M));
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(fn));
+    if (e != hipSuccess) return e;
+    const int dyn = 160 * 1024 - (int)a.sharedSizeBytes;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
 hipError_t configure_kernels()
@@ -834,18 +1186,75 @@ hipError_t configure_kernels()
 #define CAPART_ALLOW(fn) do { t = allow_lds(fn); if (t != hipSuccess) e = t; } while (0)
     CAPART_ALLOW((eval_exh_kernel<4>));
     CAPART_ALLOW((eval_exh_kernel<8>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint32_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint32_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 1>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 2>));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));
 #undef CAPART_ALLOW
+    (void)hipGetLastError();  // leave no sticky error behind for the next launch check
     return e;
 }
 
