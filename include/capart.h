@@ -252,6 +252,59 @@ capart_status capart_run_batch(capart_plan *plan, void *hip_stream);
 capart_status capart_plan_get_info(const capart_plan *plan, capart_plan_info *info);
 capart_status capart_plan_destroy(capart_plan *plan);
 
+/*
+ * Serving form.  A server keeps admitted queries (one task set each) resident
+ * in a device arena of a fixed memory budget: per-query inputs, workspace and
+ * results live in ring buffers indexed by query slot and task index.
+ * capart_server_submit admits a query if a slot and a contiguous range of the
+ * task ring are free, else returns E_AGAIN (back-pressure); it copies the
+ * query into pinned host staging and returns a ticket.  A dispatcher thread
+ * launches every admitted, not yet launched query as one batch on the next
+ * free stream (up to `streams` batches in flight), so queries that arrive while
+ * others are on the GPU start at once and their work overlaps on the device
+ * (continuous batching).  capart_server_poll returns a query's results once
+ * its batch has completed and frees its ring space.  A query's results do not
+ * depend on the other queries of its batch.  submit and poll are thread-safe.
+ * Latency is measured from submit (or the replayed arrival time) to the moment
+ * the dispatcher sees the batch complete.
+ */
+typedef struct capart_server capart_server;
+
+typedef struct capart_server_config {
+    int32_t K, alloc_mode;  /* options applied to every query (heuristic modes) */
+    uint32_t flags;
+    int32_t max_tasks;      /* bound on tasks per query, 1..64        */
+    int32_t max_M;          /* bound on M per query, 1..255           */
+    int32_t max_queries;    /* query slots (0 = 4096)                 */
+    int64_t device_bytes;   /* device budget for resident queries (0 = 256 MiB) */
+    int32_t streams;        /* batches in flight, 1..8 (0 = 4)        */
+    int32_t max_batch;      /* queries per launch (0 = no limit)      */
+} capart_server_config;
+
+typedef struct capart_server_stats {
+    int64_t submitted, completed, rejected, batches, evals;
+    double p50_us, p99_us, mean_us, max_us;  /* latency over completed queries   */
+    double elapsed_s, queries_per_s, evals_per_s, mean_batch;
+} capart_server_stats;
+
+capart_status capart_server_create(capart_ctx *ctx, const capart_server_config *cfg, capart_server **out);
+/* one_set: host pointers, one set with offsets {0, n}. */
+capart_status capart_server_submit(capart_server *srv, const capart_tasksets *one_set, uint64_t *ticket);
+/* one_out: host pointers sized for one set (sizes[K], per-task arrays[n]);
+ * *done = 1 and one_out filled when complete, else *done = 0. E_INVAL for an
+ * unknown or already collected ticket. */
+capart_status capart_server_poll(capart_server *srv, uint64_t ticket, capart_results *one_out, int32_t *done);
+/* Statistics since creation or the last reset (reset != 0 clears them). */
+capart_status capart_server_stats_get(capart_server *srv, capart_server_stats *out, int32_t reset);
+/* Open-loop replay: submits the sets of `queries` (host pointers) at their
+ * arrival times (microseconds from the start of the call), retrying rejected
+ * queries as soon as space frees, collects every result into `results` (host,
+ * sized for the whole batch, may be NULL) and returns the statistics of the
+ * replay in *stats. */
+capart_status capart_server_replay(capart_server *srv, const capart_tasksets *queries, const double *arrival_us,
+                                   capart_results *results, capart_server_stats *stats);
+capart_status capart_server_destroy(capart_server *srv);
+
 /* Launch tuning of a context (applies to later calls on it).  Every choice
  * computes identical results; they trade divergence, occupancy and block
  * count.  threads: threads per evaluation block, 0 = automatic, else 64, 128,
@@ -260,12 +313,17 @@ capart_status capart_plan_destroy(capart_plan *plan);
  * chip); loop_form: 0 = automatic, 1 = each lane runs the heuristic of one
  * partitioning per loop step, 2 = each loop step is one candidate test (a lane
  * that finishes a partitioning continues with its next one at the next step).
- * NULL restores the automatic choices.  E_INVAL for values out of range. */
+ * exh_form (exhaustive mode): 0 = automatic, 1 = every block enumerates all
+ * k^n allocations of one partitioning, 2 = per-set subset tables of partition
+ * utilisation (every task subset on every size) and a depth-first search in
+ * allocation-index order with exact pruning (sets of at most 14 tasks, K <= 4;
+ * otherwise form 1 is used).  NULL restores the automatic choices.  E_INVAL for
+ * values out of range. */
 typedef struct capart_tuning {
     int32_t threads;
     int32_t chunk;
     int32_t loop_form;
-    int32_t reserved;  /* must be 0 */
+    int32_t exh_form;
 } capart_tuning;
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);

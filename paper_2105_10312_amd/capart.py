@@ -28,7 +28,8 @@ EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count
            "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
-           "capart_plan_destroy"]
+           "capart_plan_destroy", "capart_server_create", "capart_server_submit", "capart_server_poll",
+           "capart_server_stats_get", "capart_server_replay", "capart_server_destroy"]
 
 _vp = C.c_void_p
 
@@ -50,7 +51,7 @@ class capart_results(C.Structure):
 
 
 class capart_tuning(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("exh_form", C.c_int32)]
 
 
 class capart_plan_config(C.Structure):
@@ -62,6 +63,19 @@ class capart_plan_info(C.Structure):
     _fields_ = [("n_sets", C.c_int64), ("n_items", C.c_int64), ("total_evals", C.c_int64), ("threads", C.c_int32),
                 ("loop_form", C.c_int32), ("blocks", C.c_int32), ("item_evals", C.c_int32),
                 ("candidates_tried", C.c_int32), ("use_graph", C.c_int32), ("tune_ms", C.c_double)]
+
+
+class capart_server_config(C.Structure):
+    _fields_ = [("K", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32), ("max_tasks", C.c_int32),
+                ("max_M", C.c_int32), ("max_queries", C.c_int32), ("device_bytes", C.c_int64),
+                ("streams", C.c_int32), ("max_batch", C.c_int32)]
+
+
+class capart_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("batches", C.c_int64), ("evals", C.c_int64), ("p50_us", C.c_double), ("p99_us", C.c_double),
+                ("mean_us", C.c_double), ("max_us", C.c_double), ("elapsed_s", C.c_double),
+                ("queries_per_s", C.c_double), ("evals_per_s", C.c_double), ("mean_batch", C.c_double)]
 
 
 class CapartError(RuntimeError):
@@ -108,6 +122,13 @@ def load_library():
         lib.capart_run_batch.argtypes = [_vp, _vp]
         lib.capart_plan_get_info.argtypes = [_vp, P(capart_plan_info)]
         lib.capart_plan_destroy.argtypes = [_vp]
+        lib.capart_server_create.argtypes = [_vp, P(capart_server_config), P(_vp)]
+        lib.capart_server_submit.argtypes = [_vp, P(capart_tasksets), P(C.c_uint64)]
+        lib.capart_server_poll.argtypes = [_vp, C.c_uint64, P(capart_results), P(C.c_int32)]
+        lib.capart_server_stats_get.argtypes = [_vp, P(capart_server_stats), C.c_int32]
+        lib.capart_server_replay.argtypes = [_vp, P(capart_tasksets), _vp, P(capart_results),
+                                             P(capart_server_stats)]
+        lib.capart_server_destroy.argtypes = [_vp]
         lib.capart_timing_read.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS:
             if name != "capart_last_error":
@@ -322,15 +343,15 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
                                              C.c_void_p(stream.cuda_stream)), ctx)
 
 
-def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0) -> None:
-    t = capart_tuning(int(threads), int(chunk), int(loop_form), 0)
+def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0) -> None:
+    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form))
     _check(load_library().capart_set_tuning(ctx, C.byref(t)), ctx)
 
 
 def capart_get_tuning(ctx) -> dict:
     t = capart_tuning()
     _check(load_library().capart_get_tuning(ctx, C.byref(t)), ctx)
-    return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form}
+    return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form, "exh_form": t.exh_form}
 
 
 def capart_timing_enable(ctx, enable: bool = True) -> None:
@@ -379,6 +400,93 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "handle", None):
             _check(load_library().capart_plan_destroy(self.handle), self.ctx)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stats_dict(st) -> dict:
+    return {f[0]: getattr(st, f[0]) for f in capart_server_stats._fields_}
+
+
+def host_results(S: int, N: int, K: int) -> dict:
+    out = {}
+    for name, dt, shape in RESULT_FIELDS:
+        size = S if shape == "S" else (S * K if shape == "SK" else N)
+        out[name] = np.zeros(max(size, 1), dt)
+    return out
+
+
+class Server:
+    """Serving form: admission-controlled, device-resident query state,
+    continuous batching over several streams (see capart_server_* in capart.h)."""
+
+    def __init__(self, ctx, K: int = 4, mode="BF_INA", flags: int = 0, max_tasks: int = 64, max_M: int = 108,
+                 max_queries: int = 0, device_bytes: int = 0, streams: int = 0, max_batch: int = 0):
+        self.ctx = ctx
+        self.K = int(K)
+        cfg = capart_server_config(int(K), _mode(mode), int(flags), int(max_tasks), int(max_M), int(max_queries),
+                                   int(device_bytes), int(streams), int(max_batch))
+        h = _vp()
+        _check(load_library().capart_server_create(ctx, C.byref(cfg), C.byref(h)), ctx)
+        self.handle = h
+
+    def submit(self, task: dict):
+        """Returns a ticket, or None when the server pushes back (E_AGAIN)."""
+        hts = _one_set(task)
+        st, _keep = make_tasksets(hts)
+        t = C.c_uint64(0)
+        rc = load_library().capart_server_submit(self.handle, C.byref(st), C.byref(t))
+        if rc == CAPART_E_AGAIN:
+            return None
+        _check(rc, self.ctx)
+        return int(t.value)
+
+    def poll(self, ticket: int, n: int):
+        """Returns a dict of one query's results, or None if not complete yet."""
+        out = host_results(1, n, self.K)
+        res = capart_results(*[_ptr(out[f[0]]) for f in RESULT_FIELDS], None, None)
+        done = C.c_int32(0)
+        _check(load_library().capart_server_poll(self.handle, C.c_uint64(ticket), C.byref(res), C.byref(done)),
+               self.ctx)
+        if not done.value:
+            return None
+        out["sizes"] = out["sizes"][:self.K].reshape(1, self.K)
+        for name, dt, shape in RESULT_FIELDS:
+            if shape == "N":
+                out[name] = out[name][:n]
+        return out
+
+    def stats(self, reset: bool = False) -> dict:
+        st = capart_server_stats()
+        _check(load_library().capart_server_stats_get(self.handle, C.byref(st), int(bool(reset))), self.ctx)
+        return _stats_dict(st)
+
+    def replay(self, ts: dict, arrival_us, collect: bool = True):
+        """Open-loop replay of a host batch at the given arrival times (us)."""
+        h = _host_ts(ts)
+        st, _keep = make_tasksets(h)
+        arr = np.ascontiguousarray(arrival_us, np.float64)
+        S, N = st.n_sets, st.n_tasks_total
+        out = host_results(S, N, self.K) if collect else None
+        res = capart_results(*[_ptr(out[f[0]]) for f in RESULT_FIELDS], None, None) if collect else None
+        stats = capart_server_stats()
+        _check(load_library().capart_server_replay(self.handle, C.byref(st), arr.ctypes.data,
+                                                   C.byref(res) if collect else None, C.byref(stats)), self.ctx)
+        if collect:
+            for name, dt, shape in RESULT_FIELDS:
+                size = S if shape == "S" else (S * self.K if shape == "SK" else N)
+                out[name] = out[name][:size]
+            out["sizes"] = out["sizes"].reshape(S, self.K)
+        return out, _stats_dict(stats)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _check(load_library().capart_server_destroy(self.handle), self.ctx)
             self.handle = None
 
     def __del__(self):

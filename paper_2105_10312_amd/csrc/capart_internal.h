@@ -81,6 +81,7 @@ struct Launch {
     int threads;         // threads per evaluation block
     int table_words;     // u32 words of dynamic LDS reserved for the per-set tables
     int form;            // heuristic loop form: 1 = one step per partitioning, 2 = one step per candidate test
+    int exh_form;        // exhaustive: 1 = enumerate every allocation, 2 = subset tables + pruned search
 };
 
 // Host-side sizing helpers shared by the launchers.
@@ -97,6 +98,13 @@ hipError_t launch_final(const Batch &b, const Work &w, const Out &o, const Launc
 hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
                                   hipStream_t st);
 int device_cu_count();
+// exhaustive allocation through subset tables (<= 14 tasks per set, <= 4 parts)
+constexpr int SUBSET_MAX_TASKS = 14;
+hipError_t launch_subset_tables(const Batch &b, const Work &w, const Launch &L, uint64_t *tab, int64_t s_begin, int W,
+                                int Mtab, int ntab, hipStream_t st);
+hipError_t launch_exh_dfs(const Batch &b, const Work &w, const Out &o, const Launch &L, const uint64_t *tab,
+                          int64_t s_begin, int W, int Mtab, int ntab, uint32_t Pmax, uint32_t p_lo, uint32_t p_hi,
+                          hipStream_t st);
 hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
                          uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st);
 hipError_t configure_kernels();

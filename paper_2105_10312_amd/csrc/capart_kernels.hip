@@ -971,6 +971,175 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
 }
 
 // ---------------------------------------------------------------------------
+// Exhaustive allocation through subset tables (sets of at most 14 tasks, at
+// most 4 parts).  tab[set][m-1][A] = Q32 utilisation of task subset A (bits
+// = task indices within the set) on one partition of m units, or all ones if
+// A is not schedulable there.  One block per (set, m) fills it.
+__global__ __launch_bounds__(256) void subset_table_kernel(Batch b, Work w, Launch Lp, uint64_t *tab, int64_t s_begin,
+                                                           int W, int Mtab, int ntab)
+{
+    __shared__ SetLDS L;
+    const int s_local = blockIdx.x / Mtab;
+    const int m = blockIdx.x % Mtab + 1;
+    if (s_local >= W) return;
+    const int64_t s = s_begin + s_local;
+    const uint32_t f = w.setflags[s];
+    if (!(f & SETF_VALID) || (f & SETF_LEMMA1)) return;
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    const int M = b.M[s];
+    if (m > M || n > ntab) return;
+    Tables tb;
+    stage_set(L, w, off, n, M, s, false, tb);
+    uint64_t *dst = tab + (((size_t)s_local * Mtab + (size_t)(m - 1)) << ntab);
+    const uint32_t NA = 1u << n;
+    for (uint32_t A = threadIdx.x; A < NA; A += blockDim.x) {
+        uint32_t RA = 0;
+        for (uint32_t a = A; a; a &= a - 1u) RA |= 1u << L.rank_of[__builtin_ctz(a)];
+        uint64_t u = 0;
+        dst[A] = part_test<uint32_t>(L, tb, RA, m, &u) ? u : ~0ull;
+    }
+}
+
+// Depth-first search over allocations of one (set, partitioning), in
+// allocation-index order (task 0 most significant).  Lane l owns the digits
+// of the first tasks (prefix l of k^Lpre <= blockDim) and searches the rest.
+// Exact pruning: a part that is not schedulable stays so when tasks are added;
+// part utilisations only grow, so a partial (maxU, sumU) at or above the
+// lane's best cannot lead to a better or equal key with a smaller index; among
+// parts of equal size only the labelling whose first tasks come in part order
+// is visited (it is the smallest index among the relabellings, which share
+// their key).  Blocks are dealt to XCDs by set (block b runs on XCD b mod 8),
+// so all partitionings of a set read its table from one L2.
+__global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, Launch Lp, const uint64_t *tab,
+                                                      int64_t s_begin, int W, int Mtab, int ntab, uint32_t Pmax,
+                                                      uint32_t p_lo, uint32_t p_hi)
+{
+    __shared__ Key red[16];
+    __shared__ uint64_t pw[16];
+    const uint32_t xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    const int s_local = (int)(xcd + 8u * (j / Pmax));
+    const uint32_t q = j % Pmax;
+    if (s_local >= W) return;
+    const int64_t s = s_begin + s_local;
+    const uint32_t f = w.setflags[s];
+    if (!(f & SETF_VALID)) return;
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    const int M = b.M[s];
+    const uint32_t P = w.np[np_index(Lp.K, M, M)];
+    if (q >= P) return;
+    Key best = key_none();
+    int m[4];
+    const int k = unrank<4>(w.np, M, Lp.K, q, m);
+    if (threadIdx.x == 0) {
+        uint64_t v = 1;
+        for (int i = n - 1; i >= 0; i--) { pw[i] = v; v *= (uint64_t)k; }
+    }
+    __syncthreads();
+    int Lpre = 0;
+    uint32_t npre = 1;
+    while (Lpre < n && npre * (uint32_t)k <= blockDim.x) { npre *= (uint32_t)k; Lpre++; }
+    const uint64_t msz = (uint64_t)(uint32_t)m[0] | ((uint64_t)(uint32_t)m[1] << 8) | ((uint64_t)(uint32_t)m[2] << 16) |
+                         ((uint64_t)(uint32_t)m[3] << 24);
+    if (!(f & SETF_LEMMA1) && threadIdx.x < npre && q >= p_lo && q < p_hi) {
+        const uint64_t *t = tab + (((size_t)s_local * Mtab) << ntab);
+        // prefix digits: task Lpre-1 least significant
+        uint64_t Apack = 0, aidx = 0;
+        uint32_t x = threadIdx.x;
+        for (int i = Lpre - 1; i >= 0; i--) {
+            const int d = (int)(x % (uint32_t)k);
+            x /= (uint32_t)k;
+            Apack |= (uint64_t)(1u << i) << (16 * d);
+            aidx += (uint64_t)d * pw[i];
+        }
+        uint64_t U[4];
+        bool ok = true;
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const uint32_t Ap = (uint32_t)(Apack >> (16 * p)) & 0xFFFFu;
+            U[p] = 0ull;
+            if (p < k) {
+                U[p] = t[((size_t)(m[p] - 1) << ntab) | Ap];
+                if (U[p] == ~0ull) ok = false;
+                if (p > 0 && m[p - 1] == m[p] && Ap) {
+                    const uint32_t Aq = (uint32_t)(Apack >> (16 * (p - 1))) & 0xFFFFu;
+                    if (!Aq || __builtin_ctz(Aq) > __builtin_ctz(Ap)) ok = false;
+                }
+            }
+        }
+        if (ok) {
+            uint64_t mx = 0, sm = 0;
+#pragma unroll
+            for (int p = 0; p < 4; p++) { mx = max(mx, U[p]); sm += U[p]; }
+            if (Lpre == n) {
+                best = Key{mx, sm, q, aidx};
+            } else {
+                uint64_t dig = 0;
+                int i = Lpre, p = 0;
+                for (;;) {
+                    bool placed = false;
+                    for (; p < k; p++) {
+                        const int mp = (int)((msz >> (8 * p)) & 0xFFu);
+                        if (p > 0 && (int)((msz >> (8 * (p - 1))) & 0xFFu) == mp &&
+                            ((Apack >> (16 * (p - 1))) & 0xFFFFull) == 0ull)
+                            continue;
+                        const uint32_t An = ((uint32_t)(Apack >> (16 * p)) & 0xFFFFu) | (1u << i);
+                        const uint64_t u = t[((size_t)(mp - 1) << ntab) | An];
+                        if (u == ~0ull) continue;
+                        uint64_t nmx = 0, nsm = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const uint64_t v = (r == p) ? u : U[r];
+                            nmx = max(nmx, v);
+                            nsm += v;
+                        }
+                        if (nmx > best.a || (nmx == best.a && nsm >= best.b)) continue;
+                        if (i == n - 1) {
+                            best = Key{nmx, nsm, q, aidx + (uint64_t)p * pw[i]};
+                            continue;
+                        }
+                        Apack |= (uint64_t)(1u << i) << (16 * p);
+#pragma unroll
+                        for (int r = 0; r < 4; r++)
+                            if (r == p) U[r] = u;
+                        aidx += (uint64_t)p * pw[i];
+                        dig = (dig & ~(0xFull << (4 * i))) | ((uint64_t)p << (4 * i));
+                        placed = true;
+                        break;
+                    }
+                    if (placed) {
+                        i++;
+                        p = 0;
+                        continue;
+                    }
+                    if (i == Lpre) break;
+                    i--;
+                    const int pd = (int)((dig >> (4 * i)) & 0xFull);
+                    Apack &= ~((uint64_t)(1u << i) << (16 * pd));
+                    const int mpd = (int)((msz >> (8 * pd)) & 0xFFu);
+                    const uint64_t ur = t[((size_t)(mpd - 1) << ntab) | ((uint32_t)(Apack >> (16 * pd)) & 0xFFFFu)];
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+                        if (r == pd) U[r] = ur;
+                    aidx -= (uint64_t)pd * pw[i];
+                    p = pd + 1;
+                }
+            }
+        }
+    }
+    best = block_min(best, red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = w.partial + 4 * (s * (int64_t)Lp.chunks + q);
+        dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+        if (o.dbg_key != nullptr && q >= p_lo && q < p_hi) {
+            uint64_t *d = o.dbg_key + 3 * (o.dbg_offset[s] + q);
+            d[0] = best.a; d[1] = best.b; d[2] = best.d;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One triple of one set (set 0 of the batch): every task tested, one lane each.
 template <int KMAX>
 __global__ __launch_bounds__(64) void triple_kernel(Batch b, Work w, const int32_t *sizes, int k, const int8_t *alloc,
@@ -1149,6 +1318,24 @@ hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch
     return launch_eval_range(b, w, o, L, st, 0u, 0xFFFFFFFFu);
 }
 
+hipError_t launch_subset_tables(const Batch &b, const Work &w, const Launch &L, uint64_t *tab, int64_t s_begin, int W,
+                                int Mtab, int ntab, hipStream_t st)
+{
+    hipLaunchKernelGGL(subset_table_kernel, dim3((unsigned)(W * Mtab)), dim3(256), dyn_bytes(b), st, b, w, L, tab,
+                       s_begin, W, Mtab, ntab);
+    return hipGetLastError();
+}
+
+hipError_t launch_exh_dfs(const Batch &b, const Work &w, const Out &o, const Launch &L, const uint64_t *tab,
+                          int64_t s_begin, int W, int Mtab, int ntab, uint32_t Pmax, uint32_t p_lo, uint32_t p_hi,
+                          hipStream_t st)
+{
+    const unsigned blocks = 8u * (unsigned)((W + 7) / 8) * Pmax;
+    hipLaunchKernelGGL(exh_dfs_kernel, dim3(blocks), dim3(256), 0, st, b, w, o, L, tab, s_begin, W, Mtab, ntab, Pmax,
+                       p_lo, p_hi);
+    return hipGetLastError();
+}
+
 hipError_t launch_final(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
     if (L.S <= 0) return hipSuccess;
@@ -1250,6 +1437,7 @@ hipError_t configure_kernels()
     CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 2>));
     CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 2>));
     CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 2>));
+    CAPART_ALLOW((subset_table_kernel));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));

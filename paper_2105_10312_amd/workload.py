@@ -131,7 +131,14 @@ def gen_sets(seed: int, n: np.ndarray, U: np.ndarray, M: np.ndarray, *, tmin: fl
     U = np.asarray(U, dtype=np.float64)
     M = np.asarray(M, dtype=np.int32)
     S = n.shape[0]
-    rows: list = [None] * S
+    off = np.zeros(S + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n)
+    N = int(off[-1])
+    keys = (("T", np.int64), ("D", np.int64), ("C_seq", np.int64), ("C_par", np.int64), ("k_permille", np.int32),
+            ("type", np.uint8))
+    out = TaskSets(set_offset=off, M=M.copy())
+    for key, dt in keys:
+        out[key] = np.zeros(N, dtype=dt)
     for nv in np.unique(n):
         idx = np.nonzero(n == nv)[0]
         pending = idx
@@ -139,17 +146,14 @@ def gen_sets(seed: int, n: np.ndarray, U: np.ndarray, M: np.ndarray, *, tmin: fl
             if pending.size == 0:
                 break
             g, ok = _draw_group(rng, int(nv), U[pending], M[pending], tmin, tmax, deadline, fsplit)
-            for j in np.nonzero(ok)[0]:
-                rows[pending[j]] = {key: g[key][j] for key in g}
+            acc = pending[ok]
+            # task positions of the accepted sets, row-major [set, task]
+            pos = (off[acc][:, None] + np.arange(int(nv))[None, :]).ravel()
+            for key, dt in keys:
+                out[key][pos] = g[key][ok].ravel().astype(dt)
             pending = pending[~ok]
         if pending.size:
             raise RuntimeError(f"discard loop did not converge for n={nv}")
-    off = np.zeros(S + 1, dtype=np.int64)
-    off[1:] = np.cumsum(n)
-    out = TaskSets(set_offset=off, M=M.copy())
-    for key, dt in (("T", np.int64), ("D", np.int64), ("C_seq", np.int64), ("C_par", np.int64),
-                    ("k_permille", np.int32), ("type", np.uint8)):
-        out[key] = np.concatenate([rows[s][key] for s in range(S)]).astype(dt) if S else np.zeros(0, dt)
     return out
 
 
