@@ -6,13 +6,21 @@ validation and per-set precompute (prep kernel), evaluation of every
 (task set, partitioning) pair with heuristic allocation and per-partition
 response-time tests (eval kernel), selection of the best triple, response
 times of the chosen triple and of the whole-GPU baseline (final kernel).
-Default workload: 100,000 seeded synthetic task sets, n = 10 tasks, M = 80
-compute units, at most K = 4 partitions (4263 partitionings per set), BF-INA
-heuristic allocation; 426,300,000 evaluations per step.
+
+Default workload (c2): 100,000 seeded synthetic task sets, n = 10 tasks,
+M = 80 compute units, at most K = 4 partitions (4263 partitionings per set),
+BF-INA heuristic allocation: 426,300,000 evaluations per step, run by the
+batched form (one persistent, autotuned, HIP-graph-captured launch sequence).
+The same batch is also timed through the plain one-launch-sequence path and
+the one-launch-per-set path, and a short open-loop serving run (uneven
+queries, Poisson arrivals) gives p50/p99 admission latency.
+
+Other workloads: c3 (1,000,000 uneven sets), c4 (exhaustive stress, 1,000
+sets of 12 tasks on 48 units, every allocation), c5 (serving sweep).
 
 Prints one JSON line (metric, value in evals/s, ms_per_step, roofline of the
-dominant kernel measured with HIP events on its launch stream, and the CPU
-oracle timed on a bounded sample of the same workload on the host's cores).
+dominant kernel from HIP events on its launch stream, and the CPU oracle timed
+on a bounded sample of the same workload on the host's cores).
 """
 from __future__ import annotations
 
@@ -33,7 +41,6 @@ METRIC = "schedulability evals/sec (taskset×partitioning); p99 admission latenc
 C_TERM = 12
 C_TEST = 8
 PEAK_INT_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit VALU)
-PMC_FILE = os.path.join(ROOT, "profiles", "eval_heur_c2_bf_ina_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2105_10312_amd", "csrc", "capart_kernels.hip")
 
 
@@ -46,11 +53,11 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_bytes():
+def traffic_bytes(name):
     """HBM bytes per eval launch from the committed rocprofv3 counter summary,
     or None if it is missing or was taken on a different kernel source."""
     try:
-        with open(PMC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -59,18 +66,45 @@ def traffic_bytes():
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ts, K, mode, sample_sets, threads):
+def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1):
     import numpy as np
 
     import oracle
     from paper_2105_10312_amd import workload
-    sub = workload.subset(ts, np.arange(min(sample_sets, ts.n_sets)))
+    idx = np.arange(0, ts.n_sets, stride)[:sample_sets]
+    sub = workload.subset(ts, idx)
     P = int(sum(oracle.count_partitionings(int(m), K) for m in sub["M"]))
     t0 = time.perf_counter()
     r = oracle.solve(sub, K, mode, nthreads=threads, counters=True)
     dt = time.perf_counter() - t0
     c = r["counters"].sum(axis=0)
-    return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "sets": sub.n_sets}
+    return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "combines": int(c[2]),
+            "sets": sub.n_sets}
+
+
+def timed(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) * 1000.0 / steps
+
+
+def serving_leg(eng, capart, workload, rate, n_queries, seed=5):
+    import numpy as np
+    ts = workload.config_c5(seed=seed, n_queries=n_queries)
+    srv = capart.Server(eng.ctx, K=4, mode="BF_INA", max_tasks=64, max_M=108)
+    warm = workload.subset(ts, np.arange(min(200, ts.n_sets)))
+    srv.replay(warm, np.zeros(warm.n_sets), collect=False)
+    rng = np.random.default_rng(seed)
+    arrival = np.cumsum(rng.exponential(1e6 / rate, ts.n_sets))
+    _, st = srv.replay(ts, arrival, collect=False)
+    srv.close()
+    return {"workload": f"{n_queries} queries, n log-uniform 2..64, M in {{16,48,80,108}}, K=4, BF_INA, "
+                        f"Poisson arrivals at {rate:g} q/s", "offered_qps": rate, "p50_us": st["p50_us"],
+            "p99_us": st["p99_us"], "mean_us": st["mean_us"], "max_us": st["max_us"], "qps": st["queries_per_s"],
+            "evals_per_s": st["evals_per_s"], "mean_batch": st["mean_batch"], "rejected": st["rejected"]}
 
 
 def main():
@@ -78,12 +112,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
-    ap.add_argument("--n-sets", type=int, default=100_000)
-    ap.add_argument("--cpu-sample", type=int, default=30000, help="task sets timed on the CPU oracle")
+    ap.add_argument("--n-sets", type=int, default=0, help="override the workload's number of sets")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="task sets timed on the CPU oracle (0 = default)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="0 = all host cores (at most 16)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (counts from 200 sets)")
-    ap.add_argument("--per-set-launch", action="store_true", help="plain path: one launch sequence per set")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (counts from a small sample)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain and per-set path comparisons")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--form", default="batched", choices=["batched", "plain"],
+                    help="GPU form timed for `value` (c2, c3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -107,74 +145,154 @@ def main():
 
     from paper_2105_10312_amd import capart, workload
 
+    sync = torch.cuda.synchronize
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    eng = capart.Engine(0)
     K = 4
-    log(f"[bench] generating workload: {args.n_sets} sets, n=10, M=80, K={K}")
-    ts = workload.config_c2(n_sets=args.n_sets)
-    P = capart.capart_count_partitionings(80, K)
-    evals_per_step = P * ts.n_sets
+    mode = args.mode
+    if args.workload == "c5":
+        rates = [1e4, 3e4, 1e5, 3e5, 1e6]
+        legs = []
+        for r in rates:
+            n_q = int(min(200000, max(20000, r * 0.5)))
+            log(f"[bench] serving at {r:g} q/s, {n_q} queries")
+            legs.append(serving_leg(eng, capart, workload, r, n_q))
+            log(f"[bench]   p50 {legs[-1]['p50_us']:.1f} us p99 {legs[-1]['p99_us']:.1f} us "
+                f"{legs[-1]['qps']:.4g} q/s")
+        best = max(legs, key=lambda x: x["evals_per_s"])
+        res = {"metric": METRIC, "value": best["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": len(rates),
+               "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "int64", "data": "synthetic",
+               "config": {"workload": "serving: open-loop Poisson admission queries, n log-uniform 2..64, "
+                                      "M in {16,48,80,108}, K=4, BF_INA"},
+               "serving": legs, "roofline": None, "cpu_baseline": None}
+        eng.close()
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.workload == "c2":
+        ts = workload.config_c2(n_sets=args.n_sets or 100_000)
+        max_tasks, max_M, desc = 10, 80, "n=10, M=80"
+        cpu_sample, cpu_stride = args.cpu_sample or 30000, 1
+    elif args.workload == "c3":
+        ts = workload.config_c3(n_sets=args.n_sets or 1_000_000)
+        max_tasks, max_M, desc = 32, 108, "n uniform 4..32, M in {16,48,80,108}, constrained deadlines"
+        cpu_sample, cpu_stride = args.cpu_sample or 6000, 100
+    else:
+        ts = workload.config_c4(n_sets=args.n_sets or 1000)
+        max_tasks, max_M, desc = 12, 48, "n=12, M=48, exhaustive allocation"
+        mode = "EXH"
+        cpu_sample, cpu_stride = 0, 1
+    log(f"[bench] workload {args.workload}: {ts.n_sets} sets, {desc}, K={K}, {mode}")
+    Pcount = {int(m): capart.capart_count_partitionings(int(m), K) for m in np.unique(ts["M"])}
+    evals_per_step = int(sum(Pcount[int(m)] for m in ts["M"]))
     dev = capart.device_tasksets(ts)
     out = capart.device_results(ts.n_sets, ts.n_tasks, K)
-    eng = capart.Engine(0)
-    flags = capart.CAPART_FLAG_PER_SET_LAUNCH if args.per_set_launch else 0
-    stream = torch.cuda.current_stream()
 
-    def step():
-        capart.capart_solve_async(eng.ctx, dev, K, args.mode, out, stream=stream, flags=flags, max_tasks=10,
-                                  max_M=80)
+    def plain_step():
+        capart.capart_solve_async(eng.ctx, dev, K, mode, out, max_tasks=max_tasks, max_M=max_M)
+
+    plan = None
+    if args.form == "batched" and mode != "EXH":
+        t0 = time.perf_counter()
+        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=True)
+        plan_info = plan.info()
+        log(f"[bench] plan: {plan_info} ({(time.perf_counter() - t0):.1f} s)")
+        step = plan.run
+        form = "batched (persistent work queue, autotuned, HIP graph)"
+    else:
+        plan_info = None
+        step = plain_step
+        form = "plain (one launch sequence over the batch)"
 
     for i in range(args.warmup):
         step()
-        torch.cuda.synchronize()
+        sync()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     st = out["status"][: ts.n_sets].cpu().numpy()
     if not (st == 0).all():
         raise SystemExit(f"bench: {int((st != 0).sum())} sets reported errors")
-    capart.capart_timing_enable(eng.ctx, True)
-    capart.capart_timing_read(eng.ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_k, n_k = capart.capart_timing_read(eng.ctx)
-    capart.capart_timing_enable(eng.ctx, False)
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    ms_per_step = timed(step, args.steps, sync)
     value = evals_per_step / (ms_per_step / 1000.0)
     verdicts = int(out["verdict"][: ts.n_sets].sum().item())
-    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} evals/s; kernels ms {ms_k}")
-
-    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-    if args.no_cpu:
-        cb = cpu_baseline(ts, K, args.mode, 200, threads)
-        cpu = None
-    else:
-        log(f"[bench] CPU oracle on {args.cpu_sample} sets with {threads} threads")
-        cb = cpu_baseline(ts, K, args.mode, args.cpu_sample, threads)
-        cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {cb['sets']} of the {ts.n_sets} sets ({cb['evals']} evals), "
-                         f"{cb['seconds']:.2f} s wall"}
-        log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s")
-    terms_per_eval = cb["terms"] / cb["evals"]
-    tests_per_eval = cb["tests"] / cb["evals"]
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} evals/s ({form})")
+    # kernel durations: the same steps with HIP events around each kernel on
+    # the launch stream (a plan then launches its kernels directly)
+    capart.capart_timing_enable(eng.ctx, True)
+    capart.capart_timing_read(eng.ctx)
+    ms_timed = timed(step, args.steps, sync)
+    ms_k, n_k = capart.capart_timing_read(eng.ctx)
+    capart.capart_timing_enable(eng.ctx, False)
     eval_ms = ms_k["eval"] / max(1, n_k["eval"])
-    ops = evals_per_step * (terms_per_eval * C_TERM + tests_per_eval * C_TEST)
-    achieved = ops / (eval_ms / 1000.0)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
-            "frac": achieved / PEAK_INT_LANE_OPS, "traffic": traffic_bytes(),
-            "kernel": "eval_heur_kernel", "kernel_ms": eval_ms,
-            "ops_per_launch": ops, "terms_per_eval": terms_per_eval, "tests_per_eval": tests_per_eval,
-            "ops_per_term": C_TERM, "ops_per_test": C_TEST,
-            "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
-                                 "final": ms_k["final"] / max(1, n_k["final"])}}
+    log(f"[bench] kernels per step: {ms_k} over {n_k['eval']} steps")
+
+    compare = {}
+    if not args.no_compare and args.form == "batched" and plan is not None:
+        plain_ms = timed(plain_step, max(2, args.steps // 2), sync)
+        compare["plain_path"] = {"ms_per_step": plain_ms, "value": evals_per_step / (plain_ms / 1000.0),
+                                 "batched_over_plain": plain_ms / ms_per_step}
+        log(f"[bench] plain path: {plain_ms:.2f} ms/step")
+        sub_n = min(2000, ts.n_sets)
+        sub = workload.subset(ts, np.arange(sub_n))
+        sdev = capart.device_tasksets(sub)
+        sout = capart.device_results(sub.n_sets, sub.n_tasks, K)
+
+        def per_set():
+            capart.capart_solve_async(eng.ctx, sdev, K, mode, sout, max_tasks=max_tasks, max_M=max_M,
+                                      flags=capart.CAPART_FLAG_PER_SET_LAUNCH)
+
+        per_set()
+        ps_ms = timed(per_set, 1, sync)
+        ps_evals = int(sum(Pcount[int(m)] for m in sub["M"]))
+        compare["per_set_launch"] = {"sets": sub_n, "ms": ps_ms, "value": ps_evals / (ps_ms / 1000.0)}
+        compare["per_set_launch"]["batched_over_per_set"] = value / compare["per_set_launch"]["value"]
+        log(f"[bench] one launch per set: {compare['per_set_launch']['value']:.4g} evals/s")
+
+    serving = None
+    if args.workload == "c2" and not args.no_serving:
+        serving = serving_leg(eng, capart, workload, 1e5, 20000)
+        log(f"[bench] serving at 1e5 q/s: p50 {serving['p50_us']:.1f} us, p99 {serving['p99_us']:.1f} us")
+
+    cpu = None
+    if mode == "EXH":
+        cb = None
+    elif args.no_cpu:
+        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride)
+    else:
+        log(f"[bench] CPU oracle on {cpu_sample} sets with {threads} threads")
+        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride)
+        cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"{cb['sets']} of the {ts.n_sets} sets (every {cpu_stride}th from the first), "
+                         f"{cb['evals']} evals, {cb['seconds']:.2f} s wall"}
+        log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s")
+    roof = None
+    if cb is not None:
+        kname = "eval_persistent_kernel" if plan is not None else "eval_heur_kernel"
+        terms_per_eval = cb["terms"] / cb["evals"]
+        tests_per_eval = cb["tests"] / cb["evals"]
+        ops = evals_per_step * (terms_per_eval * C_TERM + tests_per_eval * C_TEST)
+        achieved = ops / (eval_ms / 1000.0)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
+                "frac": achieved / PEAK_INT_LANE_OPS,
+                "traffic": traffic_bytes(f"{kname}_{args.workload}_{mode.lower()}_traffic.json"),
+                "kernel": kname, "kernel_ms": eval_ms, "ops_per_launch": ops, "terms_per_eval": terms_per_eval,
+                "tests_per_eval": tests_per_eval, "ops_per_term": C_TERM, "ops_per_test": C_TEST,
+                "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
+                                     "final": ms_k["final"] / max(1, n_k["final"])},
+                "step_ms_with_kernel_events": ms_timed}
+    else:
+        roof = {"bound": "alu", "kernel": "exh_dfs_kernel + subset_table_kernel", "kernel_ms": eval_ms,
+                "achieved": None, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
+                "note": "exhaustive search: work is data-dependent (pruned search); see DESIGN.md"}
     res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": f"batched plain: {ts.n_sets} task sets, n=10, M=80, K=4, {args.mode} "
-                                  f"heuristic allocation" + (", one launch per set" if args.per_set_launch else ""),
-                      "n_sets": ts.n_sets, "n": 10, "M": 80, "K": K, "alloc_mode": args.mode,
-                      "evals_per_step": evals_per_step, "schedulable_sets": verdicts},
-           "roofline": roof, "cpu_baseline": cpu}
+           "config": {"workload": f"{args.workload}: {ts.n_sets} task sets, {desc}, K={K}, {mode}, {form}",
+                      "n_sets": ts.n_sets, "K": K, "alloc_mode": mode, "evals_per_step": evals_per_step,
+                      "schedulable_sets": verdicts, "plan": plan_info},
+           "compare": compare, "serving": serving, "roofline": roof, "cpu_baseline": cpu}
+    if plan is not None:
+        plan.close()
     eng.close()
     print(json.dumps(res), flush=True)
 

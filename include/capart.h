@@ -317,13 +317,19 @@ capart_status capart_server_destroy(capart_server *srv);
  * k^n allocations of one partitioning, 2 = per-set subset tables of partition
  * utilisation (every task subset on every size) and a depth-first search in
  * allocation-index order with exact pruning (sets of at most 14 tasks, K <= 4;
- * otherwise form 1 is used).  NULL restores the automatic choices.  E_INVAL for
- * values out of range. */
+ * otherwise form 1 is used).  frontier (heuristic modes): 0 = automatic (on),
+ * 1 = on, 2 = off; when on, a set of at most 14 tasks first gets its
+ * feasibility frontier (for every task subset, the fewest units that schedule
+ * it, by exact tests) and every candidate test of the heuristic on every
+ * partitioning becomes a lookup in it.  NULL restores the automatic choices.
+ * E_INVAL for values out of range. */
 typedef struct capart_tuning {
     int32_t threads;
     int32_t chunk;
     int32_t loop_form;
     int32_t exh_form;
+    int32_t frontier;
+    int32_t reserved[3];  /* must be 0 */
 } capart_tuning;
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);

@@ -51,7 +51,8 @@ class capart_results(C.Structure):
 
 
 class capart_tuning(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("exh_form", C.c_int32)]
+    _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("exh_form", C.c_int32),
+                ("frontier", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class capart_plan_config(C.Structure):
@@ -343,15 +344,17 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
                                              C.c_void_p(stream.cuda_stream)), ctx)
 
 
-def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0) -> None:
-    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form))
+def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0,
+                      frontier: int = 0) -> None:
+    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier))
     _check(load_library().capart_set_tuning(ctx, C.byref(t)), ctx)
 
 
 def capart_get_tuning(ctx) -> dict:
     t = capart_tuning()
     _check(load_library().capart_get_tuning(ctx, C.byref(t)), ctx)
-    return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form, "exh_form": t.exh_form}
+    return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form, "exh_form": t.exh_form,
+            "frontier": t.frontier}
 
 
 def capart_timing_enable(ctx, enable: bool = True) -> None:

@@ -27,7 +27,7 @@ struct capart_ctx {
     size_t ws_bytes = 0;
     void *stage = nullptr;         // staging buffer for host-pointer calls
     size_t stage_bytes = 0;
-    capart_tuning tune{0, 0, 0, 0}; // launch tuning (0 = automatic)
+    capart_tuning tune{};          // launch tuning (0 = automatic)
     uint64_t *tab = nullptr;       // subset tables of the exhaustive search
     size_t tab_bytes = 0;
     bool timing = false;           // record kernel events
@@ -198,6 +198,21 @@ int32_t validate_set(const capart_tasksets *in, int64_t s, int K, int mode)
     return CAPART_OK;
 }
 
+// Frontier region: 2^front_n u16 after the tables, shrunk until tables,
+// frontier and (loop form 2) per-lane state fit the LDS next to the static
+// per-set arrays.
+void size_frontier(Launch &L, int max_tasks, int mode, const capart_tuning &tu)
+{
+    L.front_n = 0;
+    L.front_words = 0;
+    if (mode == CAPART_EXHAUSTIVE || tu.frontier == 2) return;
+    int fn = std::min(max_tasks, FRONTIER_MAX_TASKS);
+    const size_t lane = L.form == 2 ? (size_t)L.threads * 8 * 16 : 0;
+    while (fn > 0 && (size_t)4 * L.table_words + ((size_t)2 << fn) + lane > (size_t)150 * 1024) fn--;
+    L.front_n = fn;
+    L.front_words = fn > 0 ? (1 << fn) / 2 : 0;
+}
+
 struct Plan {
     Launch L;
     int64_t S, N;
@@ -219,6 +234,7 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
     L.form = tu.loop_form > 0 ? tu.loop_form : 1;
     // exhaustive: subset tables + pruned search when sets are small enough
+    size_frontier(L, in->max_tasks, opt->alloc_mode, tu);
     L.exh_form = (opt->K <= 4 && in->max_tasks <= SUBSET_MAX_TASKS) ? 2 : 1;
     if (tu.exh_form == 1 || tu.exh_form == 2) L.exh_form = tu.exh_form;
     if (L.exh_form == 2 && (opt->K > 4 || in->max_tasks > SUBSET_MAX_TASKS)) L.exh_form = 1;
@@ -237,6 +253,9 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
         const int64_t ch_fill = (want_blocks + std::max<int64_t>(per_set_launch, 1) - 1) / std::max<int64_t>(per_set_launch, 1);
         const int64_t chmax = std::max<int64_t>(1, (Pmax + L.threads - 1) / L.threads);
         ch = std::max<int64_t>(1, std::min(std::max(ch, ch_fill), chmax));
+        // frontier sets: the frontier is built once per block, so keep one
+        // block per set when there are enough sets to fill the chip
+        if (L.front_n > 0 && in->max_tasks <= L.front_n) ch = std::max<int64_t>(1, std::min(ch_fill, chmax));
         L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
         if (tu.chunk > 0) L.chunk = std::min<uint32_t>((uint32_t)tu.chunk, std::max<uint32_t>(Pmax, 1));
         L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
@@ -746,7 +765,7 @@ capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
 {
     if (!c) return CAPART_E_INVAL;
     if (!t) {
-        c->tune = capart_tuning{0, 0, 0, 0};
+        c->tune = capart_tuning{};
         return CAPART_OK;
     }
     if (t->threads < 0 || t->threads > 256 || (t->threads % 64) != 0)
@@ -754,6 +773,8 @@ capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
     if (t->chunk < 0) return fail(c, CAPART_E_INVAL, "chunk must be >= 0");
     if (t->loop_form < 0 || t->loop_form > 2) return fail(c, CAPART_E_INVAL, "loop_form must be 0, 1 or 2");
     if (t->exh_form < 0 || t->exh_form > 2) return fail(c, CAPART_E_INVAL, "exh_form must be 0, 1 or 2");
+    if (t->frontier < 0 || t->frontier > 2) return fail(c, CAPART_E_INVAL, "frontier must be 0, 1 or 2");
+    if (t->reserved[0] || t->reserved[1] || t->reserved[2]) return fail(c, CAPART_E_INVAL, "reserved must be 0");
     c->tune = *t;
     return CAPART_OK;
 }
@@ -847,7 +868,7 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
 // item_evals * 121 / (n+1)^2 partitionings (the response-time work of a
 // partitioning grows roughly with n^2), queued by decreasing estimated cost.
 void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M, int64_t S, const capart_tasksets *in,
-                 int K, int item_evals, std::vector<WorkItem> &items, std::vector<uint32_t> &slot_off,
+                 int K, int item_evals, int front_n, std::vector<WorkItem> &items, std::vector<uint32_t> &slot_off,
                  int64_t &total_evals)
 {
     items.clear();
@@ -864,7 +885,8 @@ void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M,
         const uint32_t P = count_parts(m, K);
         total_evals += P;
         const uint64_t w = (uint64_t)(n + 1) * (uint64_t)(n + 1);
-        const uint32_t per = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(1u << 20, (uint64_t)item_evals * 121 / w));
+        uint32_t per = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(1u << 20, (uint64_t)item_evals * 121 / w));
+        if (n <= front_n) per = std::max<uint32_t>(P, 1);  // one item: the frontier is built once
         for (uint32_t p0 = 0; p0 < P; p0 += per) {
             const uint32_t p1 = std::min(P, p0 + per);
             items.push_back(WorkItem{(uint32_t)s, p0, p1, (uint32_t)items.size()});
@@ -937,7 +959,8 @@ capart_status launch_plan_kernels(capart_ctx *c, const Batch &b, const Work &w, 
     return CAPART_OK;
 }
 
-Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int threads, int form)
+Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int threads, int form,
+                   const capart_tuning &tune)
 {
     Launch L{};
     L.s0 = 0;
@@ -950,6 +973,8 @@ Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int thr
     L.form = form;
     L.chunks = 1;
     L.chunk = 0;
+    L.exh_form = 1;
+    size_frontier(L, in->max_tasks, opt->alloc_mode, tune);
     return L;
 }
 
@@ -1011,13 +1036,14 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                         std::vector<WorkItem> items;
                         std::vector<uint32_t> so;
                         int64_t te = 0;
-                        build_items(off, M, St, in, opt->K, ie2, items, so, te);
+                        build_items(off, M, St, in, opt->K, ie2, plan_launch(&sub, opt, th, fo, c->tune).front_n,
+                                    items, so, te);
                         PlanBuffers pb;
                         if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, pb)) != CAPART_OK) {
                             if (pb.buf) hipFree(pb.buf);
                             return rc;
                         }
-                        const Launch L = plan_launch(&sub, opt, th, fo);
+                        const Launch L = plan_launch(&sub, opt, th, fo, c->tune);
                         hipEvent_t e0 = take_event(c), e1 = take_event(c);
                         double ms = 0;
                         for (int rep = 0; rep < 3 && rc == CAPART_OK; rep++) {
@@ -1056,7 +1082,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     std::vector<WorkItem> items;
     std::vector<uint32_t> so;
     int64_t te = 0;
-    build_items(off, M, S, in, opt->K, item_evals, items, so, te);
+    build_items(off, M, S, in, opt->K, item_evals, plan_launch(in, opt, threads, form, c->tune).front_n, items, so, te);
     PlanBuffers pb;
     if ((rc = alloc_plan_buffers(c, S, N, items, so, pb)) != CAPART_OK) {
         if (pb.buf) hipFree(pb.buf);
@@ -1065,7 +1091,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     }
     pl->buf = pb.buf;
     pl->w = pb.w;
-    pl->L = plan_launch(in, opt, threads, form);
+    pl->L = plan_launch(in, opt, threads, form, c->tune);
     pl->blocks = cus * bpc;
     pl->info.n_sets = S;
     pl->info.n_items = (int64_t)items.size();
@@ -1566,6 +1592,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     L.threads = eval_threads(cfg->max_tasks, cfg->max_M);
     L.table_words = (int)(table_lds_bytes(cfg->max_tasks, cfg->max_M) / 4);
     L.form = c->tune.loop_form > 0 ? c->tune.loop_form : 1;
+    L.exh_form = 1;
+    size_frontier(L, cfg->max_tasks, cfg->alloc_mode, c->tune);
     const uint32_t Pmax = count_parts(cfg->max_M, cfg->K);
     L.chunk = c->tune.chunk > 0 ? (uint32_t)c->tune.chunk : (uint32_t)L.threads;
     L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);

@@ -82,11 +82,15 @@ struct Launch {
     int table_words;     // u32 words of dynamic LDS reserved for the per-set tables
     int form;            // heuristic loop form: 1 = one step per partitioning, 2 = one step per candidate test
     int exh_form;        // exhaustive: 1 = enumerate every allocation, 2 = subset tables + pruned search
+    int front_n;         // heuristic: sets of at most front_n tasks use the feasibility frontier (0 = never)
+    int front_words;     // u32 words of dynamic LDS reserved for the frontier (2^front_n u16)
 };
 
 // Host-side sizing helpers shared by the launchers.
 size_t table_lds_bytes(int max_tasks, int max_M);
 int eval_threads(int max_tasks, int max_M);
+// largest set size answered through the feasibility frontier
+constexpr int FRONTIER_MAX_TASKS = 14;
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);

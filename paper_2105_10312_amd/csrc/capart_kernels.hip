@@ -344,6 +344,111 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 }
 
 // ---------------------------------------------------------------------------
+// Feasibility frontier of a set of at most FRONT_MAX_N tasks: ms[S] = fewest
+// units that schedule rank subset S on one partition (FRONT_NONE if even M
+// units do not).  Schedulability is monotone in m (no timing anomalies) and
+// in S (a task added to a partition never helps), so ms[S] is at least the
+// largest ms of its subsets with one task less; subsets are filled level by
+// level (by size) with a binary search above that bound.  Every candidate test
+// of the heuristic on any partitioning is then one lookup:
+// S + {tau} fits a part of m units iff ms[S + {tau}] <= m, and the fewest
+// units the merged part needs (order >>) is ms[S + {tau}] itself.
+constexpr int FRONT_MAX_N = 14;
+constexpr uint16_t FRONT_NONE = 0xFFFFu;
+
+template <typename MT>
+__device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms)
+{
+    const uint32_t NS = 1u << n;
+    if (threadIdx.x == 0) ms[0] = 0;
+    __syncthreads();
+    for (int c = 1; c <= n; c++) {
+        for (uint32_t S = threadIdx.x; S < NS; S += blockDim.x) {
+            if (__popc(S) != c) continue;
+            int lo = 1;
+            bool none = false;
+            for (uint32_t h = S; h; h &= h - 1u) {
+                const uint16_t v = ms[S & ~(h & (0u - h))];
+                none |= (v == FRONT_NONE);
+                lo = max(lo, (int)v);
+            }
+            uint16_t res = FRONT_NONE;
+            if (!none) {
+                const MT SM = (MT)S;
+                const MT cm = conflict_mask<MT>(SM, (MT)L.memmask);
+                if (test_from<MT>(L, tb, SM, 0, lo, cm)) {
+                    res = (uint16_t)lo;
+                } else if (lo < M && test_from<MT>(L, tb, SM, 0, M, cm)) {
+                    int a = lo + 1, b = M;  // schedulable at b, not at lo
+                    while (a < b) {
+                        const int mid = (a + b) >> 1;
+                        if (test_from<MT>(L, tb, SM, 0, mid, cm))
+                            b = mid;
+                        else
+                            a = mid + 1;
+                    }
+                    res = (uint16_t)a;
+                }
+            }
+            ms[S] = res;
+        }
+        __syncthreads();
+    }
+}
+
+// Q32 utilisation of S_old + {tau} on m units from that of S_old (the new
+// task's term and, when it makes the lone same-type member conflict, that
+// member's change).
+template <typename MT>
+__device__ __forceinline__ uint64_t util_add(const SetLDS &L, const Tables &tb, MT Sold, int tau, int m, uint64_t Uold)
+{
+    const int n = tb.n;
+    const MT memm = (MT)L.memmask;
+    const MT same = Sold & (mbit(memm, tau) ? memm : ~memm);
+    const int ns = mpopc(same);
+    const uint32_t *urow = tb.U + (m - 1) * 2 * n;
+    uint64_t u = Uold + (uint64_t)urow[(ns >= 1 ? n : 0) + tau] + 1ull;
+    if (ns == 1) {
+        const int flip = mctz(same);
+        u += (uint64_t)urow[n + flip] - (uint64_t)urow[flip];
+    }
+    return u;
+}
+
+// The heuristic on one fixed partitioning with every candidate test answered
+// by the frontier (same decisions as `heuristic`, which tests directly).
+template <int KMAX, bool ACT, bool SMS, typename MT>
+__device__ __forceinline__ bool heuristic_front(const SetLDS &L, const Tables &tb, const uint16_t *ms, int n,
+                                                const int (&m)[KMAX], int k, MT (&S)[KMAX], uint64_t (&U)[KMAX])
+{
+#pragma unroll
+    for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
+    for (int t = 0; t < n; t++) {
+        const int r = L.sigma[t];
+        const MT bit = MT(1) << r;
+        const MT fb = ACT ? (MT)L.forbid[r] : MT(0);
+        int best = -1, bestReq = 0;
+        uint64_t bestU = 0;
+#pragma unroll
+        for (int p = 0; p < KMAX; p++) {
+            if (p >= k) continue;
+            const MT Sp = S[p];
+            const int req = (int)ms[(uint32_t)(Sp | bit)];
+            if (req > m[p]) continue;
+            if (ACT && (fb & Sp)) continue;
+            const uint64_t Un = util_add<MT>(L, tb, Sp, r, m[p], U[p]);
+            const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
+            if (better) { best = p; bestU = Un; bestReq = req; }
+        }
+        if (best < 0) return false;
+#pragma unroll
+        for (int p = 0; p < KMAX; p++)
+            if (p == best) { S[p] |= bit; U[p] = bestU; }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Partitionings of M into at most K parts in descending lexicographic order.
 template <int KMAX>
 __device__ __forceinline__ int unrank(const uint32_t *np, int M, int K, uint32_t rank, int (&a)[KMAX])
@@ -669,15 +774,68 @@ __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_
     }
 }
 
+template <int KMAX, bool ACT, bool SMS, typename MT>
+__device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t *ms, const uint32_t *np, int n, int M,
+                               int K, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg)
+{
+    int m[KMAX];
+    int k = unrank<KMAX>(np, M, K, q0, m);
+    for (uint32_t q = q0;;) {
+        MT S[KMAX];
+        uint64_t U[KMAX];
+        const bool ok = heuristic_front<KMAX, ACT, SMS, MT>(L, tb, ms, n, m, k, S, U);
+        uint64_t mx = 0, sm = 0;
+        if (ok) {
+#pragma unroll
+            for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
+            const Key kk{mx, sm, q, 0ull};
+            if (key_less(kk, best)) best = kk;
+        }
+        if (dbg) {
+            uint64_t *d = dbg + 3 * (uint64_t)q;
+            d[0] = ok ? mx : ~0ull;
+            d[1] = ok ? sm : ~0ull;
+            d[2] = ok ? 0ull : ~0ull;
+        }
+        if (++q >= q1) break;
+        k = next_partition<KMAX>(m, K);
+    }
+}
+
+// Evaluate partitionings [p0, p1) of one staged set in this block (all
+// lanes): through the frontier when the set is small enough, else with
+// direct incremental tests.
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
+__device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, const uint32_t *np, int n, int M,
+                           uint32_t p0, uint32_t p1, uint32_t p_lo, uint32_t p_hi, Key &best, uint64_t *dbg)
+{
+    const uint32_t cnt = p1 - p0;
+    const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
+    uint32_t q0 = p0 + threadIdx.x * per, q1 = min(p1, q0 + per);
+    q0 = max(q0, p_lo);
+    q1 = min(q1, p_hi);
+    if (Lp.front_n > 0 && n <= Lp.front_n) {
+        uint16_t *ms = (uint16_t *)(capart_dyn_lds + Lp.table_words);
+        build_frontier<MT>(L, tb, n, M, ms);
+        if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg);
+        return;
+    }
+    if (q0 >= q1) return;
+    if (FORM == 2) {
+        uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words + Lp.front_words);
+        MT *lS = (MT *)(lU + KMAX * blockDim.x);
+        heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
+    } else {
+        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg);
+    }
+}
+
 template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
 __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
-    // per-lane part state follows the tables in dynamic LDS
-    uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words);
-    MT *lS = (MT *)(lU + KMAX * blockDim.x);
     const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
     const int c = blockIdx.x % Lp.chunks;
     const uint32_t f = w.setflags[s];
@@ -694,17 +852,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (!(f & SETF_LEMMA1)) {
         Tables tb;
         stage_set(L, w, off, n, M, s, ACT, tb);
-        const uint32_t cnt = p1 - p0;
-        const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
-        uint32_t q0 = p0 + threadIdx.x * per, q1 = min(p1, q0 + per);
-        q0 = max(q0, p_lo);
-        q1 = min(q1, p_hi);
-        if (q0 < q1) {
-            if (FORM == 2)
-                heur_run<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
-            else
-                heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg);
-        }
+        eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, p0, p1, p_lo, p_hi, best, dbg);
     } else if (dbg) {
         for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
             if (q < p_lo || q >= p_hi) continue;
@@ -729,8 +877,6 @@ __global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, O
     __shared__ SetLDS L;
     __shared__ Key red[16];
     __shared__ uint32_t s_item;
-    uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words);
-    MT *lS = (MT *)(lU + KMAX * blockDim.x);
     int64_t staged = -1;
     Tables tb;
     tb.C = tb.U = nullptr;
@@ -754,15 +900,7 @@ __global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, O
                 stage_set(L, w, off, n, M, s, ACT, tb);
                 staged = s;
             }
-            const uint32_t cnt = wi.p1 - wi.p0;
-            const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
-            const uint32_t q0 = wi.p0 + threadIdx.x * per, q1 = min(wi.p1, q0 + per);
-            if (q0 < q1) {
-                if (FORM == 2)
-                    heur_run<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
-                else
-                    heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, w.np, n, M, Lp.K, q0, q1, best, dbg);
-            }
+            eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg);
         } else if (dbg && (f & SETF_VALID)) {
             for (uint32_t q = wi.p0 + threadIdx.x; q < wi.p1; q += blockDim.x) {
                 uint64_t *d = dbg + 3 * (uint64_t)q;
@@ -1017,6 +1155,7 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
 {
     __shared__ Key red[16];
     __shared__ uint64_t pw[16];
+    __shared__ unsigned long long shared_mx;  // smallest maxU of any complete allocation found in the block
     const uint32_t xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
     const int s_local = (int)(xcd + 8u * (j / Pmax));
     const uint32_t q = j % Pmax;
@@ -1035,6 +1174,7 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
     if (threadIdx.x == 0) {
         uint64_t v = 1;
         for (int i = n - 1; i >= 0; i--) { pw[i] = v; v *= (uint64_t)k; }
+        shared_mx = ~0ull;
     }
     __syncthreads();
     int Lpre = 0;
@@ -1075,6 +1215,8 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
             if (Lpre == n) {
                 best = Key{mx, sm, q, aidx};
             } else {
+                // other lanes' complete allocations bound maxU strictly: a
+                // partial maxU above one can never win, whatever its index
                 uint64_t dig = 0;
                 int i = Lpre, p = 0;
                 for (;;) {
@@ -1095,8 +1237,10 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
                             nsm += v;
                         }
                         if (nmx > best.a || (nmx == best.a && nsm >= best.b)) continue;
+                        if (nmx > (uint64_t)*(volatile unsigned long long *)&shared_mx) continue;
                         if (i == n - 1) {
                             best = Key{nmx, nsm, q, aidx + (uint64_t)p * pw[i]};
+                            atomicMin(&shared_mx, (unsigned long long)nmx);
                             continue;
                         }
                         Apack |= (uint64_t)(1u << i) << (16 * p);
@@ -1200,9 +1344,10 @@ int eval_threads(int max_tasks, int max_M) { return table_lds_bytes(max_tasks, m
 static size_t dyn_bytes(const Batch &b) { return table_lds_bytes(min(b.max_tasks, MAXN), min(b.max_M, 255)); }
 
 template <int KMAX, typename MT>
-static size_t heur_dyn_bytes(const Launch &L)
+static size_t heur_dyn_bytes(const Launch &L, int form)
 {
-    return (size_t)4 * L.table_words + (size_t)L.threads * KMAX * (sizeof(MT) + sizeof(uint64_t));
+    return (size_t)4 * (L.table_words + L.front_words) +
+           (form == 2 ? (size_t)L.threads * KMAX * (sizeof(MT) + sizeof(uint64_t)) : 0);
 }
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
@@ -1217,7 +1362,7 @@ static hipError_t launch_heur(const Launch &L, const Batch &b, const Work &w, co
                               uint32_t p_lo, uint32_t p_hi)
 {
     const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
-    const size_t lds = FORM == 2 ? heur_dyn_bytes<KMAX, MT>(L) : (size_t)4 * L.table_words;
+    const size_t lds = heur_dyn_bytes<KMAX, MT>(L, FORM);
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
         hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
@@ -1257,7 +1402,7 @@ static hipError_t launch_persistent_k(const Batch &b, const Work &w, const Out &
                                       hipStream_t st)
 {
     const dim3 grid((unsigned)blocks), block((unsigned)L.threads);
-    const size_t lds = FORM == 2 ? heur_dyn_bytes<KMAX, MT>(L) : (size_t)4 * L.table_words;
+    const size_t lds = heur_dyn_bytes<KMAX, MT>(L, FORM);
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
         hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L);

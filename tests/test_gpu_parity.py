@@ -332,3 +332,26 @@ def test_c2_full_size_sampled(eng):
     task_idx = np.concatenate([np.arange(ts["set_offset"][s], ts["set_offset"][s + 1]) for s in idx])
     gsub = {f: (got[f][task_idx] if f in ("alloc", "R", "R_1g") else got[f][idx]) for f in FIELDS}
     assert_same(gsub, want, sub, "c2 full sampled")
+
+
+@pytest.mark.parametrize("mode", ["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_frontier_and_direct_tests_agree(eng, mode):
+    """Frontier lookups and direct response-time tests give identical results,
+    per partitioning (debug keys) and per set."""
+    parts = [workload.subset(workload.config_c2(seed=41, n_sets=400), np.arange(150)),
+             workload.subset(workload.config_c3(seed=42, n_sets=600), np.arange(200))]
+    for ts in parts:
+        for K in (4, 8):
+            capart.capart_set_tuning(eng.ctx, frontier=1)
+            a = eng.solve(ts, K, mode, debug=True)
+            capart.capart_set_tuning(eng.ctx, frontier=2)
+            b = eng.solve(ts, K, mode, debug=True)
+            capart.capart_set_tuning(eng.ctx)
+            for f in FIELDS + ("dbg_key",):
+                assert np.array_equal(a[f], b[f]), (mode, K, f)
+    ts = parts[0]
+    want = oracle.solve(ts, 4, mode, nthreads=THREADS)
+    capart.capart_set_tuning(eng.ctx, frontier=1)
+    got = eng.solve(ts, 4, mode)
+    capart.capart_set_tuning(eng.ctx)
+    assert_same(got, want, ts, f"frontier {mode}")
