@@ -334,6 +334,16 @@ typedef struct capart_tuning {
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);
 
+/* Algorithmic work of a heuristic solve, counted exactly by a counting
+ * variant of the evaluation kernel (for roofline accounting; not for timing):
+ * counts[0] = response-time terms (per fixed-point iteration, one plus one per
+ * higher-priority term), counts[1] = exact partition tests, counts[2] =
+ * candidate tests answered from a feasibility frontier.  Same arguments as
+ * capart_solve_async (device pointers); results are written as by it.
+ * Synchronous.  E_INVAL for exhaustive mode or per-set launches. */
+capart_status capart_count_work(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                capart_results *dev_out, void *hip_stream, int64_t *counts);
+
 /* Kernel timing.  While enabled on a context, every launch sequence of
  * capart_solve / capart_solve_async records HIP events on its own stream
  * before and after the prep, eval and final kernels (one sequence per batch,

@@ -29,7 +29,7 @@ EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
            "capart_plan_destroy", "capart_server_create", "capart_server_submit", "capart_server_poll",
-           "capart_server_stats_get", "capart_server_replay", "capart_server_destroy"]
+           "capart_server_stats_get", "capart_server_replay", "capart_server_destroy", "capart_count_work"]
 
 _vp = C.c_void_p
 
@@ -130,6 +130,7 @@ def load_library():
         lib.capart_server_replay.argtypes = [_vp, P(capart_tasksets), _vp, P(capart_results),
                                              P(capart_server_stats)]
         lib.capart_server_destroy.argtypes = [_vp]
+        lib.capart_count_work.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp, _vp]
         lib.capart_timing_read.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS:
             if name != "capart_last_error":
@@ -368,6 +369,21 @@ def capart_timing_read(ctx):
     _check(load_library().capart_timing_read(ctx, ms.ctypes.data, n.ctypes.data), ctx)
     names = ("prep", "eval", "final")
     return dict(zip(names, ms.tolist())), dict(zip(names, n.tolist()))
+
+
+def capart_count_work(ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, stream=None,
+                      flags: int = 0) -> dict:
+    """Exact algorithmic work of one heuristic solve (counting kernel variant)."""
+    import torch
+    st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
+    opt = make_options(K, mode, flags)
+    res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], None, None)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    cnt = np.zeros(3, np.int64)
+    _check(load_library().capart_count_work(ctx, C.byref(st), C.byref(opt), C.byref(res),
+                                            C.c_void_p(stream.cuda_stream), cnt.ctypes.data), ctx)
+    return {"terms": int(cnt[0]), "tests": int(cnt[1]), "lookups": int(cnt[2])}
 
 
 class Plan:

@@ -761,6 +761,49 @@ capart_status capart_allocate(capart_ctx *c, const capart_tasksets *one, const i
     return CAPART_OK;
 }
 
+capart_status capart_count_work(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                capart_results *out, void *hip_stream, int64_t *counts)
+{
+    if (!c || !counts) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
+    if (opt->alloc_mode == CAPART_EXHAUSTIVE || (opt->flags & CAPART_FLAG_PER_SET_LAUNCH))
+        return fail(c, CAPART_E_INVAL, "work counting covers batched heuristic solves");
+    if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
+    counts[0] = counts[1] = counts[2] = 0;
+    if (in->n_sets == 0) return CAPART_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const Plan p = make_plan(in, opt, c->tune);
+    const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
+    if ((rc = ensure_ws(c, l.total + 256)) != CAPART_OK) return rc;
+    char *base = (char *)c->ws;
+    Work w{};
+    w.rec = (TaskRec *)(base + l.rec);
+    w.forbid = (uint64_t *)(base + l.forbid);
+    w.sigma = (uint8_t *)(base + l.sigma);
+    w.setflags = (uint32_t *)(base + l.setflags);
+    w.memmask = (uint64_t *)(base + l.memmask);
+    w.partial = (uint64_t *)(base + l.partial);
+    w.np = c->np_dev;
+    w.counters = (uint64_t *)(base + l.total);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Batch b = make_batch(in);
+    const Out o = make_out(out);
+    (void)hipGetLastError();
+    if ((e = hipMemsetAsync(w.counters, 0, 24, st)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+    if ((e = launch_prep(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if ((e = launch_eval_count(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "counting eval launch");
+    if ((e = launch_final(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
+    uint64_t h[3] = {0, 0, 0};
+    if ((e = hipMemcpyAsync(h, w.counters, 24, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "reading counters");
+    for (int i = 0; i < 3; i++) counts[i] = (int64_t)h[i];
+    return CAPART_OK;
+}
+
 capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
 {
     if (!c) return CAPART_E_INVAL;

@@ -57,6 +57,8 @@ struct Work {            // device workspace owned by the context
     uint32_t n_items;
     uint32_t *counter;         // next item to take (reset by the prep kernel)
     const uint32_t *slot_off;  // [S + 1] partial slots of each set
+    // counting variant of the evaluation kernel only
+    uint64_t *counters;        // [3]: response-time terms, exact tests, frontier lookups
 };
 
 struct Out {             // device pointers of the caller's results
@@ -112,5 +114,7 @@ hipError_t launch_exh_dfs(const Batch &b, const Work &w, const Out &o, const Lau
 hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
                          uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st);
 hipError_t configure_kernels();
+// counting variant of the heuristic evaluation (w.counters must be set)
+hipError_t launch_eval_count(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 
 }  // namespace capart

@@ -24,6 +24,8 @@
 #include "capart_internal.h"
 #include "capart_arith.h"
 
+#include <type_traits>
+
 namespace capart {
 
 constexpr int MAXN = CAPART_MAX_TASKS;
@@ -79,6 +81,22 @@ __device__ Key block_min(Key k, Key *scratch)
 }
 
 __device__ __forceinline__ int ctz64(uint64_t x) { return __builtin_ctzll(x); }
+
+// Work tallies: the evaluation kernel is also built in a counting variant that
+// totals the work its algorithm performs (response-time terms: one per
+// iteration plus one per higher-priority term; exact partition tests; frontier
+// lookups).  NoTally compiles to nothing.
+struct NoTally {
+    __device__ __forceinline__ void term(uint32_t) {}
+    __device__ __forceinline__ void test() {}
+    __device__ __forceinline__ void look() {}
+};
+struct Tally {
+    uint64_t terms = 0, tests = 0, looks = 0;
+    __device__ __forceinline__ void term(uint32_t k) { terms += k; }
+    __device__ __forceinline__ void test() { tests++; }
+    __device__ __forceinline__ void look() { looks++; }
+};
 
 // ---------------------------------------------------------------------------
 // Per-set data in LDS (ranks are deadline-monotonic priority positions).
@@ -166,13 +184,14 @@ __device__ __forceinline__ MT conflict_mask(MT S, MT memmask)
 // higher-priority task (so the sum equals C_r + sum ceil(R/T_j) C_j), and hp
 // holds only tasks with T_j < D_r (the others never release a second job
 // before D_r).  Returns R, or 0 once R exceeds D.
-template <typename MT>
+template <typename MT, typename TY>
 __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row, int n, uint64_t base, uint32_t D,
-                                           MT hp, MT cm)
+                                           MT hp, MT cm, TY &ty)
 {
     if (base > D) return 0u;
     uint64_t R = base;
     while (hp) {
+        ty.term(1u + (uint32_t)mpopc(hp));
         const uint32_t x = (uint32_t)R - 1u;
         uint64_t W = base;
         for (MT h = hp; h; h &= h - MT(1)) {
@@ -190,9 +209,10 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
 // Test the members of S with rank >= first on one partition of m units,
 // taking the members below `first` as already schedulable (their response
 // times cannot change).  cm = conflict mask of S.
-template <typename MT>
-__device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, int m, MT cm)
+template <typename MT, typename TY>
+__device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, int m, MT cm, TY &ty)
 {
+    ty.test();
     const int n = tb.n;
     const uint32_t *row = tb.C + (m - 1) * 2 * n;
     uint64_t sumC = 0;
@@ -208,7 +228,7 @@ __device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, in
         const uint32_t Cr = row[(int)mbit(cm, r) * n + r];
         if (sat) return false;
         const MT hp = S & below<MT>(r) & (MT)L.intf[r];
-        if (!rta_fp<MT>(L, row, n, sumC + Cr, L.D[r], hp, cm)) return false;
+        if (!rta_fp<MT>(L, row, n, sumC + Cr, L.D[r], hp, cm, ty)) return false;
         sumC += Cr;
         sat |= (Cr >= L.T[r]);
     }
@@ -216,12 +236,12 @@ __device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, in
 }
 
 // Whole-partition test with its Q32 utilisation.
-template <typename MT>
-__device__ bool part_test(const SetLDS &L, const Tables &tb, MT S, int m, uint64_t *U)
+template <typename MT, typename TY>
+__device__ bool part_test(const SetLDS &L, const Tables &tb, MT S, int m, uint64_t *U, TY &ty)
 {
     const int n = tb.n;
     const MT cm = conflict_mask<MT>(S, (MT)L.memmask);
-    if (!test_from<MT>(L, tb, S, 0, m, cm)) return false;
+    if (!test_from<MT>(L, tb, S, 0, m, cm, ty)) return false;
     const uint32_t *urow = tb.U + (m - 1) * 2 * n;
     uint64_t u = 0;
     for (MT h = S; h; h &= h - MT(1)) {
@@ -236,9 +256,9 @@ __device__ bool part_test(const SetLDS &L, const Tables &tb, MT S, int m, uint64
 // utilisation U_old.  Only tau, the lower-priority members and (if tau makes
 // the single same-type member conflict) that member and those below it can
 // change; U is updated by the same differences.
-template <typename MT>
+template <typename MT, typename TY>
 __device__ bool part_test_add(const SetLDS &L, const Tables &tb, MT Sold, int tau, int m, uint64_t Uold,
-                              uint64_t *U)
+                              uint64_t *U, TY &ty)
 {
     const int n = tb.n;
     const MT memm = (MT)L.memmask;
@@ -251,7 +271,7 @@ __device__ bool part_test_add(const SetLDS &L, const Tables &tb, MT Sold, int ta
         flip = mctz(same);
         first = min(first, flip);
     }
-    if (!test_from<MT>(L, tb, S, first, m, cm)) return false;
+    if (!test_from<MT>(L, tb, S, first, m, cm, ty)) return false;
     const uint32_t *urow = tb.U + (m - 1) * 2 * n;
     uint64_t u = Uold + (uint64_t)urow[(ns >= 1 ? n : 0) + tau] + 1ull;
     if (flip >= 0) u += (uint64_t)urow[n + flip] - (uint64_t)urow[flip];
@@ -261,8 +281,8 @@ __device__ bool part_test_add(const SetLDS &L, const Tables &tb, MT Sold, int ta
 
 // Fewest units (<= mp, where S is known schedulable) that schedule S: binary
 // search, valid because schedulability is monotone in m (no timing anomalies).
-template <typename MT>
-__device__ int min_units(const SetLDS &L, const Tables &tb, MT S, int mp)
+template <typename MT, typename TY>
+__device__ int min_units(const SetLDS &L, const Tables &tb, MT S, int mp, TY &ty)
 {
     int lo = 1;
     for (MT h = S; h; h &= h - MT(1)) lo = max(lo, (int)L.mmin[mctz(h)]);
@@ -270,7 +290,7 @@ __device__ int min_units(const SetLDS &L, const Tables &tb, MT S, int mp)
     const MT cm = conflict_mask<MT>(S, (MT)L.memmask);
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (test_from<MT>(L, tb, S, 0, mid, cm))
+        if (test_from<MT>(L, tb, S, 0, mid, cm, ty))
             hi = mid;
         else
             lo = mid + 1;
@@ -294,7 +314,8 @@ __device__ uint32_t rta_one(const SetLDS &L, const Tables &tb, int m, int r, MT 
         sat |= (Cj >= L.T[j]);
     }
     if (sat) return 0u;
-    return rta_fp<MT>(L, row, n, base, L.D[r], hp & (MT)L.intf[r], cm);
+    NoTally nt;
+    return rta_fp<MT>(L, row, n, base, L.D[r], hp & (MT)L.intf[r], cm, nt);
 }
 
 template <int KMAX, typename V>
@@ -309,9 +330,9 @@ __device__ __forceinline__ V pick(const V (&a)[KMAX], int p)
 // Heuristic allocation on a fixed partitioning m[0..k) (non-increasing):
 // tasks in decreasing one-unit utilisation, each to the best-ranked part that
 // stays schedulable.  S[p] = rank masks, U[p] = Q32 utilisations.
-template <int KMAX, bool ACT, bool SMS, typename MT>
+template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
-                                          MT (&S)[KMAX], uint64_t (&U)[KMAX])
+                                          MT (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty)
 {
 #pragma unroll
     for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
@@ -329,9 +350,9 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
             if (p >= k || mm > mp) continue;
             if (ACT && (fb & Sp)) continue;
             uint64_t Un;
-            if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un)) continue;
+            if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty)) continue;
             int req = 0;
-            if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp);
+            if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp, ty);
             const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
             if (better) { best = p; bestU = Un; bestReq = req; }
         }
@@ -356,8 +377,8 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 constexpr int FRONT_MAX_N = 14;
 constexpr uint16_t FRONT_NONE = 0xFFFFu;
 
-template <typename MT>
-__device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms)
+template <typename MT, typename TY>
+__device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms, TY &ty)
 {
     const uint32_t NS = 1u << n;
     if (threadIdx.x == 0) ms[0] = 0;
@@ -376,13 +397,13 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
             if (!none) {
                 const MT SM = (MT)S;
                 const MT cm = conflict_mask<MT>(SM, (MT)L.memmask);
-                if (test_from<MT>(L, tb, SM, 0, lo, cm)) {
+                if (test_from<MT>(L, tb, SM, 0, lo, cm, ty)) {
                     res = (uint16_t)lo;
-                } else if (lo < M && test_from<MT>(L, tb, SM, 0, M, cm)) {
+                } else if (lo < M && test_from<MT>(L, tb, SM, 0, M, cm, ty)) {
                     int a = lo + 1, b = M;  // schedulable at b, not at lo
                     while (a < b) {
                         const int mid = (a + b) >> 1;
-                        if (test_from<MT>(L, tb, SM, 0, mid, cm))
+                        if (test_from<MT>(L, tb, SM, 0, mid, cm, ty))
                             b = mid;
                         else
                             a = mid + 1;
@@ -417,9 +438,10 @@ __device__ __forceinline__ uint64_t util_add(const SetLDS &L, const Tables &tb, 
 
 // The heuristic on one fixed partitioning with every candidate test answered
 // by the frontier (same decisions as `heuristic`, which tests directly).
-template <int KMAX, bool ACT, bool SMS, typename MT>
+template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ __forceinline__ bool heuristic_front(const SetLDS &L, const Tables &tb, const uint16_t *ms, int n,
-                                                const int (&m)[KMAX], int k, MT (&S)[KMAX], uint64_t (&U)[KMAX])
+                                                const int (&m)[KMAX], int k, MT (&S)[KMAX], uint64_t (&U)[KMAX],
+                                                TY &ty)
 {
 #pragma unroll
     for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
@@ -432,6 +454,7 @@ __device__ __forceinline__ bool heuristic_front(const SetLDS &L, const Tables &t
 #pragma unroll
         for (int p = 0; p < KMAX; p++) {
             if (p >= k) continue;
+            ty.look();
             const MT Sp = S[p];
             const int req = (int)ms[(uint32_t)(Sp | bit)];
             if (req > m[p]) continue;
@@ -670,9 +693,9 @@ __device__ __forceinline__ int size_of(uint64_t mpack, int p) { return (int)((mp
 // Per-lane part state (rank masks and utilisations) lives in LDS, lane-
 // interleaved (entry p of lane l at p * blockDim + l), so that the
 // data-dependent part index costs one conflict-free LDS access.
-template <int KMAX, bool ACT, bool SMS, typename MT>
+template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K, uint32_t q0,
-                         uint32_t q1, Key &best, uint64_t *dbg, MT *lS, uint64_t *lU)
+                         uint32_t q1, Key &best, uint64_t *dbg, MT *lS, uint64_t *lU, TY &ty)
 {
     const int stride = blockDim.x;
     MT *myS = lS + threadIdx.x;
@@ -695,9 +718,9 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
             const int mp = size_of(mpack, p);
             const MT Sp = myS[p * stride];
             uint64_t Un;
-            if (part_test_add<MT>(L, tb, Sp, tau, mp, myU[p * stride], &Un)) {
+            if (part_test_add<MT>(L, tb, Sp, tau, mp, myU[p * stride], &Un, ty)) {
                 int req = 0;
-                if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << tau), mp);
+                if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << tau), mp, ty);
                 const bool better = (bp < 0) || (SMS ? (req < breq || (req == breq && Un < bu)) : (Un < bu));
                 if (better) { bp = p; bu = Un; breq = req; }
             }
@@ -746,16 +769,16 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
 
 // Loop form 1: one loop step per partitioning (the heuristic of one
 // partitioning runs to completion, parts unrolled over registers).
-template <int KMAX, bool ACT, bool SMS, typename MT>
+template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
-                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg)
+                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
 {
     int m[KMAX];
     int k = unrank<KMAX>(np, M, K, q0, m);
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
-        const bool ok = heuristic<KMAX, ACT, SMS, MT>(L, tb, n, m, k, S, U);
+        const bool ok = heuristic<KMAX, ACT, SMS, MT>(L, tb, n, m, k, S, U, ty);
         uint64_t mx = 0, sm = 0;
         if (ok) {
 #pragma unroll
@@ -774,16 +797,16 @@ __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_
     }
 }
 
-template <int KMAX, bool ACT, bool SMS, typename MT>
+template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t *ms, const uint32_t *np, int n, int M,
-                               int K, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg)
+                               int K, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
 {
     int m[KMAX];
     int k = unrank<KMAX>(np, M, K, q0, m);
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
-        const bool ok = heuristic_front<KMAX, ACT, SMS, MT>(L, tb, ms, n, m, k, S, U);
+        const bool ok = heuristic_front<KMAX, ACT, SMS, MT>(L, tb, ms, n, m, k, S, U, ty);
         uint64_t mx = 0, sm = 0;
         if (ok) {
 #pragma unroll
@@ -805,9 +828,9 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
 // Evaluate partitionings [p0, p1) of one staged set in this block (all
 // lanes): through the frontier when the set is small enough, else with
 // direct incremental tests.
-template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, typename TY>
 __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, const uint32_t *np, int n, int M,
-                           uint32_t p0, uint32_t p1, uint32_t p_lo, uint32_t p_hi, Key &best, uint64_t *dbg)
+                           uint32_t p0, uint32_t p1, uint32_t p_lo, uint32_t p_hi, Key &best, uint64_t *dbg, TY &ty)
 {
     const uint32_t cnt = p1 - p0;
     const uint32_t per = (cnt + blockDim.x - 1) / blockDim.x;
@@ -816,26 +839,27 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
     q1 = min(q1, p_hi);
     if (Lp.front_n > 0 && n <= Lp.front_n) {
         uint16_t *ms = (uint16_t *)(capart_dyn_lds + Lp.table_words);
-        build_frontier<MT>(L, tb, n, M, ms);
-        if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg);
+        build_frontier<MT>(L, tb, n, M, ms, ty);
+        if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg, ty);
         return;
     }
     if (q0 >= q1) return;
     if (FORM == 2) {
         uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words + Lp.front_words);
         MT *lS = (MT *)(lU + KMAX * blockDim.x);
-        heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, lS, lU);
+        heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, lS, lU, ty);
     } else {
-        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg);
+        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty);
     }
 }
 
-template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, bool COUNT = false>
 __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
+    typename std::conditional<COUNT, Tally, NoTally>::type ty;
     const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
     const int c = blockIdx.x % Lp.chunks;
     const uint32_t f = w.setflags[s];
@@ -852,7 +876,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (!(f & SETF_LEMMA1)) {
         Tables tb;
         stage_set(L, w, off, n, M, s, ACT, tb);
-        eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, p0, p1, p_lo, p_hi, best, dbg);
+        eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, p0, p1, p_lo, p_hi, best, dbg, ty);
     } else if (dbg) {
         for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
             if (q < p_lo || q >= p_hi) continue;
@@ -864,6 +888,20 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (threadIdx.x == 0) {
         uint64_t *dst = w.partial + 4 * ((s) * (int64_t)Lp.chunks + c);
         dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+    }
+    if constexpr (COUNT) {
+        uint64_t a = ty.terms, bb = ty.tests, cc = ty.looks;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+            a += __shfl_xor(a, o2, 64);
+            bb += __shfl_xor(bb, o2, 64);
+            cc += __shfl_xor(cc, o2, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && w.counters) {
+            atomicAdd((unsigned long long *)&w.counters[0], (unsigned long long)a);
+            atomicAdd((unsigned long long *)&w.counters[1], (unsigned long long)bb);
+            atomicAdd((unsigned long long *)&w.counters[2], (unsigned long long)cc);
+        }
     }
 }
 
@@ -900,7 +938,8 @@ __global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, O
                 stage_set(L, w, off, n, M, s, ACT, tb);
                 staged = s;
             }
-            eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg);
+            NoTally nt;
+            eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg, nt);
         } else if (dbg && (f & SETF_VALID)) {
             for (uint32_t q = wi.p0 + threadIdx.x; q < wi.p1; q += blockDim.x) {
                 uint64_t *d = dbg + 3 * (uint64_t)q;
@@ -960,7 +999,8 @@ __global__ __launch_bounds__(256) void eval_exh_kernel(Batch b, Work w, Out o, L
             for (int p = 0; p < KMAX; p++) {
                 if (ok && p < k && S[p]) {
                     uint64_t u;
-                    if (!part_test<uint64_t>(L, tb, S[p], m[p], &u)) {
+                    NoTally nt;
+                    if (!part_test<uint64_t>(L, tb, S[p], m[p], &u, nt)) {
                         ok = false;
                     } else {
                         mx = max(mx, u);
@@ -1053,11 +1093,12 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
                     if (p == d) S[p] |= 1ull << L.rank_of[i];
             }
         } else {
+            NoTally nt;
             switch (Lp.mode) {
-            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false, uint64_t>(L, tb, n, m, k, S, U); break;
-            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false, uint64_t>(L, tb, n, m, k, S, U); break;
-            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true, uint64_t>(L, tb, n, m, k, S, U); break;
-            default: heuristic<KMAX, true, true, uint64_t>(L, tb, n, m, k, S, U); break;
+            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false, uint64_t>(L, tb, n, m, k, S, U, nt); break;
+            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false, uint64_t>(L, tb, n, m, k, S, U, nt); break;
+            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true, uint64_t>(L, tb, n, m, k, S, U, nt); break;
+            default: heuristic<KMAX, true, true, uint64_t>(L, tb, n, m, k, S, U, nt); break;
             }
         }
 #pragma unroll
@@ -1135,7 +1176,8 @@ __global__ __launch_bounds__(256) void subset_table_kernel(Batch b, Work w, Laun
         uint32_t RA = 0;
         for (uint32_t a = A; a; a &= a - 1u) RA |= 1u << L.rank_of[__builtin_ctz(a)];
         uint64_t u = 0;
-        dst[A] = part_test<uint32_t>(L, tb, RA, m, &u) ? u : ~0ull;
+        NoTally nt;
+        dst[A] = part_test<uint32_t>(L, tb, RA, m, &u, nt) ? u : ~0ull;
     }
 }
 
@@ -1446,6 +1488,37 @@ int device_cu_count()
     return cus;
 }
 
+template <int KMAX, typename MT>
+static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
+    const size_t lds = heur_dyn_bytes<KMAX, MT>(L, 1);
+    const uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+    switch (L.mode) {
+    case CAPART_HEUR_BF_INA:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        break;
+    case CAPART_HEUR_BF_ACT:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        break;
+    case CAPART_HEUR_SMS_INA:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        break;
+    default:
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_count(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    if (L.S <= 0 || L.mode == CAPART_EXHAUSTIVE) return hipSuccess;
+    if (b.max_tasks <= 32)
+        return L.K <= 4 ? launch_count_k<4, uint32_t>(b, w, o, L, st) : launch_count_k<8, uint32_t>(b, w, o, L, st);
+    return L.K <= 4 ? launch_count_k<4, uint64_t>(b, w, o, L, st) : launch_count_k<8, uint64_t>(b, w, o, L, st);
+}
+
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
                              uint32_t p_lo, uint32_t p_hi)
 {
@@ -1582,6 +1655,22 @@ hipError_t configure_kernels()
     CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 2>));
     CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 2>));
     CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 2>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 1, true>));
+    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 1, true>));
     CAPART_ALLOW((subset_table_kernel));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
