@@ -86,6 +86,22 @@ def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1):
             "sets": sub.n_sets}
 
 
+def lemma1_pruned(ts):
+    """Sets that the whole-GPU utilisation bound rejects before any partitioning
+    is tried (Lemma 1, floor-Q32 sum of one-unit utilisations above M), computed
+    exactly in int64: floor(Cn*2^32/T) = (Cn//T)*2^32 + floor((Cn%T)*2^32/T),
+    each term clamped above M*2^32 so the per-set sums cannot overflow."""
+    import numpy as np
+    cn = ts["C_seq"] + ts["C_par"]
+    T = ts["T"]
+    q, r = cn // T, cn % T
+    cap = (int(ts["M"].max()) + 1) << 32
+    term = np.minimum(q, cap >> 32) * (1 << 32) + (r << 32) // T
+    term = np.minimum(term, cap)
+    sums = np.add.reduceat(term, ts["set_offset"][:-1])
+    return int((sums > ts["M"].astype(np.int64) << 32).sum())
+
+
 def timed(fn, steps, sync):
     sync()
     t0 = time.perf_counter()
@@ -114,8 +130,8 @@ def serving_leg(eng, capart, workload, rate, n_queries, seed=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
     ap.add_argument("--n-sets", type=int, default=0, help="override the workload's number of sets")
@@ -140,8 +156,8 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the engine shards task sets independently and this build "
-              "runs no multi-GPU configuration (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: task sets would shard independently across GPUs, but no "
+              "multi-GPU configuration is measured (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -239,6 +255,28 @@ def main():
         del wout
         log(f"[bench] counted work per step: {work}")
 
+    # end to end: host (pinned) inputs copied in, one step, results copied out;
+    # reported beside `value`, which keeps the inputs resident
+    pinned_in = {k: v.cpu().pin_memory() for k, v in dev.items()}
+    pinned_out = {k: torch.empty(v.shape, dtype=v.dtype).pin_memory() for k, v in out.items()}
+
+    def e2e_step():
+        for k, v in pinned_in.items():
+            dev[k].copy_(v, non_blocking=True)
+        step()
+        for k, v in out.items():
+            pinned_out[k].copy_(v, non_blocking=True)
+
+    e2e_step()
+    sync()
+    e2e_ms = timed(e2e_step, max(2, args.steps // 2), sync)
+    in_bytes = sum(v.numel() * v.element_size() for v in pinned_in.values())
+    out_bytes = sum(v.numel() * v.element_size() for v in pinned_out.values())
+    end_to_end = {"ms_per_step": e2e_ms, "value": evals_per_step / (e2e_ms / 1000.0), "h2d_bytes": in_bytes,
+                  "d2h_bytes": out_bytes}
+    log(f"[bench] end to end with copies: {e2e_ms:.2f} ms/step")
+    del pinned_in, pinned_out
+
     compare = {}
     if not args.no_compare and args.form == "batched" and plan is not None:
         plain_ms = timed(plain_step, max(2, args.steps // 2), sync)
@@ -303,8 +341,8 @@ def main():
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {ts.n_sets} task sets, {desc}, K={K}, {mode}, {form}",
                       "n_sets": ts.n_sets, "K": K, "alloc_mode": mode, "evals_per_step": evals_per_step,
-                      "schedulable_sets": verdicts, "plan": plan_info},
-           "compare": compare, "serving": serving, "roofline": roof, "cpu_baseline": cpu}
+                      "schedulable_sets": verdicts, "lemma1_pruned_sets": lemma1_pruned(ts), "plan": plan_info},
+           "end_to_end_with_copies": end_to_end, "compare": compare, "serving": serving, "roofline": roof, "cpu_baseline": cpu}
     if plan is not None:
         plan.close()
     eng.close()
