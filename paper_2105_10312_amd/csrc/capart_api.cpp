@@ -21,7 +21,8 @@ struct capart_ctx {
     int device = 0;
     std::string err;
     std::vector<uint32_t> np_host;
-    uint32_t *np_dev = nullptr;
+    uint32_t *np_dev = nullptr;    // partition-count table, followed by the subset order table
+    uint16_t *order_dev = nullptr;
     hipStream_t stream = nullptr;  // for host-pointer calls
     void *ws = nullptr;            // workspace
     size_t ws_bytes = 0;
@@ -76,6 +77,23 @@ const std::vector<uint32_t> &host_np()
 {
     static std::vector<uint32_t> tab;
     if (tab.empty()) build_np(tab);
+    return tab;
+}
+
+// Subsets of {0..n-1} ordered by size, then value, for n = 1..FRONTIER_MAX_TASKS
+// one after the other (the list for n starts at entry 2^n - 2 with the empty set).
+const std::vector<uint16_t> &host_subset_order()
+{
+    static std::vector<uint16_t> tab;
+    if (tab.empty()) {
+        for (int n = 1; n <= FRONTIER_MAX_TASKS; n++) {
+            std::vector<uint16_t> v(1u << n);
+            for (uint32_t s = 0; s < (1u << n); s++) v[s] = (uint16_t)s;
+            std::stable_sort(v.begin(), v.end(),
+                             [](uint16_t a, uint16_t b) { return __builtin_popcount(a) < __builtin_popcount(b); });
+            tab.insert(tab.end(), v.begin(), v.end());
+        }
+    }
     return tab;
 }
 
@@ -342,6 +360,7 @@ capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &
     w.memmask = (uint64_t *)(base + l.memmask);
     w.partial = (uint64_t *)(base + l.partial);
     w.np = c->np_dev;
+    w.order = c->order_dev;
     if (p.L.flags & CAPART_FLAG_PER_SET_LAUNCH) {
         for (int64_t s = 0; s < p.S; s++) {
             Launch L1 = p.L;
@@ -444,12 +463,16 @@ capart_status capart_create(int device, capart_ctx **out)
         return CAPART_E_DEVICE;
     }
     const std::vector<uint32_t> &np = host_np();
-    if ((e = hipMalloc(&c->np_dev, np.size() * sizeof(uint32_t))) != hipSuccess) {
+    const std::vector<uint16_t> &ord = host_subset_order();
+    const size_t np_bytes = np.size() * sizeof(uint32_t), ord_bytes = ord.size() * sizeof(uint16_t);
+    if ((e = hipMalloc(&c->np_dev, np_bytes + ord_bytes)) != hipSuccess) {
         g_create_err = "count table allocation failed";
         delete c;
         return CAPART_E_NOMEM;
     }
-    if ((e = hipMemcpy(c->np_dev, np.data(), np.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+    c->order_dev = (uint16_t *)((char *)c->np_dev + np_bytes);
+    if ((e = hipMemcpy(c->np_dev, np.data(), np_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->order_dev, ord.data(), ord_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipStreamCreate(&c->stream)) != hipSuccess) {
         g_create_err = std::string("context setup: ") + hipGetErrorString(e);
         hipFree(c->np_dev);
@@ -697,6 +720,7 @@ capart_status capart_test_triple(capart_ctx *c, const capart_tasksets *one, cons
     w.memmask = (uint64_t *)(base + l.memmask);
     w.partial = (uint64_t *)(base + l.partial);
     w.np = c->np_dev;
+    w.order = c->order_dev;
     Out o{};
     o.status = d_status;
     const Batch b = make_batch(&d);
@@ -787,6 +811,7 @@ capart_status capart_count_work(capart_ctx *c, const capart_tasksets *in, const 
     w.memmask = (uint64_t *)(base + l.memmask);
     w.partial = (uint64_t *)(base + l.partial);
     w.np = c->np_dev;
+    w.order = c->order_dev;
     w.counters = (uint64_t *)(base + l.total);
     hipStream_t st = (hipStream_t)hip_stream;
     const Batch b = make_batch(in);
@@ -971,6 +996,7 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     pb.w.counter = (uint32_t *)(base + l.counter);
     pb.w.slot_off = (const uint32_t *)(base + l.slot_off);
     pb.w.np = c->np_dev;
+    pb.w.order = c->order_dev;
     if (!items.empty() &&
         (e = hipMemcpy(base + l.items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice)) !=
             hipSuccess)
@@ -1418,6 +1444,7 @@ void launch_batch(capart_server *v, int i)
     w.memmask = v->memmask + slot0;
     w.partial = v->partial + 4 * (size_t)slot0 * v->L.chunks;
     w.np = v->ctx->np_dev;
+    w.order = v->ctx->order_dev;
     Out o{};
     char *od = ss.out_dev;
     o.status = (int32_t *)(od + lo.status);

@@ -52,6 +52,8 @@ struct Work {            // device workspace owned by the context
     uint64_t *memmask;   // [S] memory-intensive ranks
     uint64_t *partial;   // [S * CH * 4] best key per (set, chunk), or per item slot
     const uint32_t *np;  // partition-count table
+    const uint16_t *order;  // subsets of {0..n-1} by size then value, n = 1..FRONTIER_MAX_TASKS,
+                            // the list for n at entry 2^n - 2 (frontier build)
     // batched form only
     const WorkItem *items;     // [n_items], largest first
     uint32_t n_items;

@@ -377,44 +377,97 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 constexpr int FRONT_MAX_N = 14;
 constexpr uint16_t FRONT_NONE = 0xFFFFu;
 
+// Lanes that search one subset's fewest units together (k-ary search).
+constexpr int FRONT_GROUP = 16;
+
+// Fill ms[] level by level (subsets of equal size, taken in the order of the
+// host-built list `order`: subsets of {0..n-1} by size, then value).
+// For S with lowest-priority member r (largest rank) and S' = S - {r}:
+// lo = max(ms of the subsets with one member less, m_min of r) bounds ms[S]
+// from below, and S is schedulable on m >= lo units iff the members whose
+// response times can differ from those in S' pass: r alone, or, when r makes
+// the single member j of its type in S' conflict, j and every member below j.
+// Phase 1 gives each lane one subset and tests it at lo; the subsets that
+// fail there are searched in phase 2 by groups of FRONT_GROUP lanes, each
+// round testing FRONT_GROUP evenly spaced sizes of the open interval (a, b)
+// with a failing and b passing (b = M + 1 stands for "none").
 template <typename MT, typename TY>
-__device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms, TY &ty)
+__device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms,
+                               const uint16_t *order, TY &ty)
 {
-    const uint32_t NS = 1u << n;
-    if (threadIdx.x == 0) ms[0] = 0;
-    __syncthreads();
+    __shared__ uint32_t fails[256];
+    __shared__ uint32_t nfail[2];  // alternate chunks: one is cleared while the other is read
+    const uint16_t *ord = order + ((1u << n) - 2u);
+    const MT memm = (MT)L.memmask;
+    if (threadIdx.x == 0) { ms[0] = 0; nfail[0] = 0u; nfail[1] = 0u; }
+    uint32_t cur = 0;
+    uint32_t lvl_off = 1, lvl_cnt = (uint32_t)n;  // level 1 follows the empty set
     for (int c = 1; c <= n; c++) {
-        for (uint32_t S = threadIdx.x; S < NS; S += blockDim.x) {
-            if (__popc(S) != c) continue;
-            int lo = 1;
-            bool none = false;
-            for (uint32_t h = S; h; h &= h - 1u) {
-                const uint16_t v = ms[S & ~(h & (0u - h))];
-                none |= (v == FRONT_NONE);
-                lo = max(lo, (int)v);
-            }
-            uint16_t res = FRONT_NONE;
-            if (!none) {
-                const MT SM = (MT)S;
-                const MT cm = conflict_mask<MT>(SM, (MT)L.memmask);
-                if (test_from<MT>(L, tb, SM, 0, lo, cm, ty)) {
-                    res = (uint16_t)lo;
-                } else if (lo < M && test_from<MT>(L, tb, SM, 0, M, cm, ty)) {
-                    int a = lo + 1, b = M;  // schedulable at b, not at lo
-                    while (a < b) {
-                        const int mid = (a + b) >> 1;
-                        if (test_from<MT>(L, tb, SM, 0, mid, cm, ty))
-                            b = mid;
-                        else
-                            a = mid + 1;
-                    }
-                    res = (uint16_t)a;
+        for (uint32_t base = 0; base < lvl_cnt; base += blockDim.x, cur ^= 1u) {
+            __syncthreads();  // orders the previous chunk's ms[] writes and counter reads before what follows
+            if (threadIdx.x == 0) nfail[cur ^ 1u] = 0u;
+            const uint32_t i = base + threadIdx.x;
+            if (i < lvl_cnt) {
+                const uint32_t S = ord[lvl_off + i];
+                const int r = 31 - __clz(S);
+                int lo = max(1, (int)L.mmin[r]);
+                bool none = lo > M;
+                for (uint32_t h = S; h; h &= h - 1u) {
+                    const uint16_t v = ms[S & ~(h & (0u - h))];
+                    none |= (v == FRONT_NONE);
+                    lo = max(lo, (int)v);
                 }
+                uint16_t res = FRONT_NONE;
+                if (!none) {
+                    const MT SM = (MT)S;
+                    const MT Sp = SM & ~(MT(1) << r);
+                    const MT same = Sp & (mbit(memm, r) ? memm : ~memm);
+                    const int first = (mpopc(same) == 1) ? mctz(same) : r;
+                    const MT cm = conflict_mask<MT>(SM, memm);
+                    if (test_from<MT>(L, tb, SM, first, lo, cm, ty)) {
+                        res = (uint16_t)lo;
+                    } else if (lo < M) {
+                        res = 0u;  // searched in phase 2
+                        fails[atomicAdd(&nfail[cur], 1u)] = S | ((uint32_t)first << 16) | ((uint32_t)lo << 20);
+                    }
+                }
+                if (res) ms[S] = res;
             }
-            ms[S] = res;
+            __syncthreads();
+            const uint32_t F = nfail[cur];
+            const int groups = blockDim.x / FRONT_GROUP;
+            const int g = threadIdx.x / FRONT_GROUP, li = threadIdx.x % FRONT_GROUP;
+            const int shift = (threadIdx.x & 63) & ~(FRONT_GROUP - 1);
+            for (uint32_t f = g; f < F; f += groups) {
+                const uint32_t e = fails[f];
+                const uint32_t S = e & 0xFFFFu;
+                const int first = (int)((e >> 16) & 0xFu);
+                const MT SM = (MT)S;
+                const MT cm = conflict_mask<MT>(SM, memm);
+                int a = (int)(e >> 20), b = M + 1;  // fails at a; passes at b (or none if b = M + 1)
+                while (b - a > 1) {
+                    const int span = b - a;
+                    const bool dense = span - 1 <= FRONT_GROUP;
+                    const int x = dense ? a + 1 + li : a + ((li + 1) * span) / (FRONT_GROUP + 1);
+                    const bool pass = x < b && test_from<MT>(L, tb, SM, first, x, cm, ty);
+                    const uint32_t gm = (uint32_t)(__ballot(pass) >> shift) & ((1u << FRONT_GROUP) - 1u);
+                    if (gm) {
+                        const int fl = __ffs(gm) - 1;
+                        const int xf = dense ? a + 1 + fl : a + ((fl + 1) * span) / (FRONT_GROUP + 1);
+                        const int xp = fl == 0 ? a : (dense ? a + fl : a + (fl * span) / (FRONT_GROUP + 1));
+                        a = xp;
+                        b = xf;
+                    } else {
+                        a = dense ? b - 1 : a + (FRONT_GROUP * span) / (FRONT_GROUP + 1);
+                    }
+                }
+                if (li == 0) ms[S] = (b > M) ? FRONT_NONE : (uint16_t)b;
+            }
         }
-        __syncthreads();
+        lvl_off += lvl_cnt;
+        lvl_cnt = lvl_cnt * (uint32_t)(n - c) / (uint32_t)(c + 1);
     }
+    __syncthreads();
 }
 
 // Q32 utilisation of S_old + {tau} on m units from that of S_old (the new
@@ -829,7 +882,8 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
 // lanes): through the frontier when the set is small enough, else with
 // direct incremental tests.
 template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, typename TY>
-__device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, const uint32_t *np, int n, int M,
+__device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, const uint32_t *np,
+                           const uint16_t *order, int n, int M,
                            uint32_t p0, uint32_t p1, uint32_t p_lo, uint32_t p_hi, Key &best, uint64_t *dbg, TY &ty)
 {
     const uint32_t cnt = p1 - p0;
@@ -839,7 +893,7 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
     q1 = min(q1, p_hi);
     if (Lp.front_n > 0 && n <= Lp.front_n) {
         uint16_t *ms = (uint16_t *)(capart_dyn_lds + Lp.table_words);
-        build_frontier<MT>(L, tb, n, M, ms, ty);
+        build_frontier<MT>(L, tb, n, M, ms, order, ty);
         if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg, ty);
         return;
     }
@@ -876,7 +930,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (!(f & SETF_LEMMA1)) {
         Tables tb;
         stage_set(L, w, off, n, M, s, ACT, tb);
-        eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, p0, p1, p_lo, p_hi, best, dbg, ty);
+        eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, w.order, n, M, p0, p1, p_lo, p_hi, best, dbg, ty);
     } else if (dbg) {
         for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
             if (q < p_lo || q >= p_hi) continue;
@@ -939,7 +993,7 @@ __global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, O
                 staged = s;
             }
             NoTally nt;
-            eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg, nt);
+            eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, w.order, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg, nt);
         } else if (dbg && (f & SETF_VALID)) {
             for (uint32_t q = wi.p0 + threadIdx.x; q < wi.p1; q += blockDim.x) {
                 uint64_t *d = dbg + 3 * (uint64_t)q;
