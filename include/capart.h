@@ -220,9 +220,11 @@ capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in,
  * use_graph the prep, evaluation and final kernels are captured into a HIP
  * graph; capart_run_batch then costs one graph launch.  With autotune the plan
  * times candidate tunings (threads per block, loop form, item size, blocks per
- * compute unit) on a prefix of the batch and keeps the fastest; every candidate
- * computes identical results.  Autotuning runs the path on that prefix and so
- * writes into the result buffers.  The plan owns its workspace; the caller
+ * compute unit) on a prefix of the batch (1/64 of it, at least 2048 sets) and
+ * keeps the fastest, spending at most about 5 s; every candidate computes
+ * identical results.  Sets whose frontier or test memo serves all of their
+ * partitionings form one item each.  Autotuning runs the path on that prefix
+ * and so writes into the result buffers.  The plan owns its workspace; the caller
  * keeps the bound buffers alive and unchanged in size while the plan exists.
  * Results are those of capart_solve_async on the same batch, bit for bit.
  * Exhaustive mode is not batched this way (E_INVAL).
@@ -312,7 +314,10 @@ capart_status capart_server_destroy(capart_server *srv);
  * partitionings per evaluation block, 0 = automatic (enough blocks to fill the
  * chip); loop_form: 0 = automatic, 1 = each lane runs the heuristic of one
  * partitioning per loop step, 2 = each loop step is one candidate test (a lane
- * that finishes a partitioning continues with its next one at the next step).
+ * that finishes a partitioning continues with its next one at the next step),
+ * 3 = as 1, but sets served by the test memo run a state machine in which
+ * lanes advance through memo answers and run the tests the memo cannot answer
+ * together (K <= 4; otherwise as 1).
  * exh_form (exhaustive mode): 0 = automatic, 1 = every block enumerates all
  * k^n allocations of one partitioning, 2 = per-set subset tables of partition
  * utilisation (every task subset on every size) and a depth-first search in
@@ -321,7 +326,13 @@ capart_status capart_server_destroy(capart_server *srv);
  * 1 = on, 2 = off; when on, a set of at most 14 tasks first gets its
  * feasibility frontier (for every task subset, the fewest units that schedule
  * it, by exact tests) and every candidate test of the heuristic on every
- * partitioning becomes a lookup in it.  NULL restores the automatic choices.
+ * partitioning becomes a lookup in it.  memo (heuristic modes, loop form 1,
+ * sets of more tasks than the frontier takes and at most 32): 0 = automatic
+ * (2^11 entries, fewer if the LDS is short), -1 = off, 8..13 = log2 of the
+ * entries of a per-set table in LDS that records, for each task subset met,
+ * the largest size known to fail and the smallest known to pass, so that
+ * repeated candidate tests across partitionings become lookups.  NULL
+ * restores the automatic choices.
  * E_INVAL for values out of range. */
 typedef struct capart_tuning {
     int32_t threads;
@@ -329,7 +340,8 @@ typedef struct capart_tuning {
     int32_t loop_form;
     int32_t exh_form;
     int32_t frontier;
-    int32_t reserved[3];  /* must be 0 */
+    int32_t memo;
+    int32_t reserved[2];  /* must be 0 */
 } capart_tuning;
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);

@@ -52,7 +52,7 @@ class capart_results(C.Structure):
 
 class capart_tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("exh_form", C.c_int32),
-                ("frontier", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("frontier", C.c_int32), ("memo", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class capart_plan_config(C.Structure):
@@ -346,8 +346,8 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
 
 
 def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0,
-                      frontier: int = 0) -> None:
-    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier))
+                      frontier: int = 0, memo: int = 0) -> None:
+    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier), int(memo))
     _check(load_library().capart_set_tuning(ctx, C.byref(t)), ctx)
 
 
@@ -355,7 +355,7 @@ def capart_get_tuning(ctx) -> dict:
     t = capart_tuning()
     _check(load_library().capart_get_tuning(ctx, C.byref(t)), ctx)
     return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form, "exh_form": t.exh_form,
-            "frontier": t.frontier}
+            "frontier": t.frontier, "memo": t.memo}
 
 
 def capart_timing_enable(ctx, enable: bool = True) -> None:

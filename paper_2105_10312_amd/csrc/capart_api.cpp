@@ -216,19 +216,29 @@ int32_t validate_set(const capart_tasksets *in, int64_t s, int K, int mode)
     return CAPART_OK;
 }
 
-// Frontier region: 2^front_n u16 after the tables, shrunk until tables,
-// frontier and (loop form 2) per-lane state fit the LDS next to the static
-// per-set arrays.
+// LDS regions after the tables: the frontier (2^front_n u16), shrunk until
+// tables, frontier and (loop form 2) per-lane state fit the LDS next to the
+// static per-set arrays; then (loop form 1) the test memo for the sets above
+// the frontier limit, shrunk likewise.
 void size_frontier(Launch &L, int max_tasks, int mode, const capart_tuning &tu)
 {
     L.front_n = 0;
     L.front_words = 0;
-    if (mode == CAPART_EXHAUSTIVE || tu.frontier == 2) return;
-    int fn = std::min(max_tasks, FRONTIER_MAX_TASKS);
-    const size_t lane = L.form == 2 ? (size_t)L.threads * 8 * 16 : 0;
-    while (fn > 0 && (size_t)4 * L.table_words + ((size_t)2 << fn) + lane > (size_t)150 * 1024) fn--;
-    L.front_n = fn;
-    L.front_words = fn > 0 ? (1 << fn) / 2 : 0;
+    L.memo_log2 = 0;
+    if (mode == CAPART_EXHAUSTIVE) return;
+    if (tu.frontier != 2) {
+        int fn = std::min(max_tasks, FRONTIER_MAX_TASKS);
+        const size_t lane = L.form == 2 ? (size_t)L.threads * 8 * 16 : 0;
+        while (fn > 0 && (size_t)4 * L.table_words + ((size_t)2 << fn) + lane > (size_t)150 * 1024) fn--;
+        L.front_n = fn;
+        L.front_words = fn > 0 ? (1 << fn) / 2 : 0;
+    }
+    if (L.form != 1 || tu.memo < 0 || max_tasks <= L.front_n) return;
+    int lg = tu.memo > 0 ? tu.memo : MEMO_DEFAULT_LOG2;
+    while (lg >= 8 && (size_t)4 * L.table_words + std::max((size_t)4 * L.front_words, (size_t)8 << lg) >
+                          (size_t)150 * 1024)
+        lg--;
+    L.memo_log2 = lg >= 8 ? lg : 0;
 }
 
 struct Plan {
@@ -250,7 +260,8 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
     L.threads = eval_threads(in->max_tasks, in->max_M);
     if (tu.threads > 0) L.threads = std::min(L.threads, tu.threads);
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
-    L.form = tu.loop_form > 0 ? tu.loop_form : 1;
+    L.form = tu.loop_form == 2 ? 2 : 1;
+    L.memo_packed = tu.loop_form == 3;
     // exhaustive: subset tables + pruned search when sets are small enough
     size_frontier(L, in->max_tasks, opt->alloc_mode, tu);
     L.exh_form = (opt->K <= 4 && in->max_tasks <= SUBSET_MAX_TASKS) ? 2 : 1;
@@ -273,7 +284,8 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
         ch = std::max<int64_t>(1, std::min(std::max(ch, ch_fill), chmax));
         // frontier sets: the frontier is built once per block, so keep one
         // block per set when there are enough sets to fill the chip
-        if (L.front_n > 0 && in->max_tasks <= L.front_n) ch = std::max<int64_t>(1, std::min(ch_fill, chmax));
+        if ((L.front_n > 0 && in->max_tasks <= L.front_n) || (L.memo_log2 > 0 && in->max_tasks <= MEMO_MAX_TASKS))
+            ch = std::max<int64_t>(1, std::min(ch_fill, chmax));
         L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
         if (tu.chunk > 0) L.chunk = std::min<uint32_t>((uint32_t)tu.chunk, std::max<uint32_t>(Pmax, 1));
         L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
@@ -839,10 +851,12 @@ capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
     if (t->threads < 0 || t->threads > 256 || (t->threads % 64) != 0)
         return fail(c, CAPART_E_INVAL, "threads must be 0 or a multiple of 64 up to 256");
     if (t->chunk < 0) return fail(c, CAPART_E_INVAL, "chunk must be >= 0");
-    if (t->loop_form < 0 || t->loop_form > 2) return fail(c, CAPART_E_INVAL, "loop_form must be 0, 1 or 2");
+    if (t->loop_form < 0 || t->loop_form > 3) return fail(c, CAPART_E_INVAL, "loop_form must be 0, 1, 2 or 3");
     if (t->exh_form < 0 || t->exh_form > 2) return fail(c, CAPART_E_INVAL, "exh_form must be 0, 1 or 2");
     if (t->frontier < 0 || t->frontier > 2) return fail(c, CAPART_E_INVAL, "frontier must be 0, 1 or 2");
-    if (t->reserved[0] || t->reserved[1] || t->reserved[2]) return fail(c, CAPART_E_INVAL, "reserved must be 0");
+    if (t->reserved[0] || t->reserved[1]) return fail(c, CAPART_E_INVAL, "reserved must be 0");
+    if (t->memo != 0 && t->memo != -1 && (t->memo < 8 || t->memo > MEMO_MAX_LOG2))
+        return fail(c, CAPART_E_INVAL, "memo must be 0, -1 or 8..13");
     c->tune = *t;
     return CAPART_OK;
 }
@@ -927,7 +941,7 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
     l.partial = take(32 * (size_t)n_items);
     l.items = take(sizeof(WorkItem) * (size_t)n_items);
     l.slot_off = take(4 * (size_t)(S + 1));
-    l.counter = take(4);
+    l.counter = take(8);
     l.total = o;
     return l;
 }
@@ -935,9 +949,20 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
 // Work items: each set's partitionings cut into ranges of about
 // item_evals * 121 / (n+1)^2 partitionings (the response-time work of a
 // partitioning grows roughly with n^2), queued by decreasing estimated cost.
+// Sets of at most this many tasks go to one work item each (their frontier or
+// test memo then serves all of their partitionings).
+int single_item_n(const Launch &L) { return std::max(L.front_n, L.memo_log2 > 0 ? MEMO_MAX_TASKS : 0); }
+
+// Sets of at most split_n tasks (0 = no split) are queued apart, ahead of
+// the others (they are evaluated by a launch of their own).
+int split_n_of(const Launch &L, const capart_tasksets *in)
+{
+    return (L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && in->max_tasks > L.front_n) ? L.front_n : 0;
+}
+
 void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M, int64_t S, const capart_tasksets *in,
-                 int K, int item_evals, int front_n, std::vector<WorkItem> &items, std::vector<uint32_t> &slot_off,
-                 int64_t &total_evals)
+                 int K, int item_evals, int single_n, int split_n, std::vector<WorkItem> &items,
+                 std::vector<uint32_t> &slot_off, int64_t &total_evals, uint32_t &n_front)
 {
     items.clear();
     slot_off.assign((size_t)S + 1, 0u);
@@ -954,7 +979,8 @@ void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M,
         total_evals += P;
         const uint64_t w = (uint64_t)(n + 1) * (uint64_t)(n + 1);
         uint32_t per = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(1u << 20, (uint64_t)item_evals * 121 / w));
-        if (n <= front_n) per = std::max<uint32_t>(P, 1);  // one item: the frontier is built once
+        // one item per set when its frontier or memo is built once for all partitionings
+        if (n <= single_n) per = std::max<uint32_t>(P, 1);
         for (uint32_t p0 = 0; p0 < P; p0 += per) {
             const uint32_t p1 = std::min(P, p0 + per);
             items.push_back(WorkItem{(uint32_t)s, p0, p1, (uint32_t)items.size()});
@@ -963,8 +989,16 @@ void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M,
     }
     slot_off[S] = (uint32_t)items.size();
     std::vector<uint32_t> order(items.size());
-    for (size_t i = 0; i < order.size(); i++) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    std::vector<uint8_t> cls(items.size());
+    n_front = 0;
+    for (size_t i = 0; i < order.size(); i++) {
+        order[i] = (uint32_t)i;
+        const int64_t s = items[i].set;
+        cls[i] = (split_n > 0 && off[s + 1] - off[s] > split_n) ? 1 : 0;
+        n_front += split_n > 0 && cls[i] == 0;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return cls[a] != cls[b] ? cls[a] < cls[b] : cost[a] > cost[b]; });
     std::vector<WorkItem> sorted(items.size());
     for (size_t i = 0; i < order.size(); i++) sorted[i] = items[order[i]];
     items.swap(sorted);
@@ -976,7 +1010,7 @@ struct PlanBuffers {
 };
 
 capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std::vector<WorkItem> &items,
-                                 const std::vector<uint32_t> &slot_off, PlanBuffers &pb)
+                                 const std::vector<uint32_t> &slot_off, uint32_t n_front, PlanBuffers &pb)
 {
     const PlanLayout l = plan_layout(S, N, (int64_t)items.size());
     hipError_t e = hipMalloc(&pb.buf, l.total);
@@ -993,6 +1027,7 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     pb.w.partial = (uint64_t *)(base + l.partial);
     pb.w.items = (const WorkItem *)(base + l.items);
     pb.w.n_items = (uint32_t)items.size();
+    pb.w.n_items_front = n_front;
     pb.w.counter = (uint32_t *)(base + l.counter);
     pb.w.slot_off = (const uint32_t *)(base + l.slot_off);
     pb.w.np = c->np_dev;
@@ -1039,7 +1074,8 @@ Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int thr
     L.flags = opt->flags & ~CAPART_FLAG_PER_SET_LAUNCH;
     L.threads = std::min(threads, eval_threads(in->max_tasks, in->max_M));
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
-    L.form = form;
+    L.form = form == 2 ? 2 : 1;
+    L.memo_packed = form == 3;
     L.chunks = 1;
     L.chunk = 0;
     L.exh_form = 1;
@@ -1083,8 +1119,9 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     const auto t0 = std::chrono::steady_clock::now();
     if (cf.autotune) {
         // candidates timed on a prefix of the batch (sets are independent
-        // draws, so a prefix has the batch's mix of sizes)
-        const int64_t St = std::min<int64_t>(S, std::max<int64_t>(4096, S / 16));
+        // draws, so a prefix has the batch's mix of sizes); the search stops
+        // early once it has spent a few seconds
+        const int64_t St = std::min<int64_t>(S, std::max<int64_t>(2048, S / 64));
         capart_tasksets sub = *in;
         sub.n_sets = St;
         sub.n_tasks_total = off[St];
@@ -1092,30 +1129,34 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
         double best_ms = 1e300;
         const int th_c[] = {128, 256};
         const int form_c[] = {1, 2};
-        const int ie_c[] = {1024, 4096, 16384};
-        const int bpc_c[] = {2, 4, 8};
+        const int ie_c[] = {4096, 16384};
+        const int bpc_c[] = {4, 8};
         for (int th : th_c)
             for (int fo : form_c)
                 for (int ie : ie_c)
                     for (int bp : bpc_c) {
-                        if (cf.item_evals > 0 && ie != ie_c[1]) continue;
-                        if (cf.blocks_per_cu > 0 && bp != bpc_c[1]) continue;
+                        if (cf.item_evals > 0 && ie != ie_c[0]) continue;
+                        if (cf.blocks_per_cu > 0 && bp != bpc_c[0]) continue;
+                        if (tried > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 5.0)
+                            continue;
                         const int ie2 = cf.item_evals > 0 ? cf.item_evals : ie;
                         const int bp2 = cf.blocks_per_cu > 0 ? cf.blocks_per_cu : bp;
                         std::vector<WorkItem> items;
                         std::vector<uint32_t> so;
                         int64_t te = 0;
-                        build_items(off, M, St, in, opt->K, ie2, plan_launch(&sub, opt, th, fo, c->tune).front_n,
-                                    items, so, te);
+                        uint32_t nf = 0;
+                        const Launch Lc = plan_launch(&sub, opt, th, fo, c->tune);
+                        build_items(off, M, St, in, opt->K, ie2, single_item_n(Lc), split_n_of(Lc, in), items, so, te,
+                                    nf);
                         PlanBuffers pb;
-                        if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, pb)) != CAPART_OK) {
+                        if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, nf, pb)) != CAPART_OK) {
                             if (pb.buf) hipFree(pb.buf);
                             return rc;
                         }
                         const Launch L = plan_launch(&sub, opt, th, fo, c->tune);
                         hipEvent_t e0 = take_event(c), e1 = take_event(c);
                         double ms = 0;
-                        for (int rep = 0; rep < 3 && rc == CAPART_OK; rep++) {
+                        for (int rep = 0; rep < 2 && rc == CAPART_OK; rep++) {
                             if (rep == 1) hipEventRecord(e0, c->stream);
                             rc = launch_plan_kernels(c, bs, pb.w, o, L, cus * bp2, c->stream, false);
                         }
@@ -1123,7 +1164,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                         hipError_t se = hipEventSynchronize(e1);
                         float f = 0.f;
                         if (se == hipSuccess) se = hipEventElapsedTime(&f, e0, e1);
-                        ms = f / 2.0;
+                        ms = f;
                         c->ev_free.push_back(e0);
                         c->ev_free.push_back(e1);
                         hipFree(pb.buf);
@@ -1151,9 +1192,11 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     std::vector<WorkItem> items;
     std::vector<uint32_t> so;
     int64_t te = 0;
-    build_items(off, M, S, in, opt->K, item_evals, plan_launch(in, opt, threads, form, c->tune).front_n, items, so, te);
+    uint32_t nf = 0;
+    const Launch Lp0 = plan_launch(in, opt, threads, form, c->tune);
+    build_items(off, M, S, in, opt->K, item_evals, single_item_n(Lp0), split_n_of(Lp0, in), items, so, te, nf);
     PlanBuffers pb;
-    if ((rc = alloc_plan_buffers(c, S, N, items, so, pb)) != CAPART_OK) {
+    if ((rc = alloc_plan_buffers(c, S, N, items, so, nf, pb)) != CAPART_OK) {
         if (pb.buf) hipFree(pb.buf);
         delete pl;
         return rc;
@@ -1661,7 +1704,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     L.flags = cfg->flags;
     L.threads = eval_threads(cfg->max_tasks, cfg->max_M);
     L.table_words = (int)(table_lds_bytes(cfg->max_tasks, cfg->max_M) / 4);
-    L.form = c->tune.loop_form > 0 ? c->tune.loop_form : 1;
+    L.form = c->tune.loop_form == 2 ? 2 : 1;
+    L.memo_packed = c->tune.loop_form == 3;
     L.exh_form = 1;
     size_frontier(L, cfg->max_tasks, cfg->alloc_mode, c->tune);
     const uint32_t Pmax = count_parts(cfg->max_M, cfg->K);

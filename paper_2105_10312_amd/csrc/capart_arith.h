@@ -58,6 +58,21 @@ CAPART_HD inline uint32_t util_q32_m1(uint32_t C, uint32_t T)
     return (uint32_t)(q - 1u);
 }
 
+// util_q32_m1 without a 64-bit division, from c = ceil(2^64/T) as split by
+// magic_u32 (T >= 2): y = C*chi + mul_hi(C, clo) = floor(C*c / 2^32) exceeds
+// v = C*2^32/T by less than C/2^32 < 1/2, so y is floor(v) or floor(v) + 1;
+// one product y*T (< 2^64 since y <= 2^32 + 1 and T < 2^31) settles it.
+CAPART_HD inline uint32_t util_q32_m1_magic(uint32_t C, uint32_t T, uint32_t clo, uint32_t chi)
+{
+    if (C > T) return 0xFFFFFFFFu;
+    if (T == 1u) return 0xFFFFFFFFu;  // C = T = 1: 2^32 - 1
+    const uint64_t num = (uint64_t)C << 32;
+    uint64_t y = (uint64_t)C * chi + (uint32_t)(((uint64_t)C * clo) >> 32);
+    if (y * T > num) y--;                   // now y = floor(v)
+    const uint64_t q = y + (y * T != num);  // ceil(v)
+    return (uint32_t)(q - 1u);
+}
+
 // Lemma 2 closed form: least m in [1, M] with C_seq + ceil(C_par/m) <= D.
 CAPART_HD inline uint16_t m_min(uint32_t Cs, uint32_t Cp, uint32_t D, uint32_t M)
 {

@@ -57,7 +57,8 @@ struct Work {            // device workspace owned by the context
     // batched form only
     const WorkItem *items;     // [n_items], largest first
     uint32_t n_items;
-    uint32_t *counter;         // next item to take (reset by the prep kernel)
+    uint32_t *counter;         // [2] next item to take, per queue (reset by the prep kernel)
+    uint32_t n_items_front;    // the first n_items_front items (frontier sets) form the first queue
     const uint32_t *slot_off;  // [S + 1] partial slots of each set
     // counting variant of the evaluation kernel only
     uint64_t *counters;        // [3]: response-time terms, exact tests, frontier lookups
@@ -88,6 +89,11 @@ struct Launch {
     int exh_form;        // exhaustive: 1 = enumerate every allocation, 2 = subset tables + pruned search
     int front_n;         // heuristic: sets of at most front_n tasks use the feasibility frontier (0 = never)
     int front_words;     // u32 words of dynamic LDS reserved for the frontier (2^front_n u16)
+    int memo_log2 = 0;   // heuristic, sets of front_n < n <= 32 tasks: 2^memo_log2 memo entries (0 = no memo);
+                         // the memo shares the frontier's LDS region (a set uses one or the other)
+    int memo_packed = 0; // 1: memo sets run the packed-test state machine instead of the nested loops
+    int n_lo = 0;        // this evaluation launch takes the sets of n_lo <= n (<= n_hi if n_hi > 0) tasks
+    int n_hi = 0;
 };
 
 // Host-side sizing helpers shared by the launchers.
@@ -95,6 +101,11 @@ size_t table_lds_bytes(int max_tasks, int max_M);
 int eval_threads(int max_tasks, int max_M);
 // largest set size answered through the feasibility frontier
 constexpr int FRONTIER_MAX_TASKS = 14;
+// largest set size with a test memo (32-bit rank masks), its default and
+// largest number of entries (8 bytes each)
+constexpr int MEMO_MAX_TASKS = 32;
+constexpr int MEMO_DEFAULT_LOG2 = 11;
+constexpr int MEMO_MAX_LOG2 = 13;
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);

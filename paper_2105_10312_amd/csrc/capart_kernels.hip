@@ -44,6 +44,29 @@ __device__ __forceinline__ bool key_less(const Key &x, const Key &y)
     return x.d < y.d;
 }
 
+// A heuristic result's allocation rides in the key's last word: the
+// allocation index of every heuristic result is 0 and each partitioning is
+// evaluated once, so that word never decides a comparison.  The part of
+// priority rank r sits in bits [ALLOC_BITS*r, ALLOC_BITS*r + ALLOC_BITS);
+// sets with more ranks than fit replay the heuristic in the final kernel.
+template <int KMAX>
+struct AllocPack {
+    static constexpr int BITS = KMAX <= 4 ? 2 : 3;
+    static constexpr int MAX_N = 64 / BITS;
+};
+
+template <int KMAX, typename MT>
+__device__ __forceinline__ uint64_t pack_alloc(int n, const MT (&S)[KMAX])
+{
+    if (n > AllocPack<KMAX>::MAX_N) return 0ull;
+    uint64_t w = 0ull;
+#pragma unroll
+    for (int p = 1; p < KMAX; p++)
+        for (MT h = S[p]; h; h &= h - MT(1))
+            w |= (uint64_t)p << (AllocPack<KMAX>::BITS * __builtin_ctzll((uint64_t)h));
+    return w;
+}
+
 __device__ __forceinline__ Key key_shfl_xor(const Key &k, int mask)
 {
     Key o;
@@ -122,7 +145,8 @@ struct Tables {
 
 extern __shared__ uint32_t capart_dyn_lds[];
 
-__device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act, Tables &tb)
+// Per-set records (by priority rank) and interference masks into LDS.
+__device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int64_t s, bool act)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < n; i += nt) {
@@ -142,6 +166,14 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
         for (int j = 0; j < n; j++) f |= (uint64_t)(L.T[j] < L.D[r]) << j;
         L.intf[r] = f;
     }
+}
+
+// Records plus the whole [m][conflict][rank] tables of execution times and
+// Q32 utilisations (m = 1..M).
+__device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act, Tables &tb)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    stage_records(L, w, off, n, s, act);
     uint32_t *tc = capart_dyn_lds;
     uint32_t *tu = capart_dyn_lds + 2 * n * M;
     for (int e = tid; e < n * M; e += nt) {
@@ -151,8 +183,8 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
         const int base = (m - 1) * 2 * n + r;
         tc[base] = cn;
         tc[base + n] = cc;
-        tu[base] = util_q32_m1(cn, L.T[r]);
-        tu[base + n] = util_q32_m1(cc, L.T[r]);
+        tu[base] = util_q32_m1_magic(cn, L.T[r], L.clo[r], L.chi[r]);
+        tu[base + n] = util_q32_m1_magic(cc, L.T[r], L.clo[r], L.chi[r]);
     }
     __syncthreads();
     tb.C = tc;
@@ -327,12 +359,114 @@ __device__ __forceinline__ V pick(const V (&a)[KMAX], int p)
     return v;
 }
 
+// Q32 utilisation of S_old + {tau} on m units from that of S_old (the new
+// task's term and, when it makes the lone same-type member conflict, that
+// member's change).
+template <typename MT>
+__device__ __forceinline__ uint64_t util_add(const SetLDS &L, const Tables &tb, MT Sold, int tau, int m, uint64_t Uold)
+{
+    const int n = tb.n;
+    const MT memm = (MT)L.memmask;
+    const MT same = Sold & (mbit(memm, tau) ? memm : ~memm);
+    const int ns = mpopc(same);
+    const uint32_t *urow = tb.U + (m - 1) * 2 * n;
+    uint64_t u = Uold + (uint64_t)urow[(ns >= 1 ? n : 0) + tau] + 1ull;
+    if (ns == 1) {
+        const int flip = mctz(same);
+        u += (uint64_t)urow[n + flip] - (uint64_t)urow[flip];
+    }
+    return u;
+}
+
+// ---------------------------------------------------------------------------
+// Test memo of one staged set (sets of 15..32 tasks): an open-addressing hash
+// table in LDS whose entry for a rank subset S records the largest size known
+// to fail (f, 0 = none) and the smallest size known to pass (p, 256 = none);
+// by monotonicity in m, S passes on m >= p and fails on m <= f.  Across the
+// partitionings of a set the heuristic repeats the same subsets many times.
+// Entries only ever gain exact facts (f grows, p shrinks, by compare-and-swap),
+// so lanes that race at worst repeat a test.  Entry: S in bits 0..31, f in
+// 32..40, p in 41..49; 0 = empty (S is never empty).
+constexpr int MEMO_PROBES = 8;
+
+struct Memo {
+    unsigned long long *tab;
+    uint32_t mask;  // entries - 1 (0 = no memo)
+};
+
+__device__ __forceinline__ uint32_t memo_hash(uint32_t S, uint32_t mask) { return (S * 0x9E3779B1u >> 7) & mask; }
+
+// f and p of S (0 and 256 when unknown)
+__device__ __forceinline__ void memo_get(const Memo &mo, uint32_t S, int &f, int &p)
+{
+    f = 0;
+    p = 256;
+    uint32_t h = memo_hash(S, mo.mask);
+    for (int i = 0; i < MEMO_PROBES; i++, h = (h + 1u) & mo.mask) {
+        const unsigned long long v = mo.tab[h];
+        if (v == 0ull) return;
+        if ((uint32_t)v == S) {
+            f = (int)((v >> 32) & 0x1FFu);
+            p = (int)((v >> 41) & 0x1FFu);
+            return;
+        }
+    }
+}
+
+// record that S passes (ok) or fails on m units
+__device__ __forceinline__ void memo_put(const Memo &mo, uint32_t S, int m, bool ok)
+{
+    uint32_t h = memo_hash(S, mo.mask);
+    for (int i = 0; i < MEMO_PROBES; i++, h = (h + 1u) & mo.mask) {
+        unsigned long long v = mo.tab[h];
+        if (v == 0ull) {
+            const unsigned long long nv = (unsigned long long)S | ((unsigned long long)(ok ? 0 : m) << 32) |
+                                          ((unsigned long long)(ok ? m : 256) << 41);
+            const unsigned long long old = atomicCAS(&mo.tab[h], 0ull, nv);
+            if (old == 0ull) return;
+            v = old;
+        }
+        if ((uint32_t)v != S) continue;
+        for (;;) {
+            int f = (int)((v >> 32) & 0x1FFu), p = (int)((v >> 41) & 0x1FFu);
+            if (ok) p = min(p, m); else f = max(f, m);
+            const unsigned long long nv = (unsigned long long)S | ((unsigned long long)f << 32) |
+                                          ((unsigned long long)p << 41);
+            if (nv == v) return;
+            const unsigned long long old = atomicCAS(&mo.tab[h], v, nv);
+            if (old == v) return;
+            v = old;
+        }
+    }
+}
+
+// min_units with the test memo: the search starts above the largest size
+// known to fail (f) and below the smallest known to pass (hi), and records
+// every size it tests.
+template <typename MT, typename TY>
+__device__ int min_units_memo(const SetLDS &L, const Tables &tb, MT S, int f, int hi, const Memo &mo, TY &ty)
+{
+    int lo = f + 1;
+    for (MT h = S; h; h &= h - MT(1)) lo = max(lo, (int)L.mmin[mctz(h)]);
+    const MT cm = conflict_mask<MT>(S, (MT)L.memmask);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool ok = test_from<MT>(L, tb, S, 0, mid, cm, ty);
+        memo_put(mo, (uint32_t)S, mid, ok);
+        if (ok)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
 // Heuristic allocation on a fixed partitioning m[0..k) (non-increasing):
 // tasks in decreasing one-unit utilisation, each to the best-ranked part that
 // stays schedulable.  S[p] = rank masks, U[p] = Q32 utilisations.
 template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
-                                          MT (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty)
+                                          MT (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty, const Memo &mo = Memo{nullptr, 0u})
 {
 #pragma unroll
     for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
@@ -350,9 +484,26 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
             if (p >= k || mm > mp) continue;
             if (ACT && (fb & Sp)) continue;
             uint64_t Un;
-            if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty)) continue;
             int req = 0;
-            if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp, ty);
+            if (sizeof(MT) == 4 && mo.mask) {
+                // through the memo: a recorded fact, else the incremental test (recorded)
+                const MT Sn = Sp | (MT(1) << r);
+                int f, pz;
+                ty.look();
+                memo_get(mo, (uint32_t)Sn, f, pz);
+                bool ok = mp >= pz;
+                if (!ok && mp > f) {
+                    ok = part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty);
+                    memo_put(mo, (uint32_t)Sn, mp, ok);
+                    if (ok) pz = mp;
+                }
+                if (!ok) continue;
+                Un = util_add<MT>(L, tb, Sp, r, mp, U[p]);
+                if (SMS) req = min_units_memo<MT>(L, tb, Sn, f, min(pz, mp), mo, ty);
+            } else {
+                if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty)) continue;
+                if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp, ty);
+            }
             const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
             if (better) { best = p; bestU = Un; bestReq = req; }
         }
@@ -377,8 +528,15 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 constexpr int FRONT_MAX_N = 14;
 constexpr uint16_t FRONT_NONE = 0xFFFFu;
 
-// Lanes that search one subset's fewest units together (k-ary search).
-constexpr int FRONT_GROUP = 16;
+// Offsets above the failing bound tried in the first round of a subset's
+// search by a group of 16, 8 or 4 lanes (a 0 stands for the largest size
+// still open, which also settles "none"): on random sets most subsets that
+// fail at their lower bound need one to three more units.  Wide groups end
+// most searches in one round (short dependency chains when few subsets are
+// searched), narrow ones test fewer sizes per subset (less work when many are).
+__constant__ uint8_t FRONT_STEP16[16] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 32, 0};
+__constant__ uint8_t FRONT_STEP8[8] = {1, 2, 3, 4, 6, 8, 16, 0};
+__constant__ uint8_t FRONT_STEP4[4] = {1, 2, 3, 0};
 
 // Fill ms[] level by level (subsets of equal size, taken in the order of the
 // host-built list `order`: subsets of {0..n-1} by size, then value).
@@ -387,25 +545,32 @@ constexpr int FRONT_GROUP = 16;
 // from below, and S is schedulable on m >= lo units iff the members whose
 // response times can differ from those in S' pass: r alone, or, when r makes
 // the single member j of its type in S' conflict, j and every member below j.
-// Phase 1 gives each lane one subset and tests it at lo; the subsets that
-// fail there are searched in phase 2 by groups of FRONT_GROUP lanes, each
-// round testing FRONT_GROUP evenly spaced sizes of the open interval (a, b)
-// with a failing and b passing (b = M + 1 stands for "none").
+// Per chunk of at most blockDim subsets of a level:
+//  A. one lane per subset: bounds; "none" is inherited without a test, the
+//     others are queued (so that the tests of B run on packed lanes);
+//  B. one lane per queued subset tests it at lo; failures with lo < M are
+//     queued again;
+//  C. groups of G = 16, 8 or 4 lanes (the widest that covers the queue in one
+//     pass) search those: each round tests G sizes of the open interval (a, b)
+//     with a failing and b passing (b = M + 1 stands for "none"), at the
+//     first-round offsets above a, then evenly spaced; monotonicity in m makes
+//     the first passing size of a round bracket the answer.
 template <typename MT, typename TY>
 __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, uint16_t *ms,
                                const uint16_t *order, TY &ty)
 {
-    __shared__ uint32_t fails[256];
-    __shared__ uint32_t nfail[2];  // alternate chunks: one is cleared while the other is read
+    __shared__ uint32_t q1[256], q2[256];  // queued subsets: S | first << 16 | lo << 20
+    __shared__ uint32_t cnt[2][2];         // queue lengths; chunks alternate rows (one is cleared while the other is read)
     const uint16_t *ord = order + ((1u << n) - 2u);
     const MT memm = (MT)L.memmask;
-    if (threadIdx.x == 0) { ms[0] = 0; nfail[0] = 0u; nfail[1] = 0u; }
+    if (threadIdx.x == 0) { ms[0] = 0; cnt[0][0] = cnt[0][1] = cnt[1][0] = cnt[1][1] = 0u; }
     uint32_t cur = 0;
     uint32_t lvl_off = 1, lvl_cnt = (uint32_t)n;  // level 1 follows the empty set
     for (int c = 1; c <= n; c++) {
         for (uint32_t base = 0; base < lvl_cnt; base += blockDim.x, cur ^= 1u) {
-            __syncthreads();  // orders the previous chunk's ms[] writes and counter reads before what follows
-            if (threadIdx.x == 0) nfail[cur ^ 1u] = 0u;
+            __syncthreads();  // the previous chunk's ms[] writes and queue reads are done
+            if (threadIdx.x == 0) { cnt[cur ^ 1u][0] = 0u; cnt[cur ^ 1u][1] = 0u; }
+            // A
             const uint32_t i = base + threadIdx.x;
             if (i < lvl_cnt) {
                 const uint32_t S = ord[lvl_off + i];
@@ -417,49 +582,67 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
                     none |= (v == FRONT_NONE);
                     lo = max(lo, (int)v);
                 }
-                uint16_t res = FRONT_NONE;
-                if (!none) {
-                    const MT SM = (MT)S;
-                    const MT Sp = SM & ~(MT(1) << r);
+                if (none) {
+                    ms[S] = FRONT_NONE;
+                } else {
+                    const MT Sp = (MT)S & ~(MT(1) << r);
                     const MT same = Sp & (mbit(memm, r) ? memm : ~memm);
                     const int first = (mpopc(same) == 1) ? mctz(same) : r;
-                    const MT cm = conflict_mask<MT>(SM, memm);
-                    if (test_from<MT>(L, tb, SM, first, lo, cm, ty)) {
-                        res = (uint16_t)lo;
-                    } else if (lo < M) {
-                        res = 0u;  // searched in phase 2
-                        fails[atomicAdd(&nfail[cur], 1u)] = S | ((uint32_t)first << 16) | ((uint32_t)lo << 20);
-                    }
+                    q1[atomicAdd(&cnt[cur][0], 1u)] = S | ((uint32_t)first << 16) | ((uint32_t)lo << 20);
                 }
-                if (res) ms[S] = res;
             }
             __syncthreads();
-            const uint32_t F = nfail[cur];
-            const int groups = blockDim.x / FRONT_GROUP;
-            const int g = threadIdx.x / FRONT_GROUP, li = threadIdx.x % FRONT_GROUP;
-            const int shift = (threadIdx.x & 63) & ~(FRONT_GROUP - 1);
-            for (uint32_t f = g; f < F; f += groups) {
-                const uint32_t e = fails[f];
+            // B
+            const uint32_t N1 = cnt[cur][0];
+            if (threadIdx.x < N1) {
+                const uint32_t e = q1[threadIdx.x];
+                const uint32_t S = e & 0xFFFFu;
+                const int lo = (int)(e >> 20);
+                const MT SM = (MT)S;
+                if (test_from<MT>(L, tb, SM, (int)((e >> 16) & 0xFu), lo, conflict_mask<MT>(SM, memm), ty))
+                    ms[S] = (uint16_t)lo;
+                else if (lo < M)
+                    q2[atomicAdd(&cnt[cur][1], 1u)] = e;
+                else
+                    ms[S] = FRONT_NONE;
+            }
+            __syncthreads();
+            // C
+            const uint32_t N2 = cnt[cur][1];
+            const int G = N2 * 16u <= blockDim.x ? 16 : (N2 * 8u <= blockDim.x ? 8 : 4);
+            const uint8_t *step = G == 16 ? FRONT_STEP16 : (G == 8 ? FRONT_STEP8 : FRONT_STEP4);
+            const int groups = blockDim.x / G;
+            const int g = threadIdx.x / G, li = threadIdx.x % G;
+            const int shift = (threadIdx.x & 63) & ~(G - 1);
+            const uint32_t gmask = (1u << G) - 1u;
+            for (uint32_t f = g; f < N2; f += groups) {
+                const uint32_t e = q2[f];
                 const uint32_t S = e & 0xFFFFu;
                 const int first = (int)((e >> 16) & 0xFu);
                 const MT SM = (MT)S;
                 const MT cm = conflict_mask<MT>(SM, memm);
                 int a = (int)(e >> 20), b = M + 1;  // fails at a; passes at b (or none if b = M + 1)
+                bool round1 = true;
                 while (b - a > 1) {
+                    // size tried by group lane i in this round: non-decreasing in i, within (a, b)
                     const int span = b - a;
-                    const bool dense = span - 1 <= FRONT_GROUP;
-                    const int x = dense ? a + 1 + li : a + ((li + 1) * span) / (FRONT_GROUP + 1);
-                    const bool pass = x < b && test_from<MT>(L, tb, SM, first, x, cm, ty);
-                    const uint32_t gm = (uint32_t)(__ballot(pass) >> shift) & ((1u << FRONT_GROUP) - 1u);
+                    const bool dense = span - 1 <= G;
+                    auto point = [&](int i) {
+                        if (round1) return step[i] ? min(a + (int)step[i], b - 1) : b - 1;
+                        return dense ? min(a + 1 + i, b - 1) : a + ((i + 1) * span) / (G + 1);
+                    };
+                    const int x = point(li);
+                    const bool pass = test_from<MT>(L, tb, SM, first, x, cm, ty);
+                    const uint32_t gm = (uint32_t)(__ballot(pass) >> shift) & gmask;
                     if (gm) {
                         const int fl = __ffs(gm) - 1;
-                        const int xf = dense ? a + 1 + fl : a + ((fl + 1) * span) / (FRONT_GROUP + 1);
-                        const int xp = fl == 0 ? a : (dense ? a + fl : a + (fl * span) / (FRONT_GROUP + 1));
-                        a = xp;
+                        const int xf = point(fl);
+                        a = fl == 0 ? a : point(fl - 1);
                         b = xf;
                     } else {
-                        a = dense ? b - 1 : a + (FRONT_GROUP * span) / (FRONT_GROUP + 1);
+                        a = point(G - 1);
                     }
+                    round1 = false;
                 }
                 if (li == 0) ms[S] = (b > M) ? FRONT_NONE : (uint16_t)b;
             }
@@ -468,25 +651,6 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
         lvl_cnt = lvl_cnt * (uint32_t)(n - c) / (uint32_t)(c + 1);
     }
     __syncthreads();
-}
-
-// Q32 utilisation of S_old + {tau} on m units from that of S_old (the new
-// task's term and, when it makes the lone same-type member conflict, that
-// member's change).
-template <typename MT>
-__device__ __forceinline__ uint64_t util_add(const SetLDS &L, const Tables &tb, MT Sold, int tau, int m, uint64_t Uold)
-{
-    const int n = tb.n;
-    const MT memm = (MT)L.memmask;
-    const MT same = Sold & (mbit(memm, tau) ? memm : ~memm);
-    const int ns = mpopc(same);
-    const uint32_t *urow = tb.U + (m - 1) * 2 * n;
-    uint64_t u = Uold + (uint64_t)urow[(ns >= 1 ? n : 0) + tau] + 1ull;
-    if (ns == 1) {
-        const int flip = mctz(same);
-        u += (uint64_t)urow[n + flip] - (uint64_t)urow[flip];
-    }
-    return u;
 }
 
 // The heuristic on one fixed partitioning with every candidate test answered
@@ -594,7 +758,10 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     __shared__ uint64_t sforbid[MAXN];
     const int64_t s = Lp.s0 + blockIdx.x;
     const int lane = threadIdx.x;
-    if (w.counter != nullptr && blockIdx.x == 0 && lane == 0) *w.counter = 0u;  // batched form: restart the queue
+    if (w.counter != nullptr && blockIdx.x == 0 && lane == 0) {  // batched form: restart the queues
+        w.counter[0] = 0u;
+        w.counter[1] = 0u;
+    }
     const int64_t off0 = b.off[s], off1 = b.off[s + 1];
     const int M = b.M[s];
     int status = CAPART_OK;
@@ -800,7 +967,13 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
                     sm += u;
                 }
                 const Key kk{mx, sm, q, 0ull};
-                if (key_less(kk, best)) best = kk;
+                if (key_less(kk, best)) {
+                    best = kk;
+                    MT Sl[KMAX];
+#pragma unroll
+                    for (int i = 0; i < KMAX; i++) Sl[i] = i < k ? myS[i * stride] : MT(0);
+                    best.d = pack_alloc<KMAX, MT>(n, Sl);
+                }
             }
             if (dbg) {
                 uint64_t *d = dbg + 3 * (uint64_t)q;
@@ -824,20 +997,23 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
 // partitioning runs to completion, parts unrolled over registers).
 template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
-                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
+                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty, const Memo &mo)
 {
     int m[KMAX];
     int k = unrank<KMAX>(np, M, K, q0, m);
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
-        const bool ok = heuristic<KMAX, ACT, SMS, MT>(L, tb, n, m, k, S, U, ty);
+        const bool ok = heuristic<KMAX, ACT, SMS, MT>(L, tb, n, m, k, S, U, ty, mo);
         uint64_t mx = 0, sm = 0;
         if (ok) {
 #pragma unroll
             for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
             const Key kk{mx, sm, q, 0ull};
-            if (key_less(kk, best)) best = kk;
+            if (key_less(kk, best)) {
+                best = kk;
+                best.d = pack_alloc<KMAX, MT>(n, S);
+            }
         }
         if (dbg) {
             uint64_t *d = dbg + 3 * (uint64_t)q;
@@ -865,7 +1041,10 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
 #pragma unroll
             for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
             const Key kk{mx, sm, q, 0ull};
-            if (key_less(kk, best)) best = kk;
+            if (key_less(kk, best)) {
+                best = kk;
+                best.d = pack_alloc<KMAX, MT>(n, S);
+            }
         }
         if (dbg) {
             uint64_t *d = dbg + 3 * (uint64_t)q;
@@ -878,9 +1057,179 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
     }
 }
 
+// Loop form 1 for sets with a test memo: every lane runs the heuristic on
+// its partitionings as a state machine whose step places one task, answering
+// its candidate tests from the memo; a lane that meets a test the memo cannot
+// answer parks on it, and once every lane of the wave is parked or finished,
+// the parked lanes run their tests together (packed, instead of one lane
+// testing while the others idle).  Each result is recorded in the memo and
+// kept by its lane, which resumes at the same candidate.  Candidates already
+// settled for the current task are kept in registers (bit masks), and for SMS
+// the fewest-units search of one candidate at a time keeps its bounds there,
+// so progress never depends on the memo having room.  Parts are only ever
+// indexed by compile-time constants (unrolled loops), which keeps them in
+// registers.
+template <int KMAX, bool ACT, bool SMS, typename TY>
+__device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
+                              uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty, const Memo &mo)
+{
+    typedef uint32_t MT;
+    int m[KMAX];
+    MT S[KMAX];
+    uint64_t U[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) { m[i] = 0; S[i] = 0u; U[i] = 0ull; }
+    bool active = q0 < q1;
+    int k = active ? unrank<KMAX>(np, M, K, q0, m) : 0;
+    uint32_t q = q0;
+    int t = 0;
+    uint32_t known = 0u, passm = 0u;  // candidates of the current task settled / schedulable
+    uint64_t reqs = 0ull;             // SMS: fewest units of each schedulable candidate (8 bits each)
+    int sp = -1, slo = 0, shi = 0;    // SMS: candidate being searched, sizes below slo fail, shi passes
+    bool parked = false;              // a test of (tS, tfirst, tm) is due
+    MT tS = 0u;
+    int tfirst = 0, tm = 0;
+    bool own = false, own_ok = false;  // result of this lane's last test, about (tS, tm)
+    const MT memm = (MT)L.memmask;
+    for (;;) {
+        if (!__any(active)) break;
+        while (active && !parked) {
+            const int tau = L.sigma[t];
+            const int mm = (int)L.mmin[tau];
+            const MT bit = MT(1) << tau;
+            const MT fb = ACT ? (MT)L.forbid[tau] : 0u;
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                if (parked || p >= k || ((known >> p) & 1u)) continue;
+                const int mp = m[p];
+                const MT Sp = S[p];
+                if (mm > mp || (ACT && (fb & Sp))) { known |= 1u << p; continue; }
+                const MT Sn = Sp | bit;
+                int f, pz;
+                ty.look();
+                memo_get(mo, Sn, f, pz);
+                if (own && tS == Sn) {
+                    if (own_ok) pz = min(pz, tm); else f = max(f, tm);
+                }
+                if (sp != p) {
+                    if (mp > f && mp < pz) {
+                        // the incremental test: tau, the members below it and
+                        // the lone same-type member it makes conflict (and below)
+                        const MT same = Sp & (mbit(memm, tau) ? memm : ~memm);
+                        tS = Sn;
+                        tfirst = mpopc(same) == 1 ? min(tau, mctz(same)) : tau;
+                        tm = mp;
+                        parked = true;
+                        continue;
+                    }
+                    if (mp <= f) { known |= 1u << p; continue; }
+                    if (!SMS) { known |= 1u << p; passm |= 1u << p; continue; }
+                    sp = p;
+                    slo = 1;
+                    for (MT h = Sn; h; h &= h - 1u) slo = max(slo, (int)L.mmin[mctz(h)]);
+                    shi = mp;
+                }
+                slo = max(slo, f + 1);
+                shi = min(shi, pz);
+                if (slo < shi) {
+                    tS = Sn;
+                    tfirst = 0;
+                    tm = (slo + shi) >> 1;
+                    parked = true;
+                    continue;
+                }
+                reqs |= (uint64_t)slo << (8 * p);
+                known |= 1u << p;
+                passm |= 1u << p;
+                sp = -1;
+            }
+            if (parked) break;
+            // every candidate settled: place tau on the best one, or the partitioning fails
+            int bp = -1, breq = 0;
+            uint64_t bu = 0;
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                if (!((passm >> p) & 1u)) continue;
+                const uint64_t Un = util_add<MT>(L, tb, S[p], tau, m[p], U[p]);
+                const int req = SMS ? (int)((reqs >> (8 * p)) & 0xFFu) : 0;
+                if (bp < 0 || (SMS ? (req < breq || (req == breq && Un < bu)) : (Un < bu))) {
+                    bp = p;
+                    bu = Un;
+                    breq = req;
+                }
+            }
+            known = passm = 0u;
+            reqs = 0ull;
+            bool done = false, ok = false;
+            if (bp < 0) {
+                done = true;
+            } else {
+#pragma unroll
+                for (int i = 0; i < KMAX; i++)
+                    if (i == bp) { S[i] |= bit; U[i] = bu; }
+                if (++t >= n) done = ok = true;
+            }
+            if (done) {
+                uint64_t mx = 0, sm = 0;
+                if (ok) {
+#pragma unroll
+                    for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
+                    const Key kk{mx, sm, q, 0ull};
+                    if (key_less(kk, best)) {
+                        best = kk;
+                        best.d = pack_alloc<KMAX, MT>(n, S);
+                    }
+                }
+                if (dbg) {
+                    uint64_t *d = dbg + 3 * (uint64_t)q;
+                    d[0] = ok ? mx : ~0ull;
+                    d[1] = ok ? sm : ~0ull;
+                    d[2] = ok ? 0ull : ~0ull;
+                }
+                if (++q >= q1) {
+                    active = false;
+                } else {
+                    k = next_partition<KMAX>(m, K);
+#pragma unroll
+                    for (int i = 0; i < KMAX; i++) { S[i] = 0u; U[i] = 0ull; }
+                    t = 0;
+                }
+            }
+        }
+        if (parked) {
+            own_ok = test_from<MT>(L, tb, tS, tfirst, tm, conflict_mask<MT>(tS, memm), ty);
+            memo_put(mo, tS, tm, own_ok);
+            own = true;
+            parked = false;
+        }
+    }
+}
+
+// The staged set's test memo (loop form 1, sets between the frontier limit
+// and 32 tasks), placed after the tables, where frontier sets keep their
+// frontier.
+template <typename MT>
+__device__ __forceinline__ Memo set_memo(const Launch &Lp, int n)
+{
+    if (sizeof(MT) != 4 || Lp.memo_log2 == 0 || n <= Lp.front_n || n > MEMO_MAX_TASKS) return Memo{nullptr, 0u};
+    return Memo{(unsigned long long *)(capart_dyn_lds + Lp.table_words), (1u << Lp.memo_log2) - 1u};
+}
+
+// Empty the memo for a newly staged set (all threads; ends with a barrier).
+template <typename MT, int FORM>
+__device__ __forceinline__ void memo_clear(const Launch &Lp, int n)
+{
+    const Memo mo = set_memo<MT>(Lp, n);
+    if (FORM != 1 || mo.mask == 0u) return;
+    for (uint32_t i = threadIdx.x; i <= mo.mask; i += blockDim.x) mo.tab[i] = 0ull;
+    __syncthreads();
+}
+
 // Evaluate partitionings [p0, p1) of one staged set in this block (all
-// lanes): through the frontier when the set is small enough, else with
-// direct incremental tests.
+// lanes).  FORM 0: every set of the launch is answered through its
+// frontier; FORM 1 (nested loops, or the memo state machine) and FORM 2 (one
+// candidate test per loop step): sets above the frontier limit, with direct
+// incremental tests or the test memo.  Each launch compiles only its own path.
 template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, typename TY>
 __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, const uint32_t *np,
                            const uint16_t *order, int n, int M,
@@ -891,19 +1240,27 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
     uint32_t q0 = p0 + threadIdx.x * per, q1 = min(p1, q0 + per);
     q0 = max(q0, p_lo);
     q1 = min(q1, p_hi);
-    if (Lp.front_n > 0 && n <= Lp.front_n) {
+    if constexpr (FORM == 0) {
         uint16_t *ms = (uint16_t *)(capart_dyn_lds + Lp.table_words);
         build_frontier<MT>(L, tb, n, M, ms, order, ty);
         if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg, ty);
         return;
-    }
+    } else {
     if (q0 >= q1) return;
-    if (FORM == 2) {
+    if constexpr (FORM == 2) {
         uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words + Lp.front_words);
         MT *lS = (MT *)(lU + KMAX * blockDim.x);
         heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, lS, lU, ty);
     } else {
-        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty);
+        const Memo mo = set_memo<MT>(Lp, n);
+        if constexpr (sizeof(MT) == 4 && KMAX <= 4) {  // (K = 8 keeps the nested form: fewer registers)
+            if (mo.mask && Lp.memo_packed) {
+                heur_run_memo<KMAX, ACT, SMS>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty, mo);
+                return;
+            }
+        }
+        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty, mo);
+    }
     }
 }
 
@@ -920,6 +1277,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (!(f & SETF_VALID)) return;
     const int64_t off = b.off[s];
     const int n = (int)(b.off[s + 1] - off);
+    if (n < Lp.n_lo || (Lp.n_hi > 0 && n > Lp.n_hi)) return;  // evaluated by the launch for its size
     const int M = b.M[s];
     const uint32_t P = w.np[np_index(Lp.K, M, M)];
     const uint32_t p0 = (uint32_t)c * Lp.chunk;
@@ -930,6 +1288,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
     if (!(f & SETF_LEMMA1)) {
         Tables tb;
         stage_set(L, w, off, n, M, s, ACT, tb);
+        memo_clear<MT, FORM>(Lp, n);
         eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, w.order, n, M, p0, p1, p_lo, p_hi, best, dbg, ty);
     } else if (dbg) {
         for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
@@ -990,6 +1349,7 @@ __global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, O
             const int M = b.M[s];
             if (s != staged) {
                 stage_set(L, w, off, n, M, s, ACT, tb);
+                memo_clear<MT, FORM>(Lp, n);
                 staged = s;
             }
             NoTally nt;
@@ -1129,8 +1489,22 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
     best = wave_min(best);
     const bool found = best.a != ~0ull;
     const bool act = (Lp.mode == CAPART_HEUR_BF_ACT || Lp.mode == CAPART_HEUR_SMS_ACT);
+    // the chosen allocation comes from the allocation index (exhaustive), from
+    // the allocation packed in the key (heuristic), or, for sets too large to
+    // pack, from replaying the heuristic on the chosen partitioning, which
+    // needs the whole tables; otherwise only the rows of the chosen sizes and
+    // of M are filled
+    const bool replay = found && !exh && n > AllocPack<KMAX>::MAX_N;
     Tables tb;
-    stage_set(L, w, off, n, M, s, act, tb);
+    if (replay) {
+        stage_set(L, w, off, n, M, s, act, tb);
+    } else {
+        stage_records(L, w, off, n, s, act);
+        tb.C = capart_dyn_lds;
+        tb.U = capart_dyn_lds + 2 * n * M;
+        tb.n = n;
+        __syncthreads();
+    }
     if (found && lane == 0) {
         int m[KMAX];
         int k = unrank<KMAX>(w.np, M, K, (uint32_t)best.c, m);
@@ -1146,6 +1520,14 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
                 for (int p = 0; p < KMAX; p++)
                     if (p == d) S[p] |= 1ull << L.rank_of[i];
             }
+        } else if (!replay) {
+            constexpr int B = AllocPack<KMAX>::BITS;
+            for (int r = 0; r < n; r++) {
+                const int d = (int)((best.d >> (B * r)) & ((1u << B) - 1u));
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (p == d) S[p] |= 1ull << r;
+            }
         } else {
             NoTally nt;
             switch (Lp.mode) {
@@ -1160,6 +1542,20 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         sk = k;
     }
     __syncthreads();
+    if (!replay) {
+        // execution-time rows of the chosen part sizes and of M (the whole GPU)
+        const int rows = found ? sk + 1 : 1;
+        uint32_t *tc = capart_dyn_lds;
+        for (int e = lane; e < rows * n; e += 64) {
+            const int i = e / n, r = e - i * n;
+            const int m = (i + 1 < rows) ? sm_[i] : M;
+            const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+            const int base = (m - 1) * 2 * n + r;
+            tc[base] = cn;
+            tc[base + n] = time_c(L.k[r], cn);
+        }
+        __syncthreads();
+    }
     // response times of the chosen triple
     if (lane < n) {
         const int64_t gi = off + L.orig[lane];
@@ -1195,7 +1591,7 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         o.verdict[s] = found ? 1 : 0;
         o.verdict_1g[s] = ok1 ? 1 : 0;
         o.pidx[s] = found ? (int32_t)best.c : -1;
-        o.aidx[s] = found ? (int64_t)best.d : -1;
+        o.aidx[s] = found ? (exh ? (int64_t)best.d : 0) : -1;
         o.maxU[s] = found ? best.a : 0ull;
         o.sumU[s] = found ? best.b : 0ull;
         o.n_evals[s] = (int64_t)P;
@@ -1442,7 +1838,10 @@ static size_t dyn_bytes(const Batch &b) { return table_lds_bytes(min(b.max_tasks
 template <int KMAX, typename MT>
 static size_t heur_dyn_bytes(const Launch &L, int form)
 {
-    return (size_t)4 * (L.table_words + L.front_words) +
+    const size_t front = (size_t)4 * L.front_words;
+    const size_t memo = (form == 1 && sizeof(MT) == 4 && L.memo_log2 > 0) ? (size_t)8 << L.memo_log2 : 0;
+    if (form == 0) return (size_t)4 * L.table_words + front;
+    return (size_t)4 * L.table_words + (front > memo ? front : memo) +
            (form == 2 ? (size_t)L.threads * KMAX * (sizeof(MT) + sizeof(uint64_t)) : 0);
 }
 
@@ -1451,6 +1850,12 @@ hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch
     if (L.S <= 0) return hipSuccess;
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)L.S), dim3(64), 0, st, b, w, o, L);
     return hipGetLastError();
+}
+
+// Every set of the launch is at most front_n tasks (a frontier launch).
+static bool frontier_launch(const Launch &L, const Batch &b)
+{
+    return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && (L.n_hi > 0 ? L.n_hi : b.max_tasks) <= L.front_n;
 }
 
 template <int KMAX, typename MT, int FORM>
@@ -1489,6 +1894,7 @@ static hipError_t launch_eval_k(const Batch &b, const Work &w, const Out &o, con
         hipLaunchKernelGGL((eval_exh_kernel<KMAX>), grid, block, dyn_bytes(b), st, b, w, o, L, p_lo, p_hi);
         return hipGetLastError();
     }
+    if (frontier_launch(L, b)) return launch_heur<KMAX, MT, 0>(L, b, w, o, st, p_lo, p_hi);
     return L.form == 2 ? launch_heur<KMAX, MT, 2>(L, b, w, o, st, p_lo, p_hi)
                        : launch_heur<KMAX, MT, 1>(L, b, w, o, st, p_lo, p_hi);
 }
@@ -1520,12 +1926,34 @@ template <int KMAX, typename MT>
 static hipError_t launch_persistent_f(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
                                       hipStream_t st)
 {
+    if (frontier_launch(L, b)) return launch_persistent_k<KMAX, MT, 0>(b, w, o, L, blocks, st);
     return L.form == 2 ? launch_persistent_k<KMAX, MT, 2>(b, w, o, L, blocks, st)
                        : launch_persistent_k<KMAX, MT, 1>(b, w, o, L, blocks, st);
 }
 
-hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
-                                  hipStream_t st)
+// A heuristic batch that mixes frontier sets with larger ones is evaluated by
+// two launches: one for the sets of at most front_n tasks, which reserves
+// tables for front_n tasks and the frontier, and one for the others, which
+// reserves full tables and the test memo.  Each reserves only the LDS its own
+// sets use, so more blocks fit a compute unit.
+static bool split_by_size(const Launch &L, const Batch &b)
+{
+    return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && b.max_tasks > L.front_n && L.n_lo == 0 && L.n_hi == 0;
+}
+
+static void split_launch(const Launch &L, const Batch &b, Launch &La, Launch &Lb)
+{
+    La = L;
+    Lb = L;
+    La.n_hi = L.front_n;
+    La.table_words = (int)(table_lds_bytes(L.front_n, min(b.max_M, 255)) / 4);
+    La.memo_log2 = 0;
+    Lb.n_lo = L.front_n + 1;
+    Lb.front_words = 0;
+}
+
+static hipError_t launch_eval_persistent_one(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                             hipStream_t st)
 {
     if (b.max_tasks <= 32)
         return L.K <= 4 ? launch_persistent_f<4, uint32_t>(b, w, o, L, blocks, st)
@@ -1542,41 +1970,43 @@ int device_cu_count()
     return cus;
 }
 
-template <int KMAX, typename MT>
+template <int KMAX, typename MT, int FORM>
 static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
     const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
-    const size_t lds = heur_dyn_bytes<KMAX, MT>(L, 1);
+    const size_t lds = heur_dyn_bytes<KMAX, MT>(L, FORM);
     const uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     default:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, 1, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_eval_count(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
-    if (L.S <= 0 || L.mode == CAPART_EXHAUSTIVE) return hipSuccess;
-    if (b.max_tasks <= 32)
-        return L.K <= 4 ? launch_count_k<4, uint32_t>(b, w, o, L, st) : launch_count_k<8, uint32_t>(b, w, o, L, st);
-    return L.K <= 4 ? launch_count_k<4, uint64_t>(b, w, o, L, st) : launch_count_k<8, uint64_t>(b, w, o, L, st);
+    const bool fr = frontier_launch(L, b);
+    if (b.max_tasks <= 32) {
+        if (L.K <= 4) return fr ? launch_count_k<4, uint32_t, 0>(b, w, o, L, st) : launch_count_k<4, uint32_t, 1>(b, w, o, L, st);
+        return fr ? launch_count_k<8, uint32_t, 0>(b, w, o, L, st) : launch_count_k<8, uint32_t, 1>(b, w, o, L, st);
+    }
+    if (L.K <= 4) return fr ? launch_count_k<4, uint64_t, 0>(b, w, o, L, st) : launch_count_k<4, uint64_t, 1>(b, w, o, L, st);
+    return fr ? launch_count_k<8, uint64_t, 0>(b, w, o, L, st) : launch_count_k<8, uint64_t, 1>(b, w, o, L, st);
 }
 
-hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
-                             uint32_t p_lo, uint32_t p_hi)
+static hipError_t launch_eval_range_one(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                                        uint32_t p_lo, uint32_t p_hi)
 {
-    if (L.S <= 0) return hipSuccess;
     // 32-bit rank masks when every set of the launch has at most 32 tasks
     if (b.max_tasks <= 32)
         return L.K <= 4 ? launch_eval_k<4, uint32_t>(b, w, o, L, st, p_lo, p_hi)
@@ -1585,9 +2015,48 @@ hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const 
                     : launch_eval_k<8, uint64_t>(b, w, o, L, st, p_lo, p_hi);
 }
 
+hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                             uint32_t p_lo, uint32_t p_hi)
+{
+    if (L.S <= 0) return hipSuccess;
+    if (!split_by_size(L, b)) return launch_eval_range_one(b, w, o, L, st, p_lo, p_hi);
+    Launch La, Lb;
+    split_launch(L, b, La, Lb);
+    const hipError_t e = launch_eval_range_one(b, w, o, La, st, p_lo, p_hi);
+    return e != hipSuccess ? e : launch_eval_range_one(b, w, o, Lb, st, p_lo, p_hi);
+}
+
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
     return launch_eval_range(b, w, o, L, st, 0u, 0xFFFFFFFFu);
+}
+
+hipError_t launch_eval_count(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    if (L.S <= 0 || L.mode == CAPART_EXHAUSTIVE) return hipSuccess;
+    if (!split_by_size(L, b)) return launch_eval_count_one(b, w, o, L, st);
+    Launch La, Lb;
+    split_launch(L, b, La, Lb);
+    const hipError_t e = launch_eval_count_one(b, w, o, La, st);
+    return e != hipSuccess ? e : launch_eval_count_one(b, w, o, Lb, st);
+}
+
+// Batched form: the frontier sets' items come first in the item list and form
+// their own queue (counter[0]); the other items form the second (counter[1]).
+hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+                                  hipStream_t st)
+{
+    if (!split_by_size(L, b) || w.n_items_front == 0 || w.n_items_front >= w.n_items)
+        return launch_eval_persistent_one(b, w, o, L, blocks, st);
+    Launch La, Lb;
+    split_launch(L, b, La, Lb);
+    Work wa = w, wb = w;
+    wa.n_items = w.n_items_front;
+    wb.items = w.items + w.n_items_front;
+    wb.n_items = w.n_items - w.n_items_front;
+    wb.counter = w.counter + 1;
+    const hipError_t e = launch_eval_persistent_one(b, wa, o, La, blocks, st);
+    return e != hipSuccess ? e : launch_eval_persistent_one(b, wb, o, Lb, blocks, st);
 }
 
 hipError_t launch_subset_tables(const Batch &b, const Work &w, const Launch &L, uint64_t *tab, int64_t s_begin, int W,
@@ -1639,92 +2108,47 @@ static hipError_t allow_lds(F *fn)
     return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
+// Raise the dynamic-LDS limit of every heuristic kernel instantiation
+// (policy and order variants, rank-mask width, loop form, counting variant).
+template <int KMAX, typename MT, int FORM, bool COUNT>
+static hipError_t allow_heur()
+{
+    hipError_t e = hipSuccess, t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, false, false, MT, FORM, COUNT>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, true, false, MT, FORM, COUNT>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, false, true, MT, FORM, COUNT>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, true, true, MT, FORM, COUNT>)) != hipSuccess) e = t;
+    if constexpr (!COUNT) {
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, false, MT, FORM>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, false, MT, FORM>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, true, MT, FORM>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, true, MT, FORM>)) != hipSuccess) e = t;
+    }
+    return e;
+}
+
+template <int KMAX, typename MT>
+static hipError_t allow_heur_all()
+{
+    hipError_t e = hipSuccess, t;
+    if ((t = allow_heur<KMAX, MT, 0, false>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, false>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 2, false>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 0, true>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, true>()) != hipSuccess) e = t;
+    return e;
+}
+
 hipError_t configure_kernels()
 {
     hipError_t e = hipSuccess, t;
 #define CAPART_ALLOW(fn) do { t = allow_lds(fn); if (t != hipSuccess) e = t; } while (0)
     CAPART_ALLOW((eval_exh_kernel<4>));
     CAPART_ALLOW((eval_exh_kernel<8>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, false, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<4, true, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint32_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint32_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 1>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, false, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, false, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_persistent_kernel<8, true, true, uint64_t, 2>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, false, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, false, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, false, true, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<4, true, true, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint32_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, false, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, false, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, false, true, uint64_t, 1, true>));
-    CAPART_ALLOW((eval_heur_kernel<8, true, true, uint64_t, 1, true>));
+    if ((t = allow_heur_all<4, uint32_t>()) != hipSuccess) e = t;
+    if ((t = allow_heur_all<4, uint64_t>()) != hipSuccess) e = t;
+    if ((t = allow_heur_all<8, uint32_t>()) != hipSuccess) e = t;
+    if ((t = allow_heur_all<8, uint64_t>()) != hipSuccess) e = t;
     CAPART_ALLOW((subset_table_kernel));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));

@@ -65,6 +65,13 @@ int main()
         if (t % 2) T = cn + (uint32_t)(rng() % 1000);
         if (T >= (1u << 31)) T = (1u << 31) - 1;
         uint32_t u = util_q32_m1(cn, T);
+        {
+            uint32_t lo, hi;
+            magic_u32(T, &lo, &hi);
+            CHECK(util_q32_m1_magic(cn, T, lo, hi) == u);
+            const uint32_t C2 = 1 + (uint32_t)(rng() % T);  // 1 <= C <= T over the full range
+            CHECK(util_q32_m1_magic(C2, T, lo, hi) == util_q32_m1(C2, T));
+        }
         if (cn <= T) {
             u128 q = (((u128)cn << 32) + T - 1) / T;
             CHECK((u128)u + 1 == q);
@@ -78,6 +85,21 @@ int main()
         uint32_t want = MMIN_NONE;
         for (uint32_t q = 1; q <= M; q++) if ((uint64_t)Cs + ((uint64_t)Cp + q - 1) / q <= D) { want = q; break; }
         CHECK(mm == want);
+    }
+    // division-free utilisation: every C <= T for small T, the ends of the
+    // range for large T, and T = 1
+    for (uint32_t T = 1; T < 2000; T++) {
+        uint32_t lo, hi;
+        magic_u32(T, &lo, &hi);
+        for (uint32_t C = 1; C <= T + 1; C++) CHECK(util_q32_m1_magic(C, T, lo, hi) == util_q32_m1(C, T));
+    }
+    for (uint32_t T : edge_T) {
+        uint32_t lo, hi;
+        magic_u32(T, &lo, &hi);
+        for (uint32_t d = 0; d < 3000 && d < T; d++) {
+            CHECK(util_q32_m1_magic(T - d, T, lo, hi) == util_q32_m1(T - d, T));
+            CHECK(util_q32_m1_magic(1 + d, T, lo, hi) == util_q32_m1(1 + d, T));
+        }
     }
     std::printf("%s (%d failures)\n", fails ? "FAILED" : "OK", fails);
     return fails ? 1 : 0;

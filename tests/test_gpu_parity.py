@@ -344,7 +344,7 @@ def test_frontier_and_direct_tests_agree(eng, mode):
         for K in (4, 8):
             capart.capart_set_tuning(eng.ctx, frontier=1)
             a = eng.solve(ts, K, mode, debug=True)
-            capart.capart_set_tuning(eng.ctx, frontier=2)
+            capart.capart_set_tuning(eng.ctx, frontier=2, memo=-1)
             b = eng.solve(ts, K, mode, debug=True)
             capart.capart_set_tuning(eng.ctx)
             for f in FIELDS + ("dbg_key",):
@@ -355,3 +355,40 @@ def test_frontier_and_direct_tests_agree(eng, mode):
     got = eng.solve(ts, 4, mode)
     capart.capart_set_tuning(eng.ctx)
     assert_same(got, want, ts, f"frontier {mode}")
+
+
+def memo_sets():
+    """Sets of 15..32 tasks (the test memo's range): C3's uneven sets and a few
+    light ones on which most partitionings are schedulable (deep heuristic
+    paths, many distinct subsets)."""
+    c3 = workload.config_c3(seed=43, n_sets=2500)
+    n = c3.sizes()
+    pick = np.nonzero((n >= 15) & (c3["M"] <= 48))[0][:60]
+    rng = np.random.default_rng(44)
+    light = workload.gen_sets(45, rng.integers(15, 33, 8), rng.uniform(1.0, 4.0, 8), np.full(8, 24),
+                              tmin=1e3, tmax=1e5)
+    return workload.concat([workload.subset(c3, pick), light])
+
+
+@pytest.mark.parametrize("mode", ["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_memo_matches_direct_tests(eng, mode):
+    """The per-set test memo (default size, and a 256-entry table that fills
+    up and falls back to direct tests), in both loop forms that use it, gives
+    the same key on every partitioning as direct tests, and the oracle's
+    results per set."""
+    ts = memo_sets()
+    say(f"memo {mode}: {ts.n_sets} sets, n 15..32")
+    capart.capart_set_tuning(eng.ctx, memo=-1)
+    ref = eng.solve(ts, 4, mode, debug=True)
+    for memo in (0, 8):
+        for form in (1, 3):  # nested loops; state machine with packed tests
+            capart.capart_set_tuning(eng.ctx, loop_form=form, memo=memo)
+            got = eng.solve(ts, 4, mode, debug=True)
+            for f in FIELDS + ("dbg_key",):
+                assert np.array_equal(got[f], ref[f]), (mode, memo, form, f)
+    capart.capart_set_tuning(eng.ctx)
+    idx = np.arange(0, ts.n_sets, 6)
+    sub = workload.subset(ts, idx)
+    want = oracle.solve(sub, 4, mode, nthreads=THREADS)
+    got = eng.solve(sub, 4, mode)
+    assert_same(got, want, sub, f"memo {mode}")
