@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="GPU form timed for `value` (c2, c3)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="batched form without HIP graph capture (same kernels and arguments; for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -215,11 +217,12 @@ def main():
     plan = None
     if args.form == "batched" and mode != "EXH":
         t0 = time.perf_counter()
-        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=True)
+        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=not args.no_graph)
         plan_info = plan.info()
         log(f"[bench] plan: {plan_info} ({(time.perf_counter() - t0):.1f} s)")
         step = plan.run
-        form = "batched (persistent work queue, autotuned, HIP graph)"
+        sched = "persistent work queue" if plan_info["blocks"] > 0 else "direct schedule"
+        form = f"batched ({sched}, autotuned" + (")" if args.no_graph else ", HIP graph)")
     else:
         plan_info = None
         step = plain_step
@@ -318,7 +321,8 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s")
     roof = None
     if work is not None:
-        kname = "eval_persistent_kernel" if plan is not None else "eval_heur_kernel"
+        # the plan runs a persistent grid, or the direct schedule (blocks == 0)
+        kname = "eval_persistent_kernel" if plan is not None and plan_info["blocks"] > 0 else "eval_heur_kernel"
         ops = work["terms"] * C_TERM + work["tests"] * C_TEST + work["lookups"] * C_LOOK
         achieved = ops / (eval_ms / 1000.0)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",

@@ -220,10 +220,12 @@ capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in,
  * use_graph the prep, evaluation and final kernels are captured into a HIP
  * graph; capart_run_batch then costs one graph launch.  With autotune the plan
  * times candidate tunings (threads per block, loop form, item size, blocks per
- * compute unit) on a prefix of the batch (1/64 of it, at least 2048 sets) and
+ * compute unit) on a prefix of the batch (1/64 of it, at least 8192 sets) and
  * keeps the fastest, spending at most about 5 s; every candidate computes
- * identical results.  Sets whose frontier or test memo serves all of their
- * partitionings form one item each.  Autotuning runs the path on that prefix
+ * identical results.  The candidates include the direct schedule (one block
+ * per set chunk, as capart_solve_async, no work queue), which wins when every
+ * set is one item and the persistent loop only costs registers.  Sets whose
+ * frontier or test memo serves all of their partitionings form one item each.  Autotuning runs the path on that prefix
  * and so writes into the result buffers.  The plan owns its workspace; the caller
  * keeps the bound buffers alive and unchanged in size while the plan exists.
  * Results are those of capart_solve_async on the same batch, bit for bit.
@@ -233,14 +235,14 @@ typedef struct capart_plan capart_plan;
 
 typedef struct capart_plan_config {
     int32_t autotune;       /* 1: time candidates on a prefix of the batch; 0: use the context's tuning */
-    int32_t blocks_per_cu;  /* persistent blocks per compute unit, 0 = automatic                        */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit, 0 = automatic, -1 = direct schedule   */
     int32_t item_evals;     /* partitionings per work item for a 10-task set, 0 = automatic             */
     int32_t use_graph;      /* 1: capture the launch sequence into a HIP graph                          */
 } capart_plan_config;
 
 typedef struct capart_plan_info {
     int64_t n_sets, n_items, total_evals;
-    int32_t threads, loop_form, blocks, item_evals;
+    int32_t threads, loop_form, blocks, item_evals;  /* blocks 0: direct schedule */
     int32_t candidates_tried, use_graph;
     double tune_ms;         /* host wall time spent autotuning */
 } capart_plan_info;

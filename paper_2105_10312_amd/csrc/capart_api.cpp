@@ -925,10 +925,11 @@ struct capart_plan {
 namespace {
 
 struct PlanLayout {
-    size_t rec, forbid, sigma, setflags, memmask, partial, items, slot_off, counter, total;
+    size_t rec, forbid, sigma, setflags, memmask, partial, items, slot_off, counter, partial_direct, total;
 };
 
-PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
+// direct_slots: partial keys of the one-block-per-(set, chunk) schedule (0 = none)
+PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items, int64_t direct_slots)
 {
     PlanLayout l;
     size_t o = 0;
@@ -942,6 +943,7 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items)
     l.items = take(sizeof(WorkItem) * (size_t)n_items);
     l.slot_off = take(4 * (size_t)(S + 1));
     l.counter = take(8);
+    l.partial_direct = take(32 * (size_t)direct_slots);
     l.total = o;
     return l;
 }
@@ -1006,13 +1008,15 @@ void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M,
 
 struct PlanBuffers {
     void *buf = nullptr;
-    Work w{};
+    Work w{};   // persistent schedule (work items, queues)
+    Work wd{};  // direct schedule: one block per (set, chunk), partial keys by chunk
 };
 
 capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std::vector<WorkItem> &items,
-                                 const std::vector<uint32_t> &slot_off, uint32_t n_front, PlanBuffers &pb)
+                                 const std::vector<uint32_t> &slot_off, uint32_t n_front, int64_t direct_slots,
+                                 PlanBuffers &pb)
 {
-    const PlanLayout l = plan_layout(S, N, (int64_t)items.size());
+    const PlanLayout l = plan_layout(S, N, (int64_t)items.size(), direct_slots);
     hipError_t e = hipMalloc(&pb.buf, l.total);
     if (e != hipSuccess) {
         pb.buf = nullptr;
@@ -1032,6 +1036,13 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     pb.w.slot_off = (const uint32_t *)(base + l.slot_off);
     pb.w.np = c->np_dev;
     pb.w.order = c->order_dev;
+    pb.wd = pb.w;
+    pb.wd.partial = (uint64_t *)(base + l.partial_direct);
+    pb.wd.items = nullptr;
+    pb.wd.n_items = 0;
+    pb.wd.n_items_front = 0;
+    pb.wd.counter = nullptr;
+    pb.wd.slot_off = nullptr;
     if (!items.empty() &&
         (e = hipMemcpy(base + l.items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice)) !=
             hipSuccess)
@@ -1053,7 +1064,9 @@ capart_status launch_plan_kernels(capart_ctx *c, const Batch &b, const Work &w, 
     if (timed) hipEventRecord(ev[0], st);
     if ((e = launch_prep(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
     if (timed) hipEventRecord(ev[1], st);
-    if ((e = launch_eval_persistent(b, w, o, L, blocks, st)) != hipSuccess) return hip_fail(c, e, "eval launch");
+    // blocks == 0: the direct schedule (one block per set chunk), else a persistent grid
+    if ((e = blocks > 0 ? launch_eval_persistent(b, w, o, L, blocks, st) : launch_eval(b, w, o, L, st)) != hipSuccess)
+        return hip_fail(c, e, "eval launch");
     if (timed) hipEventRecord(ev[2], st);
     if ((e = launch_final(b, w, o, L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
     if (timed) {
@@ -1121,7 +1134,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
         // candidates timed on a prefix of the batch (sets are independent
         // draws, so a prefix has the batch's mix of sizes); the search stops
         // early once it has spent a few seconds
-        const int64_t St = std::min<int64_t>(S, std::max<int64_t>(2048, S / 64));
+        const int64_t St = std::min<int64_t>(S, std::max<int64_t>(8192, S / 64));
         capart_tasksets sub = *in;
         sub.n_sets = St;
         sub.n_tasks_total = off[St];
@@ -1131,54 +1144,95 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
         const int form_c[] = {1, 2};
         const int ie_c[] = {4096, 16384};
         const int bpc_c[] = {4, 8};
-        for (int th : th_c)
-            for (int fo : form_c)
-                for (int ie : ie_c)
-                    for (int bp : bpc_c) {
-                        if (cf.item_evals > 0 && ie != ie_c[0]) continue;
-                        if (cf.blocks_per_cu > 0 && bp != bpc_c[0]) continue;
-                        if (tried > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 5.0)
-                            continue;
-                        const int ie2 = cf.item_evals > 0 ? cf.item_evals : ie;
-                        const int bp2 = cf.blocks_per_cu > 0 ? cf.blocks_per_cu : bp;
-                        std::vector<WorkItem> items;
-                        std::vector<uint32_t> so;
-                        int64_t te = 0;
-                        uint32_t nf = 0;
-                        const Launch Lc = plan_launch(&sub, opt, th, fo, c->tune);
-                        build_items(off, M, St, in, opt->K, ie2, single_item_n(Lc), split_n_of(Lc, in), items, so, te,
-                                    nf);
-                        PlanBuffers pb;
-                        if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, nf, pb)) != CAPART_OK) {
-                            if (pb.buf) hipFree(pb.buf);
-                            return rc;
+        // time one candidate (two runs on the prefix, the second timed)
+        auto time_it = [&](const Work &w, const Launch &L, int blocks, double &ms) -> capart_status {
+            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            capart_status r = CAPART_OK;
+            for (int rep = 0; rep < 2 && r == CAPART_OK; rep++) {
+                if (rep == 1) hipEventRecord(e0, c->stream);
+                r = launch_plan_kernels(c, bs, w, o, L, blocks, c->stream, false);
+            }
+            hipEventRecord(e1, c->stream);
+            hipError_t se = hipEventSynchronize(e1);
+            float f = 0.f;
+            if (se == hipSuccess) se = hipEventElapsedTime(&f, e0, e1);
+            ms = f;
+            c->ev_free.push_back(e0);
+            c->ev_free.push_back(e1);
+            if (r != CAPART_OK) return r;
+            if (se != hipSuccess) return hip_fail(c, se, "autotune timing");
+            return CAPART_OK;
+        };
+        auto over_budget = [&]() {
+            return tried > 0 && std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > 5.0;
+        };
+        if (cf.blocks_per_cu >= 0) {
+            for (int th : th_c)
+                for (int fo : form_c)
+                    for (int ie : ie_c)
+                        for (int bp : bpc_c) {
+                            if (cf.item_evals > 0 && ie != ie_c[0]) continue;
+                            if (cf.blocks_per_cu > 0 && bp != bpc_c[0]) continue;
+                            if (over_budget()) continue;
+                            // loop form 2 has no test memo: not a candidate when sets would use it
+                            if (fo == 2 && plan_launch(&sub, opt, th, 1, c->tune).memo_log2 > 0) continue;
+                            const int ie2 = cf.item_evals > 0 ? cf.item_evals : ie;
+                            const int bp2 = cf.blocks_per_cu > 0 ? cf.blocks_per_cu : bp;
+                            std::vector<WorkItem> items;
+                            std::vector<uint32_t> so;
+                            int64_t te = 0;
+                            uint32_t nf = 0;
+                            const Launch L = plan_launch(&sub, opt, th, fo, c->tune);
+                            build_items(off, M, St, in, opt->K, ie2, single_item_n(L), split_n_of(L, in), items, so,
+                                        te, nf);
+                            PlanBuffers pb;
+                            if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, nf, 0, pb)) !=
+                                CAPART_OK) {
+                                if (pb.buf) hipFree(pb.buf);
+                                return rc;
+                            }
+                            double ms = 0;
+                            rc = time_it(pb.w, L, cus * bp2, ms);
+                            hipFree(pb.buf);
+                            if (rc != CAPART_OK) return rc;
+                            tried++;
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                threads = th;
+                                form = fo;
+                                item_evals = ie2;
+                                bpc = bp2;
+                            }
                         }
-                        const Launch L = plan_launch(&sub, opt, th, fo, c->tune);
-                        hipEvent_t e0 = take_event(c), e1 = take_event(c);
-                        double ms = 0;
-                        for (int rep = 0; rep < 2 && rc == CAPART_OK; rep++) {
-                            if (rep == 1) hipEventRecord(e0, c->stream);
-                            rc = launch_plan_kernels(c, bs, pb.w, o, L, cus * bp2, c->stream, false);
-                        }
-                        hipEventRecord(e1, c->stream);
-                        hipError_t se = hipEventSynchronize(e1);
-                        float f = 0.f;
-                        if (se == hipSuccess) se = hipEventElapsedTime(&f, e0, e1);
-                        ms = f;
-                        c->ev_free.push_back(e0);
-                        c->ev_free.push_back(e1);
-                        hipFree(pb.buf);
-                        if (rc != CAPART_OK) return rc;
-                        if (se != hipSuccess) return hip_fail(c, se, "autotune timing");
-                        tried++;
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            threads = th;
-                            form = fo;
-                            item_evals = ie2;
-                            bpc = bp2;
-                        }
-                    }
+        }
+        // the direct schedule: one block per (set, chunk), no work queue
+        if (cf.blocks_per_cu <= 0 && cf.item_evals <= 0)
+            for (int th : th_c) {
+                if (over_budget()) continue;
+                capart_tuning tu = c->tune;
+                tu.threads = th;
+                const Plan dp = make_plan(&sub, opt, tu);
+                std::vector<WorkItem> none;
+                std::vector<uint32_t> so((size_t)St + 1, 0u);
+                PlanBuffers pb;
+                if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, none, so, 0, St * (int64_t)dp.L.chunks, pb)) !=
+                    CAPART_OK) {
+                    if (pb.buf) hipFree(pb.buf);
+                    return rc;
+                }
+                double ms = 0;
+                rc = time_it(pb.wd, dp.L, 0, ms);
+                hipFree(pb.buf);
+                if (rc != CAPART_OK) return rc;
+                tried++;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    threads = th;
+                    bpc = 0;
+                }
+            }
+    } else if (cf.blocks_per_cu < 0) {
+        bpc = 0;
     }
     const double tune_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1193,23 +1247,38 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     std::vector<uint32_t> so;
     int64_t te = 0;
     uint32_t nf = 0;
+    const bool direct = bpc <= 0;
+    capart_tuning tud = c->tune;
+    tud.threads = threads;
+    const Plan dp = make_plan(in, opt, tud);
     const Launch Lp0 = plan_launch(in, opt, threads, form, c->tune);
-    build_items(off, M, S, in, opt->K, item_evals, single_item_n(Lp0), split_n_of(Lp0, in), items, so, te, nf);
+    if (!direct) {
+        build_items(off, M, S, in, opt->K, item_evals, single_item_n(Lp0), split_n_of(Lp0, in), items, so, te, nf);
+    } else {
+        so.assign((size_t)S + 1, 0u);
+        for (int64_t s2 = 0; s2 < S; s2++) {
+            const int64_t n = off[s2 + 1] - off[s2];
+            const int32_t m = M[s2];
+            if (off[s2] >= 0 && n >= 1 && n <= std::min(in->max_tasks, CAPART_MAX_TASKS) && m >= 1 &&
+                m <= std::min(in->max_M, CAPART_MAX_M) && n * m <= CAPART_MAX_NM)
+                te += count_parts(m, opt->K);
+        }
+    }
     PlanBuffers pb;
-    if ((rc = alloc_plan_buffers(c, S, N, items, so, nf, pb)) != CAPART_OK) {
+    if ((rc = alloc_plan_buffers(c, S, N, items, so, nf, direct ? S * (int64_t)dp.L.chunks : 0, pb)) != CAPART_OK) {
         if (pb.buf) hipFree(pb.buf);
         delete pl;
         return rc;
     }
     pl->buf = pb.buf;
-    pl->w = pb.w;
-    pl->L = plan_launch(in, opt, threads, form, c->tune);
-    pl->blocks = cus * bpc;
+    pl->w = direct ? pb.wd : pb.w;
+    pl->L = direct ? dp.L : Lp0;
+    pl->blocks = direct ? 0 : cus * bpc;
     pl->info.n_sets = S;
     pl->info.n_items = (int64_t)items.size();
     pl->info.total_evals = te;
     pl->info.threads = pl->L.threads;
-    pl->info.loop_form = form;
+    pl->info.loop_form = direct ? pl->L.form : form;
     pl->info.blocks = pl->blocks;
     pl->info.item_evals = item_evals;
     pl->info.candidates_tried = tried;

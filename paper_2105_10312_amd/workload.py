@@ -220,11 +220,16 @@ def config_c4(seed: int = 4, n_sets: int = 1000) -> TaskSets:
 
 
 def config_c5_query_sizes(seed: int, n_queries: int):
-    """Serving queries: n = round(exp(U(ln 2, ln 64))), M from {16,48,80,108}."""
+    """Serving queries: n = round(exp(U(ln 2, ln 64))), M from {16,48,80,108},
+    U ~ U(1, min(16, n * u_safe(M))) where u_safe(M) = 1 / (0.5 + 0.5 / M) is
+    the one-task utilisation that still fits the whole GPU at the largest
+    sequential fraction (0.5): above it a query of few tasks could almost
+    never pass the discard rule."""
     rng = np.random.Generator(np.random.PCG64(seed + 1_000_003))
     n = np.rint(np.exp(rng.uniform(np.log(2), np.log(64), size=n_queries))).astype(np.int64)
     M = rng.choice(np.array([16, 48, 80, 108]), size=n_queries)
-    U = rng.uniform(1.0, 16.0, size=n_queries)
+    u_safe = 1.0 / (0.5 + 0.5 / M)
+    U = rng.uniform(1.0, np.minimum(16.0, n * u_safe), size=n_queries)
     return n, U, M
 
 

@@ -72,7 +72,8 @@ def test_batched_matches_plain_and_oracle(eng, mode):
     b, info = batched(eng, ts, 4, mode, 10, 80)
     say("plan", info)
     same(b, p, f"batched vs plain {mode}")
-    assert info["n_items"] > 0 and info["total_evals"] == 4263 * ts.n_sets
+    # a persistent grid over work items, or the direct schedule (no items)
+    assert (info["n_items"] > 0) != (info["blocks"] == 0) and info["total_evals"] == 4263 * ts.n_sets
     idx = np.arange(0, ts.n_sets, max(1, ts.n_sets // 150))
     sub = workload.subset(ts, idx)
     want = oracle.solve(sub, 4, mode, nthreads=THREADS)
@@ -93,6 +94,18 @@ def test_every_tuning_choice_gives_identical_bytes(eng):
                                     blocks_per_cu=bpc)
                 same(got, ref, f"threads={threads} form={form} item={item_evals} bpc={bpc}")
     capart.capart_set_tuning(eng.ctx, 0, 0, 0)
+
+
+def test_direct_schedule_matches_plain(eng):
+    """The plan's direct schedule (one block per set chunk) gives the plain
+    path's bytes, with and without graph capture, on even and uneven batches."""
+    for ts, mt, mm in ((workload.config_c2(seed=8, n_sets=3000), 10, 80),
+                       (workload.config_c3(seed=9, n_sets=3000), 32, 108)):
+        ref = plain(eng, ts, 4, "SMS_INA", mt, mm)
+        for graph in (False, True):
+            got, info = batched(eng, ts, 4, "SMS_INA", mt, mm, autotune=False, blocks_per_cu=-1, use_graph=graph)
+            assert info["blocks"] == 0
+            same(got, ref, f"direct graph={graph}")
 
 
 def test_graph_replays_are_identical(eng):
