@@ -284,7 +284,7 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
         ch = std::max<int64_t>(1, std::min(std::max(ch, ch_fill), chmax));
         // frontier sets: the frontier is built once per block, so keep one
         // block per set when there are enough sets to fill the chip
-        if ((L.front_n > 0 && in->max_tasks <= L.front_n) || (L.memo_log2 > 0 && in->max_tasks <= MEMO_MAX_TASKS))
+        if ((L.front_n > 0 && in->max_tasks <= L.front_n) || (L.memo_log2 > 0 && in->max_tasks <= NARROW_MAX_TASKS))
             ch = std::max<int64_t>(1, std::min(ch_fill, chmax));
         L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
         if (tu.chunk > 0) L.chunk = std::min<uint32_t>((uint32_t)tu.chunk, std::max<uint32_t>(Pmax, 1));
@@ -942,7 +942,7 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items, int64_t direct_slo
     l.partial = take(32 * (size_t)n_items);
     l.items = take(sizeof(WorkItem) * (size_t)n_items);
     l.slot_off = take(4 * (size_t)(S + 1));
-    l.counter = take(8);
+    l.counter = take(12);
     l.partial_direct = take(32 * (size_t)direct_slots);
     l.total = o;
     return l;
@@ -953,19 +953,18 @@ PlanLayout plan_layout(int64_t S, int64_t N, int64_t n_items, int64_t direct_slo
 // partitioning grows roughly with n^2), queued by decreasing estimated cost.
 // Sets of at most this many tasks go to one work item each (their frontier or
 // test memo then serves all of their partitionings).
-int single_item_n(const Launch &L) { return std::max(L.front_n, L.memo_log2 > 0 ? MEMO_MAX_TASKS : 0); }
+int single_item_n(const Launch &L) { return std::max(L.front_n, L.memo_log2 > 0 ? NARROW_MAX_TASKS : 0); }
 
-// Sets of at most split_n tasks (0 = no split) are queued apart, ahead of
-// the others (they are evaluated by a launch of their own).
-int split_n_of(const Launch &L, const capart_tasksets *in)
-{
-    return (L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && in->max_tasks > L.front_n) ? L.front_n : 0;
-}
-
+// Items are grouped by the size class of their set (classes ascending, see
+// size_classes; each class is evaluated by a launch of its own with its own
+// queue), and within a class queued by decreasing estimated cost.
 void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M, int64_t S, const capart_tasksets *in,
-                 int K, int item_evals, int single_n, int split_n, std::vector<WorkItem> &items,
-                 std::vector<uint32_t> &slot_off, int64_t &total_evals, uint32_t &n_front)
+                 int K, int item_evals, const Launch &L, std::vector<WorkItem> &items,
+                 std::vector<uint32_t> &slot_off, int64_t &total_evals, uint32_t class_end[3])
 {
+    const int single_n = single_item_n(L);
+    int hi[3];
+    const int nc = size_classes(L, in->max_tasks, hi);
     items.clear();
     slot_off.assign((size_t)S + 1, 0u);
     total_evals = 0;
@@ -992,13 +991,18 @@ void build_items(const std::vector<int64_t> &off, const std::vector<int32_t> &M,
     slot_off[S] = (uint32_t)items.size();
     std::vector<uint32_t> order(items.size());
     std::vector<uint8_t> cls(items.size());
-    n_front = 0;
+    uint32_t count[3] = {0u, 0u, 0u};
     for (size_t i = 0; i < order.size(); i++) {
         order[i] = (uint32_t)i;
-        const int64_t s = items[i].set;
-        cls[i] = (split_n > 0 && off[s + 1] - off[s] > split_n) ? 1 : 0;
-        n_front += split_n > 0 && cls[i] == 0;
+        const int64_t n = off[items[i].set + 1] - off[items[i].set];
+        int c = 0;
+        while (c + 1 < nc && n > hi[c]) c++;
+        cls[i] = (uint8_t)c;
+        count[c]++;
     }
+    class_end[0] = count[0];
+    class_end[1] = count[0] + count[1];
+    class_end[2] = count[0] + count[1] + count[2];
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t b) { return cls[a] != cls[b] ? cls[a] < cls[b] : cost[a] > cost[b]; });
     std::vector<WorkItem> sorted(items.size());
@@ -1013,8 +1017,8 @@ struct PlanBuffers {
 };
 
 capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std::vector<WorkItem> &items,
-                                 const std::vector<uint32_t> &slot_off, uint32_t n_front, int64_t direct_slots,
-                                 PlanBuffers &pb)
+                                 const std::vector<uint32_t> &slot_off, const uint32_t class_end[3],
+                                 int64_t direct_slots, PlanBuffers &pb)
 {
     const PlanLayout l = plan_layout(S, N, (int64_t)items.size(), direct_slots);
     hipError_t e = hipMalloc(&pb.buf, l.total);
@@ -1031,7 +1035,7 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     pb.w.partial = (uint64_t *)(base + l.partial);
     pb.w.items = (const WorkItem *)(base + l.items);
     pb.w.n_items = (uint32_t)items.size();
-    pb.w.n_items_front = n_front;
+    for (int i = 0; i < 3; i++) pb.w.class_end[i] = class_end[i];
     pb.w.counter = (uint32_t *)(base + l.counter);
     pb.w.slot_off = (const uint32_t *)(base + l.slot_off);
     pb.w.np = c->np_dev;
@@ -1040,7 +1044,7 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     pb.wd.partial = (uint64_t *)(base + l.partial_direct);
     pb.wd.items = nullptr;
     pb.wd.n_items = 0;
-    pb.wd.n_items_front = 0;
+    for (int i = 0; i < 3; i++) pb.wd.class_end[i] = 0u;
     pb.wd.counter = nullptr;
     pb.wd.slot_off = nullptr;
     if (!items.empty() &&
@@ -1181,12 +1185,11 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                             std::vector<WorkItem> items;
                             std::vector<uint32_t> so;
                             int64_t te = 0;
-                            uint32_t nf = 0;
+                            uint32_t ce[3];
                             const Launch L = plan_launch(&sub, opt, th, fo, c->tune);
-                            build_items(off, M, St, in, opt->K, ie2, single_item_n(L), split_n_of(L, in), items, so,
-                                        te, nf);
+                            build_items(off, M, St, in, opt->K, ie2, L, items, so, te, ce);
                             PlanBuffers pb;
-                            if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, nf, 0, pb)) !=
+                            if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, items, so, ce, 0, pb)) !=
                                 CAPART_OK) {
                                 if (pb.buf) hipFree(pb.buf);
                                 return rc;
@@ -1215,7 +1218,8 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                 std::vector<WorkItem> none;
                 std::vector<uint32_t> so((size_t)St + 1, 0u);
                 PlanBuffers pb;
-                if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, none, so, 0, St * (int64_t)dp.L.chunks, pb)) !=
+                const uint32_t ce0[3] = {0u, 0u, 0u};
+                if ((rc = alloc_plan_buffers(c, St, sub.n_tasks_total, none, so, ce0, St * (int64_t)dp.L.chunks, pb)) !=
                     CAPART_OK) {
                     if (pb.buf) hipFree(pb.buf);
                     return rc;
@@ -1246,14 +1250,14 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     std::vector<WorkItem> items;
     std::vector<uint32_t> so;
     int64_t te = 0;
-    uint32_t nf = 0;
+    uint32_t ce[3] = {0u, 0u, 0u};
     const bool direct = bpc <= 0;
     capart_tuning tud = c->tune;
     tud.threads = threads;
     const Plan dp = make_plan(in, opt, tud);
     const Launch Lp0 = plan_launch(in, opt, threads, form, c->tune);
     if (!direct) {
-        build_items(off, M, S, in, opt->K, item_evals, single_item_n(Lp0), split_n_of(Lp0, in), items, so, te, nf);
+        build_items(off, M, S, in, opt->K, item_evals, Lp0, items, so, te, ce);
     } else {
         so.assign((size_t)S + 1, 0u);
         for (int64_t s2 = 0; s2 < S; s2++) {
@@ -1265,7 +1269,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
         }
     }
     PlanBuffers pb;
-    if ((rc = alloc_plan_buffers(c, S, N, items, so, nf, direct ? S * (int64_t)dp.L.chunks : 0, pb)) != CAPART_OK) {
+    if ((rc = alloc_plan_buffers(c, S, N, items, so, ce, direct ? S * (int64_t)dp.L.chunks : 0, pb)) != CAPART_OK) {
         if (pb.buf) hipFree(pb.buf);
         delete pl;
         return rc;
@@ -1778,7 +1782,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     L.exh_form = 1;
     size_frontier(L, cfg->max_tasks, cfg->alloc_mode, c->tune);
     const uint32_t Pmax = count_parts(cfg->max_M, cfg->K);
-    L.chunk = c->tune.chunk > 0 ? (uint32_t)c->tune.chunk : (uint32_t)L.threads;
+    // 512 partitionings per block: one per lane of the widest blocks (large-set launches)
+    L.chunk = c->tune.chunk > 0 ? (uint32_t)c->tune.chunk : 512u;
     L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
     // device budget: slot rings + task rings + per-stream packed buffers
     const int64_t per_slot = 4 + 8 + 32 * (int64_t)L.chunks;

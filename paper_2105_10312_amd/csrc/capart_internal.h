@@ -57,8 +57,8 @@ struct Work {            // device workspace owned by the context
     // batched form only
     const WorkItem *items;     // [n_items], largest first
     uint32_t n_items;
-    uint32_t *counter;         // [2] next item to take, per queue (reset by the prep kernel)
-    uint32_t n_items_front;    // the first n_items_front items (frontier sets) form the first queue
+    uint32_t *counter;         // [3] next item to take, per queue (reset by the prep kernel)
+    uint32_t class_end[3];     // items of size class i are [class_end[i-1], class_end[i]) (one queue each)
     const uint32_t *slot_off;  // [S + 1] partial slots of each set
     // counting variant of the evaluation kernel only
     uint64_t *counters;        // [3]: response-time terms, exact tests, frontier lookups
@@ -101,9 +101,16 @@ size_t table_lds_bytes(int max_tasks, int max_M);
 int eval_threads(int max_tasks, int max_M);
 // largest set size answered through the feasibility frontier
 constexpr int FRONTIER_MAX_TASKS = 14;
-// largest set size with a test memo (32-bit rank masks), its default and
-// largest number of entries (8 bytes each)
-constexpr int MEMO_MAX_TASKS = 32;
+// A heuristic launch is split by set size into up to three launches, each
+// compiled for its own path and reserving only the LDS its sets use: sets of
+// at most front_n tasks (frontier), of at most NARROW_MAX_TASKS (32-bit rank
+// masks, test memo) and larger ones (64-bit masks).  Fills the classes' upper
+// task counts (ascending) and returns how many there are (0: no split).
+int size_classes(const Launch &L, int max_tasks, int hi[3]);
+// largest set size with 32-bit rank masks
+constexpr int NARROW_MAX_TASKS = 32;
+// test memo (sets between the frontier limit and 32 tasks): default and
+// largest log2 of its entries (8 bytes each)
 constexpr int MEMO_DEFAULT_LOG2 = 11;
 constexpr int MEMO_MAX_LOG2 = 13;
 

@@ -379,14 +379,17 @@ __device__ __forceinline__ uint64_t util_add(const SetLDS &L, const Tables &tb, 
 }
 
 // ---------------------------------------------------------------------------
-// Test memo of one staged set (sets of 15..32 tasks): an open-addressing hash
-// table in LDS whose entry for a rank subset S records the largest size known
-// to fail (f, 0 = none) and the smallest size known to pass (p, 256 = none);
-// by monotonicity in m, S passes on m >= p and fails on m <= f.  Across the
-// partitionings of a set the heuristic repeats the same subsets many times.
-// Entries only ever gain exact facts (f grows, p shrinks, by compare-and-swap),
-// so lanes that race at worst repeat a test.  Entry: S in bits 0..31, f in
-// 32..40, p in 41..49; 0 = empty (S is never empty).
+// Test memo of one staged set (sets between the frontier limit and 32
+// tasks): an open-addressing hash table in LDS whose entry for a rank subset S
+// records the largest size known to fail (f, 0 = none) and the smallest size
+// known to pass (p, 256 = none); by monotonicity in m, S passes on m >= p and
+// fails on m <= f.  Across the partitionings of a set the heuristic repeats
+// the same subsets many times.  Entries only ever gain exact facts (f grows,
+// p shrinks, by compare-and-swap), so lanes that race at worst repeat a test.
+// Entry: S in bits 0..31, f in 32..40, p in 41..49 (0 = empty; S is never
+// empty).  Larger sets are left to direct tests: the costly ones (schedulable
+// on many partitionings) meet so many distinct subsets that a table in LDS
+// answers few of their tests.
 constexpr int MEMO_PROBES = 8;
 
 struct Memo {
@@ -761,6 +764,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     if (w.counter != nullptr && blockIdx.x == 0 && lane == 0) {  // batched form: restart the queues
         w.counter[0] = 0u;
         w.counter[1] = 0u;
+        w.counter[2] = 0u;
     }
     const int64_t off0 = b.off[s], off1 = b.off[s + 1];
     const int M = b.M[s];
@@ -1211,7 +1215,7 @@ __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t 
 template <typename MT>
 __device__ __forceinline__ Memo set_memo(const Launch &Lp, int n)
 {
-    if (sizeof(MT) != 4 || Lp.memo_log2 == 0 || n <= Lp.front_n || n > MEMO_MAX_TASKS) return Memo{nullptr, 0u};
+    if (sizeof(MT) != 4 || Lp.memo_log2 == 0 || n <= Lp.front_n || n > NARROW_MAX_TASKS) return Memo{nullptr, 0u};
     return Memo{(unsigned long long *)(capart_dyn_lds + Lp.table_words), (1u << Lp.memo_log2) - 1u};
 }
 
@@ -1265,7 +1269,7 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
 }
 
 template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, bool COUNT = false>
-__global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
+__global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
@@ -1323,7 +1327,7 @@ __global__ __launch_bounds__(256) void eval_heur_kernel(Batch b, Work w, Out o, 
 // set's LDS tables only when the set changes, and writes the item's best key
 // to its partial slot.  Items come largest first, so the tail is short.
 template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
-__global__ __launch_bounds__(256) void eval_persistent_kernel(Batch b, Work w, Out o, Launch Lp)
+__global__ __launch_bounds__(512) void eval_persistent_kernel(Batch b, Work w, Out o, Launch Lp)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
@@ -1852,10 +1856,31 @@ hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch
     return hipGetLastError();
 }
 
+// largest set size of a launch
+static int launch_max_n(const Launch &L, const Batch &b) { return L.n_hi > 0 ? min(L.n_hi, b.max_tasks) : b.max_tasks; }
+
+// Threads per block of a loop-form-1 launch whose LDS per block leaves room
+// for only one or two blocks on a compute unit (large per-set tables): wider
+// blocks keep about 8 waves per compute unit.  Frontier and form-2 launches
+// keep their width (the frontier build and form 2's lane state assume at
+// most 256 threads).
+static Launch fit_block(const Launch &L, const Batch &b)
+{
+    Launch C = L;
+    if (L.mode == CAPART_EXHAUSTIVE || L.form != 1) return C;
+    const bool narrow = launch_max_n(L, b) <= NARROW_MAX_TASKS;
+    const size_t dyn = (size_t)4 * L.table_words + (narrow && L.memo_log2 > 0 ? (size_t)8 << L.memo_log2 : 0);
+    const size_t per_block = dyn + 8 * 1024;  // with the static per-set arrays
+    const int fit = (int)((size_t)160 * 1024 / per_block);
+    if (fit <= 1) C.threads = 512;
+    else if (fit == 2) C.threads = max(C.threads, 256);
+    return C;
+}
+
 // Every set of the launch is at most front_n tasks (a frontier launch).
 static bool frontier_launch(const Launch &L, const Batch &b)
 {
-    return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && (L.n_hi > 0 ? L.n_hi : b.max_tasks) <= L.front_n;
+    return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && launch_max_n(L, b) <= L.front_n;
 }
 
 template <int KMAX, typename MT, int FORM>
@@ -1931,31 +1956,35 @@ static hipError_t launch_persistent_f(const Batch &b, const Work &w, const Out &
                        : launch_persistent_k<KMAX, MT, 1>(b, w, o, L, blocks, st);
 }
 
-// A heuristic batch that mixes frontier sets with larger ones is evaluated by
-// two launches: one for the sets of at most front_n tasks, which reserves
-// tables for front_n tasks and the frontier, and one for the others, which
-// reserves full tables and the test memo.  Each reserves only the LDS its own
-// sets use, so more blocks fit a compute unit.
-static bool split_by_size(const Launch &L, const Batch &b)
+int size_classes(const Launch &L, int max_tasks, int hi[3])
 {
-    return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && b.max_tasks > L.front_n && L.n_lo == 0 && L.n_hi == 0;
+    if (L.mode == CAPART_EXHAUSTIVE || L.n_lo > 0 || L.n_hi > 0) return 0;
+    int c = 0;
+    if (L.front_n > 0) hi[c++] = min(L.front_n, max_tasks);
+    const int prev = c ? hi[c - 1] : 0;
+    if (max_tasks > prev && prev < NARROW_MAX_TASKS) hi[c++] = min(max_tasks, NARROW_MAX_TASKS);
+    if (max_tasks > NARROW_MAX_TASKS) hi[c++] = max_tasks;
+    return c;
 }
 
-static void split_launch(const Launch &L, const Batch &b, Launch &La, Launch &Lb)
+// The launch of size class i: its task range, tables for its largest set,
+// and the frontier region (frontier class) or the memo (others).
+static Launch class_launch(const Launch &L, const Batch &b, const int hi[3], int i)
 {
-    La = L;
-    Lb = L;
-    La.n_hi = L.front_n;
-    La.table_words = (int)(table_lds_bytes(L.front_n, min(b.max_M, 255)) / 4);
-    La.memo_log2 = 0;
-    Lb.n_lo = L.front_n + 1;
-    Lb.front_words = 0;
+    Launch C = L;
+    C.n_lo = i > 0 ? hi[i - 1] + 1 : 0;
+    C.n_hi = hi[i];
+    C.table_words = (int)(table_lds_bytes(hi[i], min(b.max_M, 255)) / 4);
+    const bool front = L.front_n > 0 && hi[i] <= L.front_n;
+    if (front) C.memo_log2 = 0; else C.front_words = 0;
+    return C;
 }
 
-static hipError_t launch_eval_persistent_one(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
+static hipError_t launch_eval_persistent_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, int blocks,
                                              hipStream_t st)
 {
-    if (b.max_tasks <= 32)
+    const Launch L = frontier_launch(L0, b) ? L0 : fit_block(L0, b);
+    if (launch_max_n(L, b) <= 32)
         return L.K <= 4 ? launch_persistent_f<4, uint32_t>(b, w, o, L, blocks, st)
                         : launch_persistent_f<8, uint32_t>(b, w, o, L, blocks, st);
     return L.K <= 4 ? launch_persistent_f<4, uint64_t>(b, w, o, L, blocks, st)
@@ -1993,10 +2022,11 @@ static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, co
     return hipGetLastError();
 }
 
-static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st)
 {
+    const Launch L = frontier_launch(L0, b) ? L0 : fit_block(L0, b);
     const bool fr = frontier_launch(L, b);
-    if (b.max_tasks <= 32) {
+    if (launch_max_n(L, b) <= 32) {
         if (L.K <= 4) return fr ? launch_count_k<4, uint32_t, 0>(b, w, o, L, st) : launch_count_k<4, uint32_t, 1>(b, w, o, L, st);
         return fr ? launch_count_k<8, uint32_t, 0>(b, w, o, L, st) : launch_count_k<8, uint32_t, 1>(b, w, o, L, st);
     }
@@ -2004,11 +2034,12 @@ static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out
     return fr ? launch_count_k<8, uint64_t, 0>(b, w, o, L, st) : launch_count_k<8, uint64_t, 1>(b, w, o, L, st);
 }
 
-static hipError_t launch_eval_range_one(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+static hipError_t launch_eval_range_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st,
                                         uint32_t p_lo, uint32_t p_hi)
 {
+    const Launch L = (L0.mode == CAPART_EXHAUSTIVE || frontier_launch(L0, b)) ? L0 : fit_block(L0, b);
     // 32-bit rank masks when every set of the launch has at most 32 tasks
-    if (b.max_tasks <= 32)
+    if (launch_max_n(L, b) <= 32)
         return L.K <= 4 ? launch_eval_k<4, uint32_t>(b, w, o, L, st, p_lo, p_hi)
                         : launch_eval_k<8, uint32_t>(b, w, o, L, st, p_lo, p_hi);
     return L.K <= 4 ? launch_eval_k<4, uint64_t>(b, w, o, L, st, p_lo, p_hi)
@@ -2019,11 +2050,14 @@ hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const 
                              uint32_t p_lo, uint32_t p_hi)
 {
     if (L.S <= 0) return hipSuccess;
-    if (!split_by_size(L, b)) return launch_eval_range_one(b, w, o, L, st, p_lo, p_hi);
-    Launch La, Lb;
-    split_launch(L, b, La, Lb);
-    const hipError_t e = launch_eval_range_one(b, w, o, La, st, p_lo, p_hi);
-    return e != hipSuccess ? e : launch_eval_range_one(b, w, o, Lb, st, p_lo, p_hi);
+    int hi[3];
+    const int nc = size_classes(L, b.max_tasks, hi);
+    if (nc <= 1) return launch_eval_range_one(b, w, o, L, st, p_lo, p_hi);
+    for (int i = 0; i < nc; i++) {
+        const hipError_t e = launch_eval_range_one(b, w, o, class_launch(L, b, hi, i), st, p_lo, p_hi);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
@@ -2034,29 +2068,35 @@ hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch
 hipError_t launch_eval_count(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
     if (L.S <= 0 || L.mode == CAPART_EXHAUSTIVE) return hipSuccess;
-    if (!split_by_size(L, b)) return launch_eval_count_one(b, w, o, L, st);
-    Launch La, Lb;
-    split_launch(L, b, La, Lb);
-    const hipError_t e = launch_eval_count_one(b, w, o, La, st);
-    return e != hipSuccess ? e : launch_eval_count_one(b, w, o, Lb, st);
+    int hi[3];
+    const int nc = size_classes(L, b.max_tasks, hi);
+    if (nc <= 1) return launch_eval_count_one(b, w, o, L, st);
+    for (int i = 0; i < nc; i++) {
+        const hipError_t e = launch_eval_count_one(b, w, o, class_launch(L, b, hi, i), st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-// Batched form: the frontier sets' items come first in the item list and form
-// their own queue (counter[0]); the other items form the second (counter[1]).
+// Batched form: the items of each size class are contiguous in the item list
+// (classes ascending) and form a queue of their own (counter[i]).
 hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
                                   hipStream_t st)
 {
-    if (!split_by_size(L, b) || w.n_items_front == 0 || w.n_items_front >= w.n_items)
-        return launch_eval_persistent_one(b, w, o, L, blocks, st);
-    Launch La, Lb;
-    split_launch(L, b, La, Lb);
-    Work wa = w, wb = w;
-    wa.n_items = w.n_items_front;
-    wb.items = w.items + w.n_items_front;
-    wb.n_items = w.n_items - w.n_items_front;
-    wb.counter = w.counter + 1;
-    const hipError_t e = launch_eval_persistent_one(b, wa, o, La, blocks, st);
-    return e != hipSuccess ? e : launch_eval_persistent_one(b, wb, o, Lb, blocks, st);
+    int hi[3];
+    const int nc = size_classes(L, b.max_tasks, hi);
+    if (nc <= 1) return launch_eval_persistent_one(b, w, o, L, blocks, st);
+    for (int i = 0; i < nc; i++) {
+        const uint32_t begin = i > 0 ? w.class_end[i - 1] : 0u, end = w.class_end[i];
+        if (end <= begin) continue;
+        Work wc = w;
+        wc.items = w.items + begin;
+        wc.n_items = end - begin;
+        wc.counter = w.counter + i;
+        const hipError_t e = launch_eval_persistent_one(b, wc, o, class_launch(L, b, hi, i), blocks, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_subset_tables(const Batch &b, const Work &w, const Launch &L, uint64_t *tab, int64_t s_begin, int W,

@@ -108,6 +108,29 @@ def test_direct_schedule_matches_plain(eng):
             same(got, ref, f"direct graph={graph}")
 
 
+def test_three_size_classes_match_plain(eng):
+    """Sets of 2..64 tasks (frontier, memo and 64-bit-mask classes, each with
+    its own launch and queue) in the batched form give the plain path's bytes,
+    and sampled sets the oracle's."""
+    ts = workload.config_c5(seed=10, n_queries=3000)
+    say("mixed sizes: 3000 sets, n 2..64")
+    ref = plain(eng, ts, 4, "BF_ACT", 64, 108)
+    for bpc in (4, -1):
+        got, info = batched(eng, ts, 4, "BF_ACT", 64, 108, autotune=False, blocks_per_cu=bpc)
+        same(got, ref, f"mixed sizes bpc={bpc}")
+    rng = np.random.default_rng(13)
+    n = ts.sizes()
+    idx = np.sort(np.concatenate([rng.choice(np.nonzero(n <= 14)[0], 20, replace=False),
+                                  rng.choice(np.nonzero((n > 14) & (n <= 32))[0], 8, replace=False),
+                                  rng.choice(np.nonzero(n > 32)[0], 4, replace=False)]))
+    sub = workload.subset(ts, idx)
+    want = oracle.solve(sub, 4, "BF_ACT", nthreads=THREADS)
+    task_idx = np.concatenate([np.arange(ts["set_offset"][s], ts["set_offset"][s + 1]) for s in idx])
+    for f in FIELDS:
+        g = ref[f][task_idx] if f in ("alloc", "R", "R_1g") else ref[f][idx]
+        assert np.array_equal(g, want[f]), f
+
+
 def test_graph_replays_are_identical(eng):
     import torch
     ts = workload.config_c2(seed=6, n_sets=4000)

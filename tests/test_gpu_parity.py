@@ -358,16 +358,21 @@ def test_frontier_and_direct_tests_agree(eng, mode):
 
 
 def memo_sets():
-    """Sets of 15..32 tasks (the test memo's range): C3's uneven sets and a few
-    light ones on which most partitionings are schedulable (deep heuristic
-    paths, many distinct subsets)."""
+    """Sets above the frontier limit (the test memo's range): C3's uneven sets
+    of 15..32 tasks, a few light ones on which most partitionings are
+    schedulable (deep heuristic paths, many distinct subsets), and serving
+    queries of 33..64 tasks."""
     c3 = workload.config_c3(seed=43, n_sets=2500)
     n = c3.sizes()
     pick = np.nonzero((n >= 15) & (c3["M"] <= 48))[0][:60]
     rng = np.random.default_rng(44)
     light = workload.gen_sets(45, rng.integers(15, 33, 8), rng.uniform(1.0, 4.0, 8), np.full(8, 24),
                               tmin=1e3, tmax=1e5)
-    return workload.concat([workload.subset(c3, pick), light])
+    # 33..64 tasks (64-bit rank masks, two-word memo entries)
+    c5 = workload.config_c5(seed=46, n_queries=600)
+    n5 = c5.sizes()
+    wide = np.nonzero((n5 > 32) & (c5["M"] <= 48))[0][:10]
+    return workload.concat([workload.subset(c3, pick), light, workload.subset(c5, wide)])
 
 
 @pytest.mark.parametrize("mode", ["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
@@ -377,7 +382,7 @@ def test_memo_matches_direct_tests(eng, mode):
     the same key on every partitioning as direct tests, and the oracle's
     results per set."""
     ts = memo_sets()
-    say(f"memo {mode}: {ts.n_sets} sets, n 15..32")
+    say(f"memo {mode}: {ts.n_sets} sets, n 15..64")
     capart.capart_set_tuning(eng.ctx, memo=-1)
     ref = eng.solve(ts, 4, mode, debug=True)
     for memo in (0, 8):
