@@ -173,10 +173,11 @@ def main():
     K = 4
     mode = args.mode
     if args.workload == "c5":
-        rates = [1e4, 3e4, 1e5, 3e5, 1e6]
+        # below and above the capacity of this query mix (about 1.4e4 queries/s)
+        rates = [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6]
         legs = []
         for r in rates:
-            n_q = int(min(200000, max(20000, r * 0.5)))
+            n_q = int(min(200000, max(2000, r * 2.0)))
             log(f"[bench] serving at {r:g} q/s, {n_q} queries")
             legs.append(serving_leg(eng, capart, workload, r, n_q))
             log(f"[bench]   p50 {legs[-1]['p50_us']:.1f} us p99 {legs[-1]['p99_us']:.1f} us "
@@ -304,8 +305,8 @@ def main():
 
     serving = None
     if args.workload == "c2" and not args.no_serving:
-        serving = serving_leg(eng, capart, workload, 1e5, 20000)
-        log(f"[bench] serving at 1e5 q/s: p50 {serving['p50_us']:.1f} us, p99 {serving['p99_us']:.1f} us")
+        serving = serving_leg(eng, capart, workload, 5e3, 10000)
+        log(f"[bench] serving at 5e3 q/s: p50 {serving['p50_us']:.1f} us, p99 {serving['p99_us']:.1f} us")
 
     cpu = None
     if mode == "EXH":
