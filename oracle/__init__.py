@@ -78,6 +78,8 @@ def _load():
         lib.or_lemma1_reject_ex.argtypes = set_args
         lib.or_u1_ex.restype = C.c_uint64
         lib.or_u1_ex.argtypes = set_args + [C.c_int]
+        lib.or_alg1_ex.restype = C.c_int
+        lib.or_alg1_ex.argtypes = set_args + [C.c_int, C.c_int, C.c_void_p, i32p, i8p, i64p, C.c_void_p]
         lib.or_time.restype = C.c_int64
         lib.or_time.argtypes = [i64p, i64p, i32p, C.c_int, C.c_int, C.c_int]
         _lib = lib
@@ -166,6 +168,30 @@ def best_on_partitioning(task: dict, sizes, mode="EXH"):
     mx, sm, ai = C.c_uint64(0), C.c_uint64(0), C.c_int64(-1)
     f = lib.or_best_on_partitioning(*_one(task), sz, len(sz), mode, al, C.byref(mx), C.byref(sm), C.byref(ai))
     return bool(f), al, int(mx.value), int(sm.value), int(ai.value)
+
+
+def alg1(task: dict, mode="BF_INA", flags: int = 0) -> dict:
+    """The paper's Algorithm 1 with free partition sizes on one set.
+
+    mode: BF_* = order ">" (Definition 5), SMS_* = order ">>" (Definition 4);
+    *_ACT fills the forbidden list beforehand.  Returns verdict, the final
+    partitions in par_list order (sizes), task -> partition (alloc), response
+    times R, and the numbers of merges tried and accepted."""
+    lib = _load()
+    mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    if mode == MODES["EXH"]:
+        raise ValueError("Algorithm 1 takes a heuristic order (BF_* or SMS_*)")
+    n = len(task["T"])
+    k = C.c_int32(0)
+    sizes = np.zeros(n, np.int32)
+    al = np.zeros(n, np.int8)
+    R = np.zeros(n, np.int64)
+    st = np.zeros(2, np.int64)
+    ok = lib.or_alg1_ex(*_one(task), mode, int(flags), C.byref(k), sizes, al, R, st.ctypes.data)
+    if ok < 0:
+        raise ValueError("set outside the oracle's limits")
+    return dict(verdict=int(ok), k=int(k.value), sizes=sizes[:k.value].copy(), alloc=al, R=R,
+                tried=int(st[0]), merged=int(st[1]))
 
 
 def m_min(task: dict, i: int) -> int:

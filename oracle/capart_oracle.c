@@ -659,3 +659,248 @@ uint64_t or_u1_ex(OR_SET_ARGS, int i)
     OR_SET_INIT(s);
     return or_u1(&s, i);
 }
+
+/* ==== Algorithm 1 with free partition sizes (Section "Heuristics") ==========
+ *
+ * The paper's own heuristic: start from one partition per task, each of the
+ * Lemma 2 size (Section "Init partitions"), and while the partitions need
+ * more than M compute units in total (Pi > M; Lemma 3: Pi <= M means every
+ * partition schedulable on its own units, so the set is), pick a first
+ * operand and merge it with an eligible partner (Algorithm 3,
+ * select_partitions); a merge (Algorithm 2) is valid when the union is
+ * schedulable on fewer units than the two partitions apart (Definition 3),
+ * tried from max(m1, m2) upwards one unit at a time; a failed merge forbids
+ * its task pairs (Section "Forbidden list"), which ACT fills beforehand for
+ * every task pair.  Readings taken where the paper is silent or garbled:
+ *   - par_list is kept in decreasing partition utilisation U(P) (Q32, as for
+ *     H(pi)), ties by the partition's lowest task index; choose_from and
+ *     choose take the first element;
+ *   - order ">" (Definition 5, "BF") ranks the partners by U of the union at
+ *     the merge's starting size max(m1, m2), which needs no merge, ties by
+ *     par_list order; order ">>" (Definition 4, "SMS") computes every
+ *     eligible merge and ranks the valid ones by merged size, then U, then
+ *     par_list order;
+ *   - a merged partition never exceeds M units;
+ *   - every failed merge, also one computed while ranking for ">>", forbids
+ *     all of its cross task pairs;
+ *   - the algorithm fails when no partition has an eligible partner left.
+ * Output: the final partitions in par_list order (sizes, task -> partition),
+ * response times, and counters of merges tried and accepted.
+ */
+typedef struct {
+    int mem[OR_MAXN];
+    int cnt, m, lead; /* members, units, lowest task index */
+    uint64_t U;       /* Q32 utilisation on m units */
+} or_part;
+
+/* Q32 utilisation of a task group on m units, schedulable or not */
+static uint64_t or_group_util(const or_set *s, const int *mem, int cnt, int m)
+{
+    u128 acc = 0;
+    int a, b;
+    for (a = 0; a < cnt; a++) {
+        int same = 0;
+        int64_t C;
+        for (b = 0; b < cnt; b++)
+            if (s->type[mem[b]] == s->type[mem[a]]) same++;
+        C = (same >= 2) ? or_cc(s, mem[a], m) : or_cn(s, mem[a], m);
+        acc += ((((u128)C) << 32) + (u128)s->T[mem[a]] - 1) / (u128)s->T[mem[a]];
+    }
+    return (uint64_t)acc;
+}
+
+static int or_part_before(const or_part *a, const or_part *b)
+{
+    if (a->U != b->U) return a->U > b->U;
+    return a->lead < b->lead;
+}
+
+static void or_sort_parts(or_part *p, int np)
+{
+    int a, b;
+    for (a = 1; a < np; a++) {
+        or_part x = p[a];
+        b = a - 1;
+        while (b >= 0 && or_part_before(&x, &p[b])) {
+            p[b + 1] = p[b];
+            b--;
+        }
+        p[b + 1] = x;
+    }
+}
+
+/* Algorithm 2: the union of a and b on the first m in [max(m1, m2), m1 + m2)
+ * (and <= M) that schedules it */
+static int or_merge(const or_set *s, const or_part *a, const or_part *b, or_part *out)
+{
+    int m, t;
+    out->cnt = 0;
+    for (t = 0; t < a->cnt; t++) out->mem[out->cnt++] = a->mem[t];
+    for (t = 0; t < b->cnt; t++) out->mem[out->cnt++] = b->mem[t];
+    out->lead = a->lead < b->lead ? a->lead : b->lead;
+    m = a->m > b->m ? a->m : b->m;
+    while (m < a->m + b->m && m <= s->M) {
+        uint64_t U = 0;
+        if (or_eval_part(s, out->mem, out->cnt, m, 1, NULL, &U)) {
+            out->m = m;
+            out->U = U;
+            return 1;
+        }
+        m++;
+    }
+    return 0;
+}
+
+static void or_forbid_cross(unsigned char *forb, int n, const or_part *a, const or_part *b)
+{
+    int x, y;
+    for (x = 0; x < a->cnt; x++)
+        for (y = 0; y < b->cnt; y++) {
+            forb[a->mem[x] * n + b->mem[y]] = 1;
+            forb[b->mem[y] * n + a->mem[x]] = 1;
+        }
+}
+
+static int or_pair_forbidden(const unsigned char *forb, int n, const or_part *a, const or_part *b)
+{
+    int x, y;
+    for (x = 0; x < a->cnt; x++)
+        for (y = 0; y < b->cnt; y++)
+            if (forb[a->mem[x] * n + b->mem[y]]) return 1;
+    return 0;
+}
+
+/* returns 1 (schedulable, Pi <= M) or 0; variant: OR_BF_* (">") or OR_SMS_* (">>") */
+static int or_alg1(const or_set *s, int variant, int flags, int *nparts, int32_t *sizes, int8_t *alloc,
+                   int64_t *R, int64_t *stats)
+{
+    const int n = s->n;
+    const int act = (variant == OR_BF_ACT || variant == OR_SMS_ACT);
+    const int sms = (variant == OR_SMS_INA || variant == OR_SMS_ACT);
+    or_part *parts = (or_part *)malloc(sizeof(or_part) * (size_t)n);
+    or_part *cand = (or_part *)malloc(sizeof(or_part) * (size_t)n);
+    unsigned char *forb = (unsigned char *)calloc((size_t)n * (size_t)n, 1);
+    int mm[OR_MAXN], okc[OR_MAXN], order[OR_MAXN];
+    uint64_t key[OR_MAXN];
+    int np = 0, i, j, c, Pi = 0, ok = 0;
+    stats[0] = stats[1] = 0;
+    *nparts = 0;
+    for (i = 0; i < n; i++) { alloc[i] = -1; R[i] = -1; }
+    if (!(flags & OR_FLAG_NO_LEMMA1) && or_lemma1_reject(s)) goto done;
+    /* init partitions (Lemma 2 sizes) */
+    for (i = 0; i < n; i++) {
+        mm[i] = or_m_min(s, i);
+        if (mm[i] >= OR_MINF) goto done;
+        parts[np].mem[0] = i;
+        parts[np].cnt = 1;
+        parts[np].m = mm[i];
+        parts[np].lead = i;
+        parts[np].U = or_group_util(s, &i, 1, mm[i]);
+        np++;
+    }
+    or_sort_parts(parts, np);
+    if (act)
+        for (i = 0; i < n; i++)
+            for (j = i + 1; j < n; j++)
+                if (or_forbidden(s, i, j, mm)) forb[i * n + j] = forb[j * n + i] = 1;
+    for (;;) {
+        int merged = 0;
+        Pi = 0;
+        for (c = 0; c < np; c++) Pi += parts[c].m;
+        if (Pi <= s->M) { ok = 1; break; }
+        /* Algorithm 3: first operand in par_list order with an eligible partner */
+        for (c = 0; c < np && !merged; c++) {
+            int ne = 0, a, b;
+            for (j = 0; j < np; j++)
+                if (j != c && !or_pair_forbidden(forb, n, &parts[c], &parts[j])) order[ne++] = j;
+            if (ne == 0) continue;
+            /* rank the eligible partners */
+            for (a = 0; a < ne; a++) {
+                j = order[a];
+                if (sms) {
+                    stats[0]++;
+                    okc[a] = or_merge(s, &parts[c], &parts[j], &cand[a]);
+                    if (!okc[a]) or_forbid_cross(forb, n, &parts[c], &parts[j]);
+                    key[a] = okc[a] ? (((uint64_t)cand[a].m) << 40) : ~0ull;
+                } else {
+                    or_part u;
+                    int m0 = parts[c].m > parts[j].m ? parts[c].m : parts[j].m, t;
+                    u.cnt = 0;
+                    for (t = 0; t < parts[c].cnt; t++) u.mem[u.cnt++] = parts[c].mem[t];
+                    for (t = 0; t < parts[j].cnt; t++) u.mem[u.cnt++] = parts[j].mem[t];
+                    key[a] = or_group_util(s, u.mem, u.cnt, m0);
+                    okc[a] = -1; /* not merged yet */
+                }
+            }
+            /* stable insertion sort of (order, key, okc, cand) by key; for ">>"
+               ties by U of the merge */
+            for (a = 1; a < ne; a++) {
+                int xo = order[a], xk2 = okc[a];
+                uint64_t xk = key[a];
+                or_part xc = cand[a];
+                b = a - 1;
+                while (b >= 0) {
+                    int later = key[b] > xk;
+                    if (sms && key[b] == xk && okc[b] == 1 && xk2 == 1) later = cand[b].U > xc.U;
+                    if (!later) break;
+                    order[b + 1] = order[b]; key[b + 1] = key[b]; okc[b + 1] = okc[b]; cand[b + 1] = cand[b];
+                    b--;
+                }
+                order[b + 1] = xo; key[b + 1] = xk; okc[b + 1] = xk2; cand[b + 1] = xc;
+            }
+            /* Algorithm 1's repeat loop: merge with the partners in order */
+            for (a = 0; a < ne && !merged; a++) {
+                or_part m3;
+                j = order[a];
+                if (sms) {
+                    if (okc[a] != 1) break; /* only failed merges remain (already forbidden) */
+                    m3 = cand[a];
+                } else {
+                    stats[0]++;
+                    if (!or_merge(s, &parts[c], &parts[j], &m3)) {
+                        or_forbid_cross(forb, n, &parts[c], &parts[j]);
+                        continue;
+                    }
+                }
+                stats[1]++;
+                /* par_list minus the two operands, plus the merge, in order */
+                {
+                    int lo = c < j ? c : j, hi = c < j ? j : c, t, w = 0;
+                    for (t = 0; t < np; t++)
+                        if (t != lo && t != hi) parts[w++] = parts[t];
+                    parts[w++] = m3;
+                    np = w;
+                    or_sort_parts(parts, np);
+                }
+                merged = 1;
+            }
+        }
+        if (!merged) break; /* no partition has an eligible partner: fail */
+    }
+done:
+    if (ok) {
+        *nparts = np;
+        for (c = 0; c < np; c++) {
+            int t;
+            sizes[c] = parts[c].m;
+            for (t = 0; t < parts[c].cnt; t++) alloc[parts[c].mem[t]] = (int8_t)c;
+            or_eval_part(s, parts[c].mem, parts[c].cnt, parts[c].m, 0, R, NULL);
+        }
+    }
+    free(parts);
+    free(cand);
+    free(forb);
+    return ok;
+}
+
+int or_alg1_ex(OR_SET_ARGS, int variant, int flags, int32_t *nparts, int32_t *sizes, int8_t *alloc, int64_t *R,
+               int64_t *stats)
+{
+    or_set s;
+    int np = 0, ok;
+    OR_SET_INIT(s);
+    if (n < 1 || n > OR_MAXN || M < 1) return -1;
+    ok = or_alg1(&s, variant, flags, &np, sizes, alloc, R, stats);
+    *nparts = np;
+    return ok;
+}
