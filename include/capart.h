@@ -210,6 +210,67 @@ capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in,
                                  capart_results *dev_out, void *hip_stream);
 
 /*
+ * Algorithm 1 with free partition sizes (Section "Heuristics": Algorithms 1,
+ * 2 and 3, Definitions 3-5, Lemma 3).  Each task starts alone on a partition
+ * of its Lemma 2 size; while the partitions need more than M units in total,
+ * the first partition in par_list order that has an eligible partner (no
+ * forbidden task pair between the two) is merged with one of them.  A merge
+ * (Algorithm 2) is valid when the union is schedulable on some m in
+ * [max(m1, m2), m1 + m2 - 1], m <= M, and takes the least such m.  par_list is
+ * kept in decreasing Q32 utilisation U(P), ties by the partition's lowest task
+ * index.  opt->alloc_mode picks the order and the forbidden list:
+ *   CAPART_HEUR_BF_*  order ">" (Definition 5): partners ranked by U of the
+ *                     union at max(m1, m2), ties by par_list position; the
+ *                     first valid merge in that order is taken;
+ *   CAPART_HEUR_SMS_* order ">>" (Definition 4): every eligible merge is
+ *                     computed and the valid one with the fewest units, then
+ *                     least U, then par_list position, is taken;
+ *   *_INA             forbidden pairs only from failed merges: a failed merge
+ *                     (for ">" one tried before the merge taken, for ">>" any)
+ *                     forbids every task pair across its two partitions;
+ *   *_ACT             in addition every pair whose two-task merge is invalid
+ *                     (Definition 3) is forbidden from the start.
+ * The set is schedulable (verdict 1) once the units fit M (Lemma 3), and not
+ * schedulable (verdict 0) when Lemma 1 rejects it (unless
+ * CAPART_FLAG_NO_LEMMA1), a task has no Lemma 2 size within M, or no partition
+ * has an eligible partner left.  opt->K is not used (any value 1..8);
+ * CAPART_EXHAUSTIVE is E_INVAL; flags other than NO_LEMMA1 have no effect.
+ * Per-set validation as for capart_solve (status[s], the set's outputs then
+ * hold the failure values).
+ *
+ * Results (caller-owned; device pointers for the async call, host pointers for
+ * capart_alg1):
+ *   status[S], verdict[S];
+ *   nparts[S]   number of partitions (0 when not schedulable);
+ *   sizes[N]    set s's partition sizes in par_list order at
+ *               sizes[set_offset[s] .. set_offset[s] + nparts[s]), the rest of
+ *               the set's slots 0 (a set of n tasks has at most n partitions);
+ *   alloc[N]    each task's partition (index into that set's sizes), -1 if none;
+ *   R[N]        response time on its partition, -1 if none;
+ *   tried[S], merged[S]  merges attempted (Algorithm 2 runs the algorithm
+ *               asks for) and accepted; both 0 for sets rejected before any.
+ * One wave of 64 lanes per set; every set of the batch runs in one launch
+ * (after the prep kernel) ordered on hip_stream.
+ */
+typedef struct capart_alg1_results {
+    int32_t *status;
+    uint8_t *verdict;
+    int32_t *nparts;
+    int32_t *sizes;
+    int8_t *alloc;
+    int64_t *R;
+    int64_t *tried;
+    int64_t *merged;
+} capart_alg1_results;
+
+/* Algorithm 1 over a batch in device memory; results in device memory. */
+capart_status capart_alg1_async(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                capart_alg1_results *dev_out, void *hip_stream);
+/* Algorithm 1 over a batch in host memory; results in host memory (synchronous). */
+capart_status capart_alg1(capart_ctx *ctx, const capart_tasksets *host_in, const capart_options *opt,
+                          capart_alg1_results *host_out);
+
+/*
  * Batched form.  A plan binds one device-resident batch (capart_tasksets with
  * device pointers) and its device result buffers, and prepares one persistent
  * launch over all of it: the per-set sizes are read back once (set_offset and

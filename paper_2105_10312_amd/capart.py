@@ -29,7 +29,8 @@ EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
            "capart_plan_destroy", "capart_server_create", "capart_server_submit", "capart_server_poll",
-           "capart_server_stats_get", "capart_server_replay", "capart_server_destroy", "capart_count_work"]
+           "capart_server_stats_get", "capart_server_replay", "capart_server_destroy", "capart_count_work",
+           "capart_alg1", "capart_alg1_async"]
 
 _vp = C.c_void_p
 
@@ -48,6 +49,16 @@ class capart_results(C.Structure):
     _fields_ = [("status", _vp), ("verdict", _vp), ("verdict_1g", _vp), ("pidx", _vp), ("sizes", _vp),
                 ("aidx", _vp), ("maxU", _vp), ("sumU", _vp), ("n_evals", _vp), ("alloc", _vp), ("R", _vp),
                 ("R_1g", _vp), ("dbg_key", _vp), ("dbg_offset", _vp)]
+
+
+class capart_alg1_results(C.Structure):
+    _fields_ = [("status", _vp), ("verdict", _vp), ("nparts", _vp), ("sizes", _vp), ("alloc", _vp), ("R", _vp),
+                ("tried", _vp), ("merged", _vp)]
+
+
+ALG1_FIELDS = [("status", np.int32, "S"), ("verdict", np.uint8, "S"), ("nparts", np.int32, "S"),
+               ("sizes", np.int32, "N"), ("alloc", np.int8, "N"), ("R", np.int64, "N"),
+               ("tried", np.int64, "S"), ("merged", np.int64, "S")]
 
 
 class capart_tuning(C.Structure):
@@ -115,6 +126,9 @@ def load_library():
                                         _vp, _vp, _vp]
         lib.capart_solve.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results)]
         lib.capart_solve_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp]
+        lib.capart_alg1.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results)]
+        lib.capart_alg1_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results),
+                                          _vp]
         lib.capart_set_tuning.argtypes = [_vp, P(capart_tuning)]
         lib.capart_get_tuning.argtypes = [_vp, P(capart_tuning)]
         lib.capart_timing_enable.argtypes = [_vp, C.c_int]
@@ -345,6 +359,42 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
                                              C.c_void_p(stream.cuda_stream)), ctx)
 
 
+def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, max_M=None) -> dict:
+    """Algorithm 1 (free partition sizes) over a host batch (synchronous); numpy results.
+    sizes[set_offset[s] : set_offset[s] + nparts[s]] are set s's partitions in par_list order."""
+    h = _host_ts(ts)
+    st, _keep = make_tasksets(h, max_tasks, max_M)
+    opt = make_options(1, mode, flags)
+    S, N = st.n_sets, st.n_tasks_total
+    out = {name: np.zeros(max(S if shape == "S" else N, 1), dt) for name, dt, shape in ALG1_FIELDS}
+    res = capart_alg1_results(*[_ptr(out[f[0]]) for f in ALG1_FIELDS])
+    _check(load_library().capart_alg1(ctx, C.byref(st), C.byref(opt), C.byref(res)), ctx)
+    return {name: out[name][:(S if shape == "S" else N)] for name, dt, shape in ALG1_FIELDS}
+
+
+def device_alg1_results(S: int, N: int, device="cuda") -> dict:
+    """Result tensors on the GPU for capart_alg1_async."""
+    import torch
+    tmap = {np.int32: torch.int32, np.uint8: torch.uint8, np.int64: torch.int64, np.int8: torch.int8}
+    return {name: torch.empty(max(S if shape == "S" else N, 1), dtype=tmap[dt], device=device)
+            for name, dt, shape in ALG1_FIELDS}
+
+
+def capart_alg1_async(ctx, dev_ts: dict, mode, dev_out: dict, stream=None, flags: int = 0, max_tasks=None,
+                      max_M=None) -> None:
+    """Algorithm 1 over a batch resident in GPU memory; results land in dev_out on `stream`."""
+    import torch
+    if max_tasks is None or max_M is None:
+        raise ValueError("device batches need declared max_tasks and max_M bounds")
+    st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
+    opt = make_options(1, mode, flags)
+    res = capart_alg1_results(*[_ptr(dev_out[f[0]]) for f in ALG1_FIELDS])
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load_library().capart_alg1_async(ctx, C.byref(st), C.byref(opt), C.byref(res),
+                                            C.c_void_p(stream.cuda_stream)), ctx)
+
+
 def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0,
                       frontier: int = 0, memo: int = 0) -> None:
     t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier), int(memo))
@@ -534,6 +584,9 @@ class Engine:
 
     def solve(self, ts, K, mode="BF_INA", flags=0, debug=False):
         return capart_solve(self.ctx, ts, K, mode, flags, debug)
+
+    def alg1(self, ts, mode="BF_INA", flags=0):
+        return capart_alg1(self.ctx, ts, mode, flags)
 
     def test_triple(self, task, sizes, alloc):
         return capart_test_triple(self.ctx, task, sizes, alloc)

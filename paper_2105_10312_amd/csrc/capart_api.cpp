@@ -357,12 +357,9 @@ capart_status launch_three(capart_ctx *c, const Batch &b, const Work &w, const O
     return CAPART_OK;
 }
 
-capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &p, hipStream_t st,
-                       uint32_t p_lo = 0u, uint32_t p_hi = 0xFFFFFFFFu)
+// Workspace arrays of the context for layout l (ensure_ws first).
+Work bind_work(capart_ctx *c, const WsLayout &l)
 {
-    const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
-    capart_status rc = ensure_ws(c, l.total);
-    if (rc != CAPART_OK) return rc;
     char *base = (char *)c->ws;
     Work w{};
     w.rec = (TaskRec *)(base + l.rec);
@@ -373,6 +370,16 @@ capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &
     w.partial = (uint64_t *)(base + l.partial);
     w.np = c->np_dev;
     w.order = c->order_dev;
+    return w;
+}
+
+capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &p, hipStream_t st,
+                       uint32_t p_lo = 0u, uint32_t p_hi = 0xFFFFFFFFu)
+{
+    const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
+    capart_status rc = ensure_ws(c, l.total);
+    if (rc != CAPART_OK) return rc;
+    const Work w = bind_work(c, l);
     if (p.L.flags & CAPART_FLAG_PER_SET_LAUNCH) {
         for (int64_t s = 0; s < p.S; s++) {
             Launch L1 = p.L;
@@ -660,6 +667,114 @@ static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const 
 capart_status capart_solve(capart_ctx *c, const capart_tasksets *in, const capart_options *opt, capart_results *out)
 {
     return solve_host(c, in, opt, out, 0u, 0xFFFFFFFFu);
+}
+
+// ---- Algorithm 1 (free partition sizes) ----------------------------------
+
+static capart_status alg1_check(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                const capart_alg1_results *out)
+{
+    if (!opt) return fail(c, CAPART_E_INVAL, "options is NULL");
+    if (opt->K < 1 || opt->K > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "K must be in [1, 8]");
+    if (opt->policy != CAPART_POLICY_FP_DM) return fail(c, CAPART_E_INVAL, "unsupported policy");
+    if (opt->alloc_mode < CAPART_HEUR_BF_INA || opt->alloc_mode > CAPART_HEUR_SMS_ACT)
+        return fail(c, CAPART_E_INVAL, "Algorithm 1 needs a heuristic order (CAPART_HEUR_*)");
+    if (opt->flags & ~(CAPART_FLAG_SKIP_1G | CAPART_FLAG_NO_LEMMA1 | CAPART_FLAG_PER_SET_LAUNCH))
+        return fail(c, CAPART_E_INVAL, "unknown flag");
+    capart_status rc = check_batch_shape(c, in);
+    if (rc != CAPART_OK) return rc;
+    if (in->n_sets > 0 && (!out || !out->status || !out->verdict || !out->nparts || !out->tried || !out->merged))
+        return fail(c, CAPART_E_INVAL, "NULL result array");
+    if (in->n_tasks_total > 0 && (!out->sizes || !out->alloc || !out->R))
+        return fail(c, CAPART_E_INVAL, "NULL result array");
+    return CAPART_OK;
+}
+
+capart_status capart_alg1_async(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                capart_alg1_results *out, void *hip_stream)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = alg1_check(c, in, opt, out)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const WsLayout l = ws_layout(in->n_sets, in->n_tasks_total, 1);
+    if ((rc = ensure_ws(c, l.total)) != CAPART_OK) return rc;
+    const Work w = bind_work(c, l);
+    Launch L{};
+    L.s0 = 0;
+    L.S = in->n_sets;
+    L.K = 1;
+    L.mode = opt->alloc_mode;
+    L.flags = opt->flags & CAPART_FLAG_NO_LEMMA1;
+    L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
+    const Batch b = make_batch(in);
+    Out po{};
+    po.status = out->status;
+    A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged};
+    const hipStream_t st = (hipStream_t)hip_stream;
+    (void)hipGetLastError();
+    if ((e = launch_prep(b, w, po, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if ((e = launch_alg1(b, w, a, L, st)) != hipSuccess) return hip_fail(c, e, "Algorithm 1 launch");
+    return CAPART_OK;
+}
+
+capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                          capart_alg1_results *out)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = alg1_check(c, in, opt, out)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    if (in->set_offset[0] != 0 || in->set_offset[in->n_sets] != in->n_tasks_total)
+        return fail(c, CAPART_E_INVAL, "set_offset must run from 0 to n_tasks_total");
+    const int64_t S = in->n_sets, N = in->n_tasks_total;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    size_t need = 0;
+    auto add = [&](size_t bytes) { need = align256(need + std::max<size_t>(bytes, 1)); };
+    add(8 * (S + 1)); add(4 * S);
+    add(8 * N); add(8 * N); add(8 * N); add(8 * N); add(4 * N); add(N);
+    add(4 * S); add(S); add(4 * S); add(4 * N); add(N); add(8 * N); add(8 * S); add(8 * S);
+    if ((rc = ensure_stage(c, need)) != CAPART_OK) return rc;
+    Bump bp{(char *)c->stage};
+    capart_tasksets d = *in;
+    int64_t *d_off = bp.take<int64_t>(S + 1);
+    int32_t *d_M = bp.take<int32_t>(S);
+    int64_t *d_T = bp.take<int64_t>(N), *d_D = bp.take<int64_t>(N), *d_Cs = bp.take<int64_t>(N),
+            *d_Cp = bp.take<int64_t>(N);
+    int32_t *d_k = bp.take<int32_t>(N);
+    uint8_t *d_ty = bp.take<uint8_t>(N);
+    capart_alg1_results r;
+    r.status = bp.take<int32_t>(S);
+    r.verdict = bp.take<uint8_t>(S);
+    r.nparts = bp.take<int32_t>(S);
+    r.sizes = bp.take<int32_t>(N);
+    r.alloc = bp.take<int8_t>(N);
+    r.R = bp.take<int64_t>(N);
+    r.tried = bp.take<int64_t>(S);
+    r.merged = bp.take<int64_t>(S);
+    const hipStream_t st = c->stream;
+    struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
+        {d_off, in->set_offset, 8 * (size_t)(S + 1)}, {d_M, in->M, 4 * (size_t)S},
+        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, 8 * (size_t)N},
+        {d_Cp, in->C_par, 8 * (size_t)N}, {d_k, in->k_permille, 4 * (size_t)N}, {d_ty, in->type, (size_t)N}};
+    for (const auto &x : h2d)
+        if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync H2D");
+    d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
+    d.type = d_ty;
+    if ((rc = capart_alg1_async(c, &d, opt, &r, st)) != CAPART_OK) return rc;
+    Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
+                {out->nparts, r.nparts, 4 * (size_t)S}, {out->sizes, r.sizes, 4 * (size_t)N},
+                {out->alloc, r.alloc, (size_t)N}, {out->R, r.R, 8 * (size_t)N},
+                {out->tried, r.tried, 8 * (size_t)S}, {out->merged, r.merged, 8 * (size_t)S}};
+    for (const auto &x : d2h)
+        if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(c, e, "hipMemcpyAsync D2H");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    return CAPART_OK;
 }
 
 static capart_status one_set_check(capart_ctx *c, const capart_tasksets *one, const int32_t *sizes, int32_t k)

@@ -115,6 +115,17 @@ constexpr int MEMO_DEFAULT_LOG2 = 11;
 constexpr int MEMO_MAX_LOG2 = 13;
 
 hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+// Algorithm 1 (free partition sizes): device pointers of the results
+struct A1Out {
+    int32_t *status;
+    uint8_t *verdict;
+    int32_t *nparts;
+    int32_t *sizes;   // [N]: set s's part sizes from set_offset[s], par_list order, 0-padded
+    int8_t *alloc;    // [N]
+    int64_t *R;       // [N]
+    int64_t *tried, *merged;
+};
+hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st);
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 // evaluation restricted to partitioning indices [p_lo, p_hi)
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,

@@ -1604,6 +1604,224 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
 }
 
 // ---------------------------------------------------------------------------
+// Algorithm 1 with free partition sizes (Section "Heuristics"), one wave per
+// set.  par_list (LDS) holds the partitions as rank masks with their units
+// and Q32 utilisations, in decreasing utilisation (ties: lowest task index).
+// While they need more than M units, the first partition with an eligible
+// partner (Algorithm 3: no forbidden task pair between them) is merged: every
+// eligible partner's merge (Algorithm 2) is computed at once, one lane per
+// partner, the fewest units in [max(m1, m2), min(m1 + m2 - 1, M)] found by
+// binary search (schedulability is monotone in m, so this is the first size
+// of the paper's upward scan).  Order ">": partners ranked by the union's
+// utilisation at max(m1, m2), the first valid merge in that order is taken
+// and the merges ranked before it (all failed) forbid their task pairs.
+// Order ">>": the valid merge with the fewest units (then utilisation, then
+// par_list position) is taken and every failed merge forbids its pairs.
+// With ACT the forbidden pairs start from Definition 3's pair test (prep).
+
+// OR of 64-bit values across the wave
+__device__ __forceinline__ uint64_t wave_or(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint64_t)__shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
+// also where C > T (an unschedulable group): C is recomputed in 64 bits
+// where the u32 table saturates.
+__device__ __forceinline__ uint64_t util_term(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
+{
+    const uint32_t u = tb.U[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
+    if (u != 0xFFFFFFFFu) return (uint64_t)u + 1ull;
+    const uint64_t T = L.T[r];
+    const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
+    const uint64_t C = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
+    return ((C / T) << 32) + ((((C % T) << 32) + T - 1ull) / T);
+}
+
+// Q32 utilisation of rank set S on m units (schedulable or not), mod 2^64
+__device__ __forceinline__ uint64_t group_util(const SetLDS &L, const Tables &tb, uint64_t S, int m, uint64_t cm)
+{
+    uint64_t u = 0;
+    for (uint64_t h = S; h; h &= h - 1ull) {
+        const int r = __builtin_ctzll(h);
+        u += util_term(L, tb, r, m, (uint32_t)((cm >> r) & 1ull));
+    }
+    return u;
+}
+
+template <bool ACT, bool SMS>
+__global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Launch Lp)
+{
+    __shared__ SetLDS L;
+    __shared__ uint64_t pmask[MAXN], pU[MAXN], fmask[MAXN], xmask[MAXN], xU[MAXN];
+    __shared__ int32_t pm[MAXN], plead[MAXN], xm[MAXN], xlead[MAXN];
+    const int64_t s = Lp.s0 + blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t f = w.setflags[s];
+    const int64_t off0 = b.off[s], off1 = b.off[s + 1];
+    auto write_failure = [&](int64_t tried, int64_t merged) {
+        if (lane == 0) {
+            o.verdict[s] = 0;
+            o.nparts[s] = 0;
+            o.tried[s] = tried;
+            o.merged[s] = merged;
+        }
+        if (off0 >= 0 && off1 >= off0 && off1 <= b.n_tasks_total)
+            for (int64_t i = off0 + lane; i < off1; i += 64) { o.sizes[i] = 0; o.alloc[i] = -1; o.R[i] = -1; }
+    };
+    if (!(f & SETF_VALID)) { write_failure(0, 0); return; }
+    const int n = (int)(off1 - off0);
+    const int M = b.M[s];
+    Tables tb;
+    stage_set(L, w, off0, n, M, s, ACT, tb);
+    if (f & SETF_LEMMA1) { write_failure(0, 0); return; }
+    const uint64_t memm = L.memmask;
+    // init partitions: one per task, of its Lemma 2 size
+    bool bad = false;
+    if (lane < n) {
+        const int m = (int)L.mmin[lane];
+        bad = m > M;
+        pmask[lane] = 1ull << lane;
+        pm[lane] = bad ? 1 : m;
+        pU[lane] = bad ? 0ull : (uint64_t)tb.U[(m - 1) * 2 * n + lane] + 1ull;
+        plead[lane] = L.orig[lane];
+        fmask[lane] = ACT ? L.forbid[lane] : 0ull;
+    }
+    if (__any(bad)) { write_failure(0, 0); return; }
+    int np = n;
+    int64_t tried = 0, merged = 0;
+    // par_list order: each partition's position = how many precede it
+    auto sort_parts = [&]() {
+        __syncthreads();
+        if (lane < np) {
+            const uint64_t u = pU[lane];
+            const int ld = plead[lane];
+            int pos = 0;
+            for (int j = 0; j < np; j++) pos += (pU[j] > u || (pU[j] == u && plead[j] < ld)) ? 1 : 0;
+            xmask[pos] = pmask[lane]; xU[pos] = u; xm[pos] = pm[lane]; xlead[pos] = ld;
+        }
+        __syncthreads();
+        if (lane < np) { pmask[lane] = xmask[lane]; pU[lane] = xU[lane]; pm[lane] = xm[lane]; plead[lane] = xlead[lane]; }
+        __syncthreads();
+    };
+    sort_parts();
+    bool ok = false;
+    for (;;) {
+        const uint64_t Pi = wave_sum_u64(lane < np ? (uint64_t)pm[lane] : 0ull);
+        if (Pi <= (uint64_t)M) { ok = true; break; }
+        bool done = false;
+        for (int c = 0; c < np && !done; c++) {
+            const uint64_t Sc = pmask[c];
+            // tasks forbidden with some member of P_c
+            const uint64_t Fc = wave_or(((Sc >> lane) & 1ull) && lane < n ? fmask[lane] : 0ull);
+            const bool elig = lane < np && lane != c && (pmask[lane] & Fc) == 0ull;
+            if (!__any(elig)) continue;
+            // every eligible partner's merge, one lane each; rank key (ka, lane):
+            // ">" the union's utilisation at max(m1, m2), ">>" (units, U) of
+            // the merge (valid merges only)
+            bool mok = false;
+            int m3 = 0;
+            uint64_t U3 = 0, ka = ~0ull;
+            uint64_t S3 = 0;
+            if (elig) {
+                S3 = Sc | pmask[lane];
+                const uint64_t cm = conflict_mask<uint64_t>(S3, memm);
+                const int mlo = max(pm[c], pm[lane]), mhi = min(pm[c] + pm[lane] - 1, M);
+                if (!SMS) ka = group_util(L, tb, S3, mlo, cm);
+                NoTally nt;
+                if (mlo <= mhi && test_from<uint64_t>(L, tb, S3, 0, mhi, cm, nt)) {
+                    int lo = mlo, hi = mhi;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (test_from<uint64_t>(L, tb, S3, 0, mid, cm, nt))
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    mok = true;
+                    m3 = lo;
+                    U3 = group_util(L, tb, S3, lo, cm);
+                }
+                if (SMS && mok) ka = ((uint64_t)m3 << 44) | U3;  // U3 <= 64 * 2^32: every member meets D <= T
+            }
+            // the merge taken: the valid one of least (ka, lane); for ">" that is
+            // the first valid merge in rank order, for ">>" the best one
+            const uint64_t best_a = wave_min_u64(mok ? ka : ~0ull);
+            const int best_l = (int)wave_min_u64(mok && ka == best_a ? (uint64_t)lane : 64ull);
+            const bool before = ka < best_a || (ka == best_a && lane < best_l);
+            // failed merges that forbid their pairs: for ">" those ranked before
+            // the merge taken (all of them if none is valid), for ">>" all
+            const bool forbid = elig && !mok && (SMS || before);
+            tried += (int64_t)__popcll(__ballot(elig && (SMS || before || lane == best_l)));
+            if (forbid) {
+                const uint64_t Sj = pmask[lane];
+                for (uint64_t h = Sc; h; h &= h - 1ull) atomicOr((unsigned long long *)&fmask[__builtin_ctzll(h)], (unsigned long long)Sj);
+                for (uint64_t h = Sj; h; h &= h - 1ull) atomicOr((unsigned long long *)&fmask[__builtin_ctzll(h)], (unsigned long long)Sc);
+            }
+            __syncthreads();
+            if (best_l == 64) continue;
+            // merge P_c with partner j: par_list minus both, plus the union
+            const int j = best_l;
+            const uint64_t Sj_all = __shfl(S3, j, 64);
+            const int mj = __shfl(m3, j, 64);
+            const uint64_t Uj = __shfl(U3, j, 64);
+            const int lead = min(plead[c], plead[j]);
+            __syncthreads();
+            if (lane == 0) {
+                int wpos = 0;
+                for (int t = 0; t < np; t++)
+                    if (t != c && t != j) {
+                        xmask[wpos] = pmask[t]; xU[wpos] = pU[t]; xm[wpos] = pm[t]; xlead[wpos] = plead[t];
+                        wpos++;
+                    }
+                xmask[wpos] = Sj_all; xU[wpos] = Uj; xm[wpos] = mj; xlead[wpos] = lead;
+                for (int t = 0; t <= wpos; t++) { pmask[t] = xmask[t]; pU[t] = xU[t]; pm[t] = xm[t]; plead[t] = xlead[t]; }
+            }
+            np -= 1;
+            merged += 1;
+            sort_parts();
+            done = true;
+        }
+        if (!done) break;  // no partition has an eligible partner: fail
+    }
+    if (!ok) { write_failure(tried, merged); return; }
+    if (lane == 0) {
+        o.verdict[s] = 1;
+        o.nparts[s] = np;
+        o.tried[s] = tried;
+        o.merged[s] = merged;
+    }
+    for (int t = lane; t < n; t += 64) o.sizes[off0 + t] = t < np ? pm[t] : 0;
+    if (lane < n) {
+        int part = 0;
+        for (int t = 0; t < np; t++)
+            if ((pmask[t] >> lane) & 1ull) part = t;
+        const uint64_t Sp = pmask[part];
+        const uint32_t R = rta_one<uint64_t>(L, tb, pm[part], lane, Sp & ((1ull << lane) - 1ull),
+                                             conflict_mask<uint64_t>(Sp, memm));
+        const int64_t gi = off0 + L.orig[lane];
+        o.alloc[gi] = (int8_t)part;
+        o.R[gi] = R ? (int64_t)R : -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Exhaustive allocation through subset tables (sets of at most 14 tasks, at
 // most 4 parts).  tab[set][m-1][A] = Q32 utilisation of task subset A (bits
 // = task indices within the set) on one partition of m units, or all ones if
@@ -2099,6 +2317,20 @@ hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, c
     return hipSuccess;
 }
 
+hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st)
+{
+    if (L.S <= 0) return hipSuccess;
+    const dim3 grid((unsigned)L.S), block(64);
+    const size_t lds = dyn_bytes(b);
+    switch (L.mode) {
+    case CAPART_HEUR_BF_INA: hipLaunchKernelGGL((alg1_kernel<false, false>), grid, block, lds, st, b, w, o, L); break;
+    case CAPART_HEUR_BF_ACT: hipLaunchKernelGGL((alg1_kernel<true, false>), grid, block, lds, st, b, w, o, L); break;
+    case CAPART_HEUR_SMS_INA: hipLaunchKernelGGL((alg1_kernel<false, true>), grid, block, lds, st, b, w, o, L); break;
+    default: hipLaunchKernelGGL((alg1_kernel<true, true>), grid, block, lds, st, b, w, o, L); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_subset_tables(const Batch &b, const Work &w, const Launch &L, uint64_t *tab, int64_t s_begin, int W,
                                 int Mtab, int ntab, hipStream_t st)
 {
@@ -2190,6 +2422,10 @@ hipError_t configure_kernels()
     if ((t = allow_heur_all<8, uint32_t>()) != hipSuccess) e = t;
     if ((t = allow_heur_all<8, uint64_t>()) != hipSuccess) e = t;
     CAPART_ALLOW((subset_table_kernel));
+    CAPART_ALLOW((alg1_kernel<false, false>));
+    CAPART_ALLOW((alg1_kernel<true, false>));
+    CAPART_ALLOW((alg1_kernel<false, true>));
+    CAPART_ALLOW((alg1_kernel<true, true>));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));

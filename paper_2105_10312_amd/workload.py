@@ -39,7 +39,7 @@ K_MEMORY = 2300
 
 __all__ = [
     "TaskSets", "uunifast", "gen_sets", "config_c1", "config_c2", "config_c3",
-    "config_c4", "config_c5_query_sizes", "concat", "subset", "TYPE_COMPUTE",
+    "config_c4", "config_c5_query_sizes", "config_paper_fig4", "concat", "subset", "TYPE_COMPUTE",
     "TYPE_MEMORY",
 ]
 
@@ -236,3 +236,18 @@ def config_c5_query_sizes(seed: int, n_queries: int):
 def config_c5(seed: int = 5, n_queries: int = 1000) -> TaskSets:
     n, U, M = config_c5_query_sizes(seed, n_queries)
     return gen_sets(seed, n, U, M, tmin=1e3, tmax=1e6)
+
+
+def config_paper_fig4(seed: int = 6, n: int = 50, M: int = 68, sets_per_point: int = 100,
+                      U_points=None) -> TaskSets:
+    """The paper's own experiment (Section "Task set generation", Fig. 4):
+    n = 50 tasks, M = 68 compute units, utilisation U = 2, 4, .., 68 with
+    100 sets per point (sets ordered by point), periods 50..4000 us
+    (log-uniform here: the paper's period list is not given), D = 0.75 T,
+    C_seq = 0.02/1.02 (compute) or 0.1/1.1 (memory) of the one-unit time,
+    k = 1.2 / 2.3, prm = 50 %."""
+    if U_points is None:
+        U_points = np.arange(2, M + 1, 2, dtype=np.float64)
+    U = np.repeat(np.asarray(U_points, np.float64), sets_per_point)
+    S = U.shape[0]
+    return gen_sets(seed, np.full(S, n), U, np.full(S, M), tmin=50, tmax=4000, deadline=0.75, fsplit="paper")
