@@ -127,12 +127,97 @@ def serving_leg(eng, capart, workload, rate, n_queries, seed=5):
             "evals_per_s": st["evals_per_s"], "mean_batch": st["mean_batch"], "rejected": st["rejected"]}
 
 
+def alg1_cpu_baseline(ts, mode, threads):
+    """The oracle's Algorithm 1 over every set of the workload, on `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        v = list(ex.map(lambda s: oracle.alg1(ts.set(s), mode)["verdict"], range(ts.n_sets)))
+    return {"seconds": time.perf_counter() - t0, "sets": ts.n_sets, "schedulable": int(sum(v))}
+
+
+def alg1_main(args, eng, capart, workload, sync, threads):
+    """Algorithm 1 with free partition sizes on the paper's Fig. 4 workload:
+    n = 50 tasks, M = 68 units, U = 2..68 step 2, `--n-sets` sets per point
+    (default 1000); one step = the whole batch through capart_alg1_async."""
+    import numpy as np
+    mode = args.mode
+    per_point = args.n_sets or 1000
+    ts = workload.config_paper_fig4(sets_per_point=per_point)
+    S, N = ts.n_sets, ts.n_tasks
+    desc = (f"paper Fig. 4: {S} task sets ({per_point} per point, U = 2..68 step 2), n=50, M=68, "
+            f"D=0.75T, T log-uniform 50..4000 us, Algorithm 1 {mode}")
+    log(f"[bench] workload fig4: {desc}")
+    dev = capart.device_tasksets(ts)
+    out = capart.device_alg1_results(S, N)
+
+    def step():
+        capart.capart_alg1_async(eng.ctx, dev, mode, out, max_tasks=50, max_M=68)
+
+    for i in range(args.warmup):
+        step()
+        sync()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    st = out["status"][:S].cpu().numpy()
+    if not (st == 0).all():
+        raise SystemExit(f"bench: {int((st != 0).sum())} sets reported errors")
+    ms_per_step = timed(step, args.steps, sync)
+    value = S / (ms_per_step / 1000.0)
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.4g} sets/s")
+    capart.capart_timing_enable(eng.ctx, True)
+    capart.capart_timing_read(eng.ctx)
+    ms_timed = timed(step, args.steps, sync)
+    ms_k, n_k = capart.capart_timing_read(eng.ctx)
+    capart.capart_timing_enable(eng.ctx, False)
+    k_ms = ms_k["eval"] / max(1, n_k["eval"])
+    verdict = out["verdict"][:S].cpu().numpy()
+    nparts = out["nparts"][:S].cpu().numpy()
+    tried = out["tried"][:S].cpu().numpy()
+    rate = verdict.reshape(-1, per_point).mean(axis=1)
+    wout = capart.device_alg1_results(S, N)
+    work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, 50, 68)
+    del wout
+    log(f"[bench] Algorithm 1 kernel {k_ms:.3f} ms/launch, counted work {work}")
+    ops = work["terms"] * C_TERM + work["tests"] * C_TEST
+    achieved = ops / (k_ms / 1000.0)
+    kname = "alg1_kernel"
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved / PEAK_INT_LANE_OPS,
+            "traffic": traffic_bytes(f"{kname}_fig4_{mode.lower()}_traffic.json"),
+            "kernel": kname, "kernel_ms": k_ms, "ops_per_launch": ops, "work_per_launch": work,
+            "ops_per_term": C_TERM, "ops_per_test": C_TEST,
+            "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"])},
+            "step_ms_with_kernel_events": ms_timed}
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle (Algorithm 1) on all {S} sets with {threads} threads")
+        cb = alg1_cpu_baseline(ts, mode, threads)
+        if cb["schedulable"] != int(verdict.sum()):
+            raise SystemExit("bench: the oracle's schedulable count differs from the GPU's")
+        cpu = {"value": cb["sets"] / cb["seconds"], "unit": "sets/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {cb['sets']} sets of the workload, {cb['seconds']:.2f} s wall"}
+        log(f"[bench] CPU oracle: {cpu['value']:.4g} sets/s")
+    res = {"metric": "Algorithm 1 task sets/sec (free partition sizes)", "value": value, "unit": "sets/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": desc, "n_sets": S, "alloc_mode": mode, "sets_per_point": per_point},
+           "schedulability_by_U": {str(2 * (i + 1)): float(r) for i, r in enumerate(rate)},
+           "mean_partitions_when_schedulable": float(nparts[verdict == 1].mean()) if verdict.any() else None,
+           "mean_merges_tried": float(tried.mean()),
+           "roofline": roof, "cpu_baseline": cpu}
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "fig4"],
+                    help="fig4: the paper's Algorithm 1 (free partition sizes) on its Fig. 4 workload")
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
     ap.add_argument("--n-sets", type=int, default=0, help="override the workload's number of sets")
     ap.add_argument("--cpu-sample", type=int, default=0, help="task sets timed on the CPU oracle (0 = default)")
@@ -191,6 +276,10 @@ def main():
                "serving": legs, "roofline": None, "cpu_baseline": None}
         eng.close()
         print(json.dumps(res), flush=True)
+        return
+
+    if args.workload == "fig4":
+        alg1_main(args, eng, capart, workload, sync, threads)
         return
 
     if args.workload == "c2":

@@ -418,11 +418,18 @@ capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);
  * Synchronous.  E_INVAL for exhaustive mode or per-set launches. */
 capart_status capart_count_work(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
                                 capart_results *dev_out, void *hip_stream, int64_t *counts);
+/* Algorithmic work of Algorithm 1 (capart_alg1_async), counted by a counting
+ * variant of its kernel: counts[0] = response-time terms, counts[1] = exact
+ * partition tests (each Algorithm 2 size tried by its binary search).  Same
+ * arguments as capart_alg1_async; results are written as by it.  Synchronous. */
+capart_status capart_alg1_count_work(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                     capart_alg1_results *dev_out, void *hip_stream, int64_t *counts);
 
 /* Kernel timing.  While enabled on a context, every launch sequence of
  * capart_solve / capart_solve_async records HIP events on its own stream
  * before and after the prep, eval and final kernels (one sequence per batch,
- * or per set with CAPART_FLAG_PER_SET_LAUNCH).  capart_timing_read waits for
+ * or per set with CAPART_FLAG_PER_SET_LAUNCH); capart_alg1 / capart_alg1_async
+ * record the same way, with the Algorithm 1 kernel as "eval" and no final.  capart_timing_read waits for
  * the recorded events, returns the summed durations in milliseconds
  * (ms[0] prep, ms[1] eval, ms[2] final) and the number of launches of each
  * (launches[3]), and clears them.  Disabling drops unread records. */

@@ -30,7 +30,7 @@ EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
            "capart_plan_destroy", "capart_server_create", "capart_server_submit", "capart_server_poll",
            "capart_server_stats_get", "capart_server_replay", "capart_server_destroy", "capart_count_work",
-           "capart_alg1", "capart_alg1_async"]
+           "capart_alg1", "capart_alg1_async", "capart_alg1_count_work"]
 
 _vp = C.c_void_p
 
@@ -129,6 +129,8 @@ def load_library():
         lib.capart_alg1.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results)]
         lib.capart_alg1_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results),
                                           _vp]
+        lib.capart_alg1_count_work.argtypes = [_vp, P(capart_tasksets), P(capart_options),
+                                               P(capart_alg1_results), _vp, _vp]
         lib.capart_set_tuning.argtypes = [_vp, P(capart_tuning)]
         lib.capart_get_tuning.argtypes = [_vp, P(capart_tuning)]
         lib.capart_timing_enable.argtypes = [_vp, C.c_int]
@@ -393,6 +395,21 @@ def capart_alg1_async(ctx, dev_ts: dict, mode, dev_out: dict, stream=None, flags
         stream = torch.cuda.current_stream()
     _check(load_library().capart_alg1_async(ctx, C.byref(st), C.byref(opt), C.byref(res),
                                             C.c_void_p(stream.cuda_stream)), ctx)
+
+
+def capart_alg1_count_work(ctx, dev_ts: dict, mode, dev_out: dict, max_tasks: int, max_M: int, stream=None,
+                           flags: int = 0) -> dict:
+    """Counted work of Algorithm 1 on a device batch: response-time terms and exact tests."""
+    import torch
+    st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
+    opt = make_options(1, mode, flags)
+    res = capart_alg1_results(*[_ptr(dev_out[f[0]]) for f in ALG1_FIELDS])
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    counts = np.zeros(2, np.int64)
+    _check(load_library().capart_alg1_count_work(ctx, C.byref(st), C.byref(opt), C.byref(res),
+                                                 C.c_void_p(stream.cuda_stream), counts.ctypes.data), ctx)
+    return {"terms": int(counts[0]), "tests": int(counts[1])}
 
 
 def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0,

@@ -690,18 +690,18 @@ static capart_status alg1_check(capart_ctx *c, const capart_tasksets *in, const 
     return CAPART_OK;
 }
 
-capart_status capart_alg1_async(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
-                                capart_alg1_results *out, void *hip_stream)
+// Prep and Algorithm 1 launches on st; with counts, the counting variant, and
+// counts[0..1] get the response-time terms and exact tests (synchronous).
+static capart_status alg1_run(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                              capart_alg1_results *out, hipStream_t st, int64_t *counts)
 {
-    if (!c) return CAPART_E_INVAL;
     capart_status rc;
-    if ((rc = alg1_check(c, in, opt, out)) != CAPART_OK) return rc;
-    if (in->n_sets == 0) return CAPART_OK;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     const WsLayout l = ws_layout(in->n_sets, in->n_tasks_total, 1);
-    if ((rc = ensure_ws(c, l.total)) != CAPART_OK) return rc;
-    const Work w = bind_work(c, l);
+    if ((rc = ensure_ws(c, l.total + (counts ? 256 : 0))) != CAPART_OK) return rc;
+    Work w = bind_work(c, l);
+    if (counts) w.counters = (uint64_t *)((char *)c->ws + l.total);
     Launch L{};
     L.s0 = 0;
     L.S = in->n_sets;
@@ -712,12 +712,53 @@ capart_status capart_alg1_async(capart_ctx *c, const capart_tasksets *in, const 
     const Batch b = make_batch(in);
     Out po{};
     po.status = out->status;
-    A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged};
-    const hipStream_t st = (hipStream_t)hip_stream;
+    const A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged};
+    std::array<hipEvent_t, 4> ev{};
+    const bool tm = c->timing && !counts;
+    if (tm)
+        for (auto &x : ev)
+            if (!(x = take_event(c))) return fail(c, CAPART_E_DEVICE, "hipEventCreate failed");
     (void)hipGetLastError();
+    if (counts && (e = hipMemsetAsync(w.counters, 0, 16, st)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+    if (tm) hipEventRecord(ev[0], st);
     if ((e = launch_prep(b, w, po, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
-    if ((e = launch_alg1(b, w, a, L, st)) != hipSuccess) return hip_fail(c, e, "Algorithm 1 launch");
+    if (tm) hipEventRecord(ev[1], st);
+    if ((e = launch_alg1(b, w, a, L, st, counts != nullptr)) != hipSuccess) return hip_fail(c, e, "Algorithm 1 launch");
+    if (tm) {
+        hipEventRecord(ev[2], st);
+        hipEventRecord(ev[3], st);
+        c->ev_pending.push_back(ev);
+    }
+    if (counts) {
+        uint64_t h[2] = {0, 0};
+        if ((e = hipMemcpyAsync(h, w.counters, 16, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(c, e, "reading counters");
+        counts[0] = (int64_t)h[0];
+        counts[1] = (int64_t)h[1];
+    }
     return CAPART_OK;
+}
+
+capart_status capart_alg1_async(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                capart_alg1_results *out, void *hip_stream)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = alg1_check(c, in, opt, out)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    return alg1_run(c, in, opt, out, (hipStream_t)hip_stream, nullptr);
+}
+
+capart_status capart_alg1_count_work(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                     capart_alg1_results *out, void *hip_stream, int64_t *counts)
+{
+    if (!c || !counts) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = alg1_check(c, in, opt, out)) != CAPART_OK) return rc;
+    counts[0] = counts[1] = 0;
+    if (in->n_sets == 0) return CAPART_OK;
+    return alg1_run(c, in, opt, out, (hipStream_t)hip_stream, counts);
 }
 
 capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,

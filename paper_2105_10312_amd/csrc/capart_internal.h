@@ -125,7 +125,9 @@ struct A1Out {
     int64_t *R;       // [N]
     int64_t *tried, *merged;
 };
-hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st);
+// count: the counting variant (adds response-time terms and exact tests to w.counters[0..1])
+hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st,
+                       bool count = false);
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 // evaluation restricted to partitioning indices [p_lo, p_hi)
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,

@@ -1665,7 +1665,7 @@ __device__ __forceinline__ uint64_t group_util(const SetLDS &L, const Tables &tb
     return u;
 }
 
-template <bool ACT, bool SMS>
+template <bool ACT, bool SMS, typename TY>
 __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Launch Lp)
 {
     __shared__ SetLDS L;
@@ -1706,6 +1706,7 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
     if (__any(bad)) { write_failure(0, 0); return; }
     int np = n;
     int64_t tried = 0, merged = 0;
+    TY ty;
     // par_list order: each partition's position = how many precede it
     auto sort_parts = [&]() {
         __syncthreads();
@@ -1744,12 +1745,11 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
                 const uint64_t cm = conflict_mask<uint64_t>(S3, memm);
                 const int mlo = max(pm[c], pm[lane]), mhi = min(pm[c] + pm[lane] - 1, M);
                 if (!SMS) ka = group_util(L, tb, S3, mlo, cm);
-                NoTally nt;
-                if (mlo <= mhi && test_from<uint64_t>(L, tb, S3, 0, mhi, cm, nt)) {
+                if (mlo <= mhi && test_from<uint64_t>(L, tb, S3, 0, mhi, cm, ty)) {
                     int lo = mlo, hi = mhi;
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
-                        if (test_from<uint64_t>(L, tb, S3, 0, mid, cm, nt))
+                        if (test_from<uint64_t>(L, tb, S3, 0, mid, cm, ty))
                             hi = mid;
                         else
                             lo = mid + 1;
@@ -1799,6 +1799,18 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
             done = true;
         }
         if (!done) break;  // no partition has an eligible partner: fail
+    }
+    if constexpr (!std::is_same<TY, NoTally>::value) {
+        uint64_t a = ty.terms, bb = ty.tests;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+            a += __shfl_xor(a, o2, 64);
+            bb += __shfl_xor(bb, o2, 64);
+        }
+        if (lane == 0 && w.counters) {
+            atomicAdd((unsigned long long *)&w.counters[0], (unsigned long long)a);
+            atomicAdd((unsigned long long *)&w.counters[1], (unsigned long long)bb);
+        }
     }
     if (!ok) { write_failure(tried, merged); return; }
     if (lane == 0) {
@@ -2317,17 +2329,26 @@ hipError_t launch_eval_persistent(const Batch &b, const Work &w, const Out &o, c
     return hipSuccess;
 }
 
-hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st)
+template <typename TY>
+static void launch_alg1_ty(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st)
 {
-    if (L.S <= 0) return hipSuccess;
     const dim3 grid((unsigned)L.S), block(64);
     const size_t lds = dyn_bytes(b);
     switch (L.mode) {
-    case CAPART_HEUR_BF_INA: hipLaunchKernelGGL((alg1_kernel<false, false>), grid, block, lds, st, b, w, o, L); break;
-    case CAPART_HEUR_BF_ACT: hipLaunchKernelGGL((alg1_kernel<true, false>), grid, block, lds, st, b, w, o, L); break;
-    case CAPART_HEUR_SMS_INA: hipLaunchKernelGGL((alg1_kernel<false, true>), grid, block, lds, st, b, w, o, L); break;
-    default: hipLaunchKernelGGL((alg1_kernel<true, true>), grid, block, lds, st, b, w, o, L); break;
+    case CAPART_HEUR_BF_INA: hipLaunchKernelGGL((alg1_kernel<false, false, TY>), grid, block, lds, st, b, w, o, L); break;
+    case CAPART_HEUR_BF_ACT: hipLaunchKernelGGL((alg1_kernel<true, false, TY>), grid, block, lds, st, b, w, o, L); break;
+    case CAPART_HEUR_SMS_INA: hipLaunchKernelGGL((alg1_kernel<false, true, TY>), grid, block, lds, st, b, w, o, L); break;
+    default: hipLaunchKernelGGL((alg1_kernel<true, true, TY>), grid, block, lds, st, b, w, o, L); break;
     }
+}
+
+hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st, bool count)
+{
+    if (L.S <= 0) return hipSuccess;
+    if (count)
+        launch_alg1_ty<Tally>(b, w, o, L, st);
+    else
+        launch_alg1_ty<NoTally>(b, w, o, L, st);
     return hipGetLastError();
 }
 
@@ -2422,10 +2443,14 @@ hipError_t configure_kernels()
     if ((t = allow_heur_all<8, uint32_t>()) != hipSuccess) e = t;
     if ((t = allow_heur_all<8, uint64_t>()) != hipSuccess) e = t;
     CAPART_ALLOW((subset_table_kernel));
-    CAPART_ALLOW((alg1_kernel<false, false>));
-    CAPART_ALLOW((alg1_kernel<true, false>));
-    CAPART_ALLOW((alg1_kernel<false, true>));
-    CAPART_ALLOW((alg1_kernel<true, true>));
+    CAPART_ALLOW((alg1_kernel<false, false, NoTally>));
+    CAPART_ALLOW((alg1_kernel<true, false, NoTally>));
+    CAPART_ALLOW((alg1_kernel<false, true, NoTally>));
+    CAPART_ALLOW((alg1_kernel<true, true, NoTally>));
+    CAPART_ALLOW((alg1_kernel<false, false, Tally>));
+    CAPART_ALLOW((alg1_kernel<true, false, Tally>));
+    CAPART_ALLOW((alg1_kernel<false, true, Tally>));
+    CAPART_ALLOW((alg1_kernel<true, true, Tally>));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));

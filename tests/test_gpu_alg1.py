@@ -224,3 +224,17 @@ def test_async_matches_host(eng):
                                     else ts.n_tasks)] for k, v in out.items()}
         assert_same(got, eng.alg1(ts, mode), ts, f"async {mode}")
     torch.cuda.synchronize()
+
+
+def test_count_work_writes_same_results(eng):
+    ts = workload.config_paper_fig4(sets_per_point=5)
+    dev = capart.device_tasksets(ts)
+    for mode in ("BF_INA", "SMS_ACT"):
+        out = capart.device_alg1_results(ts.n_sets, ts.n_tasks)
+        work = capart.capart_alg1_count_work(eng.ctx, dev, mode, out, 50, 68)
+        got = {k: v.cpu().numpy()[:(ts.n_sets if k in ("status", "verdict", "nparts", "tried", "merged")
+                                    else ts.n_tasks)] for k, v in out.items()}
+        assert_same(got, eng.alg1(ts, mode), ts, f"count_work {mode}")
+        # every merge tried runs at least one exact test
+        assert work["tests"] >= int(got["tried"].sum()) > 0
+        assert work["terms"] >= work["tests"]
