@@ -1605,21 +1605,25 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
 
 // ---------------------------------------------------------------------------
 // Algorithm 1 with free partition sizes (Section "Heuristics"), one wave per
-// set.  par_list (LDS) holds the partitions as rank masks with their units
-// and Q32 utilisations, in decreasing utilisation (ties: lowest task index).
-// While they need more than M units, the first partition with an eligible
-// partner (Algorithm 3: no forbidden task pair between them) is merged: every
-// eligible partner's merge (Algorithm 2) is computed at once, one lane per
-// partner, the fewest units in [max(m1, m2), min(m1 + m2 - 1, M)] found by
-// binary search (schedulability is monotone in m, so this is the first size
-// of the paper's upward scan).  Order ">": partners ranked by the union's
-// utilisation at max(m1, m2), the first valid merge in that order is taken
-// and the merges ranked before it (all failed) forbid their task pairs.
-// Order ">>": the valid merge with the fewest units (then utilisation, then
-// par_list position) is taken and every failed merge forbids its pairs.
-// With ACT the forbidden pairs start from Definition 3's pair test (prep).
+// set.  Lane p holds par_list position p in registers: the partition's rank
+// mask, units, Q32 utilisation, lowest task index and the mask of tasks
+// forbidden with some member (a forbidden pair recorded on both partitions,
+// so P_j is an eligible partner of P_c iff P_j meets none of P_c's mask).
+// par_list is kept in decreasing utilisation (ties: lowest task index).
+// While the partitions need more than M units, the first partition with an
+// eligible partner (Algorithm 3) is found with one ballot, and every eligible
+// partner's merge (Algorithm 2) is computed at once, one lane per partner: the
+// fewest units in [max(m1, m2), min(m1 + m2 - 1, M)], by binary search
+// (schedulability is monotone in m, so this is the first size of the paper's
+// upward scan).  Order ">": partners ranked by the union's utilisation at
+// max(m1, m2); the first valid merge in that order is taken and the merges
+// ranked before it (all failed) forbid their task pairs.  Order ">>": the
+// valid merge with the fewest units (then utilisation, then par_list
+// position) is taken and every failed merge forbids its pairs.  With ACT the
+// forbidden pairs start from Definition 3's pair test (prep kernel).  A merge
+// replaces the two partitions by their union at its place in the order: every
+// lane's new position follows from one ballot, and a forward permute moves it.
 
-// OR of 64-bit values across the wave
 __device__ __forceinline__ uint64_t wave_or(uint64_t v)
 {
 #pragma unroll
@@ -1634,24 +1638,57 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     return v;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int readlane32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// forward permute: the value of this lane goes to lane dst (a permutation of the wave)
+__device__ __forceinline__ uint64_t permute64(uint64_t v, int dst)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int permute32(int v, int dst) { return __builtin_amdgcn_ds_permute(dst << 2, v); }
+
+// Records plus the execution-time table [m-1][conflict][rank] (u32, m = 1..M)
+__device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act,
+                                Tables &tb)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    stage_records(L, w, off, n, s, act);
+    uint32_t *tc = capart_dyn_lds;
+    for (int e = tid; e < n * M; e += nt) {
+        const int m = e / n + 1, r = e - (m - 1) * n;
+        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+        const int base = (m - 1) * 2 * n + r;
+        tc[base] = cn;
+        tc[base + n] = time_c(L.k[r], cn);
+    }
+    __syncthreads();
+    tb.C = tc;
+    tb.U = nullptr;
+    tb.n = n;
 }
 
 // Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
-// also where C > T (an unschedulable group): C is recomputed in 64 bits
-// where the u32 table saturates.
+// also where C > T (an unschedulable group; C is then recomputed in 64 bits,
+// the u32 table saturating above 2^31).
 __device__ __forceinline__ uint64_t util_term(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
 {
-    const uint32_t u = tb.U[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
-    if (u != 0xFFFFFFFFu) return (uint64_t)u + 1ull;
-    const uint64_t T = L.T[r];
+    const uint32_t C = tb.C[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
+    const uint32_t T = L.T[r];
+    if (C <= T) return (uint64_t)util_q32_m1_magic(C, T, L.clo[r], L.chi[r]) + 1ull;
+    const uint64_t T64 = T;
     const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
-    const uint64_t C = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
-    return ((C / T) << 32) + ((((C % T) << 32) + T - 1ull) / T);
+    const uint64_t C64 = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
+    return ((C64 / T64) << 32) + ((((C64 % T64) << 32) + T64 - 1ull) / T64);
 }
 
 // Q32 utilisation of rank set S on m units (schedulable or not), mod 2^64
@@ -1669,8 +1706,6 @@ template <bool ACT, bool SMS, typename TY>
 __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Launch Lp)
 {
     __shared__ SetLDS L;
-    __shared__ uint64_t pmask[MAXN], pU[MAXN], fmask[MAXN], xmask[MAXN], xU[MAXN];
-    __shared__ int32_t pm[MAXN], plead[MAXN], xm[MAXN], xlead[MAXN];
     const int64_t s = Lp.s0 + blockIdx.x;
     const int lane = threadIdx.x;
     const uint32_t f = w.setflags[s];
@@ -1689,116 +1724,114 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
     const int n = (int)(off1 - off0);
     const int M = b.M[s];
     Tables tb;
-    stage_set(L, w, off0, n, M, s, ACT, tb);
+    stage_set_times(L, w, off0, n, M, s, ACT, tb);
     if (f & SETF_LEMMA1) { write_failure(0, 0); return; }
     const uint64_t memm = L.memmask;
     // init partitions: one per task, of its Lemma 2 size
+    uint64_t Pm = 0, PF = 0, PU = 0;
+    int Pmu = 0, Pl = lane;
     bool bad = false;
     if (lane < n) {
         const int m = (int)L.mmin[lane];
         bad = m > M;
-        pmask[lane] = 1ull << lane;
-        pm[lane] = bad ? 1 : m;
-        pU[lane] = bad ? 0ull : (uint64_t)tb.U[(m - 1) * 2 * n + lane] + 1ull;
-        plead[lane] = L.orig[lane];
-        fmask[lane] = ACT ? L.forbid[lane] : 0ull;
+        Pm = 1ull << lane;
+        PF = ACT ? L.forbid[lane] : 0ull;
+        Pmu = bad ? 1 : m;
+        PU = bad ? 0ull : util_term(L, tb, lane, m, 0u);
+        Pl = L.orig[lane];
     }
     if (__any(bad)) { write_failure(0, 0); return; }
+    {
+        int pos = 0;
+        for (int j = 0; j < n; j++) {
+            const uint64_t uj = readlane64(PU, j);
+            const int lj = readlane32(Pl, j);
+            pos += (uj > PU || (uj == PU && lj < Pl)) ? 1 : 0;
+        }
+        if (lane >= n) pos = lane;
+        Pm = permute64(Pm, pos); PF = permute64(PF, pos); PU = permute64(PU, pos);
+        Pmu = permute32(Pmu, pos); Pl = permute32(Pl, pos);
+    }
     int np = n;
+    int Pi = 0;
+    for (int j = 0; j < n; j++) Pi += readlane32(Pmu, j);
     int64_t tried = 0, merged = 0;
     TY ty;
-    // par_list order: each partition's position = how many precede it
-    auto sort_parts = [&]() {
-        __syncthreads();
-        if (lane < np) {
-            const uint64_t u = pU[lane];
-            const int ld = plead[lane];
-            int pos = 0;
-            for (int j = 0; j < np; j++) pos += (pU[j] > u || (pU[j] == u && plead[j] < ld)) ? 1 : 0;
-            xmask[pos] = pmask[lane]; xU[pos] = u; xm[pos] = pm[lane]; xlead[pos] = ld;
-        }
-        __syncthreads();
-        if (lane < np) { pmask[lane] = xmask[lane]; pU[lane] = xU[lane]; pm[lane] = xm[lane]; plead[lane] = xlead[lane]; }
-        __syncthreads();
-    };
-    sort_parts();
     bool ok = false;
     for (;;) {
-        const uint64_t Pi = wave_sum_u64(lane < np ? (uint64_t)pm[lane] : 0ull);
-        if (Pi <= (uint64_t)M) { ok = true; break; }
-        bool done = false;
-        for (int c = 0; c < np && !done; c++) {
-            const uint64_t Sc = pmask[c];
-            // tasks forbidden with some member of P_c
-            const uint64_t Fc = wave_or(((Sc >> lane) & 1ull) && lane < n ? fmask[lane] : 0ull);
-            const bool elig = lane < np && lane != c && (pmask[lane] & Fc) == 0ull;
-            if (!__any(elig)) continue;
-            // every eligible partner's merge, one lane each; rank key (ka, lane):
-            // ">" the union's utilisation at max(m1, m2), ">>" (units, U) of
-            // the merge (valid merges only)
-            bool mok = false;
-            int m3 = 0;
-            uint64_t U3 = 0, ka = ~0ull;
-            uint64_t S3 = 0;
-            if (elig) {
-                S3 = Sc | pmask[lane];
-                const uint64_t cm = conflict_mask<uint64_t>(S3, memm);
-                const int mlo = max(pm[c], pm[lane]), mhi = min(pm[c] + pm[lane] - 1, M);
-                if (!SMS) ka = group_util(L, tb, S3, mlo, cm);
-                if (mlo <= mhi && test_from<uint64_t>(L, tb, S3, 0, mhi, cm, ty)) {
-                    int lo = mlo, hi = mhi;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (test_from<uint64_t>(L, tb, S3, 0, mid, cm, ty))
-                            hi = mid;
-                        else
-                            lo = mid + 1;
-                    }
-                    mok = true;
-                    m3 = lo;
-                    U3 = group_util(L, tb, S3, lo, cm);
+        if (Pi <= M) { ok = true; break; }
+        // partitions with an eligible partner; the first one is the operand
+        bool has = false;
+        for (int j = 0; j < np; j++) has |= (j != lane) && ((readlane64(Pm, j) & PF) == 0ull);
+        const uint64_t cand = __ballot(has && lane < np);
+        if (!cand) break;  // no partition has an eligible partner: fail
+        const int c = __builtin_ctzll(cand);
+        const uint64_t Sc = readlane64(Pm, c), Fc = readlane64(PF, c);
+        const int mc = readlane32(Pmu, c);
+        const bool elig = lane < np && lane != c && (Pm & Fc) == 0ull;
+        // every eligible partner's merge, one lane each; rank key (ka, lane):
+        // ">" the union's utilisation at max(m1, m2), ">>" (units, U) of the
+        // merge (valid merges only)
+        bool mok = false;
+        int m3 = 0;
+        uint64_t U3 = 0, ka = ~0ull, S3 = 0;
+        if (elig) {
+            S3 = Sc | Pm;
+            const uint64_t cm = conflict_mask<uint64_t>(S3, memm);
+            const int mlo = max(mc, Pmu), mhi = min(mc + Pmu - 1, M);
+            if (!SMS) ka = group_util(L, tb, S3, mlo, cm);
+            if (test_from<uint64_t>(L, tb, S3, 0, mhi, cm, ty)) {
+                int lo = mlo, hi = mhi;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (test_from<uint64_t>(L, tb, S3, 0, mid, cm, ty))
+                        hi = mid;
+                    else
+                        lo = mid + 1;
                 }
-                if (SMS && mok) ka = ((uint64_t)m3 << 44) | U3;  // U3 <= 64 * 2^32: every member meets D <= T
+                mok = true;
+                m3 = lo;
+                U3 = group_util(L, tb, S3, lo, cm);
             }
-            // the merge taken: the valid one of least (ka, lane); for ">" that is
-            // the first valid merge in rank order, for ">>" the best one
-            const uint64_t best_a = wave_min_u64(mok ? ka : ~0ull);
-            const int best_l = (int)wave_min_u64(mok && ka == best_a ? (uint64_t)lane : 64ull);
-            const bool before = ka < best_a || (ka == best_a && lane < best_l);
-            // failed merges that forbid their pairs: for ">" those ranked before
-            // the merge taken (all of them if none is valid), for ">>" all
-            const bool forbid = elig && !mok && (SMS || before);
-            tried += (int64_t)__popcll(__ballot(elig && (SMS || before || lane == best_l)));
-            if (forbid) {
-                const uint64_t Sj = pmask[lane];
-                for (uint64_t h = Sc; h; h &= h - 1ull) atomicOr((unsigned long long *)&fmask[__builtin_ctzll(h)], (unsigned long long)Sj);
-                for (uint64_t h = Sj; h; h &= h - 1ull) atomicOr((unsigned long long *)&fmask[__builtin_ctzll(h)], (unsigned long long)Sc);
-            }
-            __syncthreads();
-            if (best_l == 64) continue;
-            // merge P_c with partner j: par_list minus both, plus the union
-            const int j = best_l;
-            const uint64_t Sj_all = __shfl(S3, j, 64);
-            const int mj = __shfl(m3, j, 64);
-            const uint64_t Uj = __shfl(U3, j, 64);
-            const int lead = min(plead[c], plead[j]);
-            __syncthreads();
-            if (lane == 0) {
-                int wpos = 0;
-                for (int t = 0; t < np; t++)
-                    if (t != c && t != j) {
-                        xmask[wpos] = pmask[t]; xU[wpos] = pU[t]; xm[wpos] = pm[t]; xlead[wpos] = plead[t];
-                        wpos++;
-                    }
-                xmask[wpos] = Sj_all; xU[wpos] = Uj; xm[wpos] = mj; xlead[wpos] = lead;
-                for (int t = 0; t <= wpos; t++) { pmask[t] = xmask[t]; pU[t] = xU[t]; pm[t] = xm[t]; plead[t] = xlead[t]; }
-            }
-            np -= 1;
-            merged += 1;
-            sort_parts();
-            done = true;
+            if (SMS && mok) ka = ((uint64_t)m3 << 44) | U3;  // U3 <= 64 * 2^32: every member meets D <= T
         }
-        if (!done) break;  // no partition has an eligible partner: fail
+        // the merge taken: the valid one of least (ka, lane); for ">" that is
+        // the first valid merge in rank order, for ">>" the best one
+        const uint64_t best_a = wave_min_u64(mok ? ka : ~0ull);
+        const int best_l = (int)wave_min_u64(mok && ka == best_a ? (uint64_t)lane : 64ull);
+        const bool before = ka < best_a || (ka == best_a && lane < best_l);
+        // failed merges that forbid their pairs: for ">" those ranked before
+        // the merge taken (all of them if none is valid), for ">>" all
+        const bool forbid = elig && !mok && (SMS || before);
+        tried += (int64_t)__popcll(__ballot(elig && (SMS || before || lane == best_l)));
+        if (forbid) PF |= Sc;
+        const uint64_t Ffail = wave_or(forbid ? Pm : 0ull);
+        if (lane == c) PF |= Ffail;
+        if (best_l == 64) continue;  // P_c has no valid merge; its partners are now forbidden
+        // merge P_c with partner j: par_list minus both, plus the union
+        const int j = best_l;
+        const uint64_t Sj3 = readlane64(S3, j), Uj3 = readlane64(U3, j);
+        const uint64_t F3 = readlane64(PF, c) | readlane64(PF, j);
+        const int mj3 = readlane32(m3, j), mj = readlane32(Pmu, j);
+        const int lead = min(readlane32(Pl, c), readlane32(Pl, j));
+        const bool rem = lane < np && lane != c && lane != j;
+        const bool bnew = rem && (PU > Uj3 || (PU == Uj3 && Pl < lead));
+        const int pos_new = __popcll(__ballot(bnew));
+        const int r = lane - (lane > c ? 1 : 0) - (lane > j ? 1 : 0);
+        int dst = lane;
+        if (rem) {
+            dst = r + (r >= pos_new ? 1 : 0);
+        } else if (lane == c) {
+            dst = pos_new;
+            Pm = Sj3; PF = F3; PU = Uj3; Pmu = mj3; Pl = lead;
+        } else if (lane == j) {
+            dst = np - 1;
+        }
+        Pm = permute64(Pm, dst); PF = permute64(PF, dst); PU = permute64(PU, dst);
+        Pmu = permute32(Pmu, dst); Pl = permute32(Pl, dst);
+        np -= 1;
+        Pi += mj3 - mc - mj;
+        merged += 1;
     }
     if constexpr (!std::is_same<TY, NoTally>::value) {
         uint64_t a = ty.terms, bb = ty.tests;
@@ -1819,13 +1852,17 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
         o.tried[s] = tried;
         o.merged[s] = merged;
     }
-    for (int t = lane; t < n; t += 64) o.sizes[off0 + t] = t < np ? pm[t] : 0;
+    if (lane < n) o.sizes[off0 + lane] = lane < np ? Pmu : 0;
+    // each task's partition, then its response time there
+    int part = 0, mp = 1;
+    uint64_t Sp = 0;
+    for (int p = 0; p < np; p++) {
+        const uint64_t mk = readlane64(Pm, p);
+        const int mm = readlane32(Pmu, p);
+        if ((mk >> lane) & 1ull) { part = p; Sp = mk; mp = mm; }
+    }
     if (lane < n) {
-        int part = 0;
-        for (int t = 0; t < np; t++)
-            if ((pmask[t] >> lane) & 1ull) part = t;
-        const uint64_t Sp = pmask[part];
-        const uint32_t R = rta_one<uint64_t>(L, tb, pm[part], lane, Sp & ((1ull << lane) - 1ull),
+        const uint32_t R = rta_one<uint64_t>(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull),
                                              conflict_mask<uint64_t>(Sp, memm));
         const int64_t gi = off0 + L.orig[lane];
         o.alloc[gi] = (int8_t)part;
@@ -2333,7 +2370,7 @@ template <typename TY>
 static void launch_alg1_ty(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st)
 {
     const dim3 grid((unsigned)L.S), block(64);
-    const size_t lds = dyn_bytes(b);
+    const size_t lds = dyn_bytes(b) / 2;  // the execution-time half of the per-set tables
     switch (L.mode) {
     case CAPART_HEUR_BF_INA: hipLaunchKernelGGL((alg1_kernel<false, false, TY>), grid, block, lds, st, b, w, o, L); break;
     case CAPART_HEUR_BF_ACT: hipLaunchKernelGGL((alg1_kernel<true, false, TY>), grid, block, lds, st, b, w, o, L); break;
