@@ -1606,9 +1606,10 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
 // ---------------------------------------------------------------------------
 // Algorithm 1 with free partition sizes (Section "Heuristics"), one wave per
 // set.  Lane p holds par_list position p in registers: the partition's rank
-// mask, units, Q32 utilisation, lowest task index and the mask of tasks
-// forbidden with some member (a forbidden pair recorded on both partitions,
-// so P_j is an eligible partner of P_c iff P_j meets none of P_c's mask).
+// mask, units, Q32 utilisation, lowest task index and the set of partitions
+// it may not merge with, as a mask of partition ids (a partition's id is its
+// lowest rank; a forbidden task pair puts each partition's id in the other's
+// mask, a merge keeps the smaller id and relabels the other one everywhere).
 // par_list is kept in decreasing utilisation (ties: lowest task index).
 // While the partitions need more than M units, the first partition with an
 // eligible partner (Algorithm 3) is found with one ballot, and every eligible
@@ -1624,25 +1625,42 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
 // replaces the two partitions by their union at its place in the order: every
 // lane's new position follows from one ballot, and a forward permute moves it.
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint64_t)__shfl_xor(v, o, 64));
-    return v;
-}
-
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// value of the lane CTRL-shifted within its row of 16 (DPP row_shr), or `id`
+// where that lane lies outside the row
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_row_shr64(uint64_t v, uint64_t id)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)id, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(id >> 32), (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// wave reductions (all 64 lanes active): row scans by DPP shifts of 1, 2, 4
+// and 8 lanes, then the four row results combined from lanes 15, 31, 47, 63
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+    v = min(v, dpp_row_shr64<0x111>(v, ~0ull));
+    v = min(v, dpp_row_shr64<0x112>(v, ~0ull));
+    v = min(v, dpp_row_shr64<0x114>(v, ~0ull));
+    v = min(v, dpp_row_shr64<0x118>(v, ~0ull));
+    return min(min(readlane64(v, 15), readlane64(v, 31)), min(readlane64(v, 47), readlane64(v, 63)));
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v)
+{
+    v |= dpp_row_shr64<0x111>(v, 0ull);
+    v |= dpp_row_shr64<0x112>(v, 0ull);
+    v |= dpp_row_shr64<0x114>(v, 0ull);
+    v |= dpp_row_shr64<0x118>(v, 0ull);
+    return readlane64(v, 15) | readlane64(v, 31) | readlane64(v, 47) | readlane64(v, 63);
 }
 
 __device__ __forceinline__ int readlane32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -1727,15 +1745,15 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
     stage_set_times(L, w, off0, n, M, s, ACT, tb);
     if (f & SETF_LEMMA1) { write_failure(0, 0); return; }
     const uint64_t memm = L.memmask;
-    // init partitions: one per task, of its Lemma 2 size
-    uint64_t Pm = 0, PF = 0, PU = 0;
+    // init partitions: one per task, of its Lemma 2 size (partition id = rank)
+    uint64_t Pm = 0, PX = 0, PU = 0;
     int Pmu = 0, Pl = lane;
     bool bad = false;
     if (lane < n) {
         const int m = (int)L.mmin[lane];
         bad = m > M;
         Pm = 1ull << lane;
-        PF = ACT ? L.forbid[lane] : 0ull;
+        PX = ACT ? L.forbid[lane] : 0ull;
         Pmu = bad ? 1 : m;
         PU = bad ? 0ull : util_term(L, tb, lane, m, 0u);
         Pl = L.orig[lane];
@@ -1749,9 +1767,10 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
             pos += (uj > PU || (uj == PU && lj < Pl)) ? 1 : 0;
         }
         if (lane >= n) pos = lane;
-        Pm = permute64(Pm, pos); PF = permute64(PF, pos); PU = permute64(PU, pos);
+        Pm = permute64(Pm, pos); PX = permute64(PX, pos); PU = permute64(PU, pos);
         Pmu = permute32(Pmu, pos); Pl = permute32(Pl, pos);
     }
+    uint64_t live = n == 64 ? ~0ull : (1ull << n) - 1ull;  // ids of the partitions
     int np = n;
     int Pi = 0;
     for (int j = 0; j < n; j++) Pi += readlane32(Pmu, j);
@@ -1761,14 +1780,14 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
     for (;;) {
         if (Pi <= M) { ok = true; break; }
         // partitions with an eligible partner; the first one is the operand
-        bool has = false;
-        for (int j = 0; j < np; j++) has |= (j != lane) && ((readlane64(Pm, j) & PF) == 0ull);
-        const uint64_t cand = __ballot(has && lane < np);
+        const uint64_t idb = Pm & (0ull - Pm);  // this partition's id bit
+        const uint64_t cand = __ballot(lane < np && (live & ~PX & ~idb) != 0ull);
         if (!cand) break;  // no partition has an eligible partner: fail
         const int c = __builtin_ctzll(cand);
-        const uint64_t Sc = readlane64(Pm, c), Fc = readlane64(PF, c);
+        const uint64_t Sc = readlane64(Pm, c), Xc = readlane64(PX, c);
+        const uint64_t idc = Sc & (0ull - Sc);
         const int mc = readlane32(Pmu, c);
-        const bool elig = lane < np && lane != c && (Pm & Fc) == 0ull;
+        const bool elig = lane < np && lane != c && (Xc & idb) == 0ull;
         // every eligible partner's merge, one lane each; rank key (ka, lane):
         // ">" the union's utilisation at max(m1, m2), ">>" (units, U) of the
         // merge (valid merges only)
@@ -1804,14 +1823,17 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
         // the merge taken (all of them if none is valid), for ">>" all
         const bool forbid = elig && !mok && (SMS || before);
         tried += (int64_t)__popcll(__ballot(elig && (SMS || before || lane == best_l)));
-        if (forbid) PF |= Sc;
-        const uint64_t Ffail = wave_or(forbid ? Pm : 0ull);
-        if (lane == c) PF |= Ffail;
+        if (forbid) PX |= idc;
+        const uint64_t Xfail = wave_or(forbid ? idb : 0ull);
+        if (lane == c) PX |= Xfail;
         if (best_l == 64) continue;  // P_c has no valid merge; its partners are now forbidden
-        // merge P_c with partner j: par_list minus both, plus the union
+        // merge P_c with partner j: par_list minus both, plus the union (which
+        // keeps the smaller id; the other id is relabelled in every mask)
         const int j = best_l;
         const uint64_t Sj3 = readlane64(S3, j), Uj3 = readlane64(U3, j);
-        const uint64_t F3 = readlane64(PF, c) | readlane64(PF, j);
+        const uint64_t X3 = readlane64(PX, c) | readlane64(PX, j);
+        const uint64_t idj = readlane64(idb, j);
+        const uint64_t keep = min(idc, idj), gone = max(idc, idj);
         const int mj3 = readlane32(m3, j), mj = readlane32(Pmu, j);
         const int lead = min(readlane32(Pl, c), readlane32(Pl, j));
         const bool rem = lane < np && lane != c && lane != j;
@@ -1823,12 +1845,14 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
             dst = r + (r >= pos_new ? 1 : 0);
         } else if (lane == c) {
             dst = pos_new;
-            Pm = Sj3; PF = F3; PU = Uj3; Pmu = mj3; Pl = lead;
+            Pm = Sj3; PX = X3; PU = Uj3; Pmu = mj3; Pl = lead;
         } else if (lane == j) {
             dst = np - 1;
         }
-        Pm = permute64(Pm, dst); PF = permute64(PF, dst); PU = permute64(PU, dst);
+        if (PX & gone) PX = (PX & ~gone) | keep;
+        Pm = permute64(Pm, dst); PX = permute64(PX, dst); PU = permute64(PU, dst);
         Pmu = permute32(Pmu, dst); Pl = permute32(Pl, dst);
+        live &= ~gone;
         np -= 1;
         Pi += mj3 - mc - mj;
         merged += 1;
