@@ -862,36 +862,36 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     __syncthreads();
     // ACT: pair (a, b), a < b in rank order, is forbidden iff no size in
     // [max(mmin), min(mmin_a + mmin_b - 1, M)] schedules both together; by
-    // monotonicity in m it suffices to test the top of that range.
-    if (lane < n) {
-        const int bb = lane;
-        const TaskRec tb = srec[bb];
-        uint64_t fb = 0ull;
-        for (int a = 0; a < bb; a++) {
-            const TaskRec ta = srec[a];
-            bool forb = true;
-            if (ta.mmin != MMIN_NONE && tb.mmin != MMIN_NONE) {
-                const uint32_t m = min((uint32_t)ta.mmin + tb.mmin - 1u, (uint32_t)M);
-                const bool conf = ta.mem == tb.mem;
-                uint32_t Ca = time_n(ta.Cs, ta.Cp, m), Cb = time_n(tb.Cs, tb.Cp, m);
-                if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
-                if (Ca <= ta.D && Ca < ta.T) {
-                    uint64_t R = (uint64_t)Cb + Ca;
-                    for (;;) {
-                        if (R > tb.D) break;
-                        const uint64_t W = (uint64_t)Cb + ((R + ta.T - 1) / ta.T) * (uint64_t)Ca;
-                        if (W > tb.D) break;
-                        if (W == R) { forb = false; break; }
-                        R = W;
-                    }
+    // monotonicity in m it suffices to test the top of that range.  The
+    // n(n-1)/2 pairs are spread evenly over the lanes: pair q = b(b-1)/2 + a.
+    const int npairs = n * (n - 1) / 2;
+    for (int q = lane; q < npairs; q += 64) {
+        int bb = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+        while (bb * (bb - 1) / 2 > q) bb--;
+        while ((bb + 1) * bb / 2 <= q) bb++;
+        const int a = q - bb * (bb - 1) / 2;
+        const TaskRec ta = srec[a], tb = srec[bb];
+        bool forb = true;
+        if (ta.mmin != MMIN_NONE && tb.mmin != MMIN_NONE) {
+            const uint32_t m = min((uint32_t)ta.mmin + tb.mmin - 1u, (uint32_t)M);
+            const bool conf = ta.mem == tb.mem;
+            uint32_t Ca = time_n(ta.Cs, ta.Cp, m), Cb = time_n(tb.Cs, tb.Cp, m);
+            if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
+            if (Ca <= ta.D && Ca < ta.T) {
+                uint64_t R = (uint64_t)Cb + Ca;
+                for (;;) {
+                    if (R > tb.D) break;
+                    const uint64_t W = (uint64_t)Cb + ((R + ta.T - 1) / ta.T) * (uint64_t)Ca;
+                    if (W > tb.D) break;
+                    if (W == R) { forb = false; break; }
+                    R = W;
                 }
             }
-            if (forb) {
-                fb |= 1ull << a;
-                atomicOr((unsigned long long *)&sforbid[a], (unsigned long long)(1ull << bb));
-            }
         }
-        atomicOr((unsigned long long *)&sforbid[bb], (unsigned long long)fb);
+        if (forb) {
+            atomicOr((unsigned long long *)&sforbid[a], (unsigned long long)(1ull << bb));
+            atomicOr((unsigned long long *)&sforbid[bb], (unsigned long long)(1ull << a));
+        }
     }
     __syncthreads();
     if (lane < n) w.forbid[off0 + lane] = sforbid[lane];
