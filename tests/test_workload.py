@@ -76,3 +76,22 @@ def test_subset_and_concat_roundtrip():
     c = w.concat([a, b])
     for k in KEYS:
         assert np.array_equal(c[k], ts[k])
+
+
+def test_paper_fig4_recipe():
+    """The paper's own experiment: n = 50, M = 68, U = 2..68 step 2 with the
+    sets ordered by point, D = 0.75 T, periods 50..4000, the type-dependent
+    sequential share b = 0.02 a (compute) or 0.1 a (memory) of C1 = a + b."""
+    ts = w.config_paper_fig4(sets_per_point=20)
+    _check(ts, n=50, M=68, implicit=False)
+    assert ts.n_sets == 34 * 20
+    assert (ts["D"] == np.floor(0.75 * ts["T"]).astype(np.int64)).all()
+    assert ts["T"].min() >= 50 and ts["T"].max() <= 4000
+    C1 = ts["C_seq"] + ts["C_par"]
+    share = np.where(ts["type"] == 1, 0.1 / 1.1, 0.02 / 1.02)
+    assert (np.abs(ts["C_seq"] - np.rint(share * C1)) <= 0.5).all()
+    u = np.add.reduceat(C1 / ts["T"], ts["set_offset"][:-1]).reshape(34, 20).mean(axis=1)
+    assert np.allclose(u, np.arange(2, 69, 2), rtol=0.03)
+    a = w.config_paper_fig4(sets_per_point=20)
+    for key in ("T", "D", "C_seq", "C_par", "k_permille", "type"):
+        assert np.array_equal(a[key], ts[key])
