@@ -394,7 +394,13 @@ capart_status capart_server_destroy(capart_server *srv);
  * (2^11 entries, fewer if the LDS is short), -1 = off, 8..13 = log2 of the
  * entries of a per-set table in LDS that records, for each task subset met,
  * the largest size known to fail and the smallest known to pass, so that
- * repeated candidate tests across partitionings become lookups.  NULL
+ * repeated candidate tests across partitionings become lookups.
+ * wide_chunk (heuristic modes, sets of more than 32 tasks): 0 = automatic
+ * (16), -1 = off, else 1..4096: partitionings per block of a launch in which
+ * each wave runs the heuristic of one partitioning at a time with the exact
+ * tests of a candidate part spread over the wave, one lane per member; off:
+ * such sets run one partitioning per lane like the others (more throughput
+ * on large batches of wide sets, much longer latency per set).  NULL
  * restores the automatic choices.
  * E_INVAL for values out of range. */
 typedef struct capart_tuning {
@@ -404,7 +410,8 @@ typedef struct capart_tuning {
     int32_t exh_form;
     int32_t frontier;
     int32_t memo;
-    int32_t reserved[2];  /* must be 0 */
+    int32_t wide_chunk;
+    int32_t reserved;  /* must be 0 */
 } capart_tuning;
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);

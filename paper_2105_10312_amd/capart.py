@@ -63,7 +63,8 @@ ALG1_FIELDS = [("status", np.int32, "S"), ("verdict", np.uint8, "S"), ("nparts",
 
 class capart_tuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("chunk", C.c_int32), ("loop_form", C.c_int32), ("exh_form", C.c_int32),
-                ("frontier", C.c_int32), ("memo", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("frontier", C.c_int32), ("memo", C.c_int32), ("wide_chunk", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class capart_plan_config(C.Structure):
@@ -413,8 +414,9 @@ def capart_alg1_count_work(ctx, dev_ts: dict, mode, dev_out: dict, max_tasks: in
 
 
 def capart_set_tuning(ctx, threads: int = 0, chunk: int = 0, loop_form: int = 0, exh_form: int = 0,
-                      frontier: int = 0, memo: int = 0) -> None:
-    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier), int(memo))
+                      frontier: int = 0, memo: int = 0, wide_chunk: int = 0) -> None:
+    t = capart_tuning(int(threads), int(chunk), int(loop_form), int(exh_form), int(frontier), int(memo),
+                      int(wide_chunk))
     _check(load_library().capart_set_tuning(ctx, C.byref(t)), ctx)
 
 
@@ -422,7 +424,7 @@ def capart_get_tuning(ctx) -> dict:
     t = capart_tuning()
     _check(load_library().capart_get_tuning(ctx, C.byref(t)), ctx)
     return {"threads": t.threads, "chunk": t.chunk, "loop_form": t.loop_form, "exh_form": t.exh_form,
-            "frontier": t.frontier, "memo": t.memo}
+            "frontier": t.frontier, "memo": t.memo, "wide_chunk": t.wide_chunk}
 
 
 def capart_timing_enable(ctx, enable: bool = True) -> None:

@@ -241,12 +241,26 @@ void size_frontier(Launch &L, int max_tasks, int mode, const capart_tuning &tu)
     L.memo_log2 = lg >= 8 ? lg : 0;
 }
 
+// Sets of more than NARROW_MAX_TASKS tasks: wave-per-partitioning blocks of
+// wchunk partitionings (unless tuned off); the partial slots per set then
+// cover ceil(P / wchunk) chunks as well.
+// wide_parts: partitionings of the batch's sets of more than NARROW_MAX_TASKS
+// tasks, or -1 where the host does not see the sets (then S decides).
+void set_wide_chunk(Launch &L, int max_tasks, uint32_t Pmax, const capart_tuning &tu, int64_t wide_parts, int64_t S)
+{
+    L.wchunk = 0;
+    if (L.mode == CAPART_EXHAUSTIVE || max_tasks <= NARROW_MAX_TASKS || tu.wide_chunk < 0) return;
+    if (tu.wide_chunk == 0 && (wide_parts >= 0 ? wide_parts >= WIDE_LANE_FILL : S > WIDE_WAVE_MAX_SETS)) return;
+    L.wchunk = tu.wide_chunk > 0 ? tu.wide_chunk : WIDE_CHUNK_DEFAULT;
+    L.chunks = std::max<int>(L.chunks, (int)((Pmax + (uint32_t)L.wchunk - 1) / (uint32_t)L.wchunk));
+}
+
 struct Plan {
     Launch L;
     int64_t S, N;
 };
 
-Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capart_tuning &tu)
+Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capart_tuning &tu, int64_t wide_parts = -1)
 {
     Plan p;
     p.S = in->n_sets;
@@ -289,8 +303,20 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
         L.chunk = (uint32_t)((Pmax + ch - 1) / ch);
         if (tu.chunk > 0) L.chunk = std::min<uint32_t>((uint32_t)tu.chunk, std::max<uint32_t>(Pmax, 1));
         L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
+        set_wide_chunk(L, in->max_tasks, Pmax, tu, wide_parts, p.S);
     }
     return p;
+}
+
+// Partitionings of the sets of more than NARROW_MAX_TASKS tasks (host arrays).
+int64_t wide_partitionings(const int64_t *off, const int32_t *M, int64_t S, int K)
+{
+    int64_t t = 0;
+    for (int64_t s = 0; s < S; s++) {
+        const int64_t n = off[s + 1] - off[s];
+        if (n > NARROW_MAX_TASKS && n <= CAPART_MAX_TASKS && M[s] >= 1 && M[s] <= CAPART_MAX_M) t += count_parts(M[s], K);
+    }
+    return t;
 }
 
 hipEvent_t take_event(capart_ctx *c)
@@ -648,7 +674,7 @@ static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const 
             return hip_fail(c, e, "hipMemcpyAsync H2D");
     d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
     d.type = d_ty;
-    const Plan p = make_plan(in, opt, c->tune);
+    const Plan p = make_plan(in, opt, c->tune, wide_partitionings(in->set_offset, in->M, S, K));
     if ((rc = run_plan(c, make_batch(&d), make_out(&r), p, st, p_lo, p_hi)) != CAPART_OK) return rc;
     Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
                 {out->verdict_1g, r.verdict_1g, (size_t)S}, {out->pidx, r.pidx, 4 * (size_t)S},
@@ -1010,7 +1036,8 @@ capart_status capart_set_tuning(capart_ctx *c, const capart_tuning *t)
     if (t->loop_form < 0 || t->loop_form > 3) return fail(c, CAPART_E_INVAL, "loop_form must be 0, 1, 2 or 3");
     if (t->exh_form < 0 || t->exh_form > 2) return fail(c, CAPART_E_INVAL, "exh_form must be 0, 1 or 2");
     if (t->frontier < 0 || t->frontier > 2) return fail(c, CAPART_E_INVAL, "frontier must be 0, 1 or 2");
-    if (t->reserved[0] || t->reserved[1]) return fail(c, CAPART_E_INVAL, "reserved must be 0");
+    if (t->reserved) return fail(c, CAPART_E_INVAL, "reserved must be 0");
+    if (t->wide_chunk < -1 || t->wide_chunk > 4096) return fail(c, CAPART_E_INVAL, "wide_chunk must be -1..4096");
     if (t->memo != 0 && t->memo != -1 && (t->memo < 8 || t->memo > MEMO_MAX_LOG2))
         return fail(c, CAPART_E_INVAL, "memo must be 0, -1 or 8..13");
     c->tune = *t;
@@ -1370,7 +1397,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                 if (over_budget()) continue;
                 capart_tuning tu = c->tune;
                 tu.threads = th;
-                const Plan dp = make_plan(&sub, opt, tu);
+                const Plan dp = make_plan(&sub, opt, tu, wide_partitionings(off.data(), M.data(), St, opt->K));
                 std::vector<WorkItem> none;
                 std::vector<uint32_t> so((size_t)St + 1, 0u);
                 PlanBuffers pb;
@@ -1410,7 +1437,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     const bool direct = bpc <= 0;
     capart_tuning tud = c->tune;
     tud.threads = threads;
-    const Plan dp = make_plan(in, opt, tud);
+    const Plan dp = make_plan(in, opt, tud, wide_partitionings(off.data(), M.data(), S, opt->K));
     const Launch Lp0 = plan_launch(in, opt, threads, form, c->tune);
     if (!direct) {
         build_items(off, M, S, in, opt->K, item_evals, Lp0, items, so, te, ce);
@@ -1672,11 +1699,12 @@ void launch_batch(capart_server *v, int i)
     char *h = ss.in_host;
     int64_t *off = (int64_t *)(h + li.off);
     int32_t *M = (int32_t *)(h + li.M);
-    int64_t acc = 0;
+    int64_t acc = 0, wide_parts = 0;
     for (int64_t s = 0; s < S; s++) {
         SrvQuery &x = v->q[(first + s) % v->Qcap];
         off[s] = acc;
         M[s] = x.M;
+        if (x.n > NARROW_MAX_TASKS) wide_parts += count_parts(x.M, v->cfg.K);
         std::memcpy(h + li.T + 8 * acc, &v->hT[x.t0], 8 * (size_t)x.n);
         std::memcpy(h + li.D + 8 * acc, &v->hD[x.t0], 8 * (size_t)x.n);
         std::memcpy(h + li.Cs + 8 * acc, &v->hCs[x.t0], 8 * (size_t)x.n);
@@ -1734,6 +1762,8 @@ void launch_batch(capart_server *v, int i)
     Launch L = v->L;
     L.s0 = 0;
     L.S = S;
+    // the wave-per-partitioning launch only while the wide queries cannot fill the chip's lanes
+    if (L.wchunk > 0 && v->ctx->tune.wide_chunk == 0 && wide_parts >= WIDE_LANE_FILL) L.wchunk = 0;
     hipError_t e;
     (void)hipGetLastError();
     if ((e = hipMemcpyAsync(ss.in_dev, ss.in_host, li.total, hipMemcpyHostToDevice, ss.st)) != hipSuccess ||
@@ -1941,6 +1971,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     // 512 partitionings per block: one per lane of the widest blocks (large-set launches)
     L.chunk = c->tune.chunk > 0 ? (uint32_t)c->tune.chunk : 512u;
     L.chunks = (int)((Pmax + L.chunk - 1) / L.chunk);
+    set_wide_chunk(L, cfg->max_tasks, Pmax, c->tune, 0, 0);  // slots sized for it; each batch then chooses
     // device budget: slot rings + task rings + per-stream packed buffers
     const int64_t per_slot = 4 + 8 + 32 * (int64_t)L.chunks;
     const int64_t per_task_ring = (int64_t)sizeof(TaskRec) + 8 + 1;

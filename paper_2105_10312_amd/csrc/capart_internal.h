@@ -94,6 +94,9 @@ struct Launch {
     int memo_packed = 0; // 1: memo sets run the packed-test state machine instead of the nested loops
     int n_lo = 0;        // this evaluation launch takes the sets of n_lo <= n (<= n_hi if n_hi > 0) tasks
     int n_hi = 0;
+    int wchunk = 0;      // heuristic, sets above NARROW_MAX_TASKS tasks: partitionings per block of the
+                         // wave-per-partitioning launch (0 = one lane per partitioning, chunk per block);
+                         // chunks then covers ceil(P / wchunk) as well
 };
 
 // Host-side sizing helpers shared by the launchers.
@@ -109,6 +112,14 @@ constexpr int FRONTIER_MAX_TASKS = 14;
 int size_classes(const Launch &L, int max_tasks, int hi[3]);
 // largest set size with 32-bit rank masks
 constexpr int NARROW_MAX_TASKS = 32;
+// partitionings per block of the wide-set (wave-per-partitioning) launch by default
+constexpr int WIDE_CHUNK_DEFAULT = 16;
+// automatic choice of that launch: while a batch's wide sets have fewer
+// partitionings than this (one lane each would leave the chip idle, so one
+// partitioning's whole heuristic in one lane sets the latency), or, where the
+// host does not see the sets, while the batch has at most WIDE_WAVE_MAX_SETS sets
+constexpr int64_t WIDE_LANE_FILL = 65536;
+constexpr int64_t WIDE_WAVE_MAX_SETS = 64;
 // test memo (sets between the frontier limit and 32 tasks): default and
 // largest log2 of its entries (8 bytes each)
 constexpr int MEMO_DEFAULT_LOG2 = 11;

@@ -192,6 +192,40 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
     tb.n = n;
 }
 
+// Records plus the execution-time table [m-1][conflict][rank] (u32, m = 1..M)
+__device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act,
+                                Tables &tb)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    stage_records(L, w, off, n, s, act);
+    uint32_t *tc = capart_dyn_lds;
+    for (int e = tid; e < n * M; e += nt) {
+        const int m = e / n + 1, r = e - (m - 1) * n;
+        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+        const int base = (m - 1) * 2 * n + r;
+        tc[base] = cn;
+        tc[base + n] = time_c(L.k[r], cn);
+    }
+    __syncthreads();
+    tb.C = tc;
+    tb.U = nullptr;
+    tb.n = n;
+}
+
+// Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
+// also where C > T (an unschedulable group; C is then recomputed in 64 bits,
+// the u32 table saturating above 2^31).
+__device__ __forceinline__ uint64_t util_term(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
+{
+    const uint32_t C = tb.C[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
+    const uint32_t T = L.T[r];
+    if (C <= T) return (uint64_t)util_q32_m1_magic(C, T, L.clo[r], L.chi[r]) + 1ull;
+    const uint64_t T64 = T;
+    const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
+    const uint64_t C64 = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
+    return ((C64 / T64) << 32) + ((((C64 % T64) << 32) + T64 - 1ull) / T64);
+}
+
 // Rank masks: 32-bit when every set of the launch has at most 32 tasks.
 __device__ __forceinline__ int mctz(uint32_t x) { return __builtin_ctz(x); }
 __device__ __forceinline__ int mctz(uint64_t x) { return __builtin_ctzll(x); }
@@ -514,6 +548,93 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
             if (p == best) { S[p] |= MT(1) << r; U[p] = bestU; }
+    }
+    return true;
+}
+
+// The same test as test_from with one lane per member (lane j tests rank j;
+// all 64 lanes call it with the same arguments): the critical path is one
+// response-time fixed point instead of all of them.  Wave-uniform result.
+template <typename TY>
+__device__ bool wave_test_from(const SetLDS &L, const Tables &tb, uint64_t S, int first, int m, uint64_t cm, TY &ty)
+{
+    const int lane = threadIdx.x & 63;
+    const int n = tb.n;
+    bool fail = false;
+    if (((S >> lane) & 1ull) && lane >= first) {
+        const uint32_t *row = tb.C + (m - 1) * 2 * n;
+        const uint64_t hp = S & ((1ull << lane) - 1ull);
+        uint64_t base = row[(int)((cm >> lane) & 1ull) * n + lane];
+        bool sat = false;  // some higher-priority member has utilisation >= 1
+        for (uint64_t h = hp; h; h &= h - 1ull) {
+            const int j = __builtin_ctzll(h);
+            const uint32_t Cj = row[(int)((cm >> j) & 1ull) * n + j];
+            base += Cj;
+            sat |= (Cj >= L.T[j]);
+        }
+        fail = sat || rta_fp<uint64_t>(L, row, n, base, L.D[lane], hp & L.intf[lane], cm, ty) == 0u;
+    }
+    if (lane == 0) ty.test();
+    return !__any(fail);
+}
+
+// heuristic() for one partitioning with the whole wave: the same decisions
+// (tasks in the heuristic order, parts in index order, the same ranks and
+// tie-breaks), each candidate test spread over the part's members.  S, U, m
+// and k are wave-uniform.
+template <int KMAX, bool ACT, bool SMS, typename TY>
+__device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
+                               uint64_t (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty)
+{
+    const uint64_t memm = L.memmask;
+#pragma unroll
+    for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; }
+    for (int t = 0; t < n; t++) {
+        const int r = L.sigma[t];
+        const int mm = (int)L.mmin[r];
+        const uint64_t fb = ACT ? L.forbid[r] : 0ull;
+        const uint64_t typ = ((memm >> r) & 1ull) ? memm : ~memm;
+        int best = -1, bestReq = 0;
+        uint64_t bestU = 0;
+#pragma unroll
+        for (int p = 0; p < KMAX; p++) {
+            const int mp = m[p];
+            const uint64_t Sp = S[p];
+            if (p >= k || mm > mp) continue;
+            if (ACT && (fb & Sp)) continue;
+            const uint64_t Sn = Sp | (1ull << r);
+            const uint64_t same = Sp & typ;
+            const int ns = __popcll(same);
+            const uint64_t cm = conflict_mask<uint64_t>(Sn, memm);
+            int first = r, flip = -1;
+            if (ns == 1) {
+                flip = __builtin_ctzll(same);
+                first = min(first, flip);
+            }
+            if (!wave_test_from(L, tb, Sn, first, mp, cm, ty)) continue;
+            uint64_t Un = U[p] + util_term(L, tb, r, mp, ns >= 1 ? 1u : 0u);
+            if (flip >= 0) Un += util_term(L, tb, flip, mp, 1u) - util_term(L, tb, flip, mp, 0u);
+            int req = 0;
+            if (SMS) {  // fewest units for Sn (binary search, as min_units)
+                int lo = 1;
+                for (uint64_t h = Sn; h; h &= h - 1ull) lo = max(lo, (int)L.mmin[__builtin_ctzll(h)]);
+                int hi = mp;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (wave_test_from(L, tb, Sn, 0, mid, cm, ty))
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                req = lo;
+            }
+            const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
+            if (better) { best = p; bestU = Un; bestReq = req; }
+        }
+        if (best < 0) return false;
+#pragma unroll
+        for (int p = 0; p < KMAX; p++)
+            if (p == best) { S[p] |= 1ull << r; U[p] = bestU; }
     }
     return true;
 }
@@ -1322,6 +1443,93 @@ __global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, 
     }
 }
 
+// eval, wide sets (launches of sets above NARROW_MAX_TASKS tasks with
+// Lp.wchunk > 0): one block per (set, chunk of Lp.wchunk partitionings), each
+// wave takes every nw-th partitioning of the chunk and runs wave_heuristic on
+// it, so a partitioning costs one test's critical path per candidate instead
+// of all of its members' fixed points in one lane.  Only the execution-time
+// table is staged (utilisations through the reciprocal of T).
+template <int KMAX, bool ACT, bool SMS, bool COUNT = false>
+__global__ __launch_bounds__(256) void eval_wide_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
+                                                        uint32_t p_hi)
+{
+    __shared__ SetLDS L;
+    __shared__ Key red[16];
+    typename std::conditional<COUNT, Tally, NoTally>::type ty;
+    const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
+    const int c = blockIdx.x % Lp.chunks;
+    const uint32_t f = w.setflags[s];
+    if (!(f & SETF_VALID)) return;
+    const int64_t off = b.off[s];
+    const int n = (int)(b.off[s + 1] - off);
+    if (n < Lp.n_lo || (Lp.n_hi > 0 && n > Lp.n_hi)) return;  // evaluated by the launch for its size
+    const int M = b.M[s];
+    const uint32_t P = w.np[np_index(Lp.K, M, M)];
+    const uint32_t p0 = (uint32_t)c * (uint32_t)Lp.wchunk;
+    if (p0 >= P) return;
+    const uint32_t p1 = min(P, p0 + (uint32_t)Lp.wchunk);
+    uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    Key best = key_none();
+    if (!(f & SETF_LEMMA1)) {
+        Tables tb;
+        stage_set_times(L, w, off, n, M, s, ACT, tb);
+        const uint32_t q0 = p0 + (uint32_t)wv;
+        if (q0 < p1) {
+            int m[KMAX];
+            int k = unrank<KMAX>(w.np, M, Lp.K, q0, m);
+            for (uint32_t q = q0;;) {
+                if (q >= p_lo && q < p_hi) {
+                    uint64_t S[KMAX], U[KMAX];
+                    const bool ok = wave_heuristic<KMAX, ACT, SMS>(L, tb, n, m, k, S, U, ty);
+                    uint64_t mx = 0, sm = 0;
+                    if (ok) {
+#pragma unroll
+                        for (int i = 0; i < KMAX; i++) { mx = max(mx, U[i]); sm += U[i]; }
+                        const Key kk{mx, sm, q, 0ull};
+                        if (key_less(kk, best)) {
+                            best = kk;
+                            best.d = pack_alloc<KMAX, uint64_t>(n, S);
+                        }
+                    }
+                    if (dbg && (threadIdx.x & 63) == 0) {
+                        uint64_t *d = dbg + 3 * (uint64_t)q;
+                        d[0] = ok ? mx : ~0ull;
+                        d[1] = ok ? sm : ~0ull;
+                        d[2] = ok ? 0ull : ~0ull;
+                    }
+                }
+                q += (uint32_t)nw;
+                if (q >= p1) break;
+                for (int i = 0; i < nw; i++) k = next_partition<KMAX>(m, Lp.K);
+            }
+        }
+    } else if (dbg) {
+        for (uint32_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+            if (q < p_lo || q >= p_hi) continue;
+            uint64_t *d = dbg + 3 * (uint64_t)q;
+            d[0] = d[1] = d[2] = ~0ull;
+        }
+    }
+    best = block_min(best, red);
+    if (threadIdx.x == 0) {
+        uint64_t *dst = w.partial + 4 * ((s) * (int64_t)Lp.chunks + c);
+        dst[0] = best.a; dst[1] = best.b; dst[2] = best.c; dst[3] = best.d;
+    }
+    if constexpr (COUNT) {
+        uint64_t a = ty.terms, bb = ty.tests;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+            a += __shfl_xor(a, o2, 64);
+            bb += __shfl_xor(bb, o2, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && w.counters) {
+            atomicAdd((unsigned long long *)&w.counters[0], (unsigned long long)a);
+            atomicAdd((unsigned long long *)&w.counters[1], (unsigned long long)bb);
+        }
+    }
+}
+
 // eval, batched form: a persistent grid; each block repeatedly takes the next
 // work item (set, partitioning range) from a global counter, restages the
 // set's LDS tables only when the set changes, and writes the item's best key
@@ -1482,8 +1690,10 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
             if (key_less(kk, best)) best = kk;
         }
     } else {
+        // partitionings per chunk: the wide-set launch uses its own chunk size
+        const uint64_t ch = (!exh && Lp.wchunk > 0 && n > NARROW_MAX_TASKS) ? (uint64_t)Lp.wchunk : (uint64_t)Lp.chunk;
         for (int c = lane; c < Lp.chunks; c += 64) {
-            const bool live = exh ? ((uint32_t)c < P) : ((uint64_t)c * Lp.chunk < P);
+            const bool live = exh ? ((uint32_t)c < P) : ((uint64_t)c * ch < P);
             if (!live) continue;
             const uint64_t *src = w.partial + 4 * (s * (int64_t)Lp.chunks + c);
             const Key kk{src[0], src[1], src[2], src[3]};
@@ -1509,13 +1719,21 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         tb.n = n;
         __syncthreads();
     }
-    if (found && lane == 0) {
+    if (found) {
         int m[KMAX];
         int k = unrank<KMAX>(w.np, M, K, (uint32_t)best.c, m);
         uint64_t S[KMAX], U[KMAX];
 #pragma unroll
         for (int p = 0; p < KMAX; p++) S[p] = 0ull;
-        if (exh) {
+        if (replay) {  // the whole wave replays the heuristic on the chosen partitioning
+            NoTally nt;
+            switch (Lp.mode) {
+            case CAPART_HEUR_BF_INA: wave_heuristic<KMAX, false, false>(L, tb, n, m, k, S, U, nt); break;
+            case CAPART_HEUR_BF_ACT: wave_heuristic<KMAX, true, false>(L, tb, n, m, k, S, U, nt); break;
+            case CAPART_HEUR_SMS_INA: wave_heuristic<KMAX, false, true>(L, tb, n, m, k, S, U, nt); break;
+            default: wave_heuristic<KMAX, true, true>(L, tb, n, m, k, S, U, nt); break;
+            }
+        } else if (lane == 0 && exh) {
             uint64_t x = best.d;
             for (int i = n - 1; i >= 0; i--) {
                 const int d = (int)(x % (uint64_t)k);
@@ -1524,7 +1742,7 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
                 for (int p = 0; p < KMAX; p++)
                     if (p == d) S[p] |= 1ull << L.rank_of[i];
             }
-        } else if (!replay) {
+        } else if (lane == 0) {
             constexpr int B = AllocPack<KMAX>::BITS;
             for (int r = 0; r < n; r++) {
                 const int d = (int)((best.d >> (B * r)) & ((1u << B) - 1u));
@@ -1532,18 +1750,12 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
                 for (int p = 0; p < KMAX; p++)
                     if (p == d) S[p] |= 1ull << r;
             }
-        } else {
-            NoTally nt;
-            switch (Lp.mode) {
-            case CAPART_HEUR_BF_INA: heuristic<KMAX, false, false, uint64_t>(L, tb, n, m, k, S, U, nt); break;
-            case CAPART_HEUR_BF_ACT: heuristic<KMAX, true, false, uint64_t>(L, tb, n, m, k, S, U, nt); break;
-            case CAPART_HEUR_SMS_INA: heuristic<KMAX, false, true, uint64_t>(L, tb, n, m, k, S, U, nt); break;
-            default: heuristic<KMAX, true, true, uint64_t>(L, tb, n, m, k, S, U, nt); break;
-            }
         }
+        if (lane == 0) {
 #pragma unroll
-        for (int p = 0; p < KMAX; p++) { sS[p] = S[p]; sm_[p] = m[p]; }
-        sk = k;
+            for (int p = 0; p < KMAX; p++) { sS[p] = S[p]; sm_[p] = m[p]; }
+            sk = k;
+        }
     }
     __syncthreads();
     if (!replay) {
@@ -1675,39 +1887,6 @@ __device__ __forceinline__ uint64_t permute64(uint64_t v, int dst)
 
 __device__ __forceinline__ int permute32(int v, int dst) { return __builtin_amdgcn_ds_permute(dst << 2, v); }
 
-// Records plus the execution-time table [m-1][conflict][rank] (u32, m = 1..M)
-__device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act,
-                                Tables &tb)
-{
-    const int tid = threadIdx.x, nt = blockDim.x;
-    stage_records(L, w, off, n, s, act);
-    uint32_t *tc = capart_dyn_lds;
-    for (int e = tid; e < n * M; e += nt) {
-        const int m = e / n + 1, r = e - (m - 1) * n;
-        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
-        const int base = (m - 1) * 2 * n + r;
-        tc[base] = cn;
-        tc[base + n] = time_c(L.k[r], cn);
-    }
-    __syncthreads();
-    tb.C = tc;
-    tb.U = nullptr;
-    tb.n = n;
-}
-
-// Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
-// also where C > T (an unschedulable group; C is then recomputed in 64 bits,
-// the u32 table saturating above 2^31).
-__device__ __forceinline__ uint64_t util_term(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
-{
-    const uint32_t C = tb.C[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
-    const uint32_t T = L.T[r];
-    if (C <= T) return (uint64_t)util_q32_m1_magic(C, T, L.clo[r], L.chi[r]) + 1ull;
-    const uint64_t T64 = T;
-    const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
-    const uint64_t C64 = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
-    return ((C64 / T64) << 32) + ((((C64 % T64) << 32) + T64 - 1ull) / T64);
-}
 
 // Q32 utilisation of rank set S on m units (schedulable or not), mod 2^64
 __device__ __forceinline__ uint64_t group_util(const SetLDS &L, const Tables &tb, uint64_t S, int m, uint64_t cm)
@@ -2290,6 +2469,33 @@ int device_cu_count()
     return cus;
 }
 
+// The wide-set launch (sets above NARROW_MAX_TASKS tasks) in its wave-per-
+// partitioning form: 256-thread blocks, the execution-time table only.
+static bool wide_launch(const Launch &L) { return L.mode != CAPART_EXHAUSTIVE && L.wchunk > 0 && L.n_lo > NARROW_MAX_TASKS; }
+
+template <int KMAX, bool COUNT>
+static hipError_t launch_wide_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
+                                uint32_t p_lo, uint32_t p_hi)
+{
+    const dim3 grid((unsigned)(L.S * L.chunks)), block(256);
+    const size_t lds = (size_t)2 * L.table_words;  // half of the [m][conflict][rank] time + utilisation tables
+    switch (L.mode) {
+    case CAPART_HEUR_BF_INA:
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, false, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    case CAPART_HEUR_BF_ACT:
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, false, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    case CAPART_HEUR_SMS_INA:
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, true, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    default:
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, true, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        break;
+    }
+    return hipGetLastError();
+}
+
 template <int KMAX, typename MT, int FORM>
 static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
@@ -2315,6 +2521,9 @@ static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, co
 
 static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st)
 {
+    if (wide_launch(L0))
+        return L0.K <= 4 ? launch_wide_k<4, true>(b, w, o, L0, st, 0u, 0xFFFFFFFFu)
+                         : launch_wide_k<8, true>(b, w, o, L0, st, 0u, 0xFFFFFFFFu);
     const Launch L = frontier_launch(L0, b) ? L0 : fit_block(L0, b);
     const bool fr = frontier_launch(L, b);
     if (launch_max_n(L, b) <= 32) {
@@ -2328,6 +2537,9 @@ static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out
 static hipError_t launch_eval_range_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st,
                                         uint32_t p_lo, uint32_t p_hi)
 {
+    if (wide_launch(L0))
+        return L0.K <= 4 ? launch_wide_k<4, false>(b, w, o, L0, st, p_lo, p_hi)
+                         : launch_wide_k<8, false>(b, w, o, L0, st, p_lo, p_hi);
     const Launch L = (L0.mode == CAPART_EXHAUSTIVE || frontier_launch(L0, b)) ? L0 : fit_block(L0, b);
     // 32-bit rank masks when every set of the launch has at most 32 tasks
     if (launch_max_n(L, b) <= 32)
@@ -2512,6 +2724,22 @@ hipError_t configure_kernels()
     CAPART_ALLOW((alg1_kernel<true, false, Tally>));
     CAPART_ALLOW((alg1_kernel<false, true, Tally>));
     CAPART_ALLOW((alg1_kernel<true, true, Tally>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, false>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, false>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, false>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, false>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, false>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, false>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, false>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, false>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, true>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, true>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, true>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, true>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, true>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, true>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, true>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, true>));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));

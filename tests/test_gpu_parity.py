@@ -397,3 +397,42 @@ def test_memo_matches_direct_tests(eng, mode):
     want = oracle.solve(sub, 4, mode, nthreads=THREADS)
     got = eng.solve(sub, 4, mode)
     assert_same(got, want, sub, f"memo {mode}")
+
+
+def wide_sets():
+    """Sets of 33..64 tasks (the wide-set launch): serving queries on the
+    smaller budgets, a few with constrained deadlines, a few light ones."""
+    c5 = workload.config_c5(seed=47, n_queries=1500)
+    n5 = c5.sizes()
+    pick = np.nonzero((n5 > 32) & (c5["M"] <= 48))[0][:14]
+    rng = np.random.default_rng(48)
+    cons = workload.gen_sets(49, rng.integers(33, 65, 4), rng.uniform(2.0, 8.0, 4), np.array([16, 48, 16, 48]),
+                             tmin=1e3, tmax=1e5, deadline="constrained")
+    light = workload.gen_sets(50, rng.integers(33, 65, 4), rng.uniform(1.0, 3.0, 4), np.full(4, 16),
+                              tmin=1e3, tmax=1e5)
+    return workload.concat([workload.subset(c5, pick), cons, light])
+
+
+@pytest.mark.parametrize("mode", ["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_wide_wave_path_matches_lane_path(eng, mode):
+    """Sets above 32 tasks: the wave-per-partitioning launch (default chunk,
+    and chunks of 1 and 7 partitionings, which leave waves idle and do not
+    divide P) gives the same key on every partitioning and the same results
+    as one lane per partitioning, for K = 4 and K = 8; the final kernel's
+    wave replay of the chosen partitioning gives the allocation; the oracle
+    agrees on the sets of 16 units."""
+    ts = wide_sets()
+    for K in (4, 8):
+        sub = ts if K == 4 else workload.subset(ts, np.nonzero(ts["M"] <= 16)[0])
+        say(f"wide {mode} K={K}: {sub.n_sets} sets, n 33..64")
+        capart.capart_set_tuning(eng.ctx, wide_chunk=-1)
+        ref = eng.solve(sub, K, mode, debug=True)
+        for wc in (0, 1, 7):
+            capart.capart_set_tuning(eng.ctx, wide_chunk=wc)
+            got = eng.solve(sub, K, mode, debug=True)
+            for f in FIELDS + ("dbg_key",):
+                assert np.array_equal(got[f], ref[f]), (mode, K, wc, f)
+        capart.capart_set_tuning(eng.ctx)
+    small = workload.subset(ts, np.nonzero(ts["M"] <= 16)[0][:6])
+    want = oracle.solve(small, 4, mode, nthreads=THREADS)
+    assert_same(eng.solve(small, 4, mode), want, small, f"wide {mode}")
