@@ -1450,7 +1450,7 @@ __global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, 
 // of all of its members' fixed points in one lane.  Only the execution-time
 // table is staged (utilisations through the reciprocal of T).
 template <int KMAX, bool ACT, bool SMS, bool COUNT = false>
-__global__ __launch_bounds__(256) void eval_wide_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
+__global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
@@ -2470,14 +2470,15 @@ int device_cu_count()
 }
 
 // The wide-set launch (sets above NARROW_MAX_TASKS tasks) in its wave-per-
-// partitioning form: 256-thread blocks, the execution-time table only.
+// partitioning form: 512-thread blocks (eight waves share one staged table),
+// the execution-time table only.
 static bool wide_launch(const Launch &L) { return L.mode != CAPART_EXHAUSTIVE && L.wchunk > 0 && L.n_lo > NARROW_MAX_TASKS; }
 
 template <int KMAX, bool COUNT>
 static hipError_t launch_wide_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
                                 uint32_t p_lo, uint32_t p_hi)
 {
-    const dim3 grid((unsigned)(L.S * L.chunks)), block(256);
+    const dim3 grid((unsigned)(L.S * L.chunks)), block(512);
     const size_t lds = (size_t)2 * L.table_words;  // half of the [m][conflict][rank] time + utilisation tables
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
