@@ -113,7 +113,7 @@ int size_classes(const Launch &L, int max_tasks, int hi[3]);
 // largest set size with 32-bit rank masks
 constexpr int NARROW_MAX_TASKS = 32;
 // partitionings per block of the wide-set (wave-per-partitioning) launch by default
-constexpr int WIDE_CHUNK_DEFAULT = 16;
+constexpr int WIDE_CHUNK_DEFAULT = 8;
 // automatic choice of that launch: while a batch's wide sets have fewer
 // partitionings than this (one lane each would leave the chip idle, so one
 // partitioning's whole heuristic in one lane sets the latency), or, where the
