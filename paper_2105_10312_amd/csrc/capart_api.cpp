@@ -1412,7 +1412,9 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
                 hipFree(pb.buf);
                 if (rc != CAPART_OK) return rc;
                 tried++;
-                if (ms < best_ms) {
+                // the direct grid's tail weighs more on the prefix than on the
+                // whole batch, so it is kept unless a queue is 5 % faster
+                if (ms < (bpc > 0 ? best_ms * 1.05 : best_ms)) {
                     best_ms = ms;
                     threads = th;
                     bpc = 0;
