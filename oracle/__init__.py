@@ -53,6 +53,7 @@ def _load():
         set_args = [C.c_int, C.c_int, i64p, i64p, i64p, i64p, i32p, u8p]
         lib.or_solve_batch.restype = C.c_int
         lib.or_solve_batch.argtypes = [C.c_int64, i64p, i32p, i64p, i64p, i64p, i64p, i32p, u8p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int, C.c_int, C.c_int, C.c_int,
                                        i32p, u8p, u8p, i32p, i32p, i64p, u64p, u64p, i64p,
                                        i8p, i64p, i64p, C.c_void_p]
@@ -79,7 +80,8 @@ def _load():
         lib.or_u1_ex.restype = C.c_uint64
         lib.or_u1_ex.argtypes = set_args + [C.c_int]
         lib.or_alg1_ex.restype = C.c_int
-        lib.or_alg1_ex.argtypes = set_args + [C.c_int, C.c_int, C.c_void_p, i32p, i8p, i64p, C.c_void_p]
+        lib.or_alg1_ex.argtypes = set_args + [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, i32p, i8p, i64p,
+                                              C.c_void_p]
         lib.or_time.restype = C.c_int64
         lib.or_time.argtypes = [i64p, i64p, i32p, C.c_int, C.c_int, C.c_int]
         _lib = lib
@@ -87,9 +89,21 @@ def _load():
 
 
 def _set_arrays(ts: dict):
+    """T, D, C_seq, C_par, k, type; with explicit time tables ("Cn_table" and
+    "Cc_table") the parametric fields may be absent (zeros are passed)."""
+    N = len(ts["T"])
+    z64, z32 = np.zeros(N, np.int64), np.zeros(N, np.int32)
     return (np.ascontiguousarray(ts["T"], np.int64), np.ascontiguousarray(ts["D"], np.int64),
-            np.ascontiguousarray(ts["C_seq"], np.int64), np.ascontiguousarray(ts["C_par"], np.int64),
-            np.ascontiguousarray(ts["k_permille"], np.int32), np.ascontiguousarray(ts["type"], np.uint8))
+            np.ascontiguousarray(ts.get("C_seq", z64), np.int64), np.ascontiguousarray(ts.get("C_par", z64), np.int64),
+            np.ascontiguousarray(ts.get("k_permille", z32), np.int32), np.ascontiguousarray(ts["type"], np.uint8))
+
+
+def _tables(ts: dict):
+    """(table_offset, Cn_table, Cc_table) arrays, or Nones for the parametric model."""
+    if ts.get("Cn_table") is None:
+        return None, None, None
+    return (np.ascontiguousarray(ts["table_offset"], np.int64), np.ascontiguousarray(ts["Cn_table"], np.int64),
+            np.ascontiguousarray(ts["Cc_table"], np.int64))
 
 
 def _one(task: dict):
@@ -111,7 +125,10 @@ def solve(ts: dict, K: int, mode="BF_INA", flags: int = 0, nthreads: int = 1, co
                maxU=np.zeros(S, np.uint64), sumU=np.zeros(S, np.uint64), n_evals=np.zeros(S, np.int64),
                alloc=np.zeros(N, np.int8), R=np.zeros(N, np.int64), R_1g=np.zeros(N, np.int64))
     cnt = np.zeros(S * 3, np.int64) if counters else None
-    rc = lib.or_solve_batch(S, off, M, T, D, Cs, Cp, k, ty, K, mode, flags, nthreads,
+    to, cn, cc = _tables(ts)
+    rc = lib.or_solve_batch(S, off, M, T, D, Cs, Cp, k, ty,
+                            to.ctypes.data if to is not None else None, cn.ctypes.data if cn is not None else None,
+                            cc.ctypes.data if cc is not None else None, K, mode, flags, nthreads,
                             out["status"], out["verdict"], out["verdict_1g"], out["pidx"], out["sizes"],
                             out["aidx"], out["maxU"], out["sumU"], out["n_evals"], out["alloc"], out["R"],
                             out["R_1g"], cnt.ctypes.data if cnt is not None else None)
@@ -187,7 +204,11 @@ def alg1(task: dict, mode="BF_INA", flags: int = 0) -> dict:
     al = np.zeros(n, np.int8)
     R = np.zeros(n, np.int64)
     st = np.zeros(2, np.int64)
-    ok = lib.or_alg1_ex(*_one(task), mode, int(flags), C.byref(k), sizes, al, R, st.ctypes.data)
+    cn = np.ascontiguousarray(task["Cn_table"], np.int64) if task.get("Cn_table") is not None else None
+    cc = np.ascontiguousarray(task["Cc_table"], np.int64) if cn is not None else None
+    ok = lib.or_alg1_ex(*_one(task), cn.ctypes.data if cn is not None else None,
+                        cc.ctypes.data if cc is not None else None, mode, int(flags), C.byref(k), sizes, al, R,
+                        st.ctypes.data)
     if ok < 0:
         raise ValueError("set outside the oracle's limits")
     return dict(verdict=int(ok), k=int(k.value), sizes=sizes[:k.value].copy(), alloc=al, R=R,

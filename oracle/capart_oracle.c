@@ -70,18 +70,24 @@ typedef struct {
     const int64_t *T, *D, *Cs, *Cp;
     const int32_t *k;
     const uint8_t *type;
+    /* explicit time tables (NULL: the parametric model from Cs, Cp, k):
+     * task i's time on m units at [i*M + m-1], without and in conflict */
+    const int64_t *Cn_tab, *Cc_tab;
     or_counters *cnt;
 } or_set;
 
 /* ---- 1. execution times ------------------------------------------------ */
 static int64_t or_cn(const or_set *s, int i, int m)
 {
+    if (s->Cn_tab) return s->Cn_tab[(int64_t)i * s->M + m - 1];
     return s->Cs[i] + (s->Cp[i] + m - 1) / m;
 }
 
 static int64_t or_cc(const or_set *s, int i, int m)
 {
-    i128 x = (i128)s->k[i] * (i128)or_cn(s, i, m);
+    i128 x;
+    if (s->Cc_tab) return s->Cc_tab[(int64_t)i * s->M + m - 1];
+    x = (i128)s->k[i] * (i128)or_cn(s, i, m);
     return (int64_t)((x + 999) / 1000);
 }
 
@@ -358,13 +364,28 @@ static int or_validate(const or_set *s, int K, int mode)
     if (s->n < 1 || s->n > OR_MAXN || s->M < 1 || s->M > 255) return OR_E_INVAL;
     if (s->n * s->M > 8192) return OR_E_INVAL; /* the boundary's per-set size limit */
     for (i = 0; i < s->n; i++) {
-        int64_t T = s->T[i], D = s->D[i], a = s->Cs[i], b = s->Cp[i];
+        int64_t T = s->T[i], D = s->D[i];
         if (T < 1 || T >= ((int64_t)1 << 31)) return OR_E_RANGE;
         if (D < 1 || D > T) return OR_E_RANGE;
-        if (a < 0 || b < 0 || a >= ((int64_t)1 << 31) || b >= ((int64_t)1 << 31)) return OR_E_RANGE;
-        if (a + b < 1 || a + b >= ((int64_t)1 << 31)) return OR_E_RANGE;
-        if (s->k[i] < 1000 || s->k[i] > 1000000) return OR_E_RANGE;
         if (s->type[i] > 1) return OR_E_RANGE;
+        if (s->Cn_tab) {
+            /* explicit tables: times in [1, 2^31), never rising with m, a
+             * conflict never faster, and no super-linear speed-up
+             * (m Cn(m) >= Cn(1), which keeps Lemma 1 sound) */
+            int m;
+            for (m = 1; m <= s->M; m++) {
+                int64_t cn = or_cn(s, i, m), cc = or_cc(s, i, m);
+                if (cn < 1 || cn >= ((int64_t)1 << 31) || cc < 1 || cc >= ((int64_t)1 << 31)) return OR_E_RANGE;
+                if (cc < cn) return OR_E_RANGE;
+                if (m > 1 && (cn > or_cn(s, i, m - 1) || cc > or_cc(s, i, m - 1))) return OR_E_RANGE;
+                if ((i128)m * cn < (i128)or_cn(s, i, 1)) return OR_E_RANGE;
+            }
+        } else {
+            int64_t a = s->Cs[i], b = s->Cp[i];
+            if (a < 0 || b < 0 || a >= ((int64_t)1 << 31) || b >= ((int64_t)1 << 31)) return OR_E_RANGE;
+            if (a + b < 1 || a + b >= ((int64_t)1 << 31)) return OR_E_RANGE;
+            if (s->k[i] < 1000 || s->k[i] > 1000000) return OR_E_RANGE;
+        }
     }
     if (mode == OR_EXH) {
         int kk = K < s->M ? K : s->M;
@@ -472,8 +493,10 @@ static void or_make_set(or_set *s, int64_t off0, int64_t off1, int32_t M, const 
 {
     s->n = (int)(off1 - off0);
     s->M = M;
-    s->T = T + off0; s->D = D + off0; s->Cs = Cs + off0; s->Cp = Cp + off0;
-    s->k = k + off0; s->type = type + off0;
+    s->T = T + off0; s->D = D + off0;
+    s->Cs = Cs ? Cs + off0 : NULL; s->Cp = Cp ? Cp + off0 : NULL; s->k = k ? k + off0 : NULL;
+    s->type = type + off0;
+    s->Cn_tab = s->Cc_tab = NULL;
     s->cnt = cnt;
 }
 
@@ -481,6 +504,7 @@ typedef struct {
     int64_t n_sets;
     const int64_t *off; const int32_t *M;
     const int64_t *T, *D, *Cs, *Cp; const int32_t *k; const uint8_t *type;
+    const int64_t *tab_off, *Cn_tab, *Cc_tab; /* explicit tables (NULL: parametric) */
     int K, mode, flags;
     int32_t *status; uint8_t *verdict, *verdict_1g; int32_t *pidx, *sizes;
     int64_t *aidx; uint64_t *maxU, *sumU; int64_t *n_evals;
@@ -498,6 +522,10 @@ static void or_batch_set(or_batch *b, int64_t si)
     int n = (int)(o1 - o0), i;
     int8_t al[OR_MAXN]; int64_t R[OR_MAXN], R1[OR_MAXN];
     or_make_set(&s, o0, o1, b->M[si], b->T, b->D, b->Cs, b->Cp, b->k, b->type, &cnt);
+    if (b->Cn_tab) {
+        s.Cn_tab = b->Cn_tab + b->tab_off[si];
+        s.Cc_tab = b->Cc_tab + b->tab_off[si];
+    }
     if (n < 0) n = 0;
     or_solve_one(&s, b->K, b->mode, b->flags, &r, b->sizes + si * b->K, al, R, R1);
     b->status[si] = r.status; b->verdict[si] = r.verdict; b->verdict_1g[si] = r.verdict_1g;
@@ -532,11 +560,15 @@ static void *or_worker(void *arg)
 }
 
 /* Solve a batch of task sets (SoA, offsets[n_sets+1]) with nthreads workers.
+ * Explicit time tables (optional, all three or none): set s's task i has its
+ * time on m units at Cn_tab/Cc_tab[tab_off[s] + i*M[s] + m-1]; Cs, Cp and k
+ * may then be NULL.
  * Outputs: per set status, verdict, verdict_1g, pidx, sizes[K], aidx, maxU,
  * sumU, n_evals; per task alloc, R, R1g; counters[3] per set (optional). */
 int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
                    const int64_t *T, const int64_t *D, const int64_t *Cs, const int64_t *Cp,
-                   const int32_t *k, const uint8_t *type, int K, int mode, int flags, int nthreads,
+                   const int32_t *k, const uint8_t *type, const int64_t *tab_off, const int64_t *Cn_tab,
+                   const int64_t *Cc_tab, int K, int mode, int flags, int nthreads,
                    int32_t *status, uint8_t *verdict, uint8_t *verdict_1g, int32_t *pidx, int32_t *sizes,
                    int64_t *aidx, uint64_t *maxU, uint64_t *sumU, int64_t *n_evals,
                    int8_t *alloc, int64_t *R, int64_t *R1g, int64_t *counters)
@@ -546,6 +578,7 @@ int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
     int t;
     if (K < 1 || K > 8 || mode < OR_EXH || mode > OR_SMS_ACT) return OR_E_INVAL;
     b.n_sets = n_sets; b.off = off; b.M = M; b.T = T; b.D = D; b.Cs = Cs; b.Cp = Cp; b.k = k;
+    b.tab_off = tab_off; b.Cn_tab = tab_off ? Cn_tab : NULL; b.Cc_tab = tab_off ? Cc_tab : NULL;
     b.type = type; b.K = K; b.mode = mode; b.flags = flags; b.status = status; b.verdict = verdict;
     b.verdict_1g = verdict_1g; b.pidx = pidx; b.sizes = sizes; b.aidx = aidx; b.maxU = maxU;
     b.sumU = sumU; b.n_evals = n_evals; b.alloc = alloc; b.R = R; b.R1g = R1g; b.counters = counters;
@@ -567,7 +600,8 @@ int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
 #define OR_SET_ARGS int n, int M, const int64_t *T, const int64_t *D, const int64_t *Cs, \
                     const int64_t *Cp, const int32_t *k, const uint8_t *type
 #define OR_SET_INIT(s) do { (s).n = n; (s).M = M; (s).T = T; (s).D = D; (s).Cs = Cs; (s).Cp = Cp; \
-                            (s).k = k; (s).type = type; (s).cnt = NULL; } while (0)
+                            (s).k = k; (s).type = type; (s).Cn_tab = NULL; (s).Cc_tab = NULL; \
+                            (s).cnt = NULL; } while (0)
 
 /* evaluate one triple; returns feasible; R_out[n] (-1 for misses or, with
  * early_exit, for tasks never reached) */
@@ -893,12 +927,15 @@ done:
     return ok;
 }
 
-int or_alg1_ex(OR_SET_ARGS, int variant, int flags, int32_t *nparts, int32_t *sizes, int8_t *alloc, int64_t *R,
-               int64_t *stats)
+/* Cn_tab/Cc_tab: explicit time tables of the set ([i*M + m-1]) or NULL */
+int or_alg1_ex(OR_SET_ARGS, const int64_t *Cn_tab, const int64_t *Cc_tab, int variant, int flags, int32_t *nparts,
+               int32_t *sizes, int8_t *alloc, int64_t *R, int64_t *stats)
 {
     or_set s;
     int np = 0, ok;
     OR_SET_INIT(s);
+    s.Cn_tab = Cn_tab;
+    s.Cc_tab = Cn_tab ? Cc_tab : NULL;
     if (n < 1 || n > OR_MAXN || M < 1) return -1;
     ok = or_alg1(&s, variant, flags, &np, sizes, alloc, R, stats);
     *nparts = np;

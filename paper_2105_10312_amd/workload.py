@@ -39,7 +39,8 @@ K_MEMORY = 2300
 
 __all__ = [
     "TaskSets", "uunifast", "gen_sets", "config_c1", "config_c2", "config_c3",
-    "config_c4", "config_c5_query_sizes", "config_paper_fig4", "concat", "subset", "TYPE_COMPUTE",
+    "config_c4", "config_c5_query_sizes", "config_paper_fig4", "with_time_tables", "concat", "subset",
+    "TYPE_COMPUTE",
     "TYPE_MEMORY",
 ]
 
@@ -60,8 +61,13 @@ class TaskSets(dict):
 
     def set(self, s: int) -> dict:
         a, b = int(self["set_offset"][s]), int(self["set_offset"][s + 1])
-        return {k: self[k][a:b] for k in ("T", "D", "C_seq", "C_par", "k_permille", "type")} | {
+        one = {k: self[k][a:b] for k in ("T", "D", "C_seq", "C_par", "k_permille", "type")} | {
             "M": int(self["M"][s])}
+        if "Cn_table" in self:
+            t0, t1 = int(self["table_offset"][s]), int(self["table_offset"][s]) + (b - a) * int(self["M"][s])
+            one["Cn_table"] = self["Cn_table"][t0:t1]
+            one["Cc_table"] = self["Cc_table"][t0:t1]
+        return one
 
 
 def uunifast(rng: np.random.Generator, n: int, U: np.ndarray) -> np.ndarray:
@@ -181,6 +187,13 @@ def subset(ts: TaskSets, idx) -> TaskSets:
     out = TaskSets(set_offset=off, M=ts["M"][idx].copy())
     for key in ("T", "D", "C_seq", "C_par", "k_permille", "type"):
         out[key] = ts[key][take].copy()
+    if "Cn_table" in ts:
+        lens = sz * ts["M"][idx].astype(np.int64)
+        out["table_offset"] = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+        rows = [np.arange(ts["table_offset"][s], ts["table_offset"][s] + ln) for s, ln in zip(idx, lens)]
+        tk = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+        out["Cn_table"] = ts["Cn_table"][tk].copy()
+        out["Cc_table"] = ts["Cc_table"][tk].copy()
     return out
 
 
@@ -251,3 +264,43 @@ def config_paper_fig4(seed: int = 6, n: int = 50, M: int = 68, sets_per_point: i
     U = np.repeat(np.asarray(U_points, np.float64), sets_per_point)
     S = U.shape[0]
     return gen_sets(seed, np.full(S, n), U, np.full(S, M), tmin=50, tmax=4000, deadline=0.75, fsplit="paper")
+
+
+def with_time_tables(ts: TaskSets, seed: int = 7) -> TaskSets:
+    """The same sets with explicit per-task time tables Cn[m], Cc[m] for
+    m = 1..M (input profiles, as measured kernels would give; laid out per set
+    as [task][m] from table_offset[s]).  Shapes: a compute-intensive task keeps
+    speeding up with more units (C_seq + ceil(C_par/m)); a memory-intensive
+    one stops beyond a saturation size m_sat ~ U{2..M} (Section "Task model",
+    Definition 1); in conflict a task pays an extra delay that shrinks with m
+    but more slowly (its own saturation size m_c ~ U{1..M}, share 0.1..1.5 of
+    its time there).  Every table is non-increasing in m, the conflict table
+    is never below the other, and m Cn(m) >= Cn(1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = ts.sizes()
+    Ms = ts["M"].astype(np.int64)
+    lens = sizes * Ms
+    out = TaskSets({k: v.copy() for k, v in ts.items()})
+    out["table_offset"] = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    total = int(lens.sum())
+    Cn = np.zeros(total, np.int64)
+    Cc = np.zeros(total, np.int64)
+    for s in range(ts.n_sets):
+        a, b, M = int(ts["set_offset"][s]), int(ts["set_offset"][s + 1]), int(Ms[s])
+        m = np.arange(1, M + 1, dtype=np.int64)[None, :]
+        n = b - a
+        cs = ts["C_seq"][a:b, None]
+        cp = ts["C_par"][a:b, None]
+        mem = ts["type"][a:b, None] == TYPE_MEMORY
+        msat = np.where(mem, rng.integers(2, M + 1, (n, 1)) if M >= 2 else 1, M)
+        cn = cs + (cp + np.minimum(m, msat) - 1) // np.minimum(m, msat)
+        mc = rng.integers(1, M + 1, (n, 1))
+        share = rng.uniform(0.1, 1.5, (n, 1))
+        extra = np.ceil(share * (cs + (cp + np.minimum(m, mc) - 1) // np.minimum(m, mc))).astype(np.int64)
+        cc = cn + extra
+        t0 = int(out["table_offset"][s])
+        Cn[t0:t0 + n * M] = cn.ravel()
+        Cc[t0:t0 + n * M] = cc.ravel()
+    out["Cn_table"] = Cn
+    out["Cc_table"] = Cc
+    return out

@@ -33,6 +33,15 @@ def exec_time(c_seq: int, c_par: int, k: int, m: int, conflict: bool) -> int:
     return base
 
 
+def task_time(task, i: int, m: int, conflict: bool) -> int:
+    """Task i's time on m units: its explicit table entry if the task set has
+    tables ("Cn_table"/"Cc_table", [i*M + m-1]), else the parametric model."""
+    if task.get("Cn_table") is not None:
+        tab = task["Cc_table"] if conflict else task["Cn_table"]
+        return int(tab[i * int(task["M"]) + m - 1])
+    return exec_time(int(task["C_seq"][i]), int(task["C_par"][i]), int(task["k_permille"][i]), m, conflict)
+
+
 def simulate_fp(C, T, D, prio):
     """Discrete-time preemptive FP simulation; prio[i] smaller = higher.
 
@@ -71,8 +80,7 @@ def partition_feasible(task, members, m):
     C = []
     for i in members:
         same = sum(1 for j in members if int(task["type"][j]) == int(task["type"][i]))
-        C.append(exec_time(int(task["C_seq"][i]), int(task["C_par"][i]), int(task["k_permille"][i]), m,
-                           same >= 2))
+        C.append(task_time(task, i, m, same >= 2))
     T = [int(task["T"][i]) for i in members]
     D = [int(task["D"][i]) for i in members]
     keyed = sorted(range(len(members)), key=lambda a: (D[a], T[a], members[a]))
@@ -165,8 +173,7 @@ def whole_gpu(task):
     C = []
     for i in mem:
         same = sum(1 for j in mem if int(task["type"][j]) == int(task["type"][i]))
-        C.append(exec_time(int(task["C_seq"][i]), int(task["C_par"][i]), int(task["k_permille"][i]), M,
-                           same >= 2))
+        C.append(task_time(task, i, M, same >= 2))
     T = [int(x) for x in task["T"]]
     D = [int(x) for x in task["D"]]
     keyed = sorted(range(n), key=lambda a: (D[a], T[a], a))
