@@ -109,6 +109,20 @@ typedef int32_t capart_status;
  * n * M <= 8192; exhaustive mode needs min(K, M)^n < 2^62.  max_tasks and
  * max_M are caller-declared bounds over the batch (the launch is sized from
  * them without reading device memory).
+ *
+ * Explicit time tables (optional; all three pointers set, or all NULL for the
+ * parametric model above): task i (0-based within set s) takes
+ * Cn_table[table_offset[s] + i*M[s] + m-1] on m units without conflict and
+ * Cc_table[same] in conflict, m = 1..M[s] (Section "Modeling kernel execution
+ * times": one time function per interference state, here given pointwise, as
+ * measured kernels give it).  C_seq, C_par and k_permille are then not read
+ * and may be NULL.  Domain (else per-set status E_RANGE): every entry in
+ * [1, 2^31), non-increasing in m, Cc >= Cn at every m, and m * Cn(m) >= Cn(1)
+ * (no super-linear speed-up, which Lemma 1 needs).  table_offset[s] >= 0 and
+ * table_offset[s] + n * M[s] <= table_len (else E_INVAL).  Tables are taken by
+ * capart_validate, capart_solve, capart_solve_async, capart_count_work and the
+ * capart_alg1 calls; the batched plans, the server and the one-set calls
+ * (capart_test_triple, capart_allocate) return E_INVAL for them.
  */
 typedef struct capart_tasksets {
     int64_t n_sets;
@@ -123,6 +137,10 @@ typedef struct capart_tasksets {
     const int64_t *C_par;        /* [n_tasks_total] part divided over m     */
     const int32_t *k_permille;   /* [n_tasks_total] conflict inflation      */
     const uint8_t *type;         /* [n_tasks_total] 0 compute, 1 memory     */
+    const int64_t *table_offset; /* [n_sets] or NULL: explicit time tables  */
+    const int64_t *Cn_table;     /* [table_len] or NULL                     */
+    const int64_t *Cc_table;     /* [table_len] or NULL                     */
+    int64_t table_len;
 } capart_tasksets;
 
 typedef struct capart_options {

@@ -38,7 +38,8 @@ _vp = C.c_void_p
 class capart_tasksets(C.Structure):
     _fields_ = [("n_sets", C.c_int64), ("n_tasks_total", C.c_int64), ("max_tasks", C.c_int32),
                 ("max_M", C.c_int32), ("set_offset", _vp), ("M", _vp), ("T", _vp), ("D", _vp),
-                ("C_seq", _vp), ("C_par", _vp), ("k_permille", _vp), ("type", _vp)]
+                ("C_seq", _vp), ("C_par", _vp), ("k_permille", _vp), ("type", _vp),
+                ("table_offset", _vp), ("Cn_table", _vp), ("Cc_table", _vp), ("table_len", C.c_int64)]
 
 
 class capart_options(C.Structure):
@@ -190,20 +191,30 @@ def make_tasksets(ts: dict, max_tasks: int | None = None, max_M: int | None = No
         Mh = ts["M"].cpu().numpy() if hasattr(ts["M"], "cpu") else ts["M"]
         max_M = int(min(255, max(1, Mh.max() if S else 1)))
     N = int(ts["T"].shape[0])
+    tab = ts.get("Cn_table") is not None
     st = capart_tasksets(S, N, int(max_tasks), int(max_M), _ptr(off), _ptr(ts["M"]), _ptr(ts["T"]),
-                         _ptr(ts["D"]), _ptr(ts["C_seq"]), _ptr(ts["C_par"]), _ptr(ts["k_permille"]),
-                         _ptr(ts["type"]))
+                         _ptr(ts["D"]), _ptr(ts.get("C_seq")), _ptr(ts.get("C_par")), _ptr(ts.get("k_permille")),
+                         _ptr(ts["type"]), _ptr(ts["table_offset"]) if tab else None,
+                         _ptr(ts["Cn_table"]) if tab else None, _ptr(ts["Cc_table"]) if tab else None,
+                         int(ts["Cn_table"].shape[0]) if tab else 0)
     return st, ts
 
 
 def _host_ts(ts: dict) -> dict:
-    return {"set_offset": np.ascontiguousarray(ts["set_offset"], np.int64),
-            "M": np.ascontiguousarray(ts["M"], np.int32),
-            "T": np.ascontiguousarray(ts["T"], np.int64), "D": np.ascontiguousarray(ts["D"], np.int64),
-            "C_seq": np.ascontiguousarray(ts["C_seq"], np.int64),
-            "C_par": np.ascontiguousarray(ts["C_par"], np.int64),
-            "k_permille": np.ascontiguousarray(ts["k_permille"], np.int32),
-            "type": np.ascontiguousarray(ts["type"], np.uint8)}
+    """SoA arrays with the boundary's dtypes; explicit time tables ("table_offset",
+    "Cn_table", "Cc_table") are kept when present, and then the parametric
+    fields may be absent."""
+    h = {"set_offset": np.ascontiguousarray(ts["set_offset"], np.int64),
+         "M": np.ascontiguousarray(ts["M"], np.int32),
+         "T": np.ascontiguousarray(ts["T"], np.int64), "D": np.ascontiguousarray(ts["D"], np.int64),
+         "type": np.ascontiguousarray(ts["type"], np.uint8)}
+    for key, dt in (("C_seq", np.int64), ("C_par", np.int64), ("k_permille", np.int32)):
+        if ts.get(key) is not None:
+            h[key] = np.ascontiguousarray(ts[key], dt)
+    if ts.get("Cn_table") is not None:
+        for key in ("table_offset", "Cn_table", "Cc_table"):
+            h[key] = np.ascontiguousarray(ts[key], np.int64)
+    return h
 
 
 # ---- C-ABI mirrors ---------------------------------------------------------------

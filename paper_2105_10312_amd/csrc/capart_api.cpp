@@ -175,10 +175,15 @@ capart_status check_batch_shape(capart_ctx *c, const capart_tasksets *in)
     if (in->max_M < 1 || in->max_M > CAPART_MAX_M) return fail(c, CAPART_E_INVAL, "max_M out of [1,255]");
     if (in->n_sets > 0 && (!in->set_offset || !in->M))
         return fail(c, CAPART_E_INVAL, "NULL set arrays");
-    if (in->n_tasks_total > 0 && (!in->T || !in->D || !in->C_seq || !in->C_par || !in->k_permille || !in->type))
+    const bool tab = in->Cn_table || in->Cc_table || in->table_offset;
+    if (tab && (!in->Cn_table || !in->Cc_table || !in->table_offset || in->table_len < 0))
+        return fail(c, CAPART_E_INVAL, "explicit time tables need table_offset, Cn_table, Cc_table and table_len");
+    if (in->n_tasks_total > 0 && (!in->T || !in->D || !in->type || (!tab && (!in->C_seq || !in->C_par || !in->k_permille))))
         return fail(c, CAPART_E_INVAL, "NULL task arrays");
     return CAPART_OK;
 }
+
+bool has_tables(const capart_tasksets *in) { return in && (in->Cn_table || in->Cc_table || in->table_offset); }
 
 bool results_ok(const capart_results *r)
 {
@@ -197,12 +202,28 @@ int32_t validate_set(const capart_tasksets *in, int64_t s, int K, int mode)
         n * M > CAPART_MAX_NM)
         return CAPART_E_INVAL;
     const int64_t L31 = (int64_t)1 << 31;
-    for (int64_t i = o0; i < o1; i++) {
-        const int64_t T = in->T[i], D = in->D[i], a = in->C_seq[i], b = in->C_par[i];
-        const int32_t k = in->k_permille[i];
-        if (T < 1 || T >= L31 || D < 1 || D > T || a < 0 || b < 0 || a >= L31 || b >= L31 || a + b < 1 ||
-            a + b >= L31 || k < 1000 || k > 1000000 || in->type[i] > 1)
-            return CAPART_E_RANGE;
+    if (has_tables(in)) {
+        const int64_t t0 = in->table_offset[s];
+        if (t0 < 0 || t0 > in->table_len - n * M) return CAPART_E_INVAL;
+        for (int64_t i = o0; i < o1; i++) {
+            const int64_t T = in->T[i], D = in->D[i];
+            if (T < 1 || T >= L31 || D < 1 || D > T || in->type[i] > 1) return CAPART_E_RANGE;
+            const int64_t *rn = in->Cn_table + t0 + (i - o0) * M, *rc = in->Cc_table + t0 + (i - o0) * M;
+            for (int m = 1; m <= M; m++) {
+                const int64_t cn = rn[m - 1], cc = rc[m - 1];
+                if (cn < 1 || cn >= L31 || cc < 1 || cc >= L31 || cc < cn) return CAPART_E_RANGE;
+                if (m > 1 && (cn > rn[m - 2] || cc > rc[m - 2])) return CAPART_E_RANGE;
+                if ((int64_t)m * cn < rn[0]) return CAPART_E_RANGE;
+            }
+        }
+    } else {
+        for (int64_t i = o0; i < o1; i++) {
+            const int64_t T = in->T[i], D = in->D[i], a = in->C_seq[i], b = in->C_par[i];
+            const int32_t k = in->k_permille[i];
+            if (T < 1 || T >= L31 || D < 1 || D > T || a < 0 || b < 0 || a >= L31 || b >= L31 || a + b < 1 ||
+                a + b >= L31 || k < 1000 || k > 1000000 || in->type[i] > 1)
+                return CAPART_E_RANGE;
+        }
     }
     if (mode == CAPART_EXHAUSTIVE) {
         const uint64_t kk = (uint64_t)std::min(K, M);
@@ -383,6 +404,14 @@ capart_status launch_three(capart_ctx *c, const Batch &b, const Work &w, const O
     return CAPART_OK;
 }
 
+// The batch's explicit time tables, for the kernels that stage a set.
+void give_tables(Work &w, const Batch &b)
+{
+    w.toff = b.toff;
+    w.tCn = b.Cn;
+    w.tCc = b.Cc;
+}
+
 // Workspace arrays of the context for layout l (ensure_ws first).
 Work bind_work(capart_ctx *c, const WsLayout &l)
 {
@@ -405,7 +434,8 @@ capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &
     const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
     capart_status rc = ensure_ws(c, l.total);
     if (rc != CAPART_OK) return rc;
-    const Work w = bind_work(c, l);
+    Work w = bind_work(c, l);
+    give_tables(w, b);
     if (p.L.flags & CAPART_FLAG_PER_SET_LAUNCH) {
         for (int64_t s = 0; s < p.S; s++) {
             Launch L1 = p.L;
@@ -432,6 +462,12 @@ Batch make_batch(const capart_tasksets *in)
     b.n_tasks_total = in->n_tasks_total;
     b.max_tasks = in->max_tasks;
     b.max_M = in->max_M;
+    if (has_tables(in)) {
+        b.toff = in->table_offset;
+        b.Cn = in->Cn_table;
+        b.Cc = in->Cc_table;
+        b.tlen = in->table_len;
+    }
     return b;
 }
 
@@ -467,6 +503,24 @@ struct Bump {
         return p;
     }
 };
+
+// Explicit time tables of a host batch into the staging buffer (d gets the
+// device pointers).
+capart_status stage_tables(capart_ctx *c, const capart_tasksets *in, Bump &bp, hipStream_t st, capart_tasksets &d)
+{
+    const int64_t S = in->n_sets, TL = in->table_len;
+    int64_t *t_off = bp.take<int64_t>(S), *t_cn = bp.take<int64_t>(TL), *t_cc = bp.take<int64_t>(TL);
+    hipError_t e;
+    if ((S && (e = hipMemcpyAsync(t_off, in->table_offset, 8 * (size_t)S, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (TL && (e = hipMemcpyAsync(t_cn, in->Cn_table, 8 * (size_t)TL, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (TL && (e = hipMemcpyAsync(t_cc, in->Cc_table, 8 * (size_t)TL, hipMemcpyHostToDevice, st)) != hipSuccess))
+        return hip_fail(c, e, "hipMemcpyAsync H2D");
+    d.table_offset = t_off;
+    d.Cn_table = t_cn;
+    d.Cc_table = t_cc;
+    d.table_len = TL;
+    return CAPART_OK;
+}
 
 size_t stage_need(int64_t S, int64_t N, int K, int64_t ndbg)
 {
@@ -638,7 +692,10 @@ static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const 
     }
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    if ((rc = ensure_stage(c, stage_need(S, N, K, ndbg))) != CAPART_OK) return rc;
+    const int64_t TL = has_tables(in) ? in->table_len : 0;
+    if ((rc = ensure_stage(c, stage_need(S, N, K, ndbg) + (TL ? align256(8 * (size_t)S) + 2 * align256(8 * (size_t)TL) + 768 : 0))) !=
+        CAPART_OK)
+        return rc;
     Bump bp{(char *)c->stage};
     capart_tasksets d = *in;
     int64_t *d_off = bp.take<int64_t>(S + 1);
@@ -666,14 +723,15 @@ static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const 
     hipStream_t st = c->stream;
     struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
         {d_off, in->set_offset, 8 * (size_t)(S + 1)}, {d_M, in->M, 4 * (size_t)S},
-        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, 8 * (size_t)N},
-        {d_Cp, in->C_par, 8 * (size_t)N}, {d_k, in->k_permille, 4 * (size_t)N}, {d_ty, in->type, (size_t)N},
+        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, in->C_seq ? 8 * (size_t)N : 0},
+        {d_Cp, in->C_par, in->C_par ? 8 * (size_t)N : 0}, {d_k, in->k_permille, in->k_permille ? 4 * (size_t)N : 0}, {d_ty, in->type, (size_t)N},
         {d_dbgoff, out->dbg_key ? (const void *)out->dbg_offset : nullptr, out->dbg_key ? 8 * (size_t)S : 0}};
     for (const auto &x : h2d)
         if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyHostToDevice, st)) != hipSuccess)
             return hip_fail(c, e, "hipMemcpyAsync H2D");
     d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
     d.type = d_ty;
+    if (TL && (rc = stage_tables(c, in, bp, st, d)) != CAPART_OK) return rc;
     const Plan p = make_plan(in, opt, c->tune, wide_partitionings(in->set_offset, in->M, S, K));
     if ((rc = run_plan(c, make_batch(&d), make_out(&r), p, st, p_lo, p_hi)) != CAPART_OK) return rc;
     Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
@@ -736,6 +794,7 @@ static capart_status alg1_run(capart_ctx *c, const capart_tasksets *in, const ca
     L.flags = opt->flags & CAPART_FLAG_NO_LEMMA1;
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
     const Batch b = make_batch(in);
+    give_tables(w, b);
     Out po{};
     po.status = out->status;
     const A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged};
@@ -804,6 +863,8 @@ capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart
     add(8 * (S + 1)); add(4 * S);
     add(8 * N); add(8 * N); add(8 * N); add(8 * N); add(4 * N); add(N);
     add(4 * S); add(S); add(4 * S); add(4 * N); add(N); add(8 * N); add(8 * S); add(8 * S);
+    const int64_t TL = has_tables(in) ? in->table_len : 0;
+    if (TL) { add(8 * S); add(8 * TL); add(8 * TL); }
     if ((rc = ensure_stage(c, need)) != CAPART_OK) return rc;
     Bump bp{(char *)c->stage};
     capart_tasksets d = *in;
@@ -825,13 +886,14 @@ capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart
     const hipStream_t st = c->stream;
     struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
         {d_off, in->set_offset, 8 * (size_t)(S + 1)}, {d_M, in->M, 4 * (size_t)S},
-        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, 8 * (size_t)N},
-        {d_Cp, in->C_par, 8 * (size_t)N}, {d_k, in->k_permille, 4 * (size_t)N}, {d_ty, in->type, (size_t)N}};
+        {d_T, in->T, 8 * (size_t)N}, {d_D, in->D, 8 * (size_t)N}, {d_Cs, in->C_seq, in->C_seq ? 8 * (size_t)N : 0},
+        {d_Cp, in->C_par, in->C_par ? 8 * (size_t)N : 0}, {d_k, in->k_permille, in->k_permille ? 4 * (size_t)N : 0}, {d_ty, in->type, (size_t)N}};
     for (const auto &x : h2d)
         if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyHostToDevice, st)) != hipSuccess)
             return hip_fail(c, e, "hipMemcpyAsync H2D");
     d.set_offset = d_off; d.M = d_M; d.T = d_T; d.D = d_D; d.C_seq = d_Cs; d.C_par = d_Cp; d.k_permille = d_k;
     d.type = d_ty;
+    if (TL && (rc = stage_tables(c, in, bp, st, d)) != CAPART_OK) return rc;
     if ((rc = capart_alg1_async(c, &d, opt, &r, st)) != CAPART_OK) return rc;
     Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
                 {out->nparts, r.nparts, 4 * (size_t)S}, {out->sizes, r.sizes, 4 * (size_t)N},
@@ -849,6 +911,7 @@ static capart_status one_set_check(capart_ctx *c, const capart_tasksets *one, co
     if (!c) return CAPART_E_INVAL;
     capart_status rc = check_batch_shape(c, one);
     if (rc != CAPART_OK) return rc;
+    if (has_tables(one)) return fail(c, CAPART_E_INVAL, "explicit time tables are taken by capart_solve, not here");
     if (one->n_sets != 1 || one->set_offset[0] != 0 || one->set_offset[1] != one->n_tasks_total)
         return fail(c, CAPART_E_INVAL, "expected exactly one set with offsets {0, n}");
     if (!sizes || k < 1 || k > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "k must be in [1, 8]");
@@ -1009,6 +1072,7 @@ capart_status capart_count_work(capart_ctx *c, const capart_tasksets *in, const 
     w.counters = (uint64_t *)(base + l.total);
     hipStream_t st = (hipStream_t)hip_stream;
     const Batch b = make_batch(in);
+    give_tables(w, b);
     const Out o = make_out(out);
     (void)hipGetLastError();
     if ((e = hipMemsetAsync(w.counters, 0, 24, st)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
@@ -1296,6 +1360,7 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
     if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
     if (opt->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "the batched form runs heuristic modes");
+    if (has_tables(in)) return fail(c, CAPART_E_INVAL, "explicit time tables are not taken by the batched form");
     if (in->n_sets < 1) return fail(c, CAPART_E_INVAL, "empty batch");
     if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
     const capart_plan_config def{1, 0, 0, 1};
@@ -1862,6 +1927,7 @@ capart_status srv_submit(capart_server *v, const capart_tasksets *one, uint64_t 
     if (one->n_sets != 1 || !one->set_offset || !one->M || one->set_offset[0] != 0 ||
         one->set_offset[1] != one->n_tasks_total)
         return srv_fail(v, CAPART_E_INVAL, "submit takes one set with offsets {0, n}");
+    if (has_tables(one)) return srv_fail(v, CAPART_E_INVAL, "explicit time tables are not taken by the server");
     const int64_t n = one->n_tasks_total;
     const int32_t M = one->M[0];
     if (n < 1 || n > v->cfg.max_tasks || M < 1 || M > v->cfg.max_M || n * M > CAPART_MAX_NM)

@@ -36,6 +36,10 @@ struct Batch {           // device pointers of the caller's batch (set range [s0
     const uint8_t *type;
     int64_t n_tasks_total;
     int32_t max_tasks, max_M;
+    // explicit time tables (nullptr: the parametric model): set s's task i on m
+    // units at Cn/Cc[toff[s] + i*M + m-1]
+    const int64_t *toff = nullptr, *Cn = nullptr, *Cc = nullptr;
+    int64_t tlen = 0;
 };
 
 // One unit of batched (persistent-kernel) work: partitionings [p0, p1) of a
@@ -62,6 +66,8 @@ struct Work {            // device workspace owned by the context
     const uint32_t *slot_off;  // [S + 1] partial slots of each set
     // counting variant of the evaluation kernel only
     uint64_t *counters;        // [3]: response-time terms, exact tests, frontier lookups
+    // explicit time tables of the batch (as in Batch; read when staging a set)
+    const int64_t *toff = nullptr, *tCn = nullptr, *tCc = nullptr;
 };
 
 struct Out {             // device pointers of the caller's results

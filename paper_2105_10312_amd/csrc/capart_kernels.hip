@@ -168,6 +168,21 @@ __device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int6
     }
 }
 
+// Times of rank r on m units, without and in conflict: the batch's explicit
+// tables (read by the task's index in its set), or the parametric model.
+__device__ __forceinline__ void exec_times(const SetLDS &L, const Work &w, int64_t s, int M, int r, int m,
+                                           uint32_t &cn, uint32_t &cc)
+{
+    if (w.tCn) {
+        const int64_t at = w.toff[s] + (int64_t)L.orig[r] * M + (m - 1);
+        cn = (uint32_t)w.tCn[at];
+        cc = (uint32_t)w.tCc[at];
+    } else {
+        cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+        cc = time_c(L.k[r], cn);
+    }
+}
+
 // Records plus the whole [m][conflict][rank] tables of execution times and
 // Q32 utilisations (m = 1..M).
 __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, int64_t s, bool act, Tables &tb)
@@ -178,8 +193,8 @@ __device__ void stage_set(SetLDS &L, const Work &w, int64_t off, int n, int M, i
     uint32_t *tu = capart_dyn_lds + 2 * n * M;
     for (int e = tid; e < n * M; e += nt) {
         const int m = e / n + 1, r = e - (m - 1) * n;
-        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
-        const uint32_t cc = time_c(L.k[r], cn);
+        uint32_t cn, cc;
+        exec_times(L, w, s, M, r, m, cn, cc);
         const int base = (m - 1) * 2 * n + r;
         tc[base] = cn;
         tc[base + n] = cc;
@@ -201,10 +216,11 @@ __device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, in
     uint32_t *tc = capart_dyn_lds;
     for (int e = tid; e < n * M; e += nt) {
         const int m = e / n + 1, r = e - (m - 1) * n;
-        const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+        uint32_t cn, cc;
+        exec_times(L, w, s, M, r, m, cn, cc);
         const int base = (m - 1) * 2 * n + r;
         tc[base] = cn;
-        tc[base + n] = time_c(L.k[r], cn);
+        tc[base + n] = cc;
     }
     __syncthreads();
     tb.C = tc;
@@ -213,16 +229,19 @@ __device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, in
 }
 
 // Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
-// also where C > T (an unschedulable group; C is then recomputed in 64 bits,
-// the u32 table saturating above 2^31).
+// also where C > T (an unschedulable group): only a table entry saturated at
+// C_SAT (a parametric conflict time of 2^31 or more) is recomputed in 64 bits.
 __device__ __forceinline__ uint64_t util_term(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
 {
     const uint32_t C = tb.C[(m - 1) * 2 * tb.n + (int)conf * tb.n + r];
     const uint32_t T = L.T[r];
     if (C <= T) return (uint64_t)util_q32_m1_magic(C, T, L.clo[r], L.chi[r]) + 1ull;
     const uint64_t T64 = T;
-    const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
-    const uint64_t C64 = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
+    uint64_t C64 = C;
+    if (C >= C_SAT) {
+        const uint64_t cn = (uint64_t)L.Cs[r] + ((uint64_t)L.Cp[r] + (uint64_t)m - 1ull) / (uint64_t)m;
+        C64 = conf ? ((uint64_t)L.k[r] * cn + 999ull) / 1000ull : cn;
+    }
     return ((C64 / T64) << 32) + ((((C64 % T64) << 32) + T64 - 1ull) / T64);
 }
 
@@ -895,6 +914,13 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     const int64_t n64 = off1 - off0;
     if (status == CAPART_OK && (n64 < 1 || n64 > nmax || M < 1 || M > Mmax || n64 * M > CAPART_MAX_NM))
         status = CAPART_E_INVAL;
+    const bool tab = b.Cn != nullptr;  // explicit time tables
+    int64_t toff = 0;
+    if (status == CAPART_OK && tab) {
+        toff = b.toff[s];
+        if (toff < 0 || toff > b.tlen - n64 * M) status = CAPART_E_INVAL;
+        if (w.tCn == nullptr) status = CAPART_E_INVAL;  // a path that does not stage tables
+    }
     if (status != CAPART_OK) {
         if (lane == 0) { o.status[s] = status; w.setflags[s] = 0u; }
         return;
@@ -903,14 +929,35 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     int64_t T = 1, D = 1, Cs = 0, Cp = 1;
     int32_t kk = 1000;
     int ty = 0;
+    uint16_t tmmin = MMIN_NONE;
     bool bad = false;
     if (lane < n) {
         T = b.T[off0 + lane]; D = b.D[off0 + lane];
-        Cs = b.Cs[off0 + lane]; Cp = b.Cp[off0 + lane];
-        kk = b.k[off0 + lane]; ty = b.type[off0 + lane];
+        ty = b.type[off0 + lane];
         const int64_t L31 = (int64_t)1 << 31;
-        bad = (T < 1 || T >= L31 || D < 1 || D > T || Cs < 0 || Cp < 0 || Cs >= L31 || Cp >= L31 ||
-               Cs + Cp < 1 || Cs + Cp >= L31 || kk < 1000 || kk > 1000000 || ty > 1);
+        bad = (T < 1 || T >= L31 || D < 1 || D > T || ty > 1);
+        if (tab) {
+            // entries in [1, 2^31), non-increasing in m, Cc >= Cn, m Cn(m) >= Cn(1);
+            // Cn(1) stands in for C_seq + C_par, Lemma 2 is the first m with Cn(m) <= D
+            const int64_t *rn = b.Cn + toff + (int64_t)lane * M, *rc = b.Cc + toff + (int64_t)lane * M;
+            const int64_t c1v = rn[0];
+            int64_t pn = rn[0], pc = rc[0];
+            for (int m = 1; m <= M; m++) {
+                const int64_t cn = rn[m - 1], cc = rc[m - 1];
+                bad |= cn < 1 || cn >= L31 || cc < 1 || cc >= L31 || cc < cn || cn > pn || cc > pc ||
+                       (int64_t)m * cn < c1v;
+                if (tmmin == MMIN_NONE && cn <= D) tmmin = (uint16_t)m;
+                pn = cn;
+                pc = cc;
+            }
+            Cs = 0;
+            Cp = (c1v >= 1 && c1v < L31) ? c1v : 1;
+        } else {
+            Cs = b.Cs[off0 + lane]; Cp = b.Cp[off0 + lane];
+            kk = b.k[off0 + lane];
+            bad |= (Cs < 0 || Cp < 0 || Cs >= L31 || Cp >= L31 || Cs + Cp < 1 || Cs + Cp >= L31 || kk < 1000 ||
+                    kk > 1000000);
+        }
     }
     if (__ballot(bad)) status = CAPART_E_RANGE;
     if (status == CAPART_OK && Lp.mode == CAPART_EXHAUSTIVE) {
@@ -966,7 +1013,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
         TaskRec r;
         r.T = (uint32_t)T; r.D = (uint32_t)D; r.Cs = (uint32_t)Cs; r.Cp = (uint32_t)Cp; r.k = (uint32_t)kk;
         magic_u32((uint32_t)T, &r.clo, &r.chi);
-        r.mmin = m_min((uint32_t)Cs, (uint32_t)Cp, (uint32_t)D, (uint32_t)M);
+        r.mmin = tab ? tmmin : m_min((uint32_t)Cs, (uint32_t)Cp, (uint32_t)D, (uint32_t)M);
         r.orig = (uint8_t)lane;
         r.mem = (uint8_t)ty;
         w.rec[off0 + rank] = r;
@@ -996,8 +1043,16 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
         if (ta.mmin != MMIN_NONE && tb.mmin != MMIN_NONE) {
             const uint32_t m = min((uint32_t)ta.mmin + tb.mmin - 1u, (uint32_t)M);
             const bool conf = ta.mem == tb.mem;
-            uint32_t Ca = time_n(ta.Cs, ta.Cp, m), Cb = time_n(tb.Cs, tb.Cp, m);
-            if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
+            uint32_t Ca, Cb;
+            if (tab) {
+                const int64_t *tt = conf ? b.Cc : b.Cn;
+                Ca = (uint32_t)tt[toff + (int64_t)ta.orig * M + (m - 1)];
+                Cb = (uint32_t)tt[toff + (int64_t)tb.orig * M + (m - 1)];
+            } else {
+                Ca = time_n(ta.Cs, ta.Cp, m);
+                Cb = time_n(tb.Cs, tb.Cp, m);
+                if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
+            }
             if (Ca <= ta.D && Ca < ta.T) {
                 uint64_t R = (uint64_t)Cb + Ca;
                 for (;;) {
@@ -1765,10 +1820,11 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         for (int e = lane; e < rows * n; e += 64) {
             const int i = e / n, r = e - i * n;
             const int m = (i + 1 < rows) ? sm_[i] : M;
-            const uint32_t cn = time_n(L.Cs[r], L.Cp[r], (uint32_t)m);
+            uint32_t cn, cc;
+            exec_times(L, w, s, M, r, m, cn, cc);
             const int base = (m - 1) * 2 * n + r;
             tc[base] = cn;
-            tc[base + n] = time_c(L.k[r], cn);
+            tc[base + n] = cc;
         }
         __syncthreads();
     }

@@ -61,7 +61,7 @@ class TaskSets(dict):
 
     def set(self, s: int) -> dict:
         a, b = int(self["set_offset"][s]), int(self["set_offset"][s + 1])
-        one = {k: self[k][a:b] for k in ("T", "D", "C_seq", "C_par", "k_permille", "type")} | {
+        one = {k: self[k][a:b] for k in ("T", "D", "C_seq", "C_par", "k_permille", "type") if k in self} | {
             "M": int(self["M"][s])}
         if "Cn_table" in self:
             t0, t1 = int(self["table_offset"][s]), int(self["table_offset"][s]) + (b - a) * int(self["M"][s])
@@ -186,7 +186,8 @@ def subset(ts: TaskSets, idx) -> TaskSets:
         if idx.size else np.zeros(0, np.int64)
     out = TaskSets(set_offset=off, M=ts["M"][idx].copy())
     for key in ("T", "D", "C_seq", "C_par", "k_permille", "type"):
-        out[key] = ts[key][take].copy()
+        if key in ts:
+            out[key] = ts[key][take].copy()
     if "Cn_table" in ts:
         lens = sz * ts["M"][idx].astype(np.int64)
         out["table_offset"] = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)

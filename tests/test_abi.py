@@ -98,3 +98,30 @@ def test_validate_rejects_bad_batch_arguments():
         capart.capart_validate(b, 9, "BF_INA")
     with pytest.raises(capart.CapartError):
         capart.capart_validate(b, 3, 7)
+
+
+def test_validate_time_tables_matches_oracle():
+    """Host validation of explicit time tables (capart_validate) gives the
+    oracle's per-set status: good tables pass, each broken rule is E_RANGE,
+    a table region past table_len is E_INVAL."""
+    ts = workload.with_time_tables(workload.config_c1(n_sets=8), seed=81)
+    M = int(ts["M"][0])
+    t = workload.TaskSets({k: v.copy() for k, v in ts.items()})
+    t["Cn_table"][1] = t["Cn_table"][0] + 1                   # set 0: rises with m
+    a1 = int(t["table_offset"][1])
+    t["Cc_table"][a1 + 2] = t["Cn_table"][a1 + 2] - 1         # set 1: faster in conflict
+    a2 = int(t["table_offset"][2])
+    t["Cn_table"][a2 + M - 1] = 1                             # set 2: super-linear
+    t["Cc_table"][a2 + M - 1] = 1
+    a3 = int(t["table_offset"][3])
+    t["Cn_table"][a3:a3 + M] = 1 << 31                        # set 3: too large
+    t["Cc_table"][a3:a3 + M] = 1 << 31
+    for key in ("C_seq", "C_par", "k_permille"):              # the parametric fields are not needed
+        del t[key]
+    got = capart.capart_validate(t, 3, "EXH")
+    want = oracle.solve(t, 3, "EXH")["status"]
+    assert list(got) == list(want)
+    assert list(got[:4]) == [capart.CAPART_E_RANGE] * 4 and (got[4:] == capart.CAPART_OK).all()
+    t["table_offset"] = t["table_offset"].copy()
+    t["table_offset"][7] = len(t["Cn_table"]) - 1             # set 7 runs past the tables
+    assert capart.capart_validate(t, 3, "EXH")[7] == capart.CAPART_E_INVAL

@@ -1,0 +1,171 @@
+"""Explicit per-task time tables on the GPU (through the C ABI).
+
+Tables that restate the parametric model give the parametric results bit for
+bit; general tables (saturating memory-intensive profiles) give the oracle's
+results bit for bit in every allocation mode, for Algorithm 1, on the host and
+device entry points; tables outside the contract get the oracle's status; the
+paths that do not take tables refuse them."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from brute import exec_time
+from paper_2105_10312_amd import capart, workload
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("status", "verdict", "verdict_1g", "pidx", "sizes", "aidx", "maxU", "sumU", "n_evals", "alloc", "R",
+          "R_1g")
+A1_FIELDS = ("status", "verdict", "nparts", "sizes", "alloc", "R", "tried", "merged")
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    e = capart.Engine(0)
+    yield e
+    e.close()
+
+
+def model_tables(ts):
+    """Tables that restate the parametric model, from brute.py's own time model."""
+    out = workload.TaskSets({k: v.copy() for k, v in ts.items()})
+    sizes, Ms = ts.sizes(), ts["M"].astype(np.int64)
+    out["table_offset"] = np.concatenate([[0], np.cumsum(sizes * Ms)[:-1]]).astype(np.int64)
+    cn, cc = [], []
+    for s in range(ts.n_sets):
+        a, b, M = int(ts["set_offset"][s]), int(ts["set_offset"][s + 1]), int(Ms[s])
+        for i in range(a, b):
+            for m in range(1, M + 1):
+                args = (int(ts["C_seq"][i]), int(ts["C_par"][i]), int(ts["k_permille"][i]), m)
+                cn.append(exec_time(*args, False))
+                cc.append(exec_time(*args, True))
+    out["Cn_table"] = np.array(cn, np.int64)
+    out["Cc_table"] = np.array(cc, np.int64)
+    return out
+
+
+def tables_only(ts):
+    """The same batch without the parametric fields (they are not read)."""
+    return workload.TaskSets({k: v for k, v in ts.items() if k not in ("C_seq", "C_par", "k_permille")})
+
+
+def same(got, want, fields, label):
+    for f in fields:
+        g, w = np.asarray(got[f]).ravel(), np.asarray(want[f]).ravel()
+        assert g.shape == w.shape and np.array_equal(g, w), f"{label}: field {f} differs"
+
+
+def alg1_oracle(ts, mode):
+    S, N = ts.n_sets, ts.n_tasks
+    off = ts["set_offset"]
+    out = dict(status=np.zeros(S, np.int32), verdict=np.zeros(S, np.uint8), nparts=np.zeros(S, np.int32),
+               sizes=np.zeros(N, np.int32), alloc=np.full(N, -1, np.int8), R=np.full(N, -1, np.int64),
+               tried=np.zeros(S, np.int64), merged=np.zeros(S, np.int64))
+    for s in range(S):
+        r = oracle.alg1(ts.set(s), mode)
+        a, b = int(off[s]), int(off[s + 1])
+        out["verdict"][s], out["tried"][s], out["merged"][s] = r["verdict"], r["tried"], r["merged"]
+        if r["verdict"]:
+            out["nparts"][s] = r["k"]
+            out["sizes"][a:a + r["k"]] = r["sizes"]
+            out["alloc"][a:b] = r["alloc"]
+            out["R"][a:b] = r["R"]
+    return out
+
+
+def test_model_tables_give_the_parametric_results(eng):
+    c1 = workload.config_c1(n_sets=60)
+    c2 = workload.subset(workload.config_c2(n_sets=2000), np.arange(200))
+    c5 = workload.subset(workload.config_c5(n_queries=400), np.arange(120))
+    for ts, K, modes in ((c1, 3, ("EXH", "BF_INA")), (c2, 4, ("BF_INA", "SMS_ACT")), (c5, 4, ("BF_ACT", "SMS_INA"))):
+        tt = tables_only(model_tables(ts))
+        for mode in modes:
+            say(f"model tables {mode}: {ts.n_sets} sets")
+            same(eng.solve(tt, K, mode), eng.solve(ts, K, mode), FIELDS, f"model tables {mode}")
+    f4 = workload.config_paper_fig4(sets_per_point=3)
+    tt = tables_only(model_tables(f4))
+    for mode in ("BF_INA", "SMS_ACT"):
+        same(eng.alg1(tt, mode), eng.alg1(f4, mode), A1_FIELDS, f"model tables alg1 {mode}")
+
+
+@pytest.mark.parametrize("mode", ["EXH", "BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_general_tables_match_oracle(eng, mode):
+    if mode == "EXH":
+        ts = workload.with_time_tables(workload.config_c1(n_sets=100), seed=91)
+        K = 3
+    else:
+        c2 = workload.subset(workload.config_c2(n_sets=2000), np.arange(300))
+        c3 = workload.subset(workload.config_c3(n_sets=2000), np.arange(150))
+        c5 = workload.config_c5(seed=92, n_queries=300)
+        wide = workload.subset(c5, np.nonzero((c5.sizes() > 32) & (c5["M"] <= 48))[0][:12])
+        ts = workload.with_time_tables(workload.concat([c2, c3, wide]), seed=93)
+        K = 4
+    tt = tables_only(ts)
+    say(f"general tables {mode}: {tt.n_sets} sets")
+    want = oracle.solve(tt, K, mode, nthreads=THREADS)
+    assert (want["status"] == oracle.OK).all()
+    same(eng.solve(tt, K, mode), want, FIELDS, f"general tables {mode}")
+
+
+def test_general_tables_alg1_match_oracle(eng):
+    f4 = workload.with_time_tables(workload.config_paper_fig4(sets_per_point=4), seed=94)
+    tt = tables_only(f4)
+    for mode in ("BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"):
+        say(f"general tables alg1 {mode}: {tt.n_sets} sets")
+        same(eng.alg1(tt, mode), alg1_oracle(tt, mode), A1_FIELDS, f"alg1 tables {mode}")
+
+
+def test_device_entry_points_with_tables(eng):
+    import torch
+    ts = tables_only(workload.with_time_tables(workload.subset(workload.config_c2(n_sets=1000), np.arange(120)),
+                                               seed=95))
+    dev = capart.device_tasksets(ts)
+    assert "Cn_table" in dev
+    out = capart.device_results(ts.n_sets, ts.n_tasks, 4)
+    capart.capart_solve_async(eng.ctx, dev, 4, "SMS_INA", out, max_tasks=10, max_M=80)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    want = eng.solve(ts, 4, "SMS_INA")
+    for f in FIELDS:
+        n = np.asarray(want[f]).size
+        assert np.array_equal(got[f].ravel()[:n], np.asarray(want[f]).ravel()), f
+    a1 = capart.device_alg1_results(ts.n_sets, ts.n_tasks)
+    capart.capart_alg1_async(eng.ctx, dev, "BF_INA", a1, max_tasks=10, max_M=80)
+    torch.cuda.synchronize()
+    want = eng.alg1(ts, "BF_INA")
+    for f in A1_FIELDS:
+        n = np.asarray(want[f]).size
+        assert np.array_equal(a1[f].cpu().numpy().ravel()[:n], np.asarray(want[f]).ravel()), f
+
+
+def test_tables_outside_the_contract(eng):
+    ts = workload.with_time_tables(workload.config_c1(n_sets=6), seed=96)
+    M = int(ts["M"][0])
+    t = tables_only(workload.TaskSets({k: v.copy() for k, v in ts.items()}))
+    t["Cn_table"][1] = t["Cn_table"][0] + 1
+    a2 = int(t["table_offset"][2])
+    t["Cn_table"][a2 + M - 1] = 1
+    t["Cc_table"][a2 + M - 1] = 1
+    got = eng.solve(t, 3, "BF_INA")
+    want = oracle.solve(t, 3, "BF_INA")
+    same(got, want, FIELDS, "invalid tables")
+    assert got["status"][0] == capart.CAPART_E_RANGE and got["status"][2] == capart.CAPART_E_RANGE
+
+
+def test_paths_without_tables_refuse_them(eng):
+    import torch
+    ts = tables_only(workload.with_time_tables(workload.config_c1(n_sets=4), seed=97))
+    dev = capart.device_tasksets(ts)
+    out = capart.device_results(ts.n_sets, ts.n_tasks, 3)
+    with pytest.raises(capart.CapartError):
+        capart.Plan(eng.ctx, dev, 3, "BF_INA", out, 5, 8)
+    torch.cuda.synchronize()
