@@ -94,7 +94,12 @@ def lemma1_pruned(ts):
     exactly in int64: floor(Cn*2^32/T) = (Cn//T)*2^32 + floor((Cn%T)*2^32/T),
     each term clamped above M*2^32 so the per-set sums cannot overflow."""
     import numpy as np
-    cn = ts["C_seq"] + ts["C_par"]
+    if "Cn_table" in ts:  # explicit tables: Cn(1) is each task's first entry
+        sizes = np.diff(ts["set_offset"])
+        local = np.arange(ts["T"].shape[0]) - np.repeat(ts["set_offset"][:-1], sizes)
+        cn = ts["Cn_table"][np.repeat(ts["table_offset"], sizes) + local * np.repeat(ts["M"].astype(np.int64), sizes)]
+    else:
+        cn = ts["C_seq"] + ts["C_par"]
     T = ts["T"]
     q, r = cn // T, cn % T
     cap = (int(ts["M"].max()) + 1) << 32
@@ -229,6 +234,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--form", default="batched", choices=["batched", "plain"],
                     help="GPU form timed for `value` (c2, c3)")
+    ap.add_argument("--tables", action="store_true",
+                    help="give the sets explicit per-task time tables (saturating memory-intensive profiles) "
+                         "instead of the parametric model; runs the plain path")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form without HIP graph capture (same kernels and arguments; for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -297,6 +305,12 @@ def main():
         max_tasks, max_M, desc = 12, 48, "n=12, M=48, exhaustive allocation"
         mode = "EXH"
         cpu_sample, cpu_stride = 0, 1
+    if args.tables:
+        ts = workload.with_time_tables(ts)
+        for key in ("C_seq", "C_par", "k_permille"):
+            del ts[key]
+        desc += ", explicit time tables"
+        args.form = "plain"
     log(f"[bench] workload {args.workload}: {ts.n_sets} sets, {desc}, K={K}, {mode}")
     Pcount = {int(m): capart.capart_count_partitionings(int(m), K) for m in np.unique(ts["M"])}
     evals_per_step = int(sum(Pcount[int(m)] for m in ts["M"]))
@@ -395,7 +409,7 @@ def main():
         log(f"[bench] one launch per set: {compare['per_set_launch']['value']:.4g} evals/s")
 
     serving = None
-    if args.workload == "c2" and not args.no_serving:
+    if args.workload == "c2" and not args.no_serving and not args.tables:
         # 2,000 queries/s: inside the capacity of this mix with its 49..64-task
         # queries (each costs tens of ms alone), so the latencies are not queue growth
         serving = serving_leg(eng, capart, workload, 2e3, 10000)

@@ -24,6 +24,19 @@ def test_lemma1_pruned_count_matches_oracle():
     assert bench.lemma1_pruned(ts) == want
 
 
+def test_lemma1_pruned_count_with_time_tables():
+    # the table profiles keep Cn(1) = C_seq + C_par, so Lemma 1 decides alike
+    rng = np.random.default_rng(2)
+    U = rng.uniform(4, 12, 300)
+    ts = workload.gen_sets(4, np.full(300, 6), U, np.full(300, 8), tmin=1e3, tmax=1e6)
+    want = sum(oracle.lemma1_reject(ts.set(i)) for i in range(ts.n_sets))
+    tt = workload.with_time_tables(ts)
+    for key in ("C_seq", "C_par", "k_permille"):
+        del tt[key]
+    assert 0 < want < ts.n_sets
+    assert bench.lemma1_pruned(tt) == want
+
+
 def test_lemma1_pruned_count_large_ratios():
     # C/T ratios far above M: the per-term clamp must keep the sum exact
     ts = workload.TaskSets(set_offset=np.array([0, 2, 3, 5]), M=np.array([4, 255, 1], np.int32))
