@@ -143,11 +143,23 @@ typedef struct capart_tasksets {
     int64_t table_len;
 } capart_tasksets;
 
+/*
+ * Admissible partition sizes (MIG-like restrictions of the sizes a partition
+ * may take; Section "Conclusion" names such partitioning mechanisms):
+ * admissible[m >> 6] bit (m & 63) set allows size m (1..255); all four words
+ * 0 allows every size.  A partitioning with a part of another size is still
+ * numbered and counted in n_evals but is infeasible (its debug key is
+ * "none"); the whole-GPU baseline is unaffected.  Honoured by capart_solve,
+ * capart_solve_async, capart_count_work and the batched plans; capart_alg1
+ * and capart_alg1_async return E_INVAL for a non-empty mask; the one-set calls
+ * evaluate the partitioning they are given.
+ */
 typedef struct capart_options {
     int32_t K;           /* maximum number of parts, 1..8      */
     int32_t policy;      /* CAPART_POLICY_FP_DM                */
     int32_t alloc_mode;  /* CAPART_EXHAUSTIVE or CAPART_HEUR_* */
     uint32_t flags;      /* CAPART_FLAG_*                      */
+    uint64_t admissible[4];  /* allowed part sizes, all 0 = every size */
 } capart_options;
 
 /*

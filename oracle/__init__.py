@@ -53,7 +53,7 @@ def _load():
         set_args = [C.c_int, C.c_int, i64p, i64p, i64p, i64p, i32p, u8p]
         lib.or_solve_batch.restype = C.c_int
         lib.or_solve_batch.argtypes = [C.c_int64, i64p, i32p, i64p, i64p, i64p, i64p, i32p, u8p,
-                                       C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int, C.c_int, C.c_int, C.c_int,
                                        i32p, u8p, u8p, i32p, i32p, i64p, u64p, u64p, i64p,
                                        i8p, i64p, i64p, C.c_void_p]
@@ -111,8 +111,18 @@ def _one(task: dict):
     return (len(arrs[0]), int(task["M"])) + arrs
 
 
-def solve(ts: dict, K: int, mode="BF_INA", flags: int = 0, nthreads: int = 1, counters: bool = False) -> dict:
-    """Solve every set of a SoA batch; returns a dict of numpy result arrays."""
+def admissible_mask(sizes) -> np.ndarray:
+    """4-word mask with bit m set for every admissible partition size m."""
+    mask = np.zeros(4, np.uint64)
+    for m in sizes:
+        mask[int(m) // 64] |= np.uint64(1) << np.uint64(int(m) % 64)
+    return mask
+
+
+def solve(ts: dict, K: int, mode="BF_INA", flags: int = 0, nthreads: int = 1, counters: bool = False,
+          admissible=None) -> dict:
+    """Solve every set of a SoA batch; returns a dict of numpy result arrays.
+    admissible: allowed partition sizes (an iterable of sizes), None = every size."""
     lib = _load()
     mode = MODES[mode] if isinstance(mode, str) else int(mode)
     off = np.ascontiguousarray(ts["set_offset"], np.int64)
@@ -126,9 +136,11 @@ def solve(ts: dict, K: int, mode="BF_INA", flags: int = 0, nthreads: int = 1, co
                alloc=np.zeros(N, np.int8), R=np.zeros(N, np.int64), R_1g=np.zeros(N, np.int64))
     cnt = np.zeros(S * 3, np.int64) if counters else None
     to, cn, cc = _tables(ts)
+    adm = admissible_mask(admissible) if admissible is not None else None
     rc = lib.or_solve_batch(S, off, M, T, D, Cs, Cp, k, ty,
                             to.ctypes.data if to is not None else None, cn.ctypes.data if cn is not None else None,
-                            cc.ctypes.data if cc is not None else None, K, mode, flags, nthreads,
+                            cc.ctypes.data if cc is not None else None, adm.ctypes.data if adm is not None else None,
+                            K, mode, flags, nthreads,
                             out["status"], out["verdict"], out["verdict_1g"], out["pidx"], out["sizes"],
                             out["aidx"], out["maxU"], out["sumU"], out["n_evals"], out["alloc"], out["R"],
                             out["R_1g"], cnt.ctypes.data if cnt is not None else None)

@@ -73,6 +73,8 @@ typedef struct {
     /* explicit time tables (NULL: the parametric model from Cs, Cp, k):
      * task i's time on m units at [i*M + m-1], without and in conflict */
     const int64_t *Cn_tab, *Cc_tab;
+    /* admissible partition sizes: bit m of the 256-bit mask (NULL: every size) */
+    const uint64_t *adm;
     or_counters *cnt;
 } or_set;
 
@@ -440,7 +442,10 @@ static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_res
     if (!reject) {
         for (pi = 0; pi < P; pi++) {
             const int *sz = table + pi * K;
-            for (k = 0; k < K && sz[k] > 0; k++) {}
+            int allowed = 1;
+            for (k = 0; k < K && sz[k] > 0; k++)
+                if (s->adm && !((s->adm[sz[k] / 64] >> (sz[k] % 64)) & 1u)) allowed = 0;
+            if (!allowed) continue; /* a part size outside the admissible set */
             if (mode == OR_EXH) {
                 int64_t a, A = 1;
                 for (i = 0; i < n; i++) A *= k;
@@ -497,6 +502,7 @@ static void or_make_set(or_set *s, int64_t off0, int64_t off1, int32_t M, const 
     s->Cs = Cs ? Cs + off0 : NULL; s->Cp = Cp ? Cp + off0 : NULL; s->k = k ? k + off0 : NULL;
     s->type = type + off0;
     s->Cn_tab = s->Cc_tab = NULL;
+    s->adm = NULL;
     s->cnt = cnt;
 }
 
@@ -505,6 +511,7 @@ typedef struct {
     const int64_t *off; const int32_t *M;
     const int64_t *T, *D, *Cs, *Cp; const int32_t *k; const uint8_t *type;
     const int64_t *tab_off, *Cn_tab, *Cc_tab; /* explicit tables (NULL: parametric) */
+    const uint64_t *adm;                      /* admissible sizes (NULL: every size) */
     int K, mode, flags;
     int32_t *status; uint8_t *verdict, *verdict_1g; int32_t *pidx, *sizes;
     int64_t *aidx; uint64_t *maxU, *sumU; int64_t *n_evals;
@@ -526,6 +533,7 @@ static void or_batch_set(or_batch *b, int64_t si)
         s.Cn_tab = b->Cn_tab + b->tab_off[si];
         s.Cc_tab = b->Cc_tab + b->tab_off[si];
     }
+    s.adm = b->adm;
     if (n < 0) n = 0;
     or_solve_one(&s, b->K, b->mode, b->flags, &r, b->sizes + si * b->K, al, R, R1);
     b->status[si] = r.status; b->verdict[si] = r.verdict; b->verdict_1g[si] = r.verdict_1g;
@@ -562,13 +570,14 @@ static void *or_worker(void *arg)
 /* Solve a batch of task sets (SoA, offsets[n_sets+1]) with nthreads workers.
  * Explicit time tables (optional, all three or none): set s's task i has its
  * time on m units at Cn_tab/Cc_tab[tab_off[s] + i*M[s] + m-1]; Cs, Cp and k
- * may then be NULL.
+ * may then be NULL.  adm (optional, 4 words): only partitionings whose part
+ * sizes all have their bit set are considered (NULL: every partitioning).
  * Outputs: per set status, verdict, verdict_1g, pidx, sizes[K], aidx, maxU,
  * sumU, n_evals; per task alloc, R, R1g; counters[3] per set (optional). */
 int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
                    const int64_t *T, const int64_t *D, const int64_t *Cs, const int64_t *Cp,
                    const int32_t *k, const uint8_t *type, const int64_t *tab_off, const int64_t *Cn_tab,
-                   const int64_t *Cc_tab, int K, int mode, int flags, int nthreads,
+                   const int64_t *Cc_tab, const uint64_t *adm, int K, int mode, int flags, int nthreads,
                    int32_t *status, uint8_t *verdict, uint8_t *verdict_1g, int32_t *pidx, int32_t *sizes,
                    int64_t *aidx, uint64_t *maxU, uint64_t *sumU, int64_t *n_evals,
                    int8_t *alloc, int64_t *R, int64_t *R1g, int64_t *counters)
@@ -579,6 +588,7 @@ int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
     if (K < 1 || K > 8 || mode < OR_EXH || mode > OR_SMS_ACT) return OR_E_INVAL;
     b.n_sets = n_sets; b.off = off; b.M = M; b.T = T; b.D = D; b.Cs = Cs; b.Cp = Cp; b.k = k;
     b.tab_off = tab_off; b.Cn_tab = tab_off ? Cn_tab : NULL; b.Cc_tab = tab_off ? Cc_tab : NULL;
+    b.adm = adm;
     b.type = type; b.K = K; b.mode = mode; b.flags = flags; b.status = status; b.verdict = verdict;
     b.verdict_1g = verdict_1g; b.pidx = pidx; b.sizes = sizes; b.aidx = aidx; b.maxU = maxU;
     b.sumU = sumU; b.n_evals = n_evals; b.alloc = alloc; b.R = R; b.R1g = R1g; b.counters = counters;
@@ -601,7 +611,7 @@ int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
                     const int64_t *Cp, const int32_t *k, const uint8_t *type
 #define OR_SET_INIT(s) do { (s).n = n; (s).M = M; (s).T = T; (s).D = D; (s).Cs = Cs; (s).Cp = Cp; \
                             (s).k = k; (s).type = type; (s).Cn_tab = NULL; (s).Cc_tab = NULL; \
-                            (s).cnt = NULL; } while (0)
+                            (s).adm = NULL; (s).cnt = NULL; } while (0)
 
 /* evaluate one triple; returns feasible; R_out[n] (-1 for misses or, with
  * early_exit, for tasks never reached) */

@@ -43,7 +43,8 @@ class capart_tasksets(C.Structure):
 
 
 class capart_options(C.Structure):
-    _fields_ = [("K", C.c_int32), ("policy", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32)]
+    _fields_ = [("K", C.c_int32), ("policy", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32),
+                ("admissible", C.c_uint64 * 4)]
 
 
 class capart_results(C.Structure):
@@ -176,8 +177,17 @@ def _mode(mode):
     return MODES[mode] if isinstance(mode, str) else int(mode)
 
 
-def make_options(K: int, mode="BF_INA", flags: int = 0) -> capart_options:
-    return capart_options(int(K), CAPART_POLICY_FP_DM, _mode(mode), int(flags))
+def admissible_mask(sizes) -> list:
+    """The 4-word mask of the admissible partition sizes (None or empty: every size)."""
+    w = [0, 0, 0, 0]
+    for m in (sizes if sizes is not None else ()):
+        w[int(m) // 64] |= 1 << (int(m) % 64)
+    return w
+
+
+def make_options(K: int, mode="BF_INA", flags: int = 0, admissible=None) -> capart_options:
+    return capart_options(int(K), CAPART_POLICY_FP_DM, _mode(mode), int(flags),
+                          (C.c_uint64 * 4)(*admissible_mask(admissible)))
 
 
 def make_tasksets(ts: dict, max_tasks: int | None = None, max_M: int | None = None) -> tuple:
@@ -313,11 +323,12 @@ def dbg_offsets(M, K: int) -> np.ndarray:
 
 
 def capart_solve(ctx, ts: dict, K: int, mode="BF_INA", flags: int = 0, debug: bool = False, max_tasks=None,
-                 max_M=None) -> dict:
-    """Solve a host batch (synchronous); returns a dict of numpy result arrays."""
+                 max_M=None, admissible=None) -> dict:
+    """Solve a host batch (synchronous); returns a dict of numpy result arrays.
+    admissible: the allowed partition sizes (None: every size)."""
     h = _host_ts(ts)
     st, _keep = make_tasksets(h, max_tasks, max_M)
-    opt = make_options(K, mode, flags)
+    opt = make_options(K, mode, flags, admissible)
     S, N = st.n_sets, st.n_tasks_total
     out = {}
     for name, dt, shape in RESULT_FIELDS:
@@ -359,13 +370,13 @@ def device_tasksets(ts: dict, device="cuda") -> dict:
 
 
 def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=None, flags: int = 0,
-                       max_tasks=None, max_M=None, dbg_key=None, dbg_offset=None) -> None:
+                       max_tasks=None, max_M=None, dbg_key=None, dbg_offset=None, admissible=None) -> None:
     """Solve a batch resident in GPU memory; results land in dev_out (torch tensors) on `stream`."""
     import torch
     if max_tasks is None or max_M is None:
         raise ValueError("device batches need declared max_tasks and max_M bounds")
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(K, mode, flags)
+    opt = make_options(K, mode, flags, admissible)
     res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -472,10 +483,10 @@ class Plan:
 
     def __init__(self, ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, flags: int = 0,
                  autotune: bool = True, blocks_per_cu: int = 0, item_evals: int = 0, use_graph: bool = True,
-                 dbg_key=None, dbg_offset=None):
+                 dbg_key=None, dbg_offset=None, admissible=None):
         self.ctx = ctx
         self._st, self._keep = make_tasksets(dev_ts, max_tasks, max_M)
-        self._opt = make_options(K, mode, flags)
+        self._opt = make_options(K, mode, flags, admissible)
         self._out = dev_out
         self._res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
         self._dbg = (dbg_key, dbg_offset)
@@ -612,8 +623,8 @@ class Engine:
         except Exception:
             pass
 
-    def solve(self, ts, K, mode="BF_INA", flags=0, debug=False):
-        return capart_solve(self.ctx, ts, K, mode, flags, debug)
+    def solve(self, ts, K, mode="BF_INA", flags=0, debug=False, admissible=None):
+        return capart_solve(self.ctx, ts, K, mode, flags, debug, admissible=admissible)
 
     def alg1(self, ts, mode="BF_INA", flags=0):
         return capart_alg1(self.ctx, ts, mode, flags)

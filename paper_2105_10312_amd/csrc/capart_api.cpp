@@ -292,6 +292,7 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
     L.K = opt->K;
     L.mode = opt->alloc_mode;
     L.flags = opt->flags;
+    for (int i = 0; i < 4; i++) L.adm.w[i] = opt->admissible[i];
     L.threads = eval_threads(in->max_tasks, in->max_M);
     if (tu.threads > 0) L.threads = std::min(L.threads, tu.threads);
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
@@ -763,6 +764,8 @@ static capart_status alg1_check(capart_ctx *c, const capart_tasksets *in, const 
     if (opt->policy != CAPART_POLICY_FP_DM) return fail(c, CAPART_E_INVAL, "unsupported policy");
     if (opt->alloc_mode < CAPART_HEUR_BF_INA || opt->alloc_mode > CAPART_HEUR_SMS_ACT)
         return fail(c, CAPART_E_INVAL, "Algorithm 1 needs a heuristic order (CAPART_HEUR_*)");
+    if (opt->admissible[0] | opt->admissible[1] | opt->admissible[2] | opt->admissible[3])
+        return fail(c, CAPART_E_INVAL, "Algorithm 1 takes every partition size (admissible must be empty)");
     if (opt->flags & ~(CAPART_FLAG_SKIP_1G | CAPART_FLAG_NO_LEMMA1 | CAPART_FLAG_PER_SET_LAUNCH))
         return fail(c, CAPART_E_INVAL, "unknown flag");
     capart_status rc = check_batch_shape(c, in);
@@ -1336,6 +1339,7 @@ Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int thr
     L.K = opt->K;
     L.mode = opt->alloc_mode;
     L.flags = opt->flags & ~CAPART_FLAG_PER_SET_LAUNCH;
+    for (int i = 0; i < 4; i++) L.adm.w[i] = opt->admissible[i];
     L.threads = std::min(threads, eval_threads(in->max_tasks, in->max_M));
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
     L.form = form == 2 ? 2 : 1;

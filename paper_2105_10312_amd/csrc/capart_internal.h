@@ -83,6 +83,12 @@ struct Out {             // device pointers of the caller's results
     const int64_t *dbg_offset;
 };
 
+// Admissible partition sizes: size m is allowed iff bit m of the 256-bit mask
+// w[0..3] is set; an all-zero mask allows every size.
+struct Adm {
+    uint64_t w[4] = {0, 0, 0, 0};
+};
+
 struct Launch {
     int64_t s0, S;       // set range
     int K, mode;
@@ -100,6 +106,7 @@ struct Launch {
     int memo_packed = 0; // 1: memo sets run the packed-test state machine instead of the nested loops
     int n_lo = 0;        // this evaluation launch takes the sets of n_lo <= n (<= n_hi if n_hi > 0) tasks
     int n_hi = 0;
+    Adm adm;             // admissible part sizes (a partitioning with another size is infeasible)
     int wchunk = 0;      // heuristic, sets above NARROW_MAX_TASKS tasks: partitionings per block of the
                          // wave-per-partitioning launch (0 = one lane per partitioning, chunk per block);
                          // chunks then covers ceil(P / wchunk) as well

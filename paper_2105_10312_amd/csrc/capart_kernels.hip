@@ -891,6 +891,24 @@ __device__ __forceinline__ int next_partition(int (&a)[KMAX], int K)
     return k;
 }
 
+// k, or 0 when a part of m[0..k) has a size outside the admissible set: such
+// a partitioning then has no part to place a task on, and is infeasible.
+template <int KMAX>
+__device__ __forceinline__ int admit(const Adm &a, const int (&m)[KMAX], int k)
+{
+    if ((a.w[0] | a.w[1] | a.w[2] | a.w[3]) == 0ull) return k;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) {
+        if (i < k) {
+            const int x = m[i];
+            const uint64_t wd = x < 64 ? a.w[0] : (x < 128 ? a.w[1] : (x < 192 ? a.w[2] : a.w[3]));
+            ok &= ((wd >> (x & 63)) & 1ull) != 0ull;
+        }
+    }
+    return ok ? k : 0;
+}
+
 // ---------------------------------------------------------------------------
 // prep: one wave per set.
 __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch Lp)
@@ -1094,14 +1112,14 @@ __device__ __forceinline__ int size_of(uint64_t mpack, int p) { return (int)((mp
 // interleaved (entry p of lane l at p * blockDim + l), so that the
 // data-dependent part index costs one conflict-free LDS access.
 template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
-__device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K, uint32_t q0,
-                         uint32_t q1, Key &best, uint64_t *dbg, MT *lS, uint64_t *lU, TY &ty)
+__device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K, const Adm &adm,
+                         uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, MT *lS, uint64_t *lU, TY &ty)
 {
     const int stride = blockDim.x;
     MT *myS = lS + threadIdx.x;
     uint64_t *myU = lU + threadIdx.x;
     int m[KMAX];
-    int k = unrank<KMAX>(np, M, K, q0, m);
+    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
     uint64_t mpack = pack_sizes<KMAX>(m);
 #pragma unroll
     for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
@@ -1162,7 +1180,7 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
                 d[2] = ok ? 0ull : ~0ull;
             }
             if (++q >= q1) break;
-            k = next_partition<KMAX>(m, K);
+            k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
             mpack = pack_sizes<KMAX>(m);
 #pragma unroll
             for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
@@ -1177,10 +1195,11 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
 // partitioning runs to completion, parts unrolled over registers).
 template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
-                                uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty, const Memo &mo)
+                                const Adm &adm, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty,
+                                const Memo &mo)
 {
     int m[KMAX];
-    int k = unrank<KMAX>(np, M, K, q0, m);
+    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
@@ -1202,16 +1221,16 @@ __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_
             d[2] = ok ? 0ull : ~0ull;
         }
         if (++q >= q1) break;
-        k = next_partition<KMAX>(m, K);
+        k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
     }
 }
 
 template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t *ms, const uint32_t *np, int n, int M,
-                               int K, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
+                               int K, const Adm &adm, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
 {
     int m[KMAX];
-    int k = unrank<KMAX>(np, M, K, q0, m);
+    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
@@ -1233,7 +1252,7 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
             d[2] = ok ? 0ull : ~0ull;
         }
         if (++q >= q1) break;
-        k = next_partition<KMAX>(m, K);
+        k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
     }
 }
 
@@ -1251,7 +1270,8 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
 // registers.
 template <int KMAX, bool ACT, bool SMS, typename TY>
 __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t *np, int n, int M, int K,
-                              uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty, const Memo &mo)
+                              const Adm &adm, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty,
+                              const Memo &mo)
 {
     typedef uint32_t MT;
     int m[KMAX];
@@ -1260,7 +1280,7 @@ __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t 
 #pragma unroll
     for (int i = 0; i < KMAX; i++) { m[i] = 0; S[i] = 0u; U[i] = 0ull; }
     bool active = q0 < q1;
-    int k = active ? unrank<KMAX>(np, M, K, q0, m) : 0;
+    int k = active ? admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m)) : 0;
     uint32_t q = q0;
     int t = 0;
     uint32_t known = 0u, passm = 0u;  // candidates of the current task settled / schedulable
@@ -1369,7 +1389,7 @@ __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t 
                 if (++q >= q1) {
                     active = false;
                 } else {
-                    k = next_partition<KMAX>(m, K);
+                    k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
 #pragma unroll
                     for (int i = 0; i < KMAX; i++) { S[i] = 0u; U[i] = 0ull; }
                     t = 0;
@@ -1423,23 +1443,23 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
     if constexpr (FORM == 0) {
         uint16_t *ms = (uint16_t *)(capart_dyn_lds + Lp.table_words);
         build_frontier<MT>(L, tb, n, M, ms, order, ty);
-        if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, q0, q1, best, dbg, ty);
+        if (q0 < q1) heur_run_front<KMAX, ACT, SMS, MT>(L, tb, ms, np, n, M, Lp.K, Lp.adm, q0, q1, best, dbg, ty);
         return;
     } else {
     if (q0 >= q1) return;
     if constexpr (FORM == 2) {
         uint64_t *lU = (uint64_t *)(capart_dyn_lds + Lp.table_words + Lp.front_words);
         MT *lS = (MT *)(lU + KMAX * blockDim.x);
-        heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, lS, lU, ty);
+        heur_run<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, Lp.adm, q0, q1, best, dbg, lS, lU, ty);
     } else {
         const Memo mo = set_memo<MT>(Lp, n);
         if constexpr (sizeof(MT) == 4 && KMAX <= 4) {  // (K = 8 keeps the nested form: fewer registers)
             if (mo.mask && Lp.memo_packed) {
-                heur_run_memo<KMAX, ACT, SMS>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty, mo);
+                heur_run_memo<KMAX, ACT, SMS>(L, tb, np, n, M, Lp.K, Lp.adm, q0, q1, best, dbg, ty, mo);
                 return;
             }
         }
-        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, q0, q1, best, dbg, ty, mo);
+        heur_run_nested<KMAX, ACT, SMS, MT>(L, tb, np, n, M, Lp.K, Lp.adm, q0, q1, best, dbg, ty, mo);
     }
     }
 }
@@ -1532,7 +1552,7 @@ __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, 
         const uint32_t q0 = p0 + (uint32_t)wv;
         if (q0 < p1) {
             int m[KMAX];
-            int k = unrank<KMAX>(w.np, M, Lp.K, q0, m);
+            int k = admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q0, m));
             for (uint32_t q = q0;;) {
                 if (q >= p_lo && q < p_hi) {
                     uint64_t S[KMAX], U[KMAX];
@@ -1557,6 +1577,7 @@ __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, 
                 q += (uint32_t)nw;
                 if (q >= p1) break;
                 for (int i = 0; i < nw; i++) k = next_partition<KMAX>(m, Lp.K);
+                k = admit<KMAX>(Lp.adm, m, k);
             }
         }
     } else if (dbg) {
@@ -1658,8 +1679,8 @@ __global__ __launch_bounds__(256) void eval_exh_kernel(Batch b, Work w, Out o, L
         Tables tb;
         stage_set(L, w, off, n, M, s, false, tb);
         int m[KMAX];
-        const int k = unrank<KMAX>(w.np, M, Lp.K, q, m);
-        uint64_t A = 1;
+        const int k = admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q, m));
+        uint64_t A = k > 0 ? 1 : 0;  // an inadmissible partitioning has no allocation
         for (int i = 0; i < n; i++) A *= (uint64_t)k;
         for (uint64_t a = threadIdx.x; a < A; a += blockDim.x) {
             uint64_t S[KMAX];
@@ -2204,7 +2225,8 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
     while (Lpre < n && npre * (uint32_t)k <= blockDim.x) { npre *= (uint32_t)k; Lpre++; }
     const uint64_t msz = (uint64_t)(uint32_t)m[0] | ((uint64_t)(uint32_t)m[1] << 8) | ((uint64_t)(uint32_t)m[2] << 16) |
                          ((uint64_t)(uint32_t)m[3] << 24);
-    if (!(f & SETF_LEMMA1) && threadIdx.x < npre && q >= p_lo && q < p_hi) {
+    const bool admitted = admit<4>(Lp.adm, m, k) > 0;
+    if (!(f & SETF_LEMMA1) && admitted && threadIdx.x < npre && q >= p_lo && q < p_hi) {
         const uint64_t *t = tab + (((size_t)s_local * Mtab) << ntab);
         // prefix digits: task Lpre-1 least significant
         uint64_t Apack = 0, aidx = 0;

@@ -125,13 +125,17 @@ def set_partitions(items):
         yield [[first]] + p
 
 
-def best_exhaustive(task, K: int):
-    """Brute-force optimum: returns (found, maxU, sumU, pidx, aidx, sizes, alloc)."""
+def best_exhaustive(task, K: int, admissible=None):
+    """Brute-force optimum: returns (found, maxU, sumU, pidx, aidx, sizes, alloc).
+    admissible: allowed part sizes (None: every size); other partitionings keep
+    their index but are skipped."""
     n = len(task["T"])
     M = int(task["M"])
     parts = integer_partitions_desc(M, K)
     best = None
     for pidx, sizes in enumerate(parts):
+        if admissible is not None and any(x not in admissible for x in sizes):
+            continue
         k = len(sizes)
         for blocks in set_partitions(list(range(n))):
             if len(blocks) > k:
