@@ -72,7 +72,7 @@ def traffic_bytes(name):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1):
+def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None):
     import numpy as np
 
     import oracle
@@ -81,7 +81,7 @@ def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1):
     sub = workload.subset(ts, idx)
     P = int(sum(oracle.count_partitionings(int(m), K) for m in sub["M"]))
     t0 = time.perf_counter()
-    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True)
+    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True, admissible=admissible)
     dt = time.perf_counter() - t0
     c = r["counters"].sum(axis=0)
     return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "combines": int(c[2]),
@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--tables", action="store_true",
                     help="give the sets explicit per-task time tables (saturating memory-intensive profiles) "
                          "instead of the parametric model; runs the plain path")
+    ap.add_argument("--admissible", default="",
+                    help="comma-separated admissible partition sizes (MIG-like restriction; default: every size)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form without HIP graph capture (same kernels and arguments; for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -305,6 +307,9 @@ def main():
         max_tasks, max_M, desc = 12, 48, "n=12, M=48, exhaustive allocation"
         mode = "EXH"
         cpu_sample, cpu_stride = 0, 1
+    adm = tuple(int(x) for x in args.admissible.split(",")) if args.admissible else None
+    if adm:
+        desc += f", admissible sizes {args.admissible}"
     if args.tables:
         ts = workload.with_time_tables(ts)
         for key in ("C_seq", "C_par", "k_permille"):
@@ -318,12 +323,13 @@ def main():
     out = capart.device_results(ts.n_sets, ts.n_tasks, K)
 
     def plain_step():
-        capart.capart_solve_async(eng.ctx, dev, K, mode, out, max_tasks=max_tasks, max_M=max_M)
+        capart.capart_solve_async(eng.ctx, dev, K, mode, out, max_tasks=max_tasks, max_M=max_M, admissible=adm)
 
     plan = None
     if args.form == "batched" and mode != "EXH":
         t0 = time.perf_counter()
-        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=not args.no_graph)
+        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=not args.no_graph,
+                           admissible=adm)
         plan_info = plan.info()
         log(f"[bench] plan: {plan_info} ({(time.perf_counter() - t0):.1f} s)")
         step = plan.run
@@ -360,7 +366,7 @@ def main():
         # the algorithm's own work, counted exactly by the counting variant of
         # the evaluation kernel (outside the timed region)
         wout = capart.device_results(ts.n_sets, ts.n_tasks, K)
-        work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M)
+        work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M, admissible=adm)
         del wout
         log(f"[bench] counted work per step: {work}")
 
@@ -399,7 +405,7 @@ def main():
 
         def per_set():
             capart.capart_solve_async(eng.ctx, sdev, K, mode, sout, max_tasks=max_tasks, max_M=max_M,
-                                      flags=capart.CAPART_FLAG_PER_SET_LAUNCH)
+                                      flags=capart.CAPART_FLAG_PER_SET_LAUNCH, admissible=adm)
 
         per_set()
         ps_ms = timed(per_set, 1, sync)
@@ -419,10 +425,10 @@ def main():
     if mode == "EXH":
         cb = None
     elif args.no_cpu:
-        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride)
+        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm)
     else:
         log(f"[bench] CPU oracle on {cpu_sample} sets with {threads} threads")
-        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride)
+        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride, adm)
         cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"{cb['sets']} of the {ts.n_sets} sets (every {cpu_stride}th from the first), "
                          f"{cb['evals']} evals, {cb['seconds']:.2f} s wall"}

@@ -463,11 +463,11 @@ def capart_timing_read(ctx):
 
 
 def capart_count_work(ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, stream=None,
-                      flags: int = 0) -> dict:
+                      flags: int = 0, admissible=None) -> dict:
     """Exact algorithmic work of one heuristic solve (counting kernel variant)."""
     import torch
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(K, mode, flags)
+    opt = make_options(K, mode, flags, admissible)
     res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], None, None)
     if stream is None:
         stream = torch.cuda.current_stream()
