@@ -276,6 +276,38 @@ void set_wide_chunk(Launch &L, int max_tasks, uint32_t Pmax, const capart_tuning
     L.chunks = std::max<int>(L.chunks, (int)((Pmax + (uint32_t)L.wchunk - 1) / (uint32_t)L.wchunk));
 }
 
+// Partitionings of M into at most K parts whose sizes are all admissible:
+// g_k[r][x] = partitions of r into at most k parts of admissible sizes <= x,
+// g_k[r][x] = g_k[r][x-1] + [x admissible, x <= r] g_{k-1}[r-x][x].
+int64_t count_admissible(int M, int K, const Adm &a)
+{
+    auto ok = [&](int x) { return ((a.w[x >> 6] >> (x & 63)) & 1ull) != 0ull; };
+    const size_t W = (size_t)M + 1;
+    std::vector<int64_t> prev(W * W, 0), cur(W * W, 0);
+    for (size_t x = 0; x < W; x++) prev[x] = 1;  // k = 0: only r = 0
+    for (int k = 1; k <= K; k++) {
+        for (int r = 0; r <= M; r++) {
+            int64_t acc = r == 0 ? 1 : 0;
+            cur[(size_t)r * W] = acc;
+            for (int x = 1; x <= M; x++) {
+                if (x <= r && ok(x)) acc += prev[(size_t)(r - x) * W + x];
+                cur[(size_t)r * W + x] = acc;
+            }
+        }
+        std::swap(prev, cur);
+    }
+    return prev[(size_t)M * W + M];
+}
+
+// The feasibility frontier costs about 2^n tests per set; with few admissible
+// partitionings, direct tests on those are cheaper, so the frontier is skipped.
+bool frontier_pays(int max_tasks, int max_M, int K, const Adm &a)
+{
+    if ((a.w[0] | a.w[1] | a.w[2] | a.w[3]) == 0ull) return true;
+    const int n = std::min(max_tasks, FRONTIER_MAX_TASKS);
+    return count_admissible(max_M, K, a) * (int64_t)max_tasks * K >= ((int64_t)1 << n);
+}
+
 struct Plan {
     Launch L;
     int64_t S, N;
@@ -299,7 +331,9 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
     L.form = tu.loop_form == 2 ? 2 : 1;
     L.memo_packed = tu.loop_form == 3;
     // exhaustive: subset tables + pruned search when sets are small enough
-    size_frontier(L, in->max_tasks, opt->alloc_mode, tu);
+    capart_tuning tf = tu;
+    if (tf.frontier == 0 && !frontier_pays(in->max_tasks, in->max_M, opt->K, L.adm)) tf.frontier = 2;
+    size_frontier(L, in->max_tasks, opt->alloc_mode, tf);
     L.exh_form = (opt->K <= 4 && in->max_tasks <= SUBSET_MAX_TASKS) ? 2 : 1;
     if (tu.exh_form == 1 || tu.exh_form == 2) L.exh_form = tu.exh_form;
     if (L.exh_form == 2 && (opt->K > 4 || in->max_tasks > SUBSET_MAX_TASKS)) L.exh_form = 1;
@@ -1347,7 +1381,9 @@ Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int thr
     L.chunks = 1;
     L.chunk = 0;
     L.exh_form = 1;
-    size_frontier(L, in->max_tasks, opt->alloc_mode, tune);
+    capart_tuning tf = tune;
+    if (tf.frontier == 0 && !frontier_pays(in->max_tasks, in->max_M, opt->K, L.adm)) tf.frontier = 2;
+    size_frontier(L, in->max_tasks, opt->alloc_mode, tf);
     return L;
 }
 
