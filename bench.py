@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--tables", action="store_true",
                     help="give the sets explicit per-task time tables (saturating memory-intensive profiles) "
                          "instead of the parametric model; runs the plain path")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "direct", "persistent"],
+                    help="batched form: the autotuner's choice, or a fixed schedule (persistent: 8 blocks per CU, "
+                         "4096-evaluation items, loop form 1; for reproducible counter runs)")
     ap.add_argument("--admissible", default="",
                     help="comma-separated admissible partition sizes (MIG-like restriction; default: every size)")
     ap.add_argument("--no-graph", action="store_true",
@@ -328,13 +331,21 @@ def main():
     plan = None
     if args.form == "batched" and mode != "EXH":
         t0 = time.perf_counter()
-        plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=True, use_graph=not args.no_graph,
-                           admissible=adm)
+        if args.schedule == "persistent":
+            capart.capart_set_tuning(eng.ctx, loop_form=1)
+            plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=False, blocks_per_cu=8,
+                               item_evals=4096, use_graph=not args.no_graph, admissible=adm)
+            capart.capart_set_tuning(eng.ctx)
+        else:
+            plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=args.schedule == "auto",
+                               blocks_per_cu=-1 if args.schedule == "direct" else 0, use_graph=not args.no_graph,
+                               admissible=adm)
         plan_info = plan.info()
         log(f"[bench] plan: {plan_info} ({(time.perf_counter() - t0):.1f} s)")
         step = plan.run
         sched = "persistent work queue" if plan_info["blocks"] > 0 else "direct schedule"
-        form = f"batched ({sched}, autotuned" + (")" if args.no_graph else ", HIP graph)")
+        tuned = ", autotuned" if args.schedule == "auto" else ", fixed"
+        form = f"batched ({sched}{tuned}" + (")" if args.no_graph else ", HIP graph)")
     else:
         plan_info = None
         step = plain_step
