@@ -23,6 +23,9 @@ LIB = os.path.join(HERE, "liboracle_capart.so")
 EXH, BF_INA, BF_ACT, SMS_INA, SMS_ACT = 0, 1, 2, 3, 4
 MODES = {"EXH": EXH, "BF_INA": BF_INA, "BF_ACT": BF_ACT, "SMS_INA": SMS_INA, "SMS_ACT": SMS_ACT}
 FLAG_NO_LEMMA1 = 1
+FLAG_EDF = 2
+POLICIES = {"FP_DM": 0, "EDF": FLAG_EDF}
+EDF_BP_STEPS, EDF_ND_CAP = 4096, 65536
 OK, E_INVAL, E_RANGE = 0, -1, -2
 M_INF = 1000000
 
@@ -120,10 +123,13 @@ def admissible_mask(sizes) -> np.ndarray:
 
 
 def solve(ts: dict, K: int, mode="BF_INA", flags: int = 0, nthreads: int = 1, counters: bool = False,
-          admissible=None) -> dict:
+          admissible=None, policy: str = "FP_DM") -> dict:
     """Solve every set of a SoA batch; returns a dict of numpy result arrays.
-    admissible: allowed partition sizes (an iterable of sizes), None = every size."""
+    admissible: allowed partition sizes (an iterable of sizes), None = every size.
+    policy: per-partition scheduling, "FP_DM" (fixed priority, deadline
+    monotonic, exact response times) or "EDF" (processor-demand test)."""
     lib = _load()
+    flags = int(flags) | POLICIES[policy]
     mode = MODES[mode] if isinstance(mode, str) else int(mode)
     off = np.ascontiguousarray(ts["set_offset"], np.int64)
     M = np.ascontiguousarray(ts["M"], np.int32)
@@ -199,7 +205,7 @@ def best_on_partitioning(task: dict, sizes, mode="EXH"):
     return bool(f), al, int(mx.value), int(sm.value), int(ai.value)
 
 
-def alg1(task: dict, mode="BF_INA", flags: int = 0) -> dict:
+def alg1(task: dict, mode="BF_INA", flags: int = 0, policy: str = "FP_DM") -> dict:
     """The paper's Algorithm 1 with free partition sizes on one set.
 
     mode: BF_* = order ">" (Definition 5), SMS_* = order ">>" (Definition 4);
@@ -207,6 +213,7 @@ def alg1(task: dict, mode="BF_INA", flags: int = 0) -> dict:
     partitions in par_list order (sizes), task -> partition (alloc), response
     times R, and the numbers of merges tried and accepted."""
     lib = _load()
+    flags = int(flags) | POLICIES[policy]
     mode = MODES[mode] if isinstance(mode, str) else int(mode)
     if mode == MODES["EXH"]:
         raise ValueError("Algorithm 1 takes a heuristic order (BF_* or SMS_*)")

@@ -56,6 +56,13 @@ typedef unsigned __int128 u128;
 enum { OR_EXH = 0, OR_BF_INA = 1, OR_BF_ACT = 2, OR_SMS_INA = 3, OR_SMS_ACT = 4 };
 enum { OR_OK = 0, OR_E_INVAL = -1, OR_E_RANGE = -2 };
 #define OR_FLAG_NO_LEMMA1 1
+#define OR_FLAG_EDF 2     /* per-partition policy: EDF instead of fixed-priority DM */
+/* EDF test limits (part of the test's definition, identical in the engine):
+ * busy-period iterations before the utilisation bound is used instead, and
+ * absolute deadlines below the horizon beyond which a partition is declared
+ * unschedulable */
+#define OR_EDF_BP_STEPS 4096
+#define OR_EDF_ND_CAP 65536
 #define OR_MAXN 64
 #define OR_MINF 1000000 /* "no such m" for Lemma 2 */
 
@@ -75,6 +82,7 @@ typedef struct {
     const int64_t *Cn_tab, *Cc_tab;
     /* admissible partition sizes: bit m of the 256-bit mask (NULL: every size) */
     const uint64_t *adm;
+    int edf;         /* 1: every partition is scheduled by EDF, 0: fixed-priority DM */
     or_counters *cnt;
 } or_set;
 
@@ -100,6 +108,99 @@ int64_t or_time(const int64_t *Cs, const int64_t *Cp, const int32_t *k, int i, i
     return conflict ? or_cc(&s, i, m) : or_cn(&s, i, m);
 }
 
+/* ---- 3'. one partition under preemptive EDF ---------------------------- */
+/* Processor-demand criterion for constrained-deadline sporadic tasks on one
+ * server (Baruah, Rosier and Howell 1990): with total utilisation U <= 1, the
+ * partition is schedulable iff at every absolute deadline d below the
+ * synchronous busy period L the demand
+ *     h(d) = sum_{j : D_j <= d} (floor((d - D_j) / T_j) + 1) * C_j
+ * is at most d.  Checking deadlines beyond L changes nothing, so any horizon
+ * H >= L gives the same answer.  Integer definition used here:
+ *   1. floor-Q32 sum of C_j 2^32 / T_j above 2^32: U > 1, unschedulable;
+ *   2. L = least fixed point of w = sum ceil(w / T_j) C_j, iterated from
+ *      sum C_j; if it has not settled after OR_EDF_BP_STEPS iterations, H is
+ *      the bound L <= sum C / (1 - U) taken with the ceil-Q32 utilisation
+ *      Uq (H = ceil(sum C 2^32 / (2^32 - Uq)), needs Uq < 2^32), else
+ *      (utilisation within n 2^-32 of 1 and no settled busy period) the
+ *      partition is declared unschedulable;
+ *   3. more than OR_EDF_ND_CAP absolute deadlines below H: unschedulable;
+ *   4. otherwise schedulable iff h(d) <= d at every absolute deadline d < H.
+ * Every job then completes within its deadline and within the busy period,
+ * so the response time reported for each member is min(D_i, H); -1 for every
+ * member of an unschedulable partition.  *U = the ceil-Q32 sum. */
+static int or_cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int or_edf_part(const or_set *s, const int *mem, int cnt, const int64_t *C, int64_t *R_out,
+                       uint64_t *U)
+{
+    const u128 one = (u128)1 << 32;
+    u128 uf = 0, uc = 0;
+    i128 sumC = 0, w, H = 0;
+    int64_t nd = 0, *dl = NULL;
+    int a, j, step, settled = 0, feasible = 0;
+    for (a = 0; a < cnt; a++) {
+        u128 num = ((u128)C[a]) << 32, den = (u128)s->T[mem[a]];
+        uf += num / den;
+        uc += (num + den - 1) / den;
+        sumC += C[a];
+    }
+    if (uf > one) goto done;
+    /* the synchronous busy period */
+    w = sumC;
+    for (step = 0; step < OR_EDF_BP_STEPS; step++) {
+        i128 W = 0;
+        for (a = 0; a < cnt; a++) {
+            W += ((w + s->T[mem[a]] - 1) / s->T[mem[a]]) * C[a];
+            if (s->cnt) s->cnt->terms++;
+        }
+        if (W == w) { settled = 1; break; }
+        w = W;
+    }
+    if (settled) {
+        H = w;
+    } else if (uc < one) {
+        u128 den = one - uc;
+        H = (i128)((((u128)sumC << 32) + den - 1) / den);
+    } else {
+        goto done;
+    }
+    /* the absolute deadlines below H */
+    for (a = 0; a < cnt; a++) {
+        i128 D = s->D[mem[a]];
+        if (D < H) nd += (int64_t)((H - 1 - D) / s->T[mem[a]] + 1);
+        if (nd > OR_EDF_ND_CAP) goto done;
+    }
+    dl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd > 0 ? nd : 1));
+    nd = 0;
+    for (a = 0; a < cnt; a++)
+        for (w = s->D[mem[a]]; w < H; w += s->T[mem[a]]) dl[nd++] = (int64_t)w;
+    qsort(dl, (size_t)nd, sizeof(int64_t), or_cmp_i64);
+    /* the demand at each of them, in increasing order */
+    feasible = 1;
+    for (j = 0; j < nd && feasible; j++) {
+        i128 d = dl[j], h = 0;
+        for (a = 0; a < cnt; a++) {
+            int64_t D = s->D[mem[a]];
+            if (D <= d) h += ((d - D) / s->T[mem[a]] + 1) * C[a];
+            if (s->cnt) s->cnt->terms++;
+        }
+        if (h > d) feasible = 0;
+    }
+    free(dl);
+done:
+    if (R_out)
+        for (a = 0; a < cnt; a++) {
+            int64_t D = s->D[mem[a]];
+            R_out[mem[a]] = feasible ? (H < D ? (int64_t)H : D) : -1;
+        }
+    if (feasible && U) *U = (uint64_t)uc;
+    return feasible;
+}
+
 /* ---- 2+3. one partition: conflicts, DM order, exact RTA --------------- */
 /* mem[0..cnt) are task indices.  R_out (indexed by task) gets the response
  * time or -1; with early_exit the test stops at the first miss (the rest of
@@ -121,6 +222,7 @@ static int or_eval_part(const or_set *s, const int *mem, int cnt, int m, int ear
         C[a] = (same >= 2) ? or_cc(s, mem[a], m) : or_cn(s, mem[a], m);
         order[a] = a;
     }
+    if (s->edf) return or_edf_part(s, mem, cnt, C, R_out, U);
     /* deadline-monotonic priority: (D, T, index) ascending; insertion sort */
     for (a = 1; a < cnt; a++) {
         int x = order[a];
@@ -503,6 +605,7 @@ static void or_make_set(or_set *s, int64_t off0, int64_t off1, int32_t M, const 
     s->type = type + off0;
     s->Cn_tab = s->Cc_tab = NULL;
     s->adm = NULL;
+    s->edf = 0;
     s->cnt = cnt;
 }
 
@@ -534,6 +637,7 @@ static void or_batch_set(or_batch *b, int64_t si)
         s.Cc_tab = b->Cc_tab + b->tab_off[si];
     }
     s.adm = b->adm;
+    s.edf = (b->flags & OR_FLAG_EDF) != 0;
     if (n < 0) n = 0;
     or_solve_one(&s, b->K, b->mode, b->flags, &r, b->sizes + si * b->K, al, R, R1);
     b->status[si] = r.status; b->verdict[si] = r.verdict; b->verdict_1g[si] = r.verdict_1g;
@@ -611,7 +715,7 @@ int or_solve_batch(int64_t n_sets, const int64_t *off, const int32_t *M,
                     const int64_t *Cp, const int32_t *k, const uint8_t *type
 #define OR_SET_INIT(s) do { (s).n = n; (s).M = M; (s).T = T; (s).D = D; (s).Cs = Cs; (s).Cp = Cp; \
                             (s).k = k; (s).type = type; (s).Cn_tab = NULL; (s).Cc_tab = NULL; \
-                            (s).adm = NULL; (s).cnt = NULL; } while (0)
+                            (s).adm = NULL; (s).edf = 0; (s).cnt = NULL; } while (0)
 
 /* evaluate one triple; returns feasible; R_out[n] (-1 for misses or, with
  * early_exit, for tasks never reached) */
@@ -946,6 +1050,7 @@ int or_alg1_ex(OR_SET_ARGS, const int64_t *Cn_tab, const int64_t *Cc_tab, int va
     OR_SET_INIT(s);
     s.Cn_tab = Cn_tab;
     s.Cc_tab = Cn_tab ? Cc_tab : NULL;
+    s.edf = (flags & OR_FLAG_EDF) != 0;
     if (n < 1 || n > OR_MAXN || M < 1) return -1;
     ok = or_alg1(&s, variant, flags, &np, sizes, alloc, R, stats);
     *nparts = np;
