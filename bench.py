@@ -72,7 +72,7 @@ def traffic_bytes(name):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None):
+def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None, policy="FP_DM"):
     import numpy as np
 
     import oracle
@@ -81,7 +81,7 @@ def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None):
     sub = workload.subset(ts, idx)
     P = int(sum(oracle.count_partitionings(int(m), K) for m in sub["M"]))
     t0 = time.perf_counter()
-    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True, admissible=admissible)
+    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True, admissible=admissible, policy=policy)
     dt = time.perf_counter() - t0
     c = r["counters"].sum(axis=0)
     return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "combines": int(c[2]),
@@ -134,14 +134,14 @@ def serving_leg(eng, capart, workload, rate, n_queries, seed=5):
             "evals_per_s": st["evals_per_s"], "mean_batch": st["mean_batch"], "rejected": st["rejected"]}
 
 
-def alg1_cpu_baseline(ts, mode, threads):
+def alg1_cpu_baseline(ts, mode, threads, policy="FP_DM"):
     """The oracle's Algorithm 1 over every set of the workload, on `threads` host threads."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
-        v = list(ex.map(lambda s: oracle.alg1(ts.set(s), mode)["verdict"], range(ts.n_sets)))
+        v = list(ex.map(lambda s: oracle.alg1(ts.set(s), mode, policy=policy)["verdict"], range(ts.n_sets)))
     return {"seconds": time.perf_counter() - t0, "sets": ts.n_sets, "schedulable": int(sum(v))}
 
 
@@ -151,17 +151,18 @@ def alg1_main(args, eng, capart, workload, sync, threads):
     (default 1000); one step = the whole batch through capart_alg1_async."""
     import numpy as np
     mode = args.mode
+    pol = args.policy
     per_point = args.n_sets or 1000
     ts = workload.config_paper_fig4(sets_per_point=per_point)
     S, N = ts.n_sets, ts.n_tasks
     desc = (f"paper Fig. 4: {S} task sets ({per_point} per point, U = 2..68 step 2), n=50, M=68, "
-            f"D=0.75T, T log-uniform 50..4000 us, Algorithm 1 {mode}")
+            f"D=0.75T, T log-uniform 50..4000 us, Algorithm 1 {mode}" + (f", {pol} per partition" if pol != "FP_DM" else ""))
     log(f"[bench] workload fig4: {desc}")
     dev = capart.device_tasksets(ts)
     out = capart.device_alg1_results(S, N)
 
     def step():
-        capart.capart_alg1_async(eng.ctx, dev, mode, out, max_tasks=50, max_M=68)
+        capart.capart_alg1_async(eng.ctx, dev, mode, out, max_tasks=50, max_M=68, policy=pol)
 
     for i in range(args.warmup):
         step()
@@ -184,7 +185,7 @@ def alg1_main(args, eng, capart, workload, sync, threads):
     tried = out["tried"][:S].cpu().numpy()
     rate = verdict.reshape(-1, per_point).mean(axis=1)
     wout = capart.device_alg1_results(S, N)
-    work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, 50, 68)
+    work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, 50, 68, policy=pol)
     del wout
     log(f"[bench] Algorithm 1 kernel {k_ms:.3f} ms/launch, counted work {work}")
     ops = work["terms"] * C_TERM + work["tests"] * C_TEST
@@ -192,7 +193,7 @@ def alg1_main(args, eng, capart, workload, sync, threads):
     kname = "alg1_kernel"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved / PEAK_INT_LANE_OPS,
-            "traffic": traffic_bytes(f"{kname}_fig4_{mode.lower()}_traffic.json"),
+            "traffic": traffic_bytes(f"{kname}_fig4_{mode.lower()}{'_edf' if pol == 'EDF' else ''}_traffic.json"),
             "kernel": kname, "kernel_ms": k_ms, "ops_per_launch": ops, "work_per_launch": work,
             "ops_per_term": C_TERM, "ops_per_test": C_TEST,
             "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"])},
@@ -200,7 +201,7 @@ def alg1_main(args, eng, capart, workload, sync, threads):
     cpu = None
     if not args.no_cpu:
         log(f"[bench] CPU oracle (Algorithm 1) on all {S} sets with {threads} threads")
-        cb = alg1_cpu_baseline(ts, mode, threads)
+        cb = alg1_cpu_baseline(ts, mode, threads, pol)
         if cb["schedulable"] != int(verdict.sum()):
             raise SystemExit("bench: the oracle's schedulable count differs from the GPU's")
         cpu = {"value": cb["sets"] / cb["seconds"], "unit": "sets/s", "cores": threads, "kind": "oracle",
@@ -209,7 +210,7 @@ def alg1_main(args, eng, capart, workload, sync, threads):
     res = {"metric": "Algorithm 1 task sets/sec (free partition sizes)", "value": value, "unit": "sets/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": desc, "n_sets": S, "alloc_mode": mode, "sets_per_point": per_point},
+           "config": {"workload": desc, "n_sets": S, "alloc_mode": mode, "policy": pol, "sets_per_point": per_point},
            "schedulability_by_U": {str(2 * (i + 1)): float(r) for i, r in enumerate(rate)},
            "mean_partitions_when_schedulable": float(nparts[verdict == 1].mean()) if verdict.any() else None,
            "mean_merges_tried": float(tried.mean()),
@@ -240,6 +241,8 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "direct", "persistent"],
                     help="batched form: the autotuner's choice, or a fixed schedule (persistent: 8 blocks per CU, "
                          "4096-evaluation items, loop form 1; for reproducible counter runs)")
+    ap.add_argument("--policy", default="FP_DM", choices=["FP_DM", "EDF"],
+                    help="per-partition scheduling: fixed-priority DM (default) or EDF")
     ap.add_argument("--admissible", default="",
                     help="comma-separated admissible partition sizes (MIG-like restriction; default: every size)")
     ap.add_argument("--no-graph", action="store_true",
@@ -313,6 +316,9 @@ def main():
     adm = tuple(int(x) for x in args.admissible.split(",")) if args.admissible else None
     if adm:
         desc += f", admissible sizes {args.admissible}"
+    pol = args.policy
+    if pol != "FP_DM":
+        desc += f", {pol} per partition"
     if args.tables:
         ts = workload.with_time_tables(ts)
         for key in ("C_seq", "C_par", "k_permille"):
@@ -326,7 +332,8 @@ def main():
     out = capart.device_results(ts.n_sets, ts.n_tasks, K)
 
     def plain_step():
-        capart.capart_solve_async(eng.ctx, dev, K, mode, out, max_tasks=max_tasks, max_M=max_M, admissible=adm)
+        capart.capart_solve_async(eng.ctx, dev, K, mode, out, max_tasks=max_tasks, max_M=max_M, admissible=adm,
+                                  policy=pol)
 
     plan = None
     if args.form == "batched" and mode != "EXH":
@@ -334,12 +341,12 @@ def main():
         if args.schedule == "persistent":
             capart.capart_set_tuning(eng.ctx, loop_form=1)
             plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=False, blocks_per_cu=8,
-                               item_evals=4096, use_graph=not args.no_graph, admissible=adm)
+                               item_evals=4096, use_graph=not args.no_graph, admissible=adm, policy=pol)
             capart.capart_set_tuning(eng.ctx)
         else:
             plan = capart.Plan(eng.ctx, dev, K, mode, out, max_tasks, max_M, autotune=args.schedule == "auto",
                                blocks_per_cu=-1 if args.schedule == "direct" else 0, use_graph=not args.no_graph,
-                               admissible=adm)
+                               admissible=adm, policy=pol)
         plan_info = plan.info()
         log(f"[bench] plan: {plan_info} ({(time.perf_counter() - t0):.1f} s)")
         step = plan.run
@@ -377,7 +384,7 @@ def main():
         # the algorithm's own work, counted exactly by the counting variant of
         # the evaluation kernel (outside the timed region)
         wout = capart.device_results(ts.n_sets, ts.n_tasks, K)
-        work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M, admissible=adm)
+        work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M, admissible=adm, policy=pol)
         del wout
         log(f"[bench] counted work per step: {work}")
 
@@ -416,7 +423,7 @@ def main():
 
         def per_set():
             capart.capart_solve_async(eng.ctx, sdev, K, mode, sout, max_tasks=max_tasks, max_M=max_M,
-                                      flags=capart.CAPART_FLAG_PER_SET_LAUNCH, admissible=adm)
+                                      flags=capart.CAPART_FLAG_PER_SET_LAUNCH, admissible=adm, policy=pol)
 
         per_set()
         ps_ms = timed(per_set, 1, sync)
@@ -426,7 +433,7 @@ def main():
         log(f"[bench] one launch per set: {compare['per_set_launch']['value']:.4g} evals/s")
 
     serving = None
-    if args.workload == "c2" and not args.no_serving and not args.tables:
+    if args.workload == "c2" and not args.no_serving and not args.tables and pol == "FP_DM":
         # 2,000 queries/s: inside the capacity of this mix with its 49..64-task
         # queries (each costs tens of ms alone), so the latencies are not queue growth
         serving = serving_leg(eng, capart, workload, 2e3, 10000)
@@ -436,10 +443,10 @@ def main():
     if mode == "EXH":
         cb = None
     elif args.no_cpu:
-        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm)
+        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm, pol)
     else:
         log(f"[bench] CPU oracle on {cpu_sample} sets with {threads} threads")
-        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride, adm)
+        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride, adm, pol)
         cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"{cb['sets']} of the {ts.n_sets} sets (every {cpu_stride}th from the first), "
                          f"{cb['evals']} evals, {cb['seconds']:.2f} s wall"}
@@ -452,7 +459,8 @@ def main():
         achieved = ops / (eval_ms / 1000.0)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
                 "frac": achieved / PEAK_INT_LANE_OPS,
-                "traffic": traffic_bytes(f"{kname}_{args.workload}_{mode.lower()}_traffic.json"),
+                "traffic": traffic_bytes(f"{kname}_{args.workload}_{mode.lower()}"
+                                         f"{'_edf' if pol == 'EDF' else ''}_traffic.json"),
                 "kernel": kname, "kernel_ms": eval_ms, "ops_per_launch": ops, "work_per_launch": work,
                 "ops_per_term": C_TERM, "ops_per_test": C_TEST, "ops_per_lookup": C_LOOK,
                 "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
@@ -469,7 +477,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {ts.n_sets} task sets, {desc}, K={K}, {mode}, {form}",
-                      "n_sets": ts.n_sets, "K": K, "alloc_mode": mode, "evals_per_step": evals_per_step,
+                      "n_sets": ts.n_sets, "K": K, "alloc_mode": mode, "policy": pol, "evals_per_step": evals_per_step,
                       "schedulable_sets": verdicts, "lemma1_pruned_sets": lemma1_pruned(ts), "plan": plan_info},
            "end_to_end_with_copies": end_to_end, "compare": compare, "serving": serving, "roofline": roof, "cpu_baseline": cpu}
     if plan is not None:

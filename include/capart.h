@@ -85,8 +85,32 @@ typedef int32_t capart_status;
 #define CAPART_HEUR_SMS_INA  3
 #define CAPART_HEUR_SMS_ACT  4
 
-/* per-partition scheduling policy */
+/* per-partition scheduling policy (Section "Schedulability test": any
+ * policy with an exact test; each partition is one server running its tasks
+ * one at a time on all its units) */
 #define CAPART_POLICY_FP_DM  0 /* preemptive fixed priority, deadline monotonic, exact RTA */
+#define CAPART_POLICY_EDF    1 /* preemptive EDF, processor-demand test (below)          */
+/*
+ * CAPART_POLICY_EDF: a partition is schedulable iff (1) its floor-Q32
+ * utilisation sum floor(C_i 2^32 / T_i) is at most 2^32, and (2) the demand
+ * h(d) = sum_{D_j <= d} (floor((d - D_j)/T_j) + 1) C_j is at most d at every
+ * absolute deadline d below the horizon H (processor-demand criterion for
+ * constrained deadlines, Baruah, Rosier and Howell 1990).  H is the
+ * synchronous busy period (least fixed point of w = sum ceil(w/T_j) C_j from
+ * sum C_j) when that iteration settles within 4096 steps, else the bound
+ * ceil(sum C 2^32 / (2^32 - Uq)) with the ceil-Q32 utilisation Uq; a
+ * partition whose utilisation is within n 2^-32 of 1 without a settled busy
+ * period, or with more than 65536 absolute deadlines below H, is declared
+ * unschedulable (a pessimistic limit that bounds the work of one test).
+ * Reported response times: min(D_i, H) for every task of a schedulable
+ * partition (each job completes by its deadline and within the busy period),
+ * -1 for every task of an unschedulable one (1G included).  Lemma 2 sizes,
+ * the Lemma 1 filter, utilisations and keys are policy-independent; ACT's
+ * pair test uses the policy.  Honoured by capart_solve, capart_solve_async,
+ * capart_count_work, capart_allocate, the batched plans and Algorithm 1;
+ * capart_test_triple and the server schedule by CAPART_POLICY_FP_DM (their
+ * arguments carry no policy).
+ */
 
 /* option flags */
 #define CAPART_FLAG_SKIP_1G         1u /* do not evaluate the whole-GPU baseline (R_1g = -1)    */
@@ -156,7 +180,7 @@ typedef struct capart_tasksets {
  */
 typedef struct capart_options {
     int32_t K;           /* maximum number of parts, 1..8      */
-    int32_t policy;      /* CAPART_POLICY_FP_DM                */
+    int32_t policy;      /* CAPART_POLICY_FP_DM or _EDF        */
     int32_t alloc_mode;  /* CAPART_EXHAUSTIVE or CAPART_HEUR_* */
     uint32_t flags;      /* CAPART_FLAG_*                      */
     uint64_t admissible[4];  /* allowed part sizes, all 0 = every size */

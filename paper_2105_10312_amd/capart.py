@@ -21,6 +21,8 @@ CAPART_E_DEVICE, CAPART_E_AGAIN, CAPART_E_STATE = -4, -5, -6
 CAPART_EXHAUSTIVE, CAPART_HEUR_BF_INA, CAPART_HEUR_BF_ACT = 0, 1, 2
 CAPART_HEUR_SMS_INA, CAPART_HEUR_SMS_ACT = 3, 4
 CAPART_POLICY_FP_DM = 0
+CAPART_POLICY_EDF = 1
+POLICIES = {"FP_DM": CAPART_POLICY_FP_DM, "EDF": CAPART_POLICY_EDF}
 CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
@@ -185,8 +187,10 @@ def admissible_mask(sizes) -> list:
     return w
 
 
-def make_options(K: int, mode="BF_INA", flags: int = 0, admissible=None) -> capart_options:
-    return capart_options(int(K), CAPART_POLICY_FP_DM, _mode(mode), int(flags),
+def make_options(K: int, mode="BF_INA", flags: int = 0, admissible=None, policy="FP_DM") -> capart_options:
+    """policy: "FP_DM" (fixed priority, deadline monotonic) or "EDF", or the C constant."""
+    pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    return capart_options(int(K), pol, _mode(mode), int(flags),
                           (C.c_uint64 * 4)(*admissible_mask(admissible)))
 
 
@@ -290,12 +294,12 @@ def capart_test_triple(ctx, task: dict, sizes, alloc):
     return bool(feas[0]), R, int(mx[0]), int(sm[0])
 
 
-def capart_allocate(ctx, task: dict, sizes, K: int, mode="BF_INA"):
+def capart_allocate(ctx, task: dict, sizes, K: int, mode="BF_INA", policy="FP_DM"):
     """Best allocation on one partitioning: (found, alloc[n], maxU, sumU, aidx)."""
     h = _one_set(task)
     st, _keep = make_tasksets(h)
     sz = np.ascontiguousarray(sizes, np.int32)
-    opt = make_options(K, mode)
+    opt = make_options(K, mode, policy=policy)
     n = len(task["T"])
     al = np.zeros(n, np.int8)
     found = np.zeros(1, np.uint8)
@@ -323,12 +327,13 @@ def dbg_offsets(M, K: int) -> np.ndarray:
 
 
 def capart_solve(ctx, ts: dict, K: int, mode="BF_INA", flags: int = 0, debug: bool = False, max_tasks=None,
-                 max_M=None, admissible=None) -> dict:
+                 max_M=None, admissible=None, policy="FP_DM") -> dict:
     """Solve a host batch (synchronous); returns a dict of numpy result arrays.
-    admissible: the allowed partition sizes (None: every size)."""
+    admissible: the allowed partition sizes (None: every size); policy:
+    per-partition scheduling ("FP_DM" or "EDF")."""
     h = _host_ts(ts)
     st, _keep = make_tasksets(h, max_tasks, max_M)
-    opt = make_options(K, mode, flags, admissible)
+    opt = make_options(K, mode, flags, admissible, policy)
     S, N = st.n_sets, st.n_tasks_total
     out = {}
     for name, dt, shape in RESULT_FIELDS:
@@ -370,13 +375,14 @@ def device_tasksets(ts: dict, device="cuda") -> dict:
 
 
 def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=None, flags: int = 0,
-                       max_tasks=None, max_M=None, dbg_key=None, dbg_offset=None, admissible=None) -> None:
+                       max_tasks=None, max_M=None, dbg_key=None, dbg_offset=None, admissible=None,
+                       policy="FP_DM") -> None:
     """Solve a batch resident in GPU memory; results land in dev_out (torch tensors) on `stream`."""
     import torch
     if max_tasks is None or max_M is None:
         raise ValueError("device batches need declared max_tasks and max_M bounds")
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(K, mode, flags, admissible)
+    opt = make_options(K, mode, flags, admissible, policy)
     res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -384,12 +390,12 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
                                              C.c_void_p(stream.cuda_stream)), ctx)
 
 
-def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, max_M=None) -> dict:
+def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, max_M=None, policy="FP_DM") -> dict:
     """Algorithm 1 (free partition sizes) over a host batch (synchronous); numpy results.
     sizes[set_offset[s] : set_offset[s] + nparts[s]] are set s's partitions in par_list order."""
     h = _host_ts(ts)
     st, _keep = make_tasksets(h, max_tasks, max_M)
-    opt = make_options(1, mode, flags)
+    opt = make_options(1, mode, flags, policy=policy)
     S, N = st.n_sets, st.n_tasks_total
     out = {name: np.zeros(max(S if shape == "S" else N, 1), dt) for name, dt, shape in ALG1_FIELDS}
     res = capart_alg1_results(*[_ptr(out[f[0]]) for f in ALG1_FIELDS])
@@ -406,13 +412,13 @@ def device_alg1_results(S: int, N: int, device="cuda") -> dict:
 
 
 def capart_alg1_async(ctx, dev_ts: dict, mode, dev_out: dict, stream=None, flags: int = 0, max_tasks=None,
-                      max_M=None) -> None:
+                      max_M=None, policy="FP_DM") -> None:
     """Algorithm 1 over a batch resident in GPU memory; results land in dev_out on `stream`."""
     import torch
     if max_tasks is None or max_M is None:
         raise ValueError("device batches need declared max_tasks and max_M bounds")
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(1, mode, flags)
+    opt = make_options(1, mode, flags, policy=policy)
     res = capart_alg1_results(*[_ptr(dev_out[f[0]]) for f in ALG1_FIELDS])
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -421,11 +427,11 @@ def capart_alg1_async(ctx, dev_ts: dict, mode, dev_out: dict, stream=None, flags
 
 
 def capart_alg1_count_work(ctx, dev_ts: dict, mode, dev_out: dict, max_tasks: int, max_M: int, stream=None,
-                           flags: int = 0) -> dict:
+                           flags: int = 0, policy="FP_DM") -> dict:
     """Counted work of Algorithm 1 on a device batch: response-time terms and exact tests."""
     import torch
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(1, mode, flags)
+    opt = make_options(1, mode, flags, policy=policy)
     res = capart_alg1_results(*[_ptr(dev_out[f[0]]) for f in ALG1_FIELDS])
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -463,11 +469,11 @@ def capart_timing_read(ctx):
 
 
 def capart_count_work(ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, stream=None,
-                      flags: int = 0, admissible=None) -> dict:
+                      flags: int = 0, admissible=None, policy="FP_DM") -> dict:
     """Exact algorithmic work of one heuristic solve (counting kernel variant)."""
     import torch
     st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
-    opt = make_options(K, mode, flags, admissible)
+    opt = make_options(K, mode, flags, admissible, policy)
     res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], None, None)
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -483,10 +489,10 @@ class Plan:
 
     def __init__(self, ctx, dev_ts: dict, K: int, mode, dev_out: dict, max_tasks: int, max_M: int, flags: int = 0,
                  autotune: bool = True, blocks_per_cu: int = 0, item_evals: int = 0, use_graph: bool = True,
-                 dbg_key=None, dbg_offset=None, admissible=None):
+                 dbg_key=None, dbg_offset=None, admissible=None, policy="FP_DM"):
         self.ctx = ctx
         self._st, self._keep = make_tasksets(dev_ts, max_tasks, max_M)
-        self._opt = make_options(K, mode, flags, admissible)
+        self._opt = make_options(K, mode, flags, admissible, policy)
         self._out = dev_out
         self._res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], _ptr(dbg_key), _ptr(dbg_offset))
         self._dbg = (dbg_key, dbg_offset)
@@ -623,11 +629,11 @@ class Engine:
         except Exception:
             pass
 
-    def solve(self, ts, K, mode="BF_INA", flags=0, debug=False, admissible=None):
-        return capart_solve(self.ctx, ts, K, mode, flags, debug, admissible=admissible)
+    def solve(self, ts, K, mode="BF_INA", flags=0, debug=False, admissible=None, policy="FP_DM"):
+        return capart_solve(self.ctx, ts, K, mode, flags, debug, admissible=admissible, policy=policy)
 
-    def alg1(self, ts, mode="BF_INA", flags=0):
-        return capart_alg1(self.ctx, ts, mode, flags)
+    def alg1(self, ts, mode="BF_INA", flags=0, policy="FP_DM"):
+        return capart_alg1(self.ctx, ts, mode, flags, policy=policy)
 
     def test_triple(self, task, sizes, alloc):
         return capart_test_triple(self.ctx, task, sizes, alloc)

@@ -159,7 +159,8 @@ capart_status check_options(capart_ctx *c, const capart_options *opt)
 {
     if (!opt) return fail(c, CAPART_E_INVAL, "options is NULL");
     if (opt->K < 1 || opt->K > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "K must be in [1, 8]");
-    if (opt->policy != CAPART_POLICY_FP_DM) return fail(c, CAPART_E_INVAL, "unsupported policy");
+    if (opt->policy != CAPART_POLICY_FP_DM && opt->policy != CAPART_POLICY_EDF)
+        return fail(c, CAPART_E_INVAL, "unsupported policy");
     if (!valid_mode(opt->alloc_mode)) return fail(c, CAPART_E_INVAL, "unknown allocation mode");
     if (opt->flags & ~(CAPART_FLAG_SKIP_1G | CAPART_FLAG_NO_LEMMA1 | CAPART_FLAG_PER_SET_LAUNCH))
         return fail(c, CAPART_E_INVAL, "unknown flag");
@@ -325,6 +326,7 @@ Plan make_plan(const capart_tasksets *in, const capart_options *opt, const capar
     L.mode = opt->alloc_mode;
     L.flags = opt->flags;
     for (int i = 0; i < 4; i++) L.adm.w[i] = opt->admissible[i];
+    L.edf = opt->policy == CAPART_POLICY_EDF;
     L.threads = eval_threads(in->max_tasks, in->max_M);
     if (tu.threads > 0) L.threads = std::min(L.threads, tu.threads);
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
@@ -795,7 +797,8 @@ static capart_status alg1_check(capart_ctx *c, const capart_tasksets *in, const 
 {
     if (!opt) return fail(c, CAPART_E_INVAL, "options is NULL");
     if (opt->K < 1 || opt->K > CAPART_MAX_K) return fail(c, CAPART_E_INVAL, "K must be in [1, 8]");
-    if (opt->policy != CAPART_POLICY_FP_DM) return fail(c, CAPART_E_INVAL, "unsupported policy");
+    if (opt->policy != CAPART_POLICY_FP_DM && opt->policy != CAPART_POLICY_EDF)
+        return fail(c, CAPART_E_INVAL, "unsupported policy");
     if (opt->alloc_mode < CAPART_HEUR_BF_INA || opt->alloc_mode > CAPART_HEUR_SMS_ACT)
         return fail(c, CAPART_E_INVAL, "Algorithm 1 needs a heuristic order (CAPART_HEUR_*)");
     if (opt->admissible[0] | opt->admissible[1] | opt->admissible[2] | opt->admissible[3])
@@ -829,6 +832,7 @@ static capart_status alg1_run(capart_ctx *c, const capart_tasksets *in, const ca
     L.K = 1;
     L.mode = opt->alloc_mode;
     L.flags = opt->flags & CAPART_FLAG_NO_LEMMA1;
+    L.edf = opt->policy == CAPART_POLICY_EDF;
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
     const Batch b = make_batch(in);
     give_tables(w, b);
@@ -1374,6 +1378,7 @@ Launch plan_launch(const capart_tasksets *in, const capart_options *opt, int thr
     L.mode = opt->alloc_mode;
     L.flags = opt->flags & ~CAPART_FLAG_PER_SET_LAUNCH;
     for (int i = 0; i < 4; i++) L.adm.w[i] = opt->admissible[i];
+    L.edf = opt->policy == CAPART_POLICY_EDF;
     L.threads = std::min(threads, eval_threads(in->max_tasks, in->max_M));
     L.table_words = (int)(table_lds_bytes(in->max_tasks, in->max_M) / 4);
     L.form = form == 2 ? 2 : 1;

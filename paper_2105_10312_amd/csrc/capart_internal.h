@@ -22,6 +22,7 @@ static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 
 constexpr uint32_t SETF_VALID = 1u;
 constexpr uint32_t SETF_LEMMA1 = 2u;  // Lemma 1 rejects the set
+constexpr uint32_t SETF_EDF = 4u;     // the set's partitions are scheduled by EDF (else fixed-priority DM)
 
 // Partition-count table: NP(r, j, x) = number of partitions of r into at most
 // j parts, each part <= x (parts >= 1); r, x in [0, 255], j in [0, 8].
@@ -107,6 +108,7 @@ struct Launch {
     int n_lo = 0;        // this evaluation launch takes the sets of n_lo <= n (<= n_hi if n_hi > 0) tasks
     int n_hi = 0;
     Adm adm;             // admissible part sizes (a partitioning with another size is infeasible)
+    int edf = 0;         // 1: per-partition EDF (processor demand) instead of fixed-priority DM
     int wchunk = 0;      // heuristic, sets above NARROW_MAX_TASKS tasks: partitionings per block of the
                          // wave-per-partitioning launch (0 = one lane per partitioning, chunk per block);
                          // chunks then covers ceil(P / wchunk) as well

@@ -108,18 +108,28 @@ __device__ __forceinline__ int ctz64(uint64_t x) { return __builtin_ctzll(x); }
 // Work tallies: the evaluation kernel is also built in a counting variant that
 // totals the work its algorithm performs (response-time terms: one per
 // iteration plus one per higher-priority term; exact partition tests; frontier
-// lookups).  NoTally compiles to nothing.
-struct NoTally {
+// lookups).  NoTally compiles to nothing.  A tally also carries the
+// per-partition policy its kernel is compiled for: POL_FP and POL_EDF fix it
+// (the other policy's test is not compiled into the kernel), POL_ANY reads
+// the staged set's flag.
+enum : int { POL_ANY = 0, POL_FP = 1, POL_EDF = 2 };
+template <int P>
+struct NoTallyP {
+    static constexpr int kPol = P;
     __device__ __forceinline__ void term(uint32_t) {}
     __device__ __forceinline__ void test() {}
     __device__ __forceinline__ void look() {}
 };
-struct Tally {
+template <int P>
+struct TallyP {
+    static constexpr int kPol = P;
     uint64_t terms = 0, tests = 0, looks = 0;
     __device__ __forceinline__ void term(uint32_t k) { terms += k; }
     __device__ __forceinline__ void test() { tests++; }
     __device__ __forceinline__ void look() { looks++; }
 };
+using NoTally = NoTallyP<POL_ANY>;
+using Tally = TallyP<POL_ANY>;
 
 // ---------------------------------------------------------------------------
 // Per-set data in LDS (ranks are deadline-monotonic priority positions).
@@ -133,7 +143,17 @@ struct SetLDS {
     uint8_t orig[MAXN];
     uint8_t rank_of[MAXN];
     uint64_t memmask;
+    uint32_t edf;  // 1: partitions are scheduled by EDF, 0: fixed-priority DM
 };
+
+// Whether a test compiled with tally type TY uses EDF on the staged set.
+template <typename TY>
+__device__ __forceinline__ bool use_edf(const SetLDS &L)
+{
+    if constexpr (TY::kPol == POL_FP) return false;
+    else if constexpr (TY::kPol == POL_EDF) return true;
+    else return L.edf != 0u;
+}
 
 // Execution-time and utilisation tables, [m-1][conflict][rank], u32:
 //   tabC: time on m units; tabU: ceil(C*2^32/T) - 1.
@@ -159,7 +179,10 @@ __device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int6
         L.sigma[i] = w.sigma[off + i];
         L.forbid[i] = act ? w.forbid[off + i] : 0ull;
     }
-    if (tid == 0) L.memmask = w.memmask[s];
+    if (tid == 0) {
+        L.memmask = w.memmask[s];
+        L.edf = (w.setflags[s] & SETF_EDF) ? 1u : 0u;
+    }
     __syncthreads();
     for (int r = tid; r < n; r += nt) {
         uint64_t f = 0ull;
@@ -291,6 +314,142 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
     return (uint32_t)R;
 }
 
+// EDF on one partition (Section "Schedulability test" admits any policy with
+// an exact test): the processor-demand criterion (Baruah, Rosier and Howell
+// 1990) for constrained deadlines, walked with Zhang and Burns' quick
+// processor-demand analysis (QPA, 2009).  Integer definition:
+//   1. floor-Q32 utilisation above 2^32: unschedulable (U > 1);
+//   2. horizon H = the synchronous busy period L (least fixed point of
+//      w = sum ceil(w/T_j) C_j, iterated from sum C_j) if the iteration settles
+//      within EDF_BP_STEPS steps, else the bound ceil(sum C 2^32 / (2^32 - Uq))
+//      >= L with the ceil-Q32 utilisation Uq (Uq >= 2^32: unschedulable);
+//   3. more than EDF_ND_CAP absolute deadlines below H: unschedulable;
+//   4. else schedulable iff h(d) <= d at every absolute deadline d < H, with
+//      h(t) = sum_{D_j <= t} (floor((t - D_j)/T_j) + 1) C_j.
+// Step 4 walks t down from the last deadline below H: to h(t) while h(t) < t,
+// else to the previous deadline, until h(t) <= min D (schedulable) or h(t) > t
+// (a miss).  h is a non-decreasing step function that changes only at
+// deadlines, so every skipped deadline d has h(d) <= d, and the walk moves
+// below at least one deadline every two points: at most 2 ND + 1 points.
+// get(j, C, T, D) reads member j.  Returns ok, H (when ok: every job of the
+// partition completes by min(D_i, H)) and the terms evaluated (members x
+// busy-period steps and demand points).  64-bit bounds: C < 2^31 and
+// T, D < 2^31; w < 2^50 over the busy-period steps (U < 1 + 2^-26); H < 2^57.
+// Kept out of line (one call on the EDF side of each test) so that the
+// fixed-priority paths keep their registers.
+constexpr int EDF_BP_STEPS = 4096;
+constexpr uint64_t EDF_ND_CAP = 65536;
+
+struct EdfRes {
+    uint64_t H;
+    uint32_t terms;
+    bool ok;
+};
+
+template <typename MT, typename GET>
+__device__ __noinline__ EdfRes edf_demand(MT S, GET get)
+{
+    constexpr uint64_t ONE = 1ull << 32;
+    const uint32_t cnt = (uint32_t)mpopc(S);
+    EdfRes res{0ull, 0u, false};
+    uint64_t uf = 0, uc = 0, sumC = 0;
+    uint32_t dmin = 0xFFFFFFFFu;
+    for (MT h = S; h; h &= h - MT(1)) {
+        uint32_t C, T, D;
+        get(mctz(h), C, T, D);
+        const uint64_t num = (uint64_t)C << 32;
+        const uint64_t q = num / T;
+        uf += q;
+        if (uf > ONE) return res;
+        uc += q + (num != q * (uint64_t)T ? 1ull : 0ull);
+        sumC += C;
+        dmin = min(dmin, D);
+    }
+    uint64_t w = sumC, H;
+    bool settled = false;
+    for (int step = 0; step < EDF_BP_STEPS; step++) {
+        uint64_t W = 0;
+        for (MT h = S; h; h &= h - MT(1)) {
+            uint32_t C, T, D;
+            get(mctz(h), C, T, D);
+            W += ((w + T - 1ull) / T) * C;
+        }
+        res.terms += cnt;
+        if (W == w) { settled = true; break; }
+        w = W;
+    }
+    if (settled) {
+        H = w;
+    } else {
+        if (uc >= ONE) return res;
+        const uint64_t den = ONE - uc, a = sumC / den, r = sumC % den;
+        // H >= 2^56 puts more than 2^25 deadlines of any member below it
+        if (a >= (1ull << 24)) return res;
+        H = (a << 32) + (((r << 32) + den - 1ull) / den);
+    }
+    uint64_t nd = 0;
+    for (MT h = S; h; h &= h - MT(1)) {
+        uint32_t C, T, D;
+        get(mctz(h), C, T, D);
+        if (D < H) nd += (H - 1ull - D) / T + 1ull;
+    }
+    if (nd > EDF_ND_CAP) return res;
+    res.H = H;
+    if (H <= dmin) {
+        res.ok = true;
+        return res;
+    }
+    auto demand = [&](uint64_t t) {
+        uint64_t d = 0;
+        for (MT h = S; h; h &= h - MT(1)) {
+            uint32_t C, T, D;
+            get(mctz(h), C, T, D);
+            if (D <= t) d += ((t - D) / T + 1ull) * C;
+        }
+        return d;
+    };
+    auto last_before = [&](uint64_t t) {  // largest absolute deadline < t (t > min D)
+        uint64_t d = 0;
+        for (MT h = S; h; h &= h - MT(1)) {
+            uint32_t C, T, D;
+            get(mctz(h), C, T, D);
+            if (D < t) d = max(d, (uint64_t)D + ((t - 1ull - D) / T) * T);
+        }
+        return d;
+    };
+    uint64_t t = last_before(H);
+    for (uint64_t it = 0; it < 2 * EDF_ND_CAP + 4; it++) {
+        const uint64_t hd = demand(t);
+        res.terms += cnt;
+        if (hd > t) return res;
+        if (hd <= dmin) {
+            res.ok = true;
+            return res;
+        }
+        t = hd < t ? hd : last_before(t);
+    }
+    return res;  // not reached (at most 2 ND + 1 points)
+}
+
+// EDF test of rank set S on m units (conflict mask cm) from the staged tables.
+template <typename MT, typename TY>
+__device__ __forceinline__ bool edf_part(const SetLDS &L, const Tables &tb, MT S, int m, MT cm, TY &ty,
+                                         uint64_t *Hout)
+{
+    const int n = tb.n;
+    const uint32_t *row = tb.C + (m - 1) * 2 * n;
+    const SetLDS *Ls = &L;
+    auto get = [=](int j, uint32_t &C, uint32_t &T, uint32_t &D) {
+        C = row[(int)mbit(cm, j) * n + j];
+        T = Ls->T[j];
+        D = Ls->D[j];
+    };
+    const EdfRes r = edf_demand<MT>(S, get);
+    ty.term(r.terms);
+    if (Hout) *Hout = r.H;
+    return r.ok;
+}
+
 // Test the members of S with rank >= first on one partition of m units,
 // taking the members below `first` as already schedulable (their response
 // times cannot change).  cm = conflict mask of S.
@@ -298,6 +457,7 @@ template <typename MT, typename TY>
 __device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, int m, MT cm, TY &ty)
 {
     ty.test();
+    if (use_edf<TY>(L)) return edf_part<MT>(L, tb, S, m, cm, ty, nullptr);  // whole-set test
     const int n = tb.n;
     const uint32_t *row = tb.C + (m - 1) * 2 * n;
     uint64_t sumC = 0;
@@ -401,6 +561,21 @@ __device__ uint32_t rta_one(const SetLDS &L, const Tables &tb, int m, int r, MT 
     if (sat) return 0u;
     NoTally nt;
     return rta_fp<MT>(L, row, n, base, L.D[r], hp & (MT)L.intf[r], cm, nt);
+}
+
+// Reported response time of rank r in partition Sp (m units, conflict mask
+// cm), 0 on a miss: the response-time fixed point under fixed priority; under
+// EDF min(D_r, H) for a schedulable partition (H bounds every busy period).
+template <typename MT, typename TY = NoTally>
+__device__ uint32_t resp_one(const SetLDS &L, const Tables &tb, int m, int r, MT Sp, MT cm)
+{
+    if (use_edf<TY>(L)) {
+        NoTally nt;
+        uint64_t H = 0;
+        if (!edf_part<MT>(L, tb, Sp, m, cm, nt, &H)) return 0u;
+        return (uint32_t)min(H, (uint64_t)L.D[r]);
+    }
+    return rta_one<MT>(L, tb, m, r, Sp & below<MT>(r), cm);
 }
 
 template <int KMAX, typename V>
@@ -579,6 +754,11 @@ __device__ bool wave_test_from(const SetLDS &L, const Tables &tb, uint64_t S, in
 {
     const int lane = threadIdx.x & 63;
     const int n = tb.n;
+    if (use_edf<TY>(L)) {  // whole-set test, the same in every lane
+        NoTally nt;
+        if (lane == 0) ty.test();
+        return edf_part<uint64_t>(L, tb, S, m, cm, nt, nullptr);
+    }
     bool fail = false;
     if (((S >> lane) & 1ull) && lane >= first) {
         const uint32_t *row = tb.C + (m - 1) * 2 * n;
@@ -1041,7 +1221,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     }
     if (lane == 0) {
         w.memmask[s] = mm;
-        w.setflags[s] = SETF_VALID | (reject ? SETF_LEMMA1 : 0u);
+        w.setflags[s] = SETF_VALID | (reject ? SETF_LEMMA1 : 0u) | (Lp.edf ? SETF_EDF : 0u);
     }
     const bool act = (Lp.mode == CAPART_HEUR_BF_ACT || Lp.mode == CAPART_HEUR_SMS_ACT);
     if (!act) return;
@@ -1071,7 +1251,15 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
                 Cb = time_n(tb.Cs, tb.Cp, m);
                 if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
             }
-            if (Ca <= ta.D && Ca < ta.T) {
+            if (Lp.edf) {
+                const uint32_t Ta = ta.T, Tb = tb.T, Da = ta.D, Db = tb.D;
+                auto get = [=](int j, uint32_t &C, uint32_t &T, uint32_t &D) {
+                    C = j ? Cb : Ca;
+                    T = j ? Tb : Ta;
+                    D = j ? Db : Da;
+                };
+                forb = !edf_demand<uint32_t>(3u, get).ok;
+            } else if (Ca <= ta.D && Ca < ta.T) {
                 uint64_t R = (uint64_t)Cb + Ca;
                 for (;;) {
                     if (R > tb.D) break;
@@ -1464,13 +1652,13 @@ __device__ void eval_range(const SetLDS &L, const Tables &tb, const Launch &Lp, 
     }
 }
 
-template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, bool COUNT = false>
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, bool COUNT = false, int POL = POL_ANY>
 __global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
-    typename std::conditional<COUNT, Tally, NoTally>::type ty;
+    typename std::conditional<COUNT, TallyP<POL>, NoTallyP<POL>>::type ty;
     const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
     const int c = blockIdx.x % Lp.chunks;
     const uint32_t f = w.setflags[s];
@@ -1524,13 +1712,13 @@ __global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, 
 // it, so a partitioning costs one test's critical path per candidate instead
 // of all of its members' fixed points in one lane.  Only the execution-time
 // table is staged (utilisations through the reciprocal of T).
-template <int KMAX, bool ACT, bool SMS, bool COUNT = false>
+template <int KMAX, bool ACT, bool SMS, bool COUNT = false, int POL = POL_ANY>
 __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, Launch Lp, uint32_t p_lo,
                                                         uint32_t p_hi)
 {
     __shared__ SetLDS L;
     __shared__ Key red[16];
-    typename std::conditional<COUNT, Tally, NoTally>::type ty;
+    typename std::conditional<COUNT, TallyP<POL>, NoTallyP<POL>>::type ty;
     const int64_t s = Lp.s0 + blockIdx.x / Lp.chunks;
     const int c = blockIdx.x % Lp.chunks;
     const uint32_t f = w.setflags[s];
@@ -1610,7 +1798,7 @@ __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, 
 // work item (set, partitioning range) from a global counter, restages the
 // set's LDS tables only when the set changes, and writes the item's best key
 // to its partial slot.  Items come largest first, so the tail is short.
-template <int KMAX, bool ACT, bool SMS, typename MT, int FORM>
+template <int KMAX, bool ACT, bool SMS, typename MT, int FORM, int POL = POL_ANY>
 __global__ __launch_bounds__(512) void eval_persistent_kernel(Batch b, Work w, Out o, Launch Lp)
 {
     __shared__ SetLDS L;
@@ -1640,7 +1828,7 @@ __global__ __launch_bounds__(512) void eval_persistent_kernel(Batch b, Work w, O
                 memo_clear<MT, FORM>(Lp, n);
                 staged = s;
             }
-            NoTally nt;
+            NoTallyP<POL> nt;
             eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, w.order, n, M, wi.p0, wi.p1, 0u, 0xFFFFFFFFu, best, dbg, nt);
         } else if (dbg && (f & SETF_VALID)) {
             for (uint32_t q = wi.p0 + threadIdx.x; q < wi.p1; q += blockDim.x) {
@@ -1857,8 +2045,7 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
             uint64_t Sp = 0;
             for (int p = 0; p < sk; p++)
                 if ((sS[p] >> lane) & 1ull) { part = p; mp = sm_[p]; Sp = sS[p]; }
-            const uint32_t R = rta_one<uint64_t>(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull),
-                                                 conflict_mask<uint64_t>(Sp, L.memmask));
+            const uint32_t R = resp_one<uint64_t>(L, tb, mp, lane, Sp, conflict_mask<uint64_t>(Sp, L.memmask));
             o.alloc[gi] = (int8_t)part;
             o.R[gi] = R ? (int64_t)R : -1;
         } else {
@@ -1872,7 +2059,7 @@ __global__ __launch_bounds__(64) void final_kernel(Batch b, Work w, Out o, Launc
         const uint64_t all = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
         uint32_t R1 = 0;
         if (lane < n) {
-            R1 = rta_one<uint64_t>(L, tb, M, lane, all & ((1ull << lane) - 1ull), conflict_mask<uint64_t>(all, L.memmask));
+            R1 = resp_one<uint64_t>(L, tb, M, lane, all, conflict_mask<uint64_t>(all, L.memmask));
             o.R_1g[off + L.orig[lane]] = R1 ? (int64_t)R1 : -1;
         }
         ok1 = !__ballot(lane < n && R1 == 0u);
@@ -2113,7 +2300,7 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
         Pi += mj3 - mc - mj;
         merged += 1;
     }
-    if constexpr (!std::is_same<TY, NoTally>::value) {
+    if constexpr (std::is_same<TY, TallyP<TY::kPol>>::value) {
         uint64_t a = ty.terms, bb = ty.tests;
 #pragma unroll
         for (int o2 = 32; o2 >= 1; o2 >>= 1) {
@@ -2142,8 +2329,7 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
         if ((mk >> lane) & 1ull) { part = p; Sp = mk; mp = mm; }
     }
     if (lane < n) {
-        const uint32_t R = rta_one<uint64_t>(L, tb, mp, lane, Sp & ((1ull << lane) - 1ull),
-                                             conflict_mask<uint64_t>(Sp, memm));
+        const uint32_t R = resp_one<uint64_t, TY>(L, tb, mp, lane, Sp, conflict_mask<uint64_t>(Sp, memm));
         const int64_t gi = off0 + L.orig[lane];
         o.alloc[gi] = (int8_t)part;
         o.R[gi] = R ? (int64_t)R : -1;
@@ -2354,7 +2540,7 @@ __global__ __launch_bounds__(64) void triple_kernel(Batch b, Work w, const int32
         const int p = alloc[L.orig[lane]];
         const uint64_t Sp = sS[p];
         const uint64_t cm = conflict_mask<uint64_t>(Sp, L.memmask);
-        R = rta_one<uint64_t>(L, tb, sizes[p], lane, Sp & ((1ull << lane) - 1ull), cm);
+        R = resp_one<uint64_t>(L, tb, sizes[p], lane, Sp, cm);
         Rout[L.orig[lane]] = R ? (int64_t)R : -1;
         if (R) {
             const uint32_t u = tb.U[(sizes[p] - 1) * 2 * n + (int)((cm >> lane) & 1ull) * n + lane];
@@ -2431,7 +2617,7 @@ static bool frontier_launch(const Launch &L, const Batch &b)
     return L.mode != CAPART_EXHAUSTIVE && L.front_n > 0 && launch_max_n(L, b) <= L.front_n;
 }
 
-template <int KMAX, typename MT, int FORM>
+template <int KMAX, typename MT, int FORM, int POL>
 static hipError_t launch_heur(const Launch &L, const Batch &b, const Work &w, const Out &o, hipStream_t st,
                               uint32_t p_lo, uint32_t p_hi)
 {
@@ -2439,19 +2625,19 @@ static hipError_t launch_heur(const Launch &L, const Batch &b, const Work &w, co
     const size_t lds = heur_dyn_bytes<KMAX, MT>(L, FORM);
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM, false, POL>), grid, block, lds, st, b, w, o, L, p_lo,
                            p_hi);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM, false, POL>), grid, block, lds, st, b, w, o, L, p_lo,
                            p_hi);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM, false, POL>), grid, block, lds, st, b, w, o, L, p_lo,
                            p_hi);
         break;
     default:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM>), grid, block, lds, st, b, w, o, L, p_lo,
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM, false, POL>), grid, block, lds, st, b, w, o, L, p_lo,
                            p_hi);
         break;
     }
@@ -2467,12 +2653,17 @@ static hipError_t launch_eval_k(const Batch &b, const Work &w, const Out &o, con
         hipLaunchKernelGGL((eval_exh_kernel<KMAX>), grid, block, dyn_bytes(b), st, b, w, o, L, p_lo, p_hi);
         return hipGetLastError();
     }
-    if (frontier_launch(L, b)) return launch_heur<KMAX, MT, 0>(L, b, w, o, st, p_lo, p_hi);
-    return L.form == 2 ? launch_heur<KMAX, MT, 2>(L, b, w, o, st, p_lo, p_hi)
-                       : launch_heur<KMAX, MT, 1>(L, b, w, o, st, p_lo, p_hi);
+    if (L.edf) {
+        if (frontier_launch(L, b)) return launch_heur<KMAX, MT, 0, POL_EDF>(L, b, w, o, st, p_lo, p_hi);
+        return L.form == 2 ? launch_heur<KMAX, MT, 2, POL_EDF>(L, b, w, o, st, p_lo, p_hi)
+                           : launch_heur<KMAX, MT, 1, POL_EDF>(L, b, w, o, st, p_lo, p_hi);
+    }
+    if (frontier_launch(L, b)) return launch_heur<KMAX, MT, 0, POL_FP>(L, b, w, o, st, p_lo, p_hi);
+    return L.form == 2 ? launch_heur<KMAX, MT, 2, POL_FP>(L, b, w, o, st, p_lo, p_hi)
+                       : launch_heur<KMAX, MT, 1, POL_FP>(L, b, w, o, st, p_lo, p_hi);
 }
 
-template <int KMAX, typename MT, int FORM>
+template <int KMAX, typename MT, int FORM, int POL>
 static hipError_t launch_persistent_k(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
                                       hipStream_t st)
 {
@@ -2480,16 +2671,16 @@ static hipError_t launch_persistent_k(const Batch &b, const Work &w, const Out &
     const size_t lds = heur_dyn_bytes<KMAX, MT>(L, FORM);
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, false, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, false, MT, FORM, POL>), grid, block, lds, st, b, w, o, L);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, false, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, false, MT, FORM, POL>), grid, block, lds, st, b, w, o, L);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, true, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, false, true, MT, FORM, POL>), grid, block, lds, st, b, w, o, L);
         break;
     default:
-        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, true, MT, FORM>), grid, block, lds, st, b, w, o, L);
+        hipLaunchKernelGGL((eval_persistent_kernel<KMAX, true, true, MT, FORM, POL>), grid, block, lds, st, b, w, o, L);
         break;
     }
     return hipGetLastError();
@@ -2499,9 +2690,14 @@ template <int KMAX, typename MT>
 static hipError_t launch_persistent_f(const Batch &b, const Work &w, const Out &o, const Launch &L, int blocks,
                                       hipStream_t st)
 {
-    if (frontier_launch(L, b)) return launch_persistent_k<KMAX, MT, 0>(b, w, o, L, blocks, st);
-    return L.form == 2 ? launch_persistent_k<KMAX, MT, 2>(b, w, o, L, blocks, st)
-                       : launch_persistent_k<KMAX, MT, 1>(b, w, o, L, blocks, st);
+    if (L.edf) {
+        if (frontier_launch(L, b)) return launch_persistent_k<KMAX, MT, 0, POL_EDF>(b, w, o, L, blocks, st);
+        return L.form == 2 ? launch_persistent_k<KMAX, MT, 2, POL_EDF>(b, w, o, L, blocks, st)
+                           : launch_persistent_k<KMAX, MT, 1, POL_EDF>(b, w, o, L, blocks, st);
+    }
+    if (frontier_launch(L, b)) return launch_persistent_k<KMAX, MT, 0, POL_FP>(b, w, o, L, blocks, st);
+    return L.form == 2 ? launch_persistent_k<KMAX, MT, 2, POL_FP>(b, w, o, L, blocks, st)
+                       : launch_persistent_k<KMAX, MT, 1, POL_FP>(b, w, o, L, blocks, st);
 }
 
 int size_classes(const Launch &L, int max_tasks, int hi[3])
@@ -2552,7 +2748,7 @@ int device_cu_count()
 // the execution-time table only.
 static bool wide_launch(const Launch &L) { return L.mode != CAPART_EXHAUSTIVE && L.wchunk > 0 && L.n_lo > NARROW_MAX_TASKS; }
 
-template <int KMAX, bool COUNT>
+template <int KMAX, bool COUNT, int POL>
 static hipError_t launch_wide_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,
                                 uint32_t p_lo, uint32_t p_hi)
 {
@@ -2560,22 +2756,22 @@ static hipError_t launch_wide_k(const Batch &b, const Work &w, const Out &o, con
     const size_t lds = (size_t)2 * L.table_words;  // half of the [m][conflict][rank] time + utilisation tables
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, false, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, false, COUNT, POL>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, false, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, false, COUNT, POL>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, true, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, false, true, COUNT, POL>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
         break;
     default:
-        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, true, COUNT>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
+        hipLaunchKernelGGL((eval_wide_kernel<KMAX, true, true, COUNT, POL>), grid, block, lds, st, b, w, o, L, p_lo, p_hi);
         break;
     }
     return hipGetLastError();
 }
 
-template <int KMAX, typename MT, int FORM>
+template <int KMAX, typename MT, int FORM, int POL>
 static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
 {
     const dim3 grid((unsigned)(L.S * L.chunks)), block((unsigned)L.threads);
@@ -2583,42 +2779,53 @@ static hipError_t launch_count_k(const Batch &b, const Work &w, const Out &o, co
     const uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     switch (L.mode) {
     case CAPART_HEUR_BF_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, false, MT, FORM, true, POL>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     case CAPART_HEUR_BF_ACT:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, false, MT, FORM, true, POL>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     case CAPART_HEUR_SMS_INA:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, false, true, MT, FORM, true, POL>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     default:
-        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM, true>), grid, block, lds, st, b, w, o, L, lo, hi);
+        hipLaunchKernelGGL((eval_heur_kernel<KMAX, true, true, MT, FORM, true, POL>), grid, block, lds, st, b, w, o, L, lo, hi);
         break;
     }
     return hipGetLastError();
 }
 
+template <int KMAX, typename MT, int FORM>
+static hipError_t launch_count_pol(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st)
+{
+    return L.edf ? launch_count_k<KMAX, MT, FORM, POL_EDF>(b, w, o, L, st)
+                 : launch_count_k<KMAX, MT, FORM, POL_FP>(b, w, o, L, st);
+}
+
 static hipError_t launch_eval_count_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st)
 {
     if (wide_launch(L0))
-        return L0.K <= 4 ? launch_wide_k<4, true>(b, w, o, L0, st, 0u, 0xFFFFFFFFu)
-                         : launch_wide_k<8, true>(b, w, o, L0, st, 0u, 0xFFFFFFFFu);
+        return L0.edf ? (L0.K <= 4 ? launch_wide_k<4, true, POL_EDF>(b, w, o, L0, st, 0u, 0xFFFFFFFFu)
+                                   : launch_wide_k<8, true, POL_EDF>(b, w, o, L0, st, 0u, 0xFFFFFFFFu))
+                      : (L0.K <= 4 ? launch_wide_k<4, true, POL_FP>(b, w, o, L0, st, 0u, 0xFFFFFFFFu)
+                                   : launch_wide_k<8, true, POL_FP>(b, w, o, L0, st, 0u, 0xFFFFFFFFu));
     const Launch L = frontier_launch(L0, b) ? L0 : fit_block(L0, b);
     const bool fr = frontier_launch(L, b);
     if (launch_max_n(L, b) <= 32) {
-        if (L.K <= 4) return fr ? launch_count_k<4, uint32_t, 0>(b, w, o, L, st) : launch_count_k<4, uint32_t, 1>(b, w, o, L, st);
-        return fr ? launch_count_k<8, uint32_t, 0>(b, w, o, L, st) : launch_count_k<8, uint32_t, 1>(b, w, o, L, st);
+        if (L.K <= 4) return fr ? launch_count_pol<4, uint32_t, 0>(b, w, o, L, st) : launch_count_pol<4, uint32_t, 1>(b, w, o, L, st);
+        return fr ? launch_count_pol<8, uint32_t, 0>(b, w, o, L, st) : launch_count_pol<8, uint32_t, 1>(b, w, o, L, st);
     }
-    if (L.K <= 4) return fr ? launch_count_k<4, uint64_t, 0>(b, w, o, L, st) : launch_count_k<4, uint64_t, 1>(b, w, o, L, st);
-    return fr ? launch_count_k<8, uint64_t, 0>(b, w, o, L, st) : launch_count_k<8, uint64_t, 1>(b, w, o, L, st);
+    if (L.K <= 4) return fr ? launch_count_pol<4, uint64_t, 0>(b, w, o, L, st) : launch_count_pol<4, uint64_t, 1>(b, w, o, L, st);
+    return fr ? launch_count_pol<8, uint64_t, 0>(b, w, o, L, st) : launch_count_pol<8, uint64_t, 1>(b, w, o, L, st);
 }
 
 static hipError_t launch_eval_range_one(const Batch &b, const Work &w, const Out &o, const Launch &L0, hipStream_t st,
                                         uint32_t p_lo, uint32_t p_hi)
 {
     if (wide_launch(L0))
-        return L0.K <= 4 ? launch_wide_k<4, false>(b, w, o, L0, st, p_lo, p_hi)
-                         : launch_wide_k<8, false>(b, w, o, L0, st, p_lo, p_hi);
+        return L0.edf ? (L0.K <= 4 ? launch_wide_k<4, false, POL_EDF>(b, w, o, L0, st, p_lo, p_hi)
+                                   : launch_wide_k<8, false, POL_EDF>(b, w, o, L0, st, p_lo, p_hi))
+                      : (L0.K <= 4 ? launch_wide_k<4, false, POL_FP>(b, w, o, L0, st, p_lo, p_hi)
+                                   : launch_wide_k<8, false, POL_FP>(b, w, o, L0, st, p_lo, p_hi));
     const Launch L = (L0.mode == CAPART_EXHAUSTIVE || frontier_launch(L0, b)) ? L0 : fit_block(L0, b);
     // 32-bit rank masks when every set of the launch has at most 32 tasks
     if (launch_max_n(L, b) <= 32)
@@ -2697,10 +2904,16 @@ static void launch_alg1_ty(const Batch &b, const Work &w, const A1Out &o, const 
 hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st, bool count)
 {
     if (L.S <= 0) return hipSuccess;
-    if (count)
-        launch_alg1_ty<Tally>(b, w, o, L, st);
-    else
-        launch_alg1_ty<NoTally>(b, w, o, L, st);
+    if (L.edf) {
+        if (count)
+            launch_alg1_ty<TallyP<POL_EDF>>(b, w, o, L, st);
+        else
+            launch_alg1_ty<NoTallyP<POL_EDF>>(b, w, o, L, st);
+    } else if (count) {
+        launch_alg1_ty<TallyP<POL_FP>>(b, w, o, L, st);
+    } else {
+        launch_alg1_ty<NoTallyP<POL_FP>>(b, w, o, L, st);
+    }
     return hipGetLastError();
 }
 
@@ -2755,19 +2968,19 @@ static hipError_t allow_lds(F *fn)
 
 // Raise the dynamic-LDS limit of every heuristic kernel instantiation
 // (policy and order variants, rank-mask width, loop form, counting variant).
-template <int KMAX, typename MT, int FORM, bool COUNT>
+template <int KMAX, typename MT, int FORM, bool COUNT, int POL>
 static hipError_t allow_heur()
 {
     hipError_t e = hipSuccess, t;
-    if ((t = allow_lds(eval_heur_kernel<KMAX, false, false, MT, FORM, COUNT>)) != hipSuccess) e = t;
-    if ((t = allow_lds(eval_heur_kernel<KMAX, true, false, MT, FORM, COUNT>)) != hipSuccess) e = t;
-    if ((t = allow_lds(eval_heur_kernel<KMAX, false, true, MT, FORM, COUNT>)) != hipSuccess) e = t;
-    if ((t = allow_lds(eval_heur_kernel<KMAX, true, true, MT, FORM, COUNT>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, false, false, MT, FORM, COUNT, POL>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, true, false, MT, FORM, COUNT, POL>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, false, true, MT, FORM, COUNT, POL>)) != hipSuccess) e = t;
+    if ((t = allow_lds(eval_heur_kernel<KMAX, true, true, MT, FORM, COUNT, POL>)) != hipSuccess) e = t;
     if constexpr (!COUNT) {
-        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, false, MT, FORM>)) != hipSuccess) e = t;
-        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, false, MT, FORM>)) != hipSuccess) e = t;
-        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, true, MT, FORM>)) != hipSuccess) e = t;
-        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, true, MT, FORM>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, false, MT, FORM, POL>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, false, MT, FORM, POL>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, false, true, MT, FORM, POL>)) != hipSuccess) e = t;
+        if ((t = allow_lds(eval_persistent_kernel<KMAX, true, true, MT, FORM, POL>)) != hipSuccess) e = t;
     }
     return e;
 }
@@ -2776,11 +2989,16 @@ template <int KMAX, typename MT>
 static hipError_t allow_heur_all()
 {
     hipError_t e = hipSuccess, t;
-    if ((t = allow_heur<KMAX, MT, 0, false>()) != hipSuccess) e = t;
-    if ((t = allow_heur<KMAX, MT, 1, false>()) != hipSuccess) e = t;
-    if ((t = allow_heur<KMAX, MT, 2, false>()) != hipSuccess) e = t;
-    if ((t = allow_heur<KMAX, MT, 0, true>()) != hipSuccess) e = t;
-    if ((t = allow_heur<KMAX, MT, 1, true>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 0, false, POL_FP>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, false, POL_FP>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 2, false, POL_FP>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 0, true, POL_FP>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, true, POL_FP>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 0, false, POL_EDF>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, false, POL_EDF>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 2, false, POL_EDF>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 0, true, POL_EDF>()) != hipSuccess) e = t;
+    if ((t = allow_heur<KMAX, MT, 1, true, POL_EDF>()) != hipSuccess) e = t;
     return e;
 }
 
@@ -2795,30 +3013,54 @@ hipError_t configure_kernels()
     if ((t = allow_heur_all<8, uint32_t>()) != hipSuccess) e = t;
     if ((t = allow_heur_all<8, uint64_t>()) != hipSuccess) e = t;
     CAPART_ALLOW((subset_table_kernel));
-    CAPART_ALLOW((alg1_kernel<false, false, NoTally>));
-    CAPART_ALLOW((alg1_kernel<true, false, NoTally>));
-    CAPART_ALLOW((alg1_kernel<false, true, NoTally>));
-    CAPART_ALLOW((alg1_kernel<true, true, NoTally>));
-    CAPART_ALLOW((alg1_kernel<false, false, Tally>));
-    CAPART_ALLOW((alg1_kernel<true, false, Tally>));
-    CAPART_ALLOW((alg1_kernel<false, true, Tally>));
-    CAPART_ALLOW((alg1_kernel<true, true, Tally>));
-    CAPART_ALLOW((eval_wide_kernel<4, false, false, false>));
-    CAPART_ALLOW((eval_wide_kernel<4, true, false, false>));
-    CAPART_ALLOW((eval_wide_kernel<4, false, true, false>));
-    CAPART_ALLOW((eval_wide_kernel<4, true, true, false>));
-    CAPART_ALLOW((eval_wide_kernel<8, false, false, false>));
-    CAPART_ALLOW((eval_wide_kernel<8, true, false, false>));
-    CAPART_ALLOW((eval_wide_kernel<8, false, true, false>));
-    CAPART_ALLOW((eval_wide_kernel<8, true, true, false>));
-    CAPART_ALLOW((eval_wide_kernel<4, false, false, true>));
-    CAPART_ALLOW((eval_wide_kernel<4, true, false, true>));
-    CAPART_ALLOW((eval_wide_kernel<4, false, true, true>));
-    CAPART_ALLOW((eval_wide_kernel<4, true, true, true>));
-    CAPART_ALLOW((eval_wide_kernel<8, false, false, true>));
-    CAPART_ALLOW((eval_wide_kernel<8, true, false, true>));
-    CAPART_ALLOW((eval_wide_kernel<8, false, true, true>));
-    CAPART_ALLOW((eval_wide_kernel<8, true, true, true>));
+    CAPART_ALLOW((alg1_kernel<false, false, NoTallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<true, false, NoTallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<false, true, NoTallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<true, true, NoTallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<false, false, TallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<true, false, TallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<false, true, TallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<true, true, TallyP<POL_FP>>));
+    CAPART_ALLOW((alg1_kernel<false, false, NoTallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<true, false, NoTallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<false, true, NoTallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<true, true, NoTallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<false, false, TallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<true, false, TallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<false, true, TallyP<POL_EDF>>));
+    CAPART_ALLOW((alg1_kernel<true, true, TallyP<POL_EDF>>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, false, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, true, POL_FP>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, false, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, false, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, false, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, false, true, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<4, true, true, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, false, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, false, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, false, true, true, POL_EDF>));
+    CAPART_ALLOW((eval_wide_kernel<8, true, true, true, POL_EDF>));
     CAPART_ALLOW((final_kernel<4>));
     CAPART_ALLOW((final_kernel<8>));
     CAPART_ALLOW((triple_kernel<8>));

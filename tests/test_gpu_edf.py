@@ -1,0 +1,169 @@
+"""EDF per-partition policy on the GPU (through the C ABI): bit-exact with the
+oracle's EDF in every allocation mode and on every evaluation path (loop
+forms, feasibility frontier, test memo, wide-set wave path, exhaustive forms,
+batched plans, device entry points, Algorithm 1), over the random input
+domain and at the test's stated limits."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10312_amd import capart, workload
+from test_gpu_random_domain import random_batch
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("status", "verdict", "verdict_1g", "pidx", "sizes", "aidx", "maxU", "sumU", "n_evals", "alloc", "R",
+          "R_1g")
+A1_FIELDS = ("status", "verdict", "nparts", "sizes", "alloc", "R", "tried", "merged")
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    e = capart.Engine(0)
+    yield e
+    e.close()
+
+
+def same(got, want, fields, label):
+    for f in fields:
+        g, w = np.asarray(got[f]).ravel(), np.asarray(want[f]).ravel()
+        if not (g.shape == w.shape and np.array_equal(g, w)):
+            bad = np.nonzero(g != w)[0][:3] if g.shape == w.shape else []
+            raise AssertionError(f"{label}: field {f} differs at {list(bad)}")
+
+
+def mixed():
+    """Implicit (C2), constrained (C3) and wide (C5, 33..64 tasks) sets."""
+    c2 = workload.subset(workload.config_c2(n_sets=2000), np.arange(100))
+    c3 = workload.subset(workload.config_c3(n_sets=2000), np.arange(60))
+    c5 = workload.config_c5(seed=101, n_queries=300)
+    wide = workload.subset(c5, np.nonzero((c5.sizes() > 32) & (c5["M"] <= 48))[0][:6])
+    return workload.concat([c2, c3, wide])
+
+
+def limit_sets():
+    """Sets at the EDF test's stated limits, as one-unit partitions with
+    sequential times (k = 1000): a busy period that takes the utilisation
+    bound, deadline counts either side of the limit, utilisation exactly 1
+    (implicit, and constrained but still schedulable), just above 1, and a
+    single task meeting or missing its deadline."""
+    cases = [
+        ([9_999, 5_000], [10_000, 1_000_000_000], [10_000, 1_000_000_000]),
+        ([10_000, 5_000], [10_000, 1_000_000_000], [10_000, 1_000_000_000]),
+        ([1, 50_000], [2, 1 << 30], [2, 1 << 30]),
+        ([1, 200_000], [2, 1 << 30], [2, 1 << 30]),
+        ([1, 3, 3], [4, 6, 12], [4, 6, 12]),
+        ([1, 3, 3], [4, 6, 12], [3, 6, 12]),
+        ([2, 3, 4], [4, 6, 12], [4, 6, 12]),
+        ([7], [100], [7]),
+        ([7], [100], [6]),
+    ]
+    off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cases])]).astype(np.int64)
+    cat = lambda i, dt: np.concatenate([np.asarray(c[i], dt) for c in cases])
+    N = int(off[-1])
+    return workload.TaskSets(set_offset=off, M=np.ones(len(cases), np.int32), T=cat(1, np.int64),
+                             D=cat(2, np.int64), C_seq=cat(0, np.int64), C_par=np.zeros(N, np.int64),
+                             k_permille=np.full(N, 1000, np.int32), type=np.zeros(N, np.uint8))
+
+
+@pytest.mark.parametrize("mode", ["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_heuristic_paths_match_oracle(eng, mode):
+    ts = mixed()
+    say(f"EDF {mode}: {ts.n_sets} sets")
+    want = oracle.solve(ts, 4, mode, nthreads=THREADS, policy="EDF")
+    fp = oracle.solve(ts, 4, mode, nthreads=THREADS)
+    assert (want["verdict_1g"] >= fp["verdict_1g"]).all()
+    for tune in ({}, {"loop_form": 2}, {"loop_form": 3}, {"frontier": 2, "memo": -1}, {"wide_chunk": -1}):
+        capart.capart_set_tuning(eng.ctx, **tune)
+        same(eng.solve(ts, 4, mode, policy="EDF"), want, FIELDS, f"EDF {mode} {tune}")
+    capart.capart_set_tuning(eng.ctx)
+    # the FP results on the same context are untouched
+    same(eng.solve(ts, 4, mode), fp, FIELDS, f"FP {mode}")
+
+
+def test_exhaustive_matches_oracle(eng):
+    ts = workload.config_c1(n_sets=100)
+    small = random_batch(7001, 60, 3, 7, 12, 10 ** 9)
+    for batch, K in ((ts, 3), (small, 3)):
+        want = oracle.solve(batch, K, "EXH", policy="EDF")
+        for exh_form in (1, 2):
+            capart.capart_set_tuning(eng.ctx, exh_form=exh_form)
+            same(eng.solve(batch, K, "EXH", policy="EDF"), want, FIELDS, f"EDF EXH form {exh_form}")
+    capart.capart_set_tuning(eng.ctx)
+
+
+@pytest.mark.parametrize("K", [1, 3, 8])
+def test_random_domain_matches_oracle(eng, K):
+    ts = random_batch(5000 + K, 150, K, 64, 255, 40000)
+    for mode in ("BF_INA", "SMS_ACT"):
+        say(f"EDF random domain {mode} K={K}")
+        want = oracle.solve(ts, K, mode, nthreads=THREADS, policy="EDF")
+        same(eng.solve(ts, K, mode, policy="EDF"), want, FIELDS, f"EDF random {mode} K={K}")
+
+
+def test_limits_match_oracle(eng):
+    ts = limit_sets()
+    want = oracle.solve(ts, 1, "BF_INA", policy="EDF")
+    got = eng.solve(ts, 1, "BF_INA", policy="EDF")
+    same(got, want, FIELDS, "EDF limits")
+    assert list(got["verdict_1g"]) == [1, 0, 1, 0, 1, 1, 0, 1, 0]
+
+
+def test_alg1_matches_oracle(eng):
+    f4 = workload.config_paper_fig4(sets_per_point=3)
+    c3 = workload.subset(workload.config_c3(n_sets=2000), np.arange(60))
+    for ts in (f4, c3):
+        off = ts["set_offset"]
+        for mode in ("BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"):
+            say(f"EDF alg1 {mode}: {ts.n_sets} sets")
+            got = eng.alg1(ts, mode, policy="EDF")
+            for s in range(ts.n_sets):
+                w = oracle.alg1(ts.set(s), mode, policy="EDF")
+                a, b = int(off[s]), int(off[s + 1])
+                assert int(got["verdict"][s]) == w["verdict"], (mode, s)
+                assert int(got["tried"][s]) == w["tried"] and int(got["merged"][s]) == w["merged"], (mode, s)
+                if w["verdict"]:
+                    assert int(got["nparts"][s]) == w["k"]
+                    assert np.array_equal(got["sizes"][a:a + w["k"]], w["sizes"]), (mode, s)
+                    assert np.array_equal(got["alloc"][a:b], w["alloc"]), (mode, s)
+                    assert np.array_equal(got["R"][a:b], w["R"]), (mode, s)
+
+
+def test_batched_plans_and_device_entry(eng):
+    import torch
+    ts = workload.concat([workload.subset(workload.config_c2(n_sets=2000), np.arange(100)),
+                          workload.subset(workload.config_c3(n_sets=2000), np.arange(60))])
+    want = eng.solve(ts, 4, "BF_INA", policy="EDF")
+    dev = capart.device_tasksets(ts)
+    for bpc in (8, -1):
+        out = capart.device_results(ts.n_sets, ts.n_tasks, 4)
+        plan = capart.Plan(eng.ctx, dev, 4, "BF_INA", out, 32, 108, autotune=False, blocks_per_cu=bpc,
+                           policy="EDF")
+        plan.run()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        plan.close()
+        for f in FIELDS:
+            w = np.asarray(want[f]).ravel()
+            assert np.array_equal(got[f].ravel()[:w.size], w), (bpc, f)
+    out = capart.device_results(ts.n_sets, ts.n_tasks, 4)
+    capart.capart_solve_async(eng.ctx, dev, 4, "BF_INA", out, max_tasks=32, max_M=108, policy="EDF")
+    torch.cuda.synchronize()
+    for f in FIELDS:
+        w = np.asarray(want[f]).ravel()
+        assert np.array_equal(out[f].cpu().numpy().ravel()[:w.size], w), f
+
+
+def test_unknown_policy_is_rejected(eng):
+    ts = workload.config_c1(n_sets=2)
+    with pytest.raises(capart.CapartError):
+        eng.solve(ts, 3, "BF_INA", policy=7)
