@@ -335,8 +335,13 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
 // partition completes by min(D_i, H)) and the terms evaluated (members x
 // busy-period steps and demand points).  64-bit bounds: C < 2^31 and
 // T, D < 2^31; w < 2^50 over the busy-period steps (U < 1 + 2^-26); H < 2^57.
+// Shortcut when H is not wanted: density sum ceil(C 2^32 / D) <= 2^32 and
+// Uq < 2^32, with at most EDF_ND_CAP deadlines below the utilisation bound
+// Hb, answer schedulable at once.  That is the definition's answer: density
+// at most 1 is sufficient for EDF (h(t) <= t everywhere), the defined H
+// (L, or Hb itself) is at most Hb, so its deadline count is within the limit.
 // Kept out of line (one call on the EDF side of each test) so that the
-// fixed-priority paths keep their registers.
+// runtime-policy kernels keep most of their registers.
 constexpr int EDF_BP_STEPS = 4096;
 constexpr uint64_t EDF_ND_CAP = 65536;
 
@@ -347,12 +352,13 @@ struct EdfRes {
 };
 
 template <typename MT, typename GET>
-__device__ __noinline__ EdfRes edf_demand(MT S, GET get)
+__device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
 {
     constexpr uint64_t ONE = 1ull << 32;
     const uint32_t cnt = (uint32_t)mpopc(S);
     EdfRes res{0ull, 0u, false};
-    uint64_t uf = 0, uc = 0, sumC = 0;
+    uint64_t uf = 0, uc = 0, dc = 0, sumC = 0;
+    bool dense = false;  // some C_j / D_j above 1 (no density shortcut)
     uint32_t dmin = 0xFFFFFFFFu;
     for (MT h = S; h; h &= h - MT(1)) {
         uint32_t C, T, D;
@@ -362,8 +368,30 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get)
         uf += q;
         if (uf > ONE) return res;
         uc += q + (num != q * (uint64_t)T ? 1ull : 0ull);
+        if (!need_h) {
+            const uint64_t qd = D == T ? q : num / D;
+            if (qd > ONE) dense = true;
+            else dc += qd + (num != qd * (uint64_t)D ? 1ull : 0ull);
+        }
         sumC += C;
         dmin = min(dmin, D);
+    }
+    if (!need_h && !dense && dc <= ONE && uc < ONE) {
+        const uint64_t den = ONE - uc, a = sumC / den, r = sumC % den;
+        if (a < (1ull << 24)) {
+            const uint64_t Hb = (a << 32) + (((r << 32) + den - 1ull) / den);
+            uint64_t nd = 0;
+            for (MT h = S; h; h &= h - MT(1)) {
+                uint32_t C, T, D;
+                get(mctz(h), C, T, D);
+                if (D < Hb) nd += (Hb - 1ull - D) / T + 1ull;
+            }
+            res.terms += cnt;
+            if (nd <= EDF_ND_CAP) {
+                res.ok = true;
+                return res;
+            }
+        }
     }
     uint64_t w = sumC, H;
     bool settled = false;
@@ -444,7 +472,7 @@ __device__ __forceinline__ bool edf_part(const SetLDS &L, const Tables &tb, MT S
         T = Ls->T[j];
         D = Ls->D[j];
     };
-    const EdfRes r = edf_demand<MT>(S, get);
+    const EdfRes r = edf_demand<MT>(S, get, Hout != nullptr);
     ty.term(r.terms);
     if (Hout) *Hout = r.H;
     return r.ok;
@@ -1258,7 +1286,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
                     T = j ? Tb : Ta;
                     D = j ? Db : Da;
                 };
-                forb = !edf_demand<uint32_t>(3u, get).ok;
+                forb = !edf_demand<uint32_t>(3u, get, false).ok;
             } else if (Ca <= ta.D && Ca < ta.T) {
                 uint64_t R = (uint64_t)Cb + Ca;
                 for (;;) {
