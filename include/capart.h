@@ -107,9 +107,9 @@ typedef int32_t capart_status;
  * -1 for every task of an unschedulable one (1G included).  Lemma 2 sizes,
  * the Lemma 1 filter, utilisations and keys are policy-independent; ACT's
  * pair test uses the policy.  Honoured by capart_solve, capart_solve_async,
- * capart_count_work, capart_allocate, the batched plans and Algorithm 1;
- * capart_test_triple and the server schedule by CAPART_POLICY_FP_DM (their
- * arguments carry no policy).
+ * capart_count_work, capart_allocate, the batched plans, Algorithm 1 and
+ * the server (capart_server_config.policy); capart_test_triple schedules by
+ * CAPART_POLICY_FP_DM (its arguments carry no policy).
  */
 
 /* option flags */
@@ -398,6 +398,7 @@ typedef struct capart_server_config {
     int64_t device_bytes;   /* device budget for resident queries (0 = 256 MiB) */
     int32_t streams;        /* batches in flight, 1..8 (0 = 4)        */
     int32_t max_batch;      /* queries per launch (0 = no limit)      */
+    int32_t policy;         /* CAPART_POLICY_FP_DM (0) or CAPART_POLICY_EDF, every query */
 } capart_server_config;
 
 typedef struct capart_server_stats {

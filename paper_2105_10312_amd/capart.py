@@ -85,7 +85,7 @@ class capart_plan_info(C.Structure):
 class capart_server_config(C.Structure):
     _fields_ = [("K", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32), ("max_tasks", C.c_int32),
                 ("max_M", C.c_int32), ("max_queries", C.c_int32), ("device_bytes", C.c_int64),
-                ("streams", C.c_int32), ("max_batch", C.c_int32)]
+                ("streams", C.c_int32), ("max_batch", C.c_int32), ("policy", C.c_int32)]
 
 
 class capart_server_stats(C.Structure):
@@ -542,11 +542,13 @@ class Server:
     continuous batching over several streams (see capart_server_* in capart.h)."""
 
     def __init__(self, ctx, K: int = 4, mode="BF_INA", flags: int = 0, max_tasks: int = 64, max_M: int = 108,
-                 max_queries: int = 0, device_bytes: int = 0, streams: int = 0, max_batch: int = 0):
+                 max_queries: int = 0, device_bytes: int = 0, streams: int = 0, max_batch: int = 0,
+                 policy="FP_DM"):
         self.ctx = ctx
         self.K = int(K)
+        pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
         cfg = capart_server_config(int(K), _mode(mode), int(flags), int(max_tasks), int(max_M), int(max_queries),
-                                   int(device_bytes), int(streams), int(max_batch))
+                                   int(device_bytes), int(streams), int(max_batch), pol)
         h = _vp()
         _check(load_library().capart_server_create(ctx, C.byref(cfg), C.byref(h)), ctx)
         self.handle = h

@@ -2047,7 +2047,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
 {
     if (!c || !cfg || !out) return CAPART_E_INVAL;
     *out = nullptr;
-    capart_options opt{cfg->K, CAPART_POLICY_FP_DM, cfg->alloc_mode, cfg->flags};
+    capart_options opt{cfg->K, cfg->policy, cfg->alloc_mode, cfg->flags};
     capart_status rc = check_options(c, &opt);
     if (rc != CAPART_OK) return rc;
     if (cfg->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "serving runs heuristic modes");
@@ -2074,6 +2074,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     L.K = cfg->K;
     L.mode = cfg->alloc_mode;
     L.flags = cfg->flags;
+    L.edf = cfg->policy == CAPART_POLICY_EDF;
     L.threads = eval_threads(cfg->max_tasks, cfg->max_M);
     L.table_words = (int)(table_lds_bytes(cfg->max_tasks, cfg->max_M) / 4);
     L.form = c->tune.loop_form == 2 ? 2 : 1;

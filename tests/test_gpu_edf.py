@@ -167,3 +167,40 @@ def test_unknown_policy_is_rejected(eng):
     ts = workload.config_c1(n_sets=2)
     with pytest.raises(capart.CapartError):
         eng.solve(ts, 3, "BF_INA", policy=7)
+
+
+def test_server_matches_solve(eng):
+    """Queries served under EDF (continuous batching over several streams)
+    give the batch solve's results bit for bit."""
+    c5 = workload.config_c5(seed=103, n_queries=150)
+    want = eng.solve(c5, 4, "BF_INA", policy="EDF")
+    srv = capart.Server(eng.ctx, K=4, mode="BF_INA", max_tasks=64, max_M=108, policy="EDF")
+    rng = np.random.default_rng(3)
+    arrival = np.cumsum(rng.exponential(1e6 / 5000.0, c5.n_sets))
+    say(f"EDF serving: {c5.n_sets} queries")
+    mix, stats = srv.replay(c5, arrival)
+    srv.close()
+    assert stats["completed"] == c5.n_sets
+    same(mix, want, FIELDS, "EDF server")
+
+
+def test_tables_and_admissible_sizes_under_edf(eng):
+    from test_gpu_tables import tables_only
+    c2 = workload.subset(workload.config_c2(n_sets=2000), np.arange(100))
+    c3 = workload.subset(workload.config_c3(n_sets=2000), np.arange(40))
+    tt = tables_only(workload.with_time_tables(workload.concat([c2, c3]), seed=98))
+    adm = (1, 2) + tuple(range(4, 256, 4))
+    for mode in ("BF_INA", "SMS_ACT"):
+        say(f"EDF tables + admissible {mode}: {tt.n_sets} sets")
+        want = oracle.solve(tt, 4, mode, nthreads=THREADS, admissible=adm, policy="EDF")
+        same(eng.solve(tt, 4, mode, admissible=adm, policy="EDF"), want, FIELDS, f"EDF tables {mode}")
+    f4 = tables_only(workload.with_time_tables(workload.config_paper_fig4(sets_per_point=2), seed=99))
+    off = f4["set_offset"]
+    got = eng.alg1(f4, "BF_ACT", policy="EDF")
+    for s in range(f4.n_sets):
+        w = oracle.alg1(f4.set(s), "BF_ACT", policy="EDF")
+        a, b = int(off[s]), int(off[s + 1])
+        assert int(got["verdict"][s]) == w["verdict"] and int(got["tried"][s]) == w["tried"], s
+        if w["verdict"]:
+            assert np.array_equal(got["sizes"][a:a + w["k"]], w["sizes"]), s
+            assert np.array_equal(got["alloc"][a:b], w["alloc"]) and np.array_equal(got["R"][a:b], w["R"]), s
