@@ -6,7 +6,9 @@ benchmark's CPU-baseline leg, never by the engine.  The arithmetic lives in
 this module compiles it with gcc and marshals numpy arrays through ctypes.
 
 Modes: EXH (exhaustive allocation), BF_INA, BF_ACT, SMS_INA, SMS_ACT
-(heuristic allocation over each fixed partitioning).
+(heuristic allocation over each fixed partitioning).  Per-partition policy:
+FP_DM (fixed priority, deadline monotonic, exact response times) or EDF
+(processor-demand test).
 """
 from __future__ import annotations
 

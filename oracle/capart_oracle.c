@@ -24,6 +24,9 @@
  *      compute units, preemptive fixed priority, deadline-monotonic order by
  *      (D, T, index), exact response-time fixed point
  *        R = C_i + sum_{j in hp(i)} ceil(R / T_j) * C_j ,  R <= D_i;
+ *      or, with OR_FLAG_EDF, preemptive EDF on the same server: the
+ *      processor-demand criterion below the synchronous busy period, with
+ *      the limits stated at or_edf_part;
  *   4. Lemma 1 (necessary test): sum_i Cn_i(1)/T_i > M => unschedulable,
  *      evaluated as floor-Q32 utilisations so the rejection is sound;
  *   5. Lemma 2: smallest partition for one task, m_min = min{m : Cn(m) <= D};
