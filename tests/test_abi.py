@@ -125,3 +125,52 @@ def test_validate_time_tables_matches_oracle():
     t["table_offset"] = t["table_offset"].copy()
     t["table_offset"][7] = len(t["Cn_table"]) - 1             # set 7 runs past the tables
     assert capart.capart_validate(t, 3, "EXH")[7] == capart.CAPART_E_INVAL
+
+
+def _header_defines():
+    import re
+    out = {}
+    with open(os.path.join(ROOT, "include", "capart.h")) as f:
+        for line in f:
+            m = re.match(r"#define (CAPART_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", line)
+            if m:
+                out[m.group(1)] = int(m.group(2))
+    return out
+
+
+def test_header_constants_match_the_binding():
+    defs = _header_defines()
+    assert len(defs) >= 20
+    for name, value in defs.items():
+        if hasattr(capart, name):
+            assert getattr(capart, name) == value, name
+    for name in ("CAPART_POLICY_EDF", "CAPART_POLICY_FP_DM", "CAPART_E_AGAIN", "CAPART_FLAG_PER_SET_LAUNCH"):
+        assert name in defs and hasattr(capart, name), name
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """Every struct of the C ABI: size and field offsets as the C compiler
+    lays them out equal the ctypes mirrors of the binding."""
+    import subprocess
+    names = [n for n in dir(capart) if n.startswith("capart_") and isinstance(getattr(capart, n), type)
+             and issubclass(getattr(capart, n), ctypes.Structure)]
+    assert len(names) >= 9
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "capart.h"', "int main(void) {"]
+    for n in names:
+        lines.append(f'    printf("{n} size %zu\\n", sizeof({n}));')
+        for fname, _t in getattr(capart, n)._fields_:
+            lines.append(f'    printf("{n} {fname} %zu\\n", offsetof({n}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for n in names:
+        cls = getattr(capart, n)
+        assert got[(n, "size")] == ctypes.sizeof(cls), n
+        for fname, _t in cls._fields_:
+            assert got[(n, fname)] == getattr(cls, fname).offset, (n, fname)
