@@ -466,6 +466,9 @@ def main():
                 "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
                                      "final": ms_k["final"] / max(1, n_k["final"])},
                 "step_ms_with_kernel_events": ms_timed}
+        if pol == "EDF":
+            roof["note"] = ("EDF terms (members x density shortcut, busy-period steps and demand points) are priced "
+                            "at the fixed-priority term cost; each is a 64-bit division, so frac is a lower bound")
         if cb is not None:
             roof["oracle_plain_order_terms_per_eval"] = cb["terms"] / cb["evals"]
             roof["oracle_plain_order_tests_per_eval"] = cb["tests"] / cb["evals"]
