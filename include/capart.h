@@ -227,6 +227,10 @@ capart_status capart_destroy(capart_ctx *ctx);
 /* Message for the last failing call on ctx (or for capart_create when ctx is
  * NULL); never NULL; valid until the next call on ctx. */
 const char *capart_last_error(const capart_ctx *ctx);
+/* Hash (16 hex digits) of the kernel and host sources this library was built
+ * from; never NULL, static storage.  A caller that ships sources beside the
+ * library compares it with the sources' hash to refuse a stale build. */
+const char *capart_build_hash(void);
 
 /* Number of partitionings of M into at most K positive parts (host only). */
 capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count);

@@ -26,7 +26,7 @@ POLICIES = {"FP_DM": CAPART_POLICY_FP_DM, "EDF": CAPART_POLICY_EDF}
 CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
-EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_count_partitionings",
+EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_build_hash", "capart_count_partitionings",
            "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
@@ -118,6 +118,13 @@ def load_library():
         except ImportError:
             pass
         lib = C.CDLL(LIB_PATH)
+        lib.capart_build_hash.argtypes = []
+        lib.capart_build_hash.restype = C.c_char_p
+        built = lib.capart_build_hash().decode()
+        from . import build as _build
+        if os.path.isdir(_build.CSRC) and built != _build.source_hash():
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, sources "
+                               f"{_build.source_hash()}): rebuild it with __graft_entry__.build()")
         P = C.POINTER
         lib.capart_create.argtypes = [C.c_int, P(_vp)]
         lib.capart_destroy.argtypes = [_vp]
@@ -154,7 +161,7 @@ def load_library():
         lib.capart_count_work.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp, _vp]
         lib.capart_timing_read.argtypes = [_vp, _vp, _vp]
         for name in EXPORTS:
-            if name != "capart_last_error":
+            if name not in ("capart_last_error", "capart_build_hash"):
                 getattr(lib, name).restype = C.c_int32
         _lib = lib
     return _lib

@@ -643,6 +643,11 @@ capart_status capart_destroy(capart_ctx *c)
 
 const char *capart_last_error(const capart_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
+#ifndef CAPART_BUILD_HASH
+#define CAPART_BUILD_HASH "unknown"
+#endif
+const char *capart_build_hash(void) { return CAPART_BUILD_HASH; }
+
 capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count)
 {
     if (!count || M < 1 || M > CAPART_MAX_M || K < 1 || K > CAPART_MAX_K) return CAPART_E_INVAL;
