@@ -26,7 +26,7 @@
  *        R = C_i + sum_{j in hp(i)} ceil(R / T_j) * C_j ,  R <= D_i;
  *      or, with OR_FLAG_EDF, preemptive EDF on the same server: the
  *      processor-demand criterion below the synchronous busy period, with
- *      the limits stated at or_edf_part;
+ *      the density bound and the work limits stated at or_edf_part;
  *   4. Lemma 1 (necessary test): sum_i Cn_i(1)/T_i > M => unschedulable,
  *      evaluated as floor-Q32 utilisations so the rejection is sound;
  *   5. Lemma 2: smallest partition for one task, m_min = min{m : Cn(m) <= D};
@@ -60,10 +60,10 @@ enum { OR_EXH = 0, OR_BF_INA = 1, OR_BF_ACT = 2, OR_SMS_INA = 3, OR_SMS_ACT = 4 
 enum { OR_OK = 0, OR_E_INVAL = -1, OR_E_RANGE = -2 };
 #define OR_FLAG_NO_LEMMA1 1
 #define OR_FLAG_EDF 2     /* per-partition policy: EDF instead of fixed-priority DM */
-/* EDF test limits (part of the test's definition, identical in the engine):
+/* EDF work limits (part of the test's definition, identical in the engine):
  * busy-period iterations before the utilisation bound is used instead, and
- * absolute deadlines below the horizon beyond which a partition is declared
- * unschedulable */
+ * absolute deadlines below the horizon beyond which the exact demand check
+ * gives way to the sufficient fixed-priority test */
 #define OR_EDF_BP_STEPS 4096
 #define OR_EDF_ND_CAP 65536
 #define OR_MAXN 64
@@ -111,136 +111,15 @@ int64_t or_time(const int64_t *Cs, const int64_t *Cp, const int32_t *k, int i, i
     return conflict ? or_cc(&s, i, m) : or_cn(&s, i, m);
 }
 
-/* ---- 3'. one partition under preemptive EDF ---------------------------- */
-/* Processor-demand criterion for constrained-deadline sporadic tasks on one
- * server (Baruah, Rosier and Howell 1990): with total utilisation U <= 1, the
- * partition is schedulable iff at every absolute deadline d below the
- * synchronous busy period L the demand
- *     h(d) = sum_{j : D_j <= d} (floor((d - D_j) / T_j) + 1) * C_j
- * is at most d.  Checking deadlines beyond L changes nothing, so any horizon
- * H >= L gives the same answer.  Integer definition used here:
- *   1. floor-Q32 sum of C_j 2^32 / T_j above 2^32: U > 1, unschedulable;
- *   2. L = least fixed point of w = sum ceil(w / T_j) C_j, iterated from
- *      sum C_j; if it has not settled after OR_EDF_BP_STEPS iterations, H is
- *      the bound L <= sum C / (1 - U) taken with the ceil-Q32 utilisation
- *      Uq (H = ceil(sum C 2^32 / (2^32 - Uq)), needs Uq < 2^32), else
- *      (utilisation within n 2^-32 of 1 and no settled busy period) the
- *      partition is declared unschedulable;
- *   3. more than OR_EDF_ND_CAP absolute deadlines below H: unschedulable;
- *   4. otherwise schedulable iff h(d) <= d at every absolute deadline d < H.
- * Every job then completes within its deadline and within the busy period,
- * so the response time reported for each member is min(D_i, H); -1 for every
- * member of an unschedulable partition.  *U = the ceil-Q32 sum. */
-static int or_cmp_i64(const void *a, const void *b)
+/* ---- 3. fixed priority: exact response times in DM order ------------- */
+/* order[0..cnt) lists positions in mem[] by deadline-monotonic priority.
+ * R_out (indexed by task) gets the response time or -1; with early_exit the
+ * test stops at the first miss (the rest of R_out is left untouched).
+ * Returns 1 iff every task meets its deadline. */
+static int or_fp_part(const or_set *s, const int *mem, int cnt, const int64_t *C, const int *order, int early_exit,
+                      int64_t *R_out)
 {
-    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
-    return (x > y) - (x < y);
-}
-
-static int or_edf_part(const or_set *s, const int *mem, int cnt, const int64_t *C, int64_t *R_out,
-                       uint64_t *U)
-{
-    const u128 one = (u128)1 << 32;
-    u128 uf = 0, uc = 0;
-    i128 sumC = 0, w, H = 0;
-    int64_t nd = 0, *dl = NULL;
-    int a, j, step, settled = 0, feasible = 0;
-    for (a = 0; a < cnt; a++) {
-        u128 num = ((u128)C[a]) << 32, den = (u128)s->T[mem[a]];
-        uf += num / den;
-        uc += (num + den - 1) / den;
-        sumC += C[a];
-    }
-    if (uf > one) goto done;
-    /* the synchronous busy period */
-    w = sumC;
-    for (step = 0; step < OR_EDF_BP_STEPS; step++) {
-        i128 W = 0;
-        for (a = 0; a < cnt; a++) {
-            W += ((w + s->T[mem[a]] - 1) / s->T[mem[a]]) * C[a];
-            if (s->cnt) s->cnt->terms++;
-        }
-        if (W == w) { settled = 1; break; }
-        w = W;
-    }
-    if (settled) {
-        H = w;
-    } else if (uc < one) {
-        u128 den = one - uc;
-        H = (i128)((((u128)sumC << 32) + den - 1) / den);
-    } else {
-        goto done;
-    }
-    /* the absolute deadlines below H */
-    for (a = 0; a < cnt; a++) {
-        i128 D = s->D[mem[a]];
-        if (D < H) nd += (int64_t)((H - 1 - D) / s->T[mem[a]] + 1);
-        if (nd > OR_EDF_ND_CAP) goto done;
-    }
-    dl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd > 0 ? nd : 1));
-    nd = 0;
-    for (a = 0; a < cnt; a++)
-        for (w = s->D[mem[a]]; w < H; w += s->T[mem[a]]) dl[nd++] = (int64_t)w;
-    qsort(dl, (size_t)nd, sizeof(int64_t), or_cmp_i64);
-    /* the demand at each of them, in increasing order */
-    feasible = 1;
-    for (j = 0; j < nd && feasible; j++) {
-        i128 d = dl[j], h = 0;
-        for (a = 0; a < cnt; a++) {
-            int64_t D = s->D[mem[a]];
-            if (D <= d) h += ((d - D) / s->T[mem[a]] + 1) * C[a];
-            if (s->cnt) s->cnt->terms++;
-        }
-        if (h > d) feasible = 0;
-    }
-    free(dl);
-done:
-    if (R_out)
-        for (a = 0; a < cnt; a++) {
-            int64_t D = s->D[mem[a]];
-            R_out[mem[a]] = feasible ? (H < D ? (int64_t)H : D) : -1;
-        }
-    if (feasible && U) *U = (uint64_t)uc;
-    return feasible;
-}
-
-/* ---- 2+3. one partition: conflicts, DM order, exact RTA --------------- */
-/* mem[0..cnt) are task indices.  R_out (indexed by task) gets the response
- * time or -1; with early_exit the test stops at the first miss (the rest of
- * R_out is left untouched).  Returns 1 iff every task meets its deadline and
- * then *U = sum ceil(C_i 2^32 / T_i). */
-static int or_eval_part(const or_set *s, const int *mem, int cnt, int m, int early_exit,
-                        int64_t *R_out, uint64_t *U)
-{
-    int order[OR_MAXN];
-    int64_t C[OR_MAXN];
-    int a, b, t, u;
-    int feasible = 1;
-    if (s->cnt) s->cnt->tests++;
-    for (a = 0; a < cnt; a++) {
-        int same = 0;
-        for (b = 0; b < cnt; b++)
-            if (s->type[mem[b]] == s->type[mem[a]]) same++;
-        /* "same" counts the task itself: a conflict needs one other task */
-        C[a] = (same >= 2) ? or_cc(s, mem[a], m) : or_cn(s, mem[a], m);
-        order[a] = a;
-    }
-    if (s->edf) return or_edf_part(s, mem, cnt, C, R_out, U);
-    /* deadline-monotonic priority: (D, T, index) ascending; insertion sort */
-    for (a = 1; a < cnt; a++) {
-        int x = order[a];
-        b = a - 1;
-        while (b >= 0) {
-            int y = order[b];
-            int64_t dx = s->D[mem[x]], dy = s->D[mem[y]];
-            int64_t tx = s->T[mem[x]], ty = s->T[mem[y]];
-            int later = (dy > dx) || (dy == dx && (ty > tx || (ty == tx && mem[y] > mem[x])));
-            if (!later) break;
-            order[b + 1] = y;
-            b--;
-        }
-        order[b + 1] = x;
-    }
+    int t, u, feasible = 1;
     for (t = 0; t < cnt; t++) {
         int pi = order[t], i = mem[pi];
         i128 R = C[pi], W;
@@ -264,6 +143,157 @@ static int or_eval_part(const or_set *s, const int *mem, int cnt, int m, int ear
             if (early_exit) return 0;
         }
     }
+    return feasible;
+}
+
+/* ---- 3'. one partition under preemptive EDF ---------------------------- */
+/* Processor-demand criterion for constrained-deadline sporadic tasks on one
+ * server (Baruah, Rosier and Howell 1990): with total utilisation U <= 1, the
+ * partition is schedulable iff at every absolute deadline d below the
+ * synchronous busy period L the demand
+ *     h(d) = sum_{j : D_j <= d} (floor((d - D_j) / T_j) + 1) * C_j
+ * is at most d.  Checking deadlines beyond L changes nothing, so any horizon
+ * H >= L gives the same answer.  Integer definition used here, in order:
+ *   1. floor-Q32 sum of C_j 2^32 / T_j above 2^32: U > 1, unschedulable;
+ *   2. ceil-Q32 density sum of C_j 2^32 / D_j at most 2^32: density at most 1,
+ *      which is sufficient for EDF (h(t) <= t at every t), schedulable;
+ *   3. the horizon: L = least fixed point of w = sum ceil(w / T_j) C_j,
+ *      iterated from sum C_j; if it has not settled after OR_EDF_BP_STEPS
+ *      iterations, H is the bound L <= sum C / (1 - U) taken with the ceil-Q32
+ *      utilisation Uq (H = ceil(sum C 2^32 / (2^32 - Uq)), needs Uq < 2^32),
+ *      else H is undetermined;
+ *   4. H determined and at most OR_EDF_ND_CAP absolute deadlines below it:
+ *      schedulable iff h(d) <= d at every absolute deadline d < H (exact);
+ *   5. otherwise (a work limit reached): schedulable iff every member passes
+ *      the fixed-priority deadline-monotonic response-time test.  That is
+ *      sufficient for EDF (EDF is optimal on one preemptive server, so a set
+ *      that DM schedules, EDF schedules), so the answer is never optimistic
+ *      and EDF verdicts always dominate fixed-priority ones.
+ * Every job of a schedulable partition completes within its deadline and
+ * within the longest (synchronous) busy period, so the response time reported
+ * for each member is min(D_i, H) where H is determined, D_i where it is not;
+ * -1 for every member of an unschedulable partition.  *U = the ceil-Q32 sum. */
+static int or_cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int or_edf_part(const or_set *s, const int *mem, int cnt, const int64_t *C, const int *order,
+                       int64_t *R_out, uint64_t *U)
+{
+    const u128 one = (u128)1 << 32;
+    u128 uf = 0, uc = 0, dc = 0;
+    i128 sumC = 0, w, H = 0;
+    int64_t nd = 0, *dl = NULL;
+    int a, j, step, settled = 0, have_h = 0, feasible = 0, decided = 0;
+    for (a = 0; a < cnt; a++) {
+        u128 num = ((u128)C[a]) << 32, den = (u128)s->T[mem[a]], dd = (u128)s->D[mem[a]];
+        uf += num / den;
+        uc += (num + den - 1) / den;
+        dc += (num + dd - 1) / dd;
+        sumC += C[a];
+    }
+    if (uf > one) goto done; /* 1 */
+    if (dc <= one) { feasible = 1; decided = 1; } /* 2 */
+    /* 3: the synchronous busy period */
+    w = sumC;
+    for (step = 0; step < OR_EDF_BP_STEPS; step++) {
+        i128 W = 0;
+        for (a = 0; a < cnt; a++) {
+            W += ((w + s->T[mem[a]] - 1) / s->T[mem[a]]) * C[a];
+            if (s->cnt) s->cnt->terms++;
+        }
+        if (W == w) { settled = 1; break; }
+        w = W;
+    }
+    if (settled) {
+        H = w;
+        have_h = 1;
+    } else if (uc < one) {
+        u128 den = one - uc;
+        H = (i128)((((u128)sumC << 32) + den - 1) / den);
+        have_h = 1;
+    }
+    if (decided) goto done;
+    /* 4: the absolute deadlines below H, if there are not too many */
+    if (have_h) {
+        i128 cntd = 0;
+        for (a = 0; a < cnt && cntd <= OR_EDF_ND_CAP; a++) {
+            i128 D = s->D[mem[a]];
+            if (D < H) cntd += (H - 1 - D) / s->T[mem[a]] + 1;
+        }
+        nd = cntd > OR_EDF_ND_CAP ? OR_EDF_ND_CAP + 1 : (int64_t)cntd;
+    }
+    if (!have_h || nd > OR_EDF_ND_CAP) {
+        feasible = or_fp_part(s, mem, cnt, C, order, 1, NULL); /* 5 */
+        goto done;
+    }
+    dl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd > 0 ? nd : 1));
+    nd = 0;
+    for (a = 0; a < cnt; a++)
+        for (w = s->D[mem[a]]; w < H; w += s->T[mem[a]]) dl[nd++] = (int64_t)w;
+    qsort(dl, (size_t)nd, sizeof(int64_t), or_cmp_i64);
+    /* the demand at each of them, in increasing order */
+    feasible = 1;
+    for (j = 0; j < nd && feasible; j++) {
+        i128 d = dl[j], h = 0;
+        for (a = 0; a < cnt; a++) {
+            int64_t D = s->D[mem[a]];
+            if (D <= d) h += ((d - D) / s->T[mem[a]] + 1) * C[a];
+            if (s->cnt) s->cnt->terms++;
+        }
+        if (h > d) feasible = 0;
+    }
+    free(dl);
+done:
+    if (R_out)
+        for (a = 0; a < cnt; a++) {
+            int64_t D = s->D[mem[a]];
+            R_out[mem[a]] = feasible ? ((have_h && H < D) ? (int64_t)H : D) : -1;
+        }
+    if (feasible && U) *U = (uint64_t)uc;
+    return feasible;
+}
+
+/* ---- 2+3. one partition: conflicts, DM order, the policy's test -------- */
+/* mem[0..cnt) are task indices.  R_out (indexed by task) gets the response
+ * time or -1; with early_exit a fixed-priority test stops at the first miss
+ * (the rest of R_out is left untouched).  Returns 1 iff every task meets its
+ * deadline and then *U = sum ceil(C_i 2^32 / T_i). */
+static int or_eval_part(const or_set *s, const int *mem, int cnt, int m, int early_exit,
+                        int64_t *R_out, uint64_t *U)
+{
+    int order[OR_MAXN];
+    int64_t C[OR_MAXN];
+    int a, b;
+    int feasible;
+    if (s->cnt) s->cnt->tests++;
+    for (a = 0; a < cnt; a++) {
+        int same = 0;
+        for (b = 0; b < cnt; b++)
+            if (s->type[mem[b]] == s->type[mem[a]]) same++;
+        /* "same" counts the task itself: a conflict needs one other task */
+        C[a] = (same >= 2) ? or_cc(s, mem[a], m) : or_cn(s, mem[a], m);
+        order[a] = a;
+    }
+    /* deadline-monotonic priority: (D, T, index) ascending; insertion sort */
+    for (a = 1; a < cnt; a++) {
+        int x = order[a];
+        b = a - 1;
+        while (b >= 0) {
+            int y = order[b];
+            int64_t dx = s->D[mem[x]], dy = s->D[mem[y]];
+            int64_t tx = s->T[mem[x]], ty = s->T[mem[y]];
+            int later = (dy > dx) || (dy == dx && (ty > tx || (ty == tx && mem[y] > mem[x])));
+            if (!later) break;
+            order[b + 1] = y;
+            b--;
+        }
+        order[b + 1] = x;
+    }
+    if (s->edf) return or_edf_part(s, mem, cnt, C, order, R_out, U);
+    feasible = or_fp_part(s, mem, cnt, C, order, early_exit, R_out);
     if (feasible && U) {
         u128 acc = 0;
         for (a = 0; a < cnt; a++) {

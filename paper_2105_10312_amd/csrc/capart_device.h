@@ -323,29 +323,31 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
 // EDF on one partition (Section "Schedulability test" admits any policy with
 // an exact test): the processor-demand criterion (Baruah, Rosier and Howell
 // 1990) for constrained deadlines, walked with Zhang and Burns' quick
-// processor-demand analysis (QPA, 2009).  Integer definition:
+// processor-demand analysis (QPA, 2009).  Integer definition, in order:
 //   1. floor-Q32 utilisation above 2^32: unschedulable (U > 1);
-//   2. horizon H = the synchronous busy period L (least fixed point of
+//   2. ceil-Q32 density sum ceil(C 2^32 / D) at most 2^32: schedulable
+//      (density at most 1 is sufficient for EDF);
+//   3. horizon H = the synchronous busy period L (least fixed point of
 //      w = sum ceil(w/T_j) C_j, iterated from sum C_j) if the iteration settles
 //      within EDF_BP_STEPS steps, else the bound ceil(sum C 2^32 / (2^32 - Uq))
-//      >= L with the ceil-Q32 utilisation Uq (Uq >= 2^32: unschedulable);
-//   3. more than EDF_ND_CAP absolute deadlines below H: unschedulable;
-//   4. else schedulable iff h(d) <= d at every absolute deadline d < H, with
-//      h(t) = sum_{D_j <= t} (floor((t - D_j)/T_j) + 1) C_j.
+//      >= L with the ceil-Q32 utilisation Uq, else (Uq >= 2^32) undetermined;
+//   4. H determined with at most EDF_ND_CAP absolute deadlines below it:
+//      schedulable iff h(d) <= d at every absolute deadline d < H, with
+//      h(t) = sum_{D_j <= t} (floor((t - D_j)/T_j) + 1) C_j;
+//   5. otherwise (a work limit reached): schedulable iff every member passes
+//      the fixed-priority deadline-monotonic response-time test, which is
+//      sufficient for EDF (members are walked in rank order, which is DM order).
 // Step 4 walks t down from the last deadline below H: to h(t) while h(t) < t,
 // else to the previous deadline, until h(t) <= min D (schedulable) or h(t) > t
 // (a miss).  h is a non-decreasing step function that changes only at
 // deadlines, so every skipped deadline d has h(d) <= d, and the walk moves
 // below at least one deadline every two points: at most 2 ND + 1 points.
-// get(j, C, T, D) reads member j.  Returns ok, H (when ok: every job of the
-// partition completes by min(D_i, H)) and the terms evaluated (members x
-// busy-period steps and demand points).  64-bit bounds: C < 2^31 and
-// T, D < 2^31; w < 2^50 over the busy-period steps (U < 1 + 2^-26); H < 2^57.
-// Shortcut when H is not wanted: density sum ceil(C 2^32 / D) <= 2^32 and
-// Uq < 2^32, with at most EDF_ND_CAP deadlines below the utilisation bound
-// Hb, answer schedulable at once.  That is the definition's answer: density
-// at most 1 is sufficient for EDF (h(t) <= t everywhere), the defined H
-// (L, or Hb itself) is at most Hb, so its deadline count is within the limit.
+// get(j, C, T, D) reads member j.  Returns ok, H (0 where undetermined or not
+// wanted; when ok every job of the partition completes by min(D_i, H)) and
+// the terms evaluated (members x busy-period steps, demand points and DM
+// fixed-point steps).  64-bit bounds: C < 2^31 and T, D < 2^31; w < 2^50 over
+// the busy-period steps (U < 1 + 2^-26); H < 2^57 (a larger bound puts more
+// than 2^25 deadlines below it, so H is not needed: step 5 decides).
 // Kept out of line (one call on the EDF side of each test) so that the
 // runtime-policy kernels keep most of their registers.
 constexpr int EDF_BP_STEPS = 4096;
@@ -364,7 +366,7 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     const uint32_t cnt = (uint32_t)mpopc(S);
     EdfRes res{0ull, 0u, false};
     uint64_t uf = 0, uc = 0, dc = 0, sumC = 0;
-    bool dense = false;  // some C_j / D_j above 1 (no density shortcut)
+    bool dense = false;  // some C_j / D_j above 1
     uint32_t dmin = 0xFFFFFFFFu;
     for (MT h = S; h; h &= h - MT(1)) {
         uint32_t C, T, D;
@@ -374,32 +376,19 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
         uf += q;
         if (uf > ONE) return res;
         uc += q + (num != q * (uint64_t)T ? 1ull : 0ull);
-        if (!need_h) {
-            const uint64_t qd = D == T ? q : num / D;
-            if (qd > ONE) dense = true;
-            else dc += qd + (num != qd * (uint64_t)D ? 1ull : 0ull);
-        }
+        const uint64_t qd = D == T ? q : num / D;
+        if (qd > ONE) dense = true;
+        else dc += qd + (num != qd * (uint64_t)D ? 1ull : 0ull);
         sumC += C;
         dmin = min(dmin, D);
     }
-    if (!need_h && !dense && dc <= ONE && uc < ONE) {
-        const uint64_t den = ONE - uc, a = sumC / den, r = sumC % den;
-        if (a < (1ull << 24)) {
-            const uint64_t Hb = (a << 32) + (((r << 32) + den - 1ull) / den);
-            uint64_t nd = 0;
-            for (MT h = S; h; h &= h - MT(1)) {
-                uint32_t C, T, D;
-                get(mctz(h), C, T, D);
-                if (D < Hb) nd += (Hb - 1ull - D) / T + 1ull;
-            }
-            res.terms += cnt;
-            if (nd <= EDF_ND_CAP) {
-                res.ok = true;
-                return res;
-            }
-        }
+    res.terms += cnt;
+    const bool density_ok = !dense && dc <= ONE;
+    if (density_ok && !need_h) {
+        res.ok = true;
+        return res;
     }
-    uint64_t w = sumC, H;
+    uint64_t w = sumC, H = 0;
     bool settled = false;
     for (int step = 0; step < EDF_BP_STEPS; step++) {
         uint64_t W = 0;
@@ -414,21 +403,54 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     }
     if (settled) {
         H = w;
-    } else {
-        if (uc >= ONE) return res;
+    } else if (uc < ONE) {
         const uint64_t den = ONE - uc, a = sumC / den, r = sumC % den;
-        // H >= 2^56 puts more than 2^25 deadlines of any member below it
-        if (a >= (1ull << 24)) return res;
-        H = (a << 32) + (((r << 32) + den - 1ull) / den);
+        if (a < (1ull << 24)) H = (a << 32) + (((r << 32) + den - 1ull) / den);
     }
-    uint64_t nd = 0;
-    for (MT h = S; h; h &= h - MT(1)) {
-        uint32_t C, T, D;
-        get(mctz(h), C, T, D);
-        if (D < H) nd += (H - 1ull - D) / T + 1ull;
-    }
-    if (nd > EDF_ND_CAP) return res;
     res.H = H;
+    if (density_ok) {
+        res.ok = true;
+        return res;
+    }
+    uint64_t nd = EDF_ND_CAP + 1ull;
+    if (H != 0ull) {
+        nd = 0;
+        for (MT h = S; h; h &= h - MT(1)) {
+            uint32_t C, T, D;
+            get(mctz(h), C, T, D);
+            if (D < H) nd += (H - 1ull - D) / T + 1ull;
+        }
+    }
+    if (nd > EDF_ND_CAP) {
+        // step 5: deadline-monotonic response times, members in rank order
+        for (MT rem = S; rem; rem &= rem - MT(1)) {
+            const int r = mctz(rem);
+            uint32_t Cr, Tr, Dr;
+            get(r, Cr, Tr, Dr);
+            const MT hp = S & below<MT>(r);
+            uint64_t R = Cr;
+            for (MT h = hp; h; h &= h - MT(1)) {
+                uint32_t C, T, D;
+                get(mctz(h), C, T, D);
+                R += C;
+            }
+            if (R > Dr) return res;
+            for (;;) {
+                uint64_t W = Cr;
+                for (MT h = hp; h; h &= h - MT(1)) {
+                    uint32_t C, T, D;
+                    get(mctz(h), C, T, D);
+                    W += ((R + T - 1ull) / T) * C;
+                    if (W > Dr) return res;
+                }
+                res.terms += 1u + (uint32_t)mpopc(hp);
+                if (W == R) break;
+                R = W;
+            }
+        }
+        res.ok = true;
+        return res;
+    }
     if (H <= dmin) {
         res.ok = true;
         return res;
@@ -599,7 +621,8 @@ __device__ uint32_t rta_one(const SetLDS &L, const Tables &tb, int m, int r, MT 
 
 // Reported response time of rank r in partition Sp (m units, conflict mask
 // cm), 0 on a miss: the response-time fixed point under fixed priority; under
-// EDF min(D_r, H) for a schedulable partition (H bounds every busy period).
+// EDF min(D_r, H) for a schedulable partition (H bounds every busy period),
+// D_r where H is undetermined.
 template <typename MT, typename TY = NoTally>
 __device__ uint32_t resp_one(const SetLDS &L, const Tables &tb, int m, int r, MT Sp, MT cm)
 {
@@ -607,7 +630,7 @@ __device__ uint32_t resp_one(const SetLDS &L, const Tables &tb, int m, int r, MT
         NoTally nt;
         uint64_t H = 0;
         if (!edf_part<MT>(L, tb, Sp, m, cm, nt, &H)) return 0u;
-        return (uint32_t)min(H, (uint64_t)L.D[r]);
+        return H ? (uint32_t)min(H, (uint64_t)L.D[r]) : L.D[r];
     }
     return rta_one<MT>(L, tb, m, r, Sp & below<MT>(r), cm);
 }
@@ -788,10 +811,14 @@ __device__ bool wave_test_from(const SetLDS &L, const Tables &tb, uint64_t S, in
 {
     const int lane = threadIdx.x & 63;
     const int n = tb.n;
-    if (use_edf<TY>(L)) {  // whole-set test, the same in every lane
-        NoTally nt;
-        if (lane == 0) ty.test();
-        return edf_part<uint64_t>(L, tb, S, m, cm, nt, nullptr);
+    if (use_edf<TY>(L)) {  // whole-set test, the same in every lane, tallied once
+        Tally one;
+        const bool ok = edf_part<uint64_t>(L, tb, S, m, cm, one, nullptr);
+        if (lane == 0) {
+            ty.test();
+            ty.term((uint32_t)one.terms);
+        }
+        return ok;
     }
     bool fail = false;
     if (((S >> lane) & 1ull) && lane >= first) {

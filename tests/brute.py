@@ -186,3 +186,46 @@ def whole_gpu(task):
         prio[a] = r
     resp = simulate_fp(C, T, D, prio)
     return all(r >= 0 for r in resp), resp
+
+
+def simulate_long(C, T, D, policy, horizon):
+    """Unit-step preemptive schedule of one server from a synchronous release
+    with periodic arrivals over [0, horizon), for long horizons (per-task job
+    queues, O(n) per step).  policy "EDF": earliest absolute deadline first,
+    ties to the lower task index; "DM": fixed priority by (D, T, index).
+    Returns (first missed absolute deadline or None, first-job completion
+    times (None if not completed), the first instant t > 0 by which all work
+    released before t is done (the synchronous busy period) or None)."""
+    from collections import deque
+    n = len(C)
+    queues = [deque() for _ in range(n)]  # [absolute deadline, remaining]
+    dm = sorted(range(n), key=lambda i: (D[i], T[i], i))
+    first_done = [None] * n
+    jobs_done = [0] * n
+    idle = None
+    for t in range(horizon):
+        if idle is None and t > 0 and not any(queues):
+            idle = t  # all work released before t is done
+        for i in range(n):
+            if t % T[i] == 0:
+                queues[i].append([t + D[i], C[i]])
+        for i in range(n):
+            if queues[i] and queues[i][0][0] <= t:
+                return queues[i][0][0], first_done, idle
+        if policy == "EDF":
+            run = None
+            for i in range(n):
+                if queues[i] and (run is None or queues[i][0][0] < queues[run][0][0]):
+                    run = i
+        else:
+            run = next((i for i in dm if queues[i]), None)
+        if run is None:
+            continue
+        job = queues[run][0]
+        job[1] -= 1
+        if job[1] == 0:
+            queues[run].popleft()
+            if jobs_done[run] == 0:
+                first_done[run] = t + 1
+            jobs_done[run] += 1
+    return None, first_done, idle

@@ -53,9 +53,12 @@ def mixed():
 def limit_sets():
     """Sets at the EDF test's stated limits, as one-unit partitions with
     sequential times (k = 1000): a busy period that takes the utilisation
-    bound, deadline counts either side of the limit, utilisation exactly 1
-    (implicit, and constrained but still schedulable), just above 1, and a
-    single task meeting or missing its deadline."""
+    bound, deadline counts either side of the limit (density at most 1
+    deciding first), utilisation exactly 1 (implicit, and constrained but
+    still schedulable), just above 1, a single task meeting or missing its
+    deadline, and three constrained-deadline sets beyond the deadline limit
+    that the fixed-priority fallback decides (schedulable, a true miss, and
+    the fallback's pessimism)."""
     cases = [
         ([9_999, 5_000], [10_000, 1_000_000_000], [10_000, 1_000_000_000]),
         ([10_000, 5_000], [10_000, 1_000_000_000], [10_000, 1_000_000_000]),
@@ -66,6 +69,9 @@ def limit_sets():
         ([2, 3, 4], [4, 6, 12], [4, 6, 12]),
         ([7], [100], [7]),
         ([7], [100], [6]),
+        ([1, 300_000], [4, 1 << 30], [1, 600_000]),
+        ([1, 200_000], [2, 1 << 30], [2, 399_998]),
+        ([1, 200_000], [2, 1 << 30], [2, 399_999]),
     ]
     off = np.concatenate([[0], np.cumsum([len(c[0]) for c in cases])]).astype(np.int64)
     cat = lambda i, dt: np.concatenate([np.asarray(c[i], dt) for c in cases])
@@ -115,7 +121,7 @@ def test_limits_match_oracle(eng):
     want = oracle.solve(ts, 1, "BF_INA", policy="EDF")
     got = eng.solve(ts, 1, "BF_INA", policy="EDF")
     same(got, want, FIELDS, "EDF limits")
-    assert list(got["verdict_1g"]) == [1, 0, 1, 0, 1, 1, 0, 1, 0]
+    assert list(got["verdict_1g"]) == [1, 0, 1, 1, 1, 1, 0, 1, 0, 1, 0, 0]
 
 
 def test_alg1_matches_oracle(eng):

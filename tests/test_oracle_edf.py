@@ -10,6 +10,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+import brute
 import oracle
 from paper_2105_10312_amd import workload
 
@@ -134,22 +135,67 @@ def test_single_task_is_its_own_test():
         assert R == ([C] if C <= D else [-1])
 
 
-def test_deadline_limit_is_applied():
-    """Two tasks, U about 0.5, whose busy period (about 2 C_B) holds about C_B
-    deadlines of the short task: schedulable below the deadline limit,
-    declared unschedulable above it (the stated pessimism of the definition)."""
-    for CB, want in ((50_000, True), (200_000, False)):
-        C, T = [1, CB], [2, 1 << 30]
-        D = [2, 1 << 30]
-        w = sum(C)
-        while True:
-            W = sum(-(-w // t) * c for c, t in zip(C, T))
-            if W == w:
-                break
-            w = W
-        nd = sum((w - 1 - d) // t + 1 for d, t in zip(D, T) if d < w)
-        assert (nd <= oracle.EDF_ND_CAP) == want
-        assert edf_1g(C, T, D)[0] == want
+def deadlines_below(T, D, H):
+    return sum((H - 1 - d) // t + 1 for d, t in zip(D, T) if d < H)
+
+
+# (C, T, D, exact EDF verdict, DM verdict): two-task partitions whose demand
+# check would need more than EDF_ND_CAP absolute deadlines below the busy period
+LIMIT_CASES = [
+    ([1, 200_000], [2, 1 << 30], [2, 1 << 30], True, True),  # implicit deadlines, U = 1/2 + 200000/2^30
+    ([1, 300_000], [4, 1 << 30], [1, 600_000], True, True),  # density 1.5, DM meets every deadline
+    ([1, 200_000], [2, 1 << 30], [2, 399_998], False, False),  # EDF misses at t = 399998
+    ([1, 200_000], [2, 1 << 30], [2, 399_999], True, False),  # EDF meets every deadline, DM does not
+]
+
+
+@pytest.mark.parametrize("case", range(len(LIMIT_CASES)))
+def test_deadline_limit_cases(case):
+    """Beyond the deadline-count limit the definition falls back on the
+    fixed-priority DM test, which is sufficient for EDF.  Pinned by unit-step
+    simulation of the first busy period (brute.simulate_long) under EDF and
+    under DM, and by Liu and Layland's exact U <= 1 for implicit deadlines:
+    density at most 1 decides before any limit applies; otherwise the verdict
+    is DM's, which equals the exact EDF answer except in the last case (the
+    definition's one pessimism: EDF would meet every deadline there)."""
+    C, T, D, edf_exact, dm_ok = LIMIT_CASES[case]
+    horizon = 900_000
+    miss, _, L = brute.simulate_long(C, T, D, "EDF", horizon)
+    assert (miss is None) == edf_exact
+    dm_miss, dm_first, _ = brute.simulate_long(C, T, D, "DM", max(D) + 1 if max(D) < horizon else horizon)
+    assert (dm_miss is None and all(f is not None and f <= d for f, d in zip(dm_first, D))) == dm_ok
+    if case == 0:
+        assert sum(Fraction(c, t) for c, t in zip(C, T)) <= 1
+    L = L if L is not None else 400_000  # the simulated schedules all have the busy period 400000
+    assert deadlines_below(T, D, L) > oracle.EDF_ND_CAP
+    ok, R = edf_1g(C, T, D)
+    assert ok == dm_ok
+    if ok:
+        # every job ends by its deadline and inside the synchronous busy period
+        assert R == [min(d, L) for d in D]
+    else:
+        assert R == [-1, -1]
+
+
+def test_limits_keep_edf_above_fixed_priority():
+    """On partitions that reach the deadline-count limit, EDF's verdict is never
+    below fixed priority's, and a schedulable verdict is confirmed by EDF
+    simulation of the first busy period."""
+    rng = np.random.default_rng(91)
+    seen = 0
+    for _ in range(6):
+        t0 = int(rng.integers(2, 5))
+        cb = int(rng.integers(150_000, 250_000))
+        db = int(rng.integers(cb + cb // t0, 3 * cb))
+        C, T, D = [1, cb], [t0, 1 << 30], [int(rng.integers(1, t0 + 1)), db]
+        ok_edf, _ = edf_1g(C, T, D)
+        fp = oracle.solve(one_partition(C, T, D), 1, "BF_INA")
+        assert ok_edf >= bool(fp["verdict_1g"][0])
+        miss, _, L = brute.simulate_long(C, T, D, "EDF", 2 * db)
+        if ok_edf:
+            assert miss is None
+        seen += L is not None and deadlines_below(T, D, L) > oracle.EDF_ND_CAP
+    assert seen >= 3
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
