@@ -129,6 +129,20 @@ def test_golden_merge_example(eng):
         assert list(got["sizes"][a:a + 3]) == g["w1_cases"]["M8"]["sizes"]
 
 
+def test_golden_orders_merge_different_partners(eng):
+    """The hand-derived set on which orders > and >> merge different partners."""
+    with open(os.path.join(HERE, "golden", "w6_alg1_orders.json")) as f:
+        g = json.load(f)
+    ts = as_batch([g["set"]])
+    for mode in MODES:
+        got = run_both(eng, ts, mode, "w6")
+        want = g["BF_INA" if mode.startswith("BF") else "SMS_INA"]
+        assert int(got["verdict"][0]) == want["verdict"]
+        assert list(got["sizes"][:got["nparts"][0]]) == want["sizes"], mode
+        assert list(got["alloc"]) == want["alloc"] and list(got["R"]) == want["R"], mode
+        assert int(got["tried"][0]) == want["tried"] and int(got["merged"][0]) == want["merged"], mode
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_random_tiny_sets(eng, mode):
     ts = as_batch(random_tiny(11, 3000))

@@ -248,6 +248,46 @@ def test_flags_and_per_set_launch(eng):
     assert np.array_equal(skip["R"], base["R"]) and np.array_equal(skip["pidx"], base["pidx"])
 
 
+@pytest.mark.parametrize("policy", ["FP_DM", "EDF"])
+@pytest.mark.parametrize("mode", ["EXH", "BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
+def test_per_set_launch_matches_oracle(eng, mode, policy):
+    """The plain one-launch-sequence-per-set path against the oracle, field by
+    field: exhaustive on the n=5, M=8 sets, the heuristics on n=10, M=80 sets
+    and on uneven sets with constrained deadlines."""
+    if mode == "EXH":
+        batches = [(workload.config_c1(n_sets=40, seed=21), 3)]
+    else:
+        c3 = workload.config_c3(n_sets=400, seed=22)
+        small = np.nonzero(c3.sizes() <= 20)[0][:30]
+        batches = [(workload.subset(workload.config_c2(n_sets=300, seed=23), np.arange(30)), 4),
+                   (workload.subset(c3, small), 4)]
+    for ts, K in batches:
+        say(f"per-set launch {mode} {policy}: {ts.n_sets} sets")
+        got = eng.solve(ts, K, mode, flags=capart.CAPART_FLAG_PER_SET_LAUNCH, policy=policy)
+        want = oracle.solve(ts, K, mode, nthreads=THREADS, policy=policy)
+        assert_same(got, want, ts, f"per-set {mode} {policy}")
+
+
+def test_golden_bf_and_sms_rank_differently(eng):
+    """The hand-derived partitioning on which BF and SMS place a task on
+    different parts: the one-partitioning allocation and the solve restricted
+    to that partitioning by admissible sizes."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "w5_bf_vs_sms.json")) as f:
+        w = json.load(f)
+    task = dict(w["set"])
+    ts = as_batch([task])
+    for mode, alloc in w["alloc"].items():
+        found, al, mx, sm = eng.allocate(task, w["partitioning"], 2, mode)[:4]
+        assert found and al.tolist() == alloc, mode
+        got = eng.solve(ts, 2, mode, admissible=tuple(w["admissible"]))
+        assert int(got["pidx"][0]) == w["pidx"] and got["alloc"].tolist() == alloc, mode
+        assert got["R_1g"].tolist() == w["R_1g"] and int(got["n_evals"][0]) == w["n_evals"]
+        if mode in w["key"]:
+            assert [mx, sm] == w["key"][mode] and got["R"].tolist() == w["R"][mode], mode
+            assert [int(got["maxU"][0]), int(got["sumU"][0])] == w["key"][mode], mode
+
+
 def test_async_device_path_matches_host_path(eng):
     import torch
     ts = workload.subset(workload.config_c2(n_sets=500), np.arange(200))

@@ -35,6 +35,20 @@ def test_merge_example():
                 assert r["tried"] == case["tried"] and r["merged"] == case["merged"]
 
 
+def test_orders_merge_different_partners():
+    """A set on which order > (lower utilisation of the union) and order >>
+    (fewer units of the valid merge) merge the operand with different partners
+    (hand-derived, tests/golden/w6_alg1_orders.json)."""
+    g = load("w6_alg1_orders.json")
+    for variant in ("INA", "ACT"):  # ACT forbids no pair of this set beforehand
+        for order in ("BF", "SMS"):
+            want = g[f"{order}_INA"]
+            r = oracle.alg1(g["set"], f"{order}_{variant}")
+            assert r["verdict"] == want["verdict"] and list(r["sizes"]) == want["sizes"], order
+            assert list(r["alloc"]) == want["alloc"] and list(r["R"]) == want["R"], order
+            assert r["tried"] == want["tried"] and r["merged"] == want["merged"], order
+
+
 def test_worked_example_m7_m8():
     w1 = load("w1_worked_example.json")
     g = load("w4_alg1_merge_example.json")["w1_cases"]

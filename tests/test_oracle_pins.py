@@ -95,6 +95,25 @@ def test_w1_heuristic_traces():
         assert int(r["pidx"][0]) == 9 and r["alloc"].tolist() == [0, 1, 2]
 
 
+def test_w5_bf_and_sms_rank_differently():
+    """A fixed partitioning on which the two orders of H(pi) place a task on
+    different parts (hand-derived, tests/golden/w5_bf_vs_sms.json): BF's lower
+    merged utilisation puts b beside a, SMS's fewest units puts b alone."""
+    w = load("w5_bf_vs_sms.json")
+    t = as_task(w["set"])
+    for mode, alloc in w["alloc"].items():
+        assert oracle.heuristic(t, w["partitioning"], mode).tolist() == alloc, mode
+    for mode in ("BF_INA", "SMS_INA"):
+        f, R, mx, sm = oracle.eval_triple(t, w["partitioning"], w["alloc"][mode])
+        assert f and R.tolist() == w["R"][mode] and [mx, sm] == w["key"][mode], mode
+        r = oracle.solve(as_batch([t]), 2, mode, admissible=tuple(w["admissible"]))
+        assert int(r["verdict"][0]) == 1 and int(r["pidx"][0]) == w["pidx"] and int(r["n_evals"][0]) == w["n_evals"]
+        assert r["alloc"].tolist() == w["alloc"][mode] and r["R"].tolist() == w["R"][mode], mode
+        assert [int(r["maxU"][0]), int(r["sumU"][0])] == w["key"][mode], mode
+        assert r["R_1g"].tolist() == w["R_1g"]
+    assert oracle.forbidden(t, 0, 1)
+
+
 def test_w2_rta_textbook():
     w = load("w2_rta_textbook.json")
     t = as_task(w["set"])
