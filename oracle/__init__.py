@@ -6,7 +6,10 @@ benchmark's CPU-baseline leg, never by the engine.  The arithmetic lives in
 this module compiles it with gcc and marshals numpy arrays through ctypes.
 
 Modes: EXH (exhaustive allocation), BF_INA, BF_ACT, SMS_INA, SMS_ACT
-(heuristic allocation over each fixed partitioning).  Per-partition policy:
+(heuristic allocation over each fixed partitioning).  FLAG_EXH_FAST gives the
+exhaustive mode through a memo of partition tests ("oracle_fast": the same
+search, every allocation of every partitioning, scored from a table of
+(task subset, size) tests; checked against the plain search).  Per-partition policy:
 FP_DM (fixed priority, deadline monotonic, exact response times) or EDF
 (processor-demand test).
 """
@@ -26,6 +29,7 @@ EXH, BF_INA, BF_ACT, SMS_INA, SMS_ACT = 0, 1, 2, 3, 4
 MODES = {"EXH": EXH, "BF_INA": BF_INA, "BF_ACT": BF_ACT, "SMS_INA": SMS_INA, "SMS_ACT": SMS_ACT}
 FLAG_NO_LEMMA1 = 1
 FLAG_EDF = 2
+FLAG_EXH_FAST = 4  # exhaustive mode scored through a memo of partition tests (sets of at most 16 tasks)
 POLICIES = {"FP_DM": 0, "EDF": FLAG_EDF}
 EDF_BP_STEPS, EDF_ND_CAP = 4096, 65536
 OK, E_INVAL, E_RANGE = 0, -1, -2

@@ -60,6 +60,7 @@ enum { OR_EXH = 0, OR_BF_INA = 1, OR_BF_ACT = 2, OR_SMS_INA = 3, OR_SMS_ACT = 4 
 enum { OR_OK = 0, OR_E_INVAL = -1, OR_E_RANGE = -2 };
 #define OR_FLAG_NO_LEMMA1 1
 #define OR_FLAG_EDF 2     /* per-partition policy: EDF instead of fixed-priority DM */
+#define OR_FLAG_EXH_FAST 4 /* exhaustive mode through the memo of partition tests (or_exh_memo) */
 /* EDF work limits (part of the test's definition, identical in the engine):
  * busy-period iterations before the utilisation bound is used instead, and
  * absolute deadlines below the horizon beyond which the exact demand check
@@ -536,6 +537,99 @@ static int or_validate(const or_set *s, int K, int mode)
 }
 
 /* ---- one set ----------------------------------------------------------- */
+/* ---- 7'. exhaustive allocation through a memo of partition tests ------- */
+/* The same search as step 7 over every allocation, with each partition's
+ * test memoised: U[m-1][A] for every task subset A (bit i = task i) and size
+ * m = 1..M, filled by or_eval_part (an empty part is schedulable with U = 0;
+ * an unschedulable subset holds OR_MEMO_NONE, above any schedulable U, which
+ * is at most 2^32 + n).  Every allocation index of every partitioning is
+ * then scored from the memo in increasing index order, so the result (best
+ * key (maxU, sumU, partitioning index, allocation index)) is the plain
+ * search's by construction; tests/test_oracle_fast.py checks it against the
+ * plain search.  Sets of at most OR_FAST_MAXN tasks. */
+#define OR_FAST_MAXN 16
+
+#define OR_MEMO_NONE (~(uint64_t)0)
+
+typedef struct {
+    int n, M;
+    uint64_t *U;  /* [M][2^n] */
+} or_memo;
+
+static int or_memo_build(const or_set *s, or_memo *mo)
+{
+    const int64_t W = (int64_t)1 << s->n;
+    int64_t A;
+    int m, i;
+    mo->n = s->n; mo->M = s->M;
+    mo->U = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(W * s->M));
+    if (!mo->U) return 0;
+    for (m = 1; m <= s->M; m++)
+        for (A = 0; A < W; A++) {
+            int mem[OR_MAXN], cnt = 0;
+            uint64_t U = 0;
+            for (i = 0; i < s->n; i++)
+                if ((A >> i) & 1) mem[cnt++] = i;
+            if (cnt > 0 && !or_eval_part(s, mem, cnt, m, 1, NULL, &U)) U = OR_MEMO_NONE;
+            mo->U[(m - 1) * W + A] = U;
+        }
+    return 1;
+}
+
+/* Score every allocation of partitioning sz[0..k) (task 0 the most
+ * significant base-k digit); keeps the best (maxU, sumU) seen so far, which
+ * a later index replaces only when strictly smaller.  The indices are taken
+ * in runs of k that differ only in the last task's part d: the other parts'
+ * memo entries are read once per run. */
+static void or_memo_scan(const or_set *s, const or_memo *mo, const int *sz, int k, int64_t pidx, int *found,
+                         uint64_t *best_max, uint64_t *best_sum, int64_t *best_pidx, int64_t *best_aidx,
+                         int8_t *best_alloc)
+{
+    const int n = s->n, last = n - 1;
+    const int64_t W = (int64_t)1 << n;
+    const uint32_t lbit = 1u << last;
+    int digit[OR_MAXN];
+    uint32_t mask[8];
+    uint64_t u0[8], u1[8];
+    int64_t r, runs = 1;
+    int i, p, d;
+    for (i = 0; i < last; i++) { digit[i] = 0; runs *= k; }
+    for (p = 0; p < k; p++) mask[p] = 0;
+    mask[0] = (uint32_t)(W - 1) & ~lbit;
+    for (r = 0; r < runs; r++) {
+        int bad = 0, badp = -1;
+        for (p = 0; p < k; p++) {
+            const uint64_t *row = mo->U + (int64_t)(sz[p] - 1) * W;
+            u0[p] = row[mask[p]];          /* part p without the last task */
+            u1[p] = row[mask[p] | lbit];   /* part p with it */
+            if (u0[p] == OR_MEMO_NONE) { bad++; badp = p; }
+        }
+        for (d = 0; d < k; d++) {
+            uint64_t mx = 0, sm = 0;
+            if (s->cnt) s->cnt->combines++;
+            /* parts other than d must be schedulable as they are, part d with the last task */
+            if (bad > 1 || (bad == 1 && badp != d) || u1[d] == OR_MEMO_NONE) continue;
+            for (p = 0; p < k; p++) {
+                const uint64_t u = p == d ? u1[p] : u0[p];
+                if (u > mx) mx = u;
+                sm += u;
+            }
+            if (!*found || mx < *best_max || (mx == *best_max && sm < *best_sum)) {
+                *found = 1; *best_max = mx; *best_sum = sm; *best_pidx = pidx; *best_aidx = r * k + d;
+                for (i = 0; i < last; i++) best_alloc[i] = (int8_t)digit[i];
+                best_alloc[last] = (int8_t)d;
+            }
+        }
+        /* next run: increment the base-k number of tasks 0..n-2, task n-2 least significant */
+        for (i = last - 1; i >= 0; i--) {
+            mask[digit[i]] &= ~(1u << i);
+            if (++digit[i] < k) { mask[digit[i]] |= 1u << i; break; }
+            digit[i] = 0;
+            mask[0] |= 1u << i;
+        }
+    }
+}
+
 typedef struct {
     int32_t status;
     uint8_t verdict, verdict_1g;
@@ -556,7 +650,8 @@ static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_res
     int best_found = 0;
     int64_t best_pidx = -1, best_aidx = -1;
     uint64_t best_max = 0, best_sum = 0;
-    int reject;
+    int reject, use_memo;
+    or_memo memo = {0, 0, NULL};
     int one[1];
     int8_t zeros[OR_MAXN];
 
@@ -574,6 +669,8 @@ static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_res
     table = (int *)malloc(sizeof(int) * (size_t)(P * K));
     or_enumerate_partitionings(s->M, K, table, P);
     reject = (flags & OR_FLAG_NO_LEMMA1) ? 0 : or_lemma1_reject(s);
+    use_memo = !reject && mode == OR_EXH && (flags & OR_FLAG_EXH_FAST) && n <= OR_FAST_MAXN &&
+               or_memo_build(s, &memo);
     if (!reject) {
         for (pi = 0; pi < P; pi++) {
             const int *sz = table + pi * K;
@@ -581,7 +678,10 @@ static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_res
             for (k = 0; k < K && sz[k] > 0; k++)
                 if (s->adm && !((s->adm[sz[k] / 64] >> (sz[k] % 64)) & 1u)) allowed = 0;
             if (!allowed) continue; /* a part size outside the admissible set */
-            if (mode == OR_EXH) {
+            if (use_memo) {
+                or_memo_scan(s, &memo, sz, k, pi, &best_found, &best_max, &best_sum, &best_pidx, &best_aidx,
+                             best_alloc);
+            } else if (mode == OR_EXH) {
                 int64_t a, A = 1;
                 for (i = 0; i < n; i++) A *= k;
                 for (a = 0; a < A; a++) {
@@ -624,6 +724,7 @@ static void or_solve_one(const or_set *s, int K, int mode, int flags, or_set_res
     memset(zeros, 0, sizeof zeros);
     res->verdict_1g = (uint8_t)or_eval_triple(s, one, 1, zeros, 0, R1g_out, NULL, NULL);
     free(table);
+    free(memo.U);
 }
 
 /* ---- exported entry points ----------------------------------------------- */

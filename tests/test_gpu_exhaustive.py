@@ -123,3 +123,29 @@ def test_c4_stress_sampled(eng):
     g = [(int(a), int(b)) for a, b in zip(got["maxU"][both], got["sumU"][both])]
     h = [(int(a), int(b)) for a, b in zip(heur["maxU"][both], heur["sumU"][both])]
     assert all(x <= y for x, y in zip(g, h))
+
+
+def test_c4_full_selection_matches_memo_oracle(eng):
+    """The whole exhaustive search of 16 sets of the stress workload (every
+    allocation of all 1,033 partitionings of 48 units into at most 4 parts)
+    against the oracle's memoised exhaustive search, stored by
+    tests/golden/make_c4_exhaustive.py: every output field, bit for bit,
+    through the subset-table search (form 2) and, on two sets, through plain
+    enumeration (form 1)."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c4_exhaustive_16sets.json")) as f:
+        g = json.load(f)
+    idx = np.array(g["generator"]["indices"])
+    ts = workload.subset(workload.config_c4(n_sets=g["generator"]["n_sets"]), idx)
+    want = {f: np.array(g[f]) for f in FIELDS}
+    assert want["verdict"].sum() >= 8
+    say(f"c4 full selection: {ts.n_sets} sets, form 2")
+    got = solve_form(eng, ts, g["K"], 2)
+    for f in FIELDS:
+        assert np.array_equal(np.asarray(got[f]).reshape(want[f].shape), want[f]), ("form 2", f)
+    two = workload.subset(ts, np.array([int(np.argmax(want["verdict"])), 0]))
+    say("c4 full selection: 2 sets, form 1")
+    got1 = solve_form(eng, two, g["K"], 1)
+    want2 = solve_form(eng, two, g["K"], 2)
+    for f in FIELDS:
+        assert np.array_equal(got1[f], want2[f]), ("form 1", f)
