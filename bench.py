@@ -7,18 +7,21 @@ validation and per-set precompute (prep kernel), evaluation of every
 response-time tests (eval kernel), selection of the best triple, response
 times of the chosen triple and of the whole-GPU baseline (final kernel).
 
-Default workload (c2): 100,000 seeded synthetic task sets, n = 10 tasks,
-M = 80 compute units, at most K = 4 partitions (4263 partitionings per set),
-BF-INA heuristic allocation: 426,300,000 evaluations per step, run by the
-batched form (one persistent, autotuned, HIP-graph-captured launch sequence).
-The same batch is also timed through the plain one-launch-sequence path and
-the one-launch-per-set path, and a short open-loop serving run (uneven
-queries, Poisson arrivals) gives p50/p99 admission latency.
+Default workload (c3): 1,000,000 seeded synthetic task sets of uneven size,
+n uniform in 4..32 tasks, M drawn from {16, 48, 80, 108} compute units,
+constrained deadlines, at most K = 4 partitions (3.84e9 evaluations per
+step), BF-INA heuristic allocation, run by the batched form (persistent,
+autotuned, HIP-graph-captured launch sequences, one per size class).  The
+same batch is also timed through the plain one-launch-sequence path, the
+first 2,000 sets through the one-launch-per-set path, the 100,000-set n = 10,
+M = 80 workload (c2) through its own batched plan, and open-loop serving runs
+(uneven queries, Poisson arrivals from 10,000 queries/s up) give p50/p99
+admission latency and the saturation rate.
 
-Other workloads: c3 (1,000,000 uneven sets), c4 (exhaustive stress, 1,000
-sets of 12 tasks on 48 units, every allocation), c5 (serving sweep), fig4
-(the paper's Algorithm 1 with free partition sizes on its Fig. 4 workload:
-34,000 sets of 50 tasks on 68 units; value in task sets/s).
+Other workloads: c2 (100,000 sets, n = 10, M = 80), c4 (exhaustive stress,
+1,000 sets of 12 tasks on 48 units, every allocation), c5 (serving sweep),
+fig4 (the paper's Algorithm 1 with free partition sizes on its Fig. 4
+workload: 34,000 sets of 50 tasks on 68 units; value in task sets/s).
 
 Prints one JSON line (metric, value in evals/s, ms_per_step, roofline of the
 dominant kernel from HIP events on its launch stream, and the CPU oracle timed
@@ -27,7 +30,6 @@ on a bounded sample of the same workload on the host's cores).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -46,8 +48,11 @@ METRIC = "schedulability evals/sec (taskset×partitioning); p99 admission latenc
 C_TERM = 12
 C_TEST = 8
 C_LOOK = 6
-PEAK_INT_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit VALU)
-KERNEL_SRC = os.path.join(ROOT, "paper_2105_10312_amd", "csrc", "capart_kernels.hip")
+# 256 CUs x 128 full-rate 32-bit VALU lane-operations per clock x 2.4 GHz: the
+# chip's vector rate (its fp32 vector peak of 157.3 TFLOP/s is 78.6 T fused
+# multiply-adds per second, 128 lanes per CU per clock); an add-chain kernel
+# measures 65 T lane-operations/s on the device (reported beside it)
+PEAK_INT_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def log(msg):
@@ -55,8 +60,9 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the engine library is built from (the library carries the same)."""
+    from paper_2105_10312_amd import build
+    return build.source_hash()
 
 
 def traffic_bytes(name):
@@ -72,7 +78,7 @@ def traffic_bytes(name):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None, policy="FP_DM"):
+def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None, policy="FP_DM", flags=0):
     import numpy as np
 
     import oracle
@@ -81,11 +87,23 @@ def cpu_baseline(ts, K, mode, sample_sets, threads, stride=1, admissible=None, p
     sub = workload.subset(ts, idx)
     P = int(sum(oracle.count_partitionings(int(m), K) for m in sub["M"]))
     t0 = time.perf_counter()
-    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True, admissible=admissible, policy=policy)
+    r = oracle.solve(sub, K, mode, nthreads=threads, counters=True, admissible=admissible, policy=policy,
+                     flags=flags)
     dt = time.perf_counter() - t0
     c = r["counters"].sum(axis=0)
     return {"evals": P, "seconds": dt, "terms": int(c[0]), "tests": int(c[1]), "combines": int(c[2]),
             "sets": sub.n_sets}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def lemma1_pruned(ts):
@@ -145,7 +163,7 @@ def alg1_cpu_baseline(ts, mode, threads, policy="FP_DM"):
     return {"seconds": time.perf_counter() - t0, "sets": ts.n_sets, "schedulable": int(sum(v))}
 
 
-def alg1_main(args, eng, capart, workload, sync, threads):
+def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
     """Algorithm 1 with free partition sizes on the paper's Fig. 4 workload:
     n = 50 tasks, M = 68 units, U = 2..68 step 2, `--n-sets` sets per point
     (default 1000); one step = the whole batch through capart_alg1_async."""
@@ -197,15 +215,20 @@ def alg1_main(args, eng, capart, workload, sync, threads):
             "kernel": kname, "kernel_ms": k_ms, "ops_per_launch": ops, "work_per_launch": work,
             "ops_per_term": C_TERM, "ops_per_test": C_TEST,
             "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"])},
-            "step_ms_with_kernel_events": ms_timed}
+            "step_ms_with_kernel_events": ms_timed,
+            "peak_measured": valu_ops / 1e12, "frac_of_measured_peak": achieved / valu_ops}
     cpu = None
     if not args.no_cpu:
         log(f"[bench] CPU oracle (Algorithm 1) on all {S} sets with {threads} threads")
         cb = alg1_cpu_baseline(ts, mode, threads, pol)
         if cb["schedulable"] != int(verdict.sum()):
             raise SystemExit("bench: the oracle's schedulable count differs from the GPU's")
+        one = alg1_cpu_baseline(workload.subset(ts, np.arange(0, S, max(1, S // 500))), mode, 1, pol)
         cpu = {"value": cb["sets"] / cb["seconds"], "unit": "sets/s", "cores": threads, "kind": "oracle",
-               "sample": f"all {cb['sets']} sets of the workload, {cb['seconds']:.2f} s wall"}
+               "sample": f"all {cb['sets']} sets of the workload, {cb['seconds']:.2f} s wall",
+               "single_core": {"value": one["sets"] / one["seconds"],
+                               "sample": f"{one['sets']} sets spread over the workload, {one['seconds']:.2f} s"},
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         log(f"[bench] CPU oracle: {cpu['value']:.4g} sets/s")
     res = {"metric": "Algorithm 1 task sets/sec (free partition sizes)", "value": value, "unit": "sets/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -224,7 +247,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "fig4"],
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fig4"],
                     help="fig4: the paper's Algorithm 1 (free partition sizes) on its Fig. 4 workload")
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
     ap.add_argument("--n-sets", type=int, default=0, help="override the workload's number of sets")
@@ -275,6 +298,10 @@ def main():
     eng = capart.Engine(0)
     K = 4
     mode = args.mode
+    # the integer VALU peak as measured on this device (reported beside the
+    # nominal 256 CUs x 64 lanes x 2.4 GHz that `frac` uses)
+    valu_ops, valu_ms = capart.capart_measure_valu(eng.ctx)
+    log(f"[bench] measured full-rate int32 VALU: {valu_ops / 1e12:.2f} T lane-ops/s (kernel {valu_ms:.2f} ms)")
     if args.workload == "c5":
         # below and above the capacity of this query mix (about 1.4e4 queries/s)
         rates = [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6]
@@ -297,7 +324,7 @@ def main():
         return
 
     if args.workload == "fig4":
-        alg1_main(args, eng, capart, workload, sync, threads)
+        alg1_main(args, eng, capart, workload, sync, threads, valu_ops)
         return
 
     if args.workload == "c2":
@@ -431,26 +458,62 @@ def main():
         compare["per_set_launch"] = {"sets": sub_n, "ms": ps_ms, "value": ps_evals / (ps_ms / 1000.0)}
         compare["per_set_launch"]["batched_over_per_set"] = value / compare["per_set_launch"]["value"]
         log(f"[bench] one launch per set: {compare['per_set_launch']['value']:.4g} evals/s")
+        del sdev, sout
+        if args.workload == "c3" and not adm and not args.tables:
+            # the 100,000-set n = 10, M = 80 workload through its own batched plan
+            c2 = workload.config_c2(n_sets=100_000)
+            c2dev = capart.device_tasksets(c2)
+            c2out = capart.device_results(c2.n_sets, c2.n_tasks, K)
+            c2plan = capart.Plan(eng.ctx, c2dev, K, mode, c2out, 10, 80, autotune=True, use_graph=True, policy=pol)
+            c2plan.run()
+            sync()
+            c2_ms = timed(c2plan.run, max(3, args.steps // 2), sync)
+            c2_evals = c2.n_sets * capart.capart_count_partitionings(80, K)
+            compare["c2_batched"] = {"workload": "100000 task sets, n=10, M=80, K=4", "ms_per_step": c2_ms,
+                                     "value": c2_evals / (c2_ms / 1000.0), "plan": c2plan.info()}
+            log(f"[bench] c2 batched: {c2_ms:.2f} ms/step, {compare['c2_batched']['value']:.4g} evals/s")
+            c2plan.close()
+            del c2dev, c2out
 
     serving = None
-    if args.workload == "c2" and not args.no_serving and not args.tables and pol == "FP_DM":
-        # 2,000 queries/s: inside the capacity of this mix with its 49..64-task
-        # queries (each costs tens of ms alone), so the latencies are not queue growth
-        serving = serving_leg(eng, capart, workload, 2e3, 10000)
-        log(f"[bench] serving at 2e3 q/s: p50 {serving['p50_us']:.1f} us, p99 {serving['p99_us']:.1f} us")
+    if args.workload in ("c2", "c3") and not args.no_serving and not args.tables and pol == "FP_DM" and not adm:
+        # the serving workload's lowest configured rate (10,000 queries/s) and two
+        # above it, one second of arrivals each; the headline p99 is the first
+        legs = []
+        for rate in (1e4, 3e4, 1e5):
+            leg = serving_leg(eng, capart, workload, rate, int(min(50000, rate)))
+            legs.append(leg)
+            log(f"[bench] serving at {rate:g} q/s: {leg['qps']:.4g} q/s served, p50 {leg['p50_us']:.1f} us, "
+                f"p99 {leg['p99_us']:.1f} us, rejected {leg['rejected']}")
+        serving = dict(legs[0])
+        serving["sweep"] = legs
+        serving["saturation_qps"] = max(x["qps"] for x in legs)
 
     cpu = None
+    cflags = 0
     if mode == "EXH":
-        cb = None
-    elif args.no_cpu:
-        cb = cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm, pol)
+        # the oracle's memoised exhaustive search (every allocation of every
+        # partitioning scored from a table of subset tests; the plain search
+        # decodes every triple and would take hours per set)
+        import oracle
+        cflags = oracle.FLAG_EXH_FAST
+        cpu_sample = args.cpu_sample or 1
+        threads = min(threads, cpu_sample)
+    if args.no_cpu:
+        cb = None if mode == "EXH" else cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm, pol)
     else:
         log(f"[bench] CPU oracle on {cpu_sample} sets with {threads} threads")
-        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride, adm, pol)
+        cb = cpu_baseline(ts, K, mode, cpu_sample, threads, cpu_stride, adm, pol, cflags)
+        one = cpu_baseline(ts, K, mode, max(1, cpu_sample // threads), 1, cpu_stride, adm, pol, cflags) \
+            if threads > 1 else cb
         cpu = {"value": cb["evals"] / cb["seconds"], "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"{cb['sets']} of the {ts.n_sets} sets (every {cpu_stride}th from the first), "
-                         f"{cb['evals']} evals, {cb['seconds']:.2f} s wall"}
-        log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s")
+                         f"{cb['evals']} evals, {cb['seconds']:.2f} s wall"
+                         + (", memoised exhaustive search" if mode == "EXH" else ""),
+               "single_core": {"value": one["evals"] / one["seconds"], "sample": f"the first {one['sets']} of "
+                               f"those sets, {one['seconds']:.2f} s"},
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s ({cpu['single_core']['value']:.4g} on one core)")
     roof = None
     if work is not None:
         # the plan runs a persistent grid, or the direct schedule (blocks == 0)
@@ -465,7 +528,8 @@ def main():
                 "ops_per_term": C_TERM, "ops_per_test": C_TEST, "ops_per_lookup": C_LOOK,
                 "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"]),
                                      "final": ms_k["final"] / max(1, n_k["final"])},
-                "step_ms_with_kernel_events": ms_timed}
+                "step_ms_with_kernel_events": ms_timed,
+                "peak_measured": valu_ops / 1e12, "frac_of_measured_peak": achieved / valu_ops}
         if pol == "EDF":
             roof["note"] = ("EDF terms (members x density shortcut, busy-period steps and demand points) are priced "
                             "at the fixed-priority term cost; each is a 64-bit division, so frac is a lower bound")
@@ -475,6 +539,7 @@ def main():
     else:
         roof = {"bound": "alu", "kernel": "exh_dfs_kernel + subset_table_kernel", "kernel_ms": eval_ms,
                 "achieved": None, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
+                "peak_measured": valu_ops / 1e12,
                 "note": "exhaustive search: work is data-dependent (pruned search); see DESIGN.md"}
     res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

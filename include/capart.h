@@ -232,6 +232,14 @@ const char *capart_last_error(const capart_ctx *ctx);
  * library compares it with the sources' hash to refuse a stale build. */
 const char *capart_build_hash(void);
 
+/* Measure the full-rate 32-bit VALU throughput of the context's device: a
+ * kernel of independent integer-add chains (eight per lane, eight waves per
+ * SIMD), best of three timed launches.  *lane_ops_per_s gets lane-operations
+ * per second (for the integer roofline beside the nominal 256 CUs x 64 lanes
+ * x clock), *kernel_ms the best launch's time.  Synchronous; E_DEVICE on a
+ * HIP error. */
+capart_status capart_measure_valu(capart_ctx *ctx, double *lane_ops_per_s, double *kernel_ms);
+
 /* Number of partitionings of M into at most K positive parts (host only). */
 capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count);
 /* Write them in canonical order into sizes[count*K] (0-padded); at most

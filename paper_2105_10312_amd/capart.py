@@ -26,7 +26,8 @@ POLICIES = {"FP_DM": CAPART_POLICY_FP_DM, "EDF": CAPART_POLICY_EDF}
 CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
-EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_build_hash", "capart_count_partitionings",
+EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_build_hash", "capart_measure_valu",
+           "capart_count_partitionings",
            "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
@@ -131,6 +132,7 @@ def load_library():
         lib.capart_last_error.argtypes = [_vp]
         lib.capart_last_error.restype = C.c_char_p
         lib.capart_count_partitionings.argtypes = [C.c_int32, C.c_int32, P(C.c_int64)]
+        lib.capart_measure_valu.argtypes = [_vp, P(C.c_double), P(C.c_double)]
         lib.capart_enumerate_partitionings.argtypes = [C.c_int32, C.c_int32, _vp, C.c_int64, P(C.c_int64)]
         lib.capart_validate.argtypes = [P(capart_tasksets), P(capart_options), _vp]
         lib.capart_test_triple.argtypes = [_vp, P(capart_tasksets), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp]
@@ -299,6 +301,13 @@ def capart_test_triple(ctx, task: dict, sizes, alloc):
     _check(load_library().capart_test_triple(ctx, C.byref(st), sz.ctypes.data, len(sz), al.ctypes.data,
                                              feas.ctypes.data, R.ctypes.data, mx.ctypes.data, sm.ctypes.data), ctx)
     return bool(feas[0]), R, int(mx[0]), int(sm[0])
+
+
+def capart_measure_valu(ctx) -> tuple:
+    """(full-rate 32-bit VALU lane-operations per second, best kernel ms) measured on the device."""
+    ops, ms = C.c_double(0.0), C.c_double(0.0)
+    _check(load_library().capart_measure_valu(ctx, C.byref(ops), C.byref(ms)), ctx)
+    return ops.value, ms.value
 
 
 def capart_allocate(ctx, task: dict, sizes, K: int, mode="BF_INA", policy="FP_DM"):

@@ -648,6 +648,15 @@ const char *capart_last_error(const capart_ctx *c) { return c ? c->err.c_str() :
 #endif
 const char *capart_build_hash(void) { return CAPART_BUILD_HASH; }
 
+capart_status capart_measure_valu(capart_ctx *c, double *lane_ops_per_s, double *kernel_ms)
+{
+    if (!c || !lane_ops_per_s || !kernel_ms) return CAPART_E_INVAL;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if ((e = measure_valu(c->stream, lane_ops_per_s, kernel_ms)) != hipSuccess) return hip_fail(c, e, "VALU benchmark");
+    return CAPART_OK;
+}
+
 capart_status capart_count_partitionings(int32_t M, int32_t K, int64_t *count)
 {
     if (!count || M < 1 || M > CAPART_MAX_M || K < 1 || K > CAPART_MAX_K) return CAPART_E_INVAL;
