@@ -275,6 +275,28 @@ capart_status capart_solve(capart_ctx *ctx, const capart_tasksets *host_in, cons
 capart_status capart_solve_async(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
                                  capart_results *dev_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as capart_solve_async, bit for bit, with no
+ * allocation at all (no hipMalloc, hipFree or allocating library routine;
+ * the context, created beforehand, keeps the device tables it allocated at
+ * set-up).  Its workspace (per-task records, forbidden-pair masks, heuristic
+ * order, per-set flags and masks, one 32-byte key per set chunk) lives in one
+ * file-scope device array of CAPART_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds until the process ends.  A batch whose workspace exceeds it
+ * returns CAPART_E_RANGE (message from capart_last_error) before anything is
+ * launched; roughly 41 bytes per task plus 44 bytes per set plus 32 bytes per
+ * set chunk, so 100,000 sets of 10 tasks fit.  Exhaustive allocation runs by
+ * plain enumeration (the subset-table form needs its own memory); timing
+ * events are not recorded.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads or contexts) race and give undefined results; calls ordered on one
+ * stream do not.  Nothing in the array needs clearing between calls (every
+ * word a launch reads is written earlier in the same launch sequence). */
+#define CAPART_NOALLOC_SCRATCH_BYTES (64u << 20)
+capart_status capart_solve_async_noalloc(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
+                                         capart_results *dev_out, void *hip_stream);
+
 /*
  * Algorithm 1 with free partition sizes (Section "Heuristics": Algorithms 1,
  * 2 and 3, Definitions 3-5, Lemma 3).  Each task starts alone on a partition

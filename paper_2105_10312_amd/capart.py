@@ -27,7 +27,7 @@ CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
 EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_build_hash", "capart_measure_valu",
-           "capart_count_partitionings",
+           "capart_count_partitionings", "capart_solve_async_noalloc",
            "capart_enumerate_partitionings", "capart_validate", "capart_test_triple", "capart_allocate",
            "capart_solve", "capart_solve_async", "capart_set_tuning", "capart_get_tuning", "capart_timing_enable",
            "capart_timing_read", "capart_plan_batch", "capart_run_batch", "capart_plan_get_info",
@@ -140,6 +140,8 @@ def load_library():
                                         _vp, _vp, _vp]
         lib.capart_solve.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results)]
         lib.capart_solve_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results), _vp]
+        lib.capart_solve_async_noalloc.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_results),
+                                                   _vp]
         lib.capart_alg1.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results)]
         lib.capart_alg1_async.argtypes = [_vp, P(capart_tasksets), P(capart_options), P(capart_alg1_results),
                                           _vp]
@@ -404,6 +406,23 @@ def capart_solve_async(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=No
         stream = torch.cuda.current_stream()
     _check(load_library().capart_solve_async(ctx, C.byref(st), C.byref(opt), C.byref(res),
                                              C.c_void_p(stream.cuda_stream)), ctx)
+
+
+def capart_solve_async_noalloc(ctx, dev_ts: dict, K: int, mode, dev_out: dict, stream=None, flags: int = 0,
+                               max_tasks=None, max_M=None, admissible=None, policy="FP_DM") -> None:
+    """capart_solve_async without any device allocation (the library's per-GPU
+    scratch array holds the workspace); raises CapartError (E_RANGE) for a
+    batch whose workspace exceeds CAPART_NOALLOC_SCRATCH_BYTES."""
+    import torch
+    if max_tasks is None or max_M is None:
+        raise ValueError("device batches need declared max_tasks and max_M bounds")
+    st, _keep = make_tasksets(dev_ts, max_tasks, max_M)
+    opt = make_options(K, mode, flags, admissible, policy)
+    res = capart_results(*[_ptr(dev_out[f[0]]) for f in RESULT_FIELDS], None, None)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load_library().capart_solve_async_noalloc(ctx, C.byref(st), C.byref(opt), C.byref(res),
+                                                     C.c_void_p(stream.cuda_stream)), ctx)
 
 
 def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, max_M=None, policy="FP_DM") -> dict:

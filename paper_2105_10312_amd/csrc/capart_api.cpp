@@ -29,6 +29,7 @@ struct capart_ctx {
     void *stage = nullptr;         // staging buffer for host-pointer calls
     size_t stage_bytes = 0;
     capart_tuning tune{};          // launch tuning (0 = automatic)
+    void *scratch = nullptr;       // this device's no-allocation workspace (device address)
     uint64_t *tab = nullptr;       // subset tables of the exhaustive search
     size_t tab_bytes = 0;
     bool timing = false;           // record kernel events
@@ -449,10 +450,10 @@ void give_tables(Work &w, const Batch &b)
     w.tCc = b.Cc;
 }
 
-// Workspace arrays of the context for layout l (ensure_ws first).
-Work bind_work(capart_ctx *c, const WsLayout &l)
+// Workspace arrays at base for layout l.
+Work bind_work_at(capart_ctx *c, const WsLayout &l, void *ws)
 {
-    char *base = (char *)c->ws;
+    char *base = (char *)ws;
     Work w{};
     w.rec = (TaskRec *)(base + l.rec);
     w.forbid = (uint64_t *)(base + l.forbid);
@@ -464,6 +465,9 @@ Work bind_work(capart_ctx *c, const WsLayout &l)
     w.order = c->order_dev;
     return w;
 }
+
+// Workspace arrays of the context for layout l (ensure_ws first).
+Work bind_work(capart_ctx *c, const WsLayout &l) { return bind_work_at(c, l, c->ws); }
 
 capart_status run_plan(capart_ctx *c, const Batch &b, const Out &o, const Plan &p, hipStream_t st,
                        uint32_t p_lo = 0u, uint32_t p_hi = 0xFFFFFFFFu)
@@ -620,6 +624,12 @@ capart_status capart_create(int device, capart_ctx **out)
     // runtime refuses, launches needing more than the default report E_DEVICE
     e = configure_kernels();
     c->err = (e == hipSuccess) ? "no error" : std::string("LDS limit not raised: ") + hipGetErrorString(e);
+    // the no-allocation workspace of this device (the entry point reports it
+    // unusable if the runtime gives no address)
+    if (scratch_address(&c->scratch) != hipSuccess) {
+        c->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     *out = c;
     return CAPART_OK;
 }
@@ -719,6 +729,46 @@ capart_status capart_solve_async(capart_ctx *c, const capart_tasksets *in, const
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     const Plan p = make_plan(in, opt, c->tune);
     return run_plan(c, make_batch(in), make_out(out), p, (hipStream_t)hip_stream);
+}
+
+capart_status capart_solve_async_noalloc(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,
+                                         capart_results *out, void *hip_stream)
+{
+    if (!c) return CAPART_E_INVAL;
+    capart_status rc;
+    if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
+    if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
+    if (in->n_sets == 0) return CAPART_OK;
+    if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
+    if (!c->scratch) return fail(c, CAPART_E_DEVICE, "no address for the no-allocation workspace on this device");
+    Plan p = make_plan(in, opt, c->tune);
+    if (p.L.mode == CAPART_EXHAUSTIVE) p.L.exh_form = 1;  // the subset-table form needs memory of its own
+    const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
+    if (l.total > (size_t)CAPART_NOALLOC_SCRATCH_BYTES)
+        return fail(c, CAPART_E_RANGE, "the batch needs " + std::to_string(l.total) +
+                                           " bytes of workspace, above the no-allocation limit of " +
+                                           std::to_string((size_t)CAPART_NOALLOC_SCRATCH_BYTES) + " bytes");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const Batch b = make_batch(in);
+    const Out o = make_out(out);
+    Work w = bind_work_at(c, l, c->scratch);
+    give_tables(w, b);
+    const bool tm = c->timing;  // timing events would be created on demand
+    c->timing = false;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (p.L.flags & CAPART_FLAG_PER_SET_LAUNCH) {
+        for (int64_t s = 0; s < p.S && rc == CAPART_OK; s++) {
+            Launch L1 = p.L;
+            L1.s0 = s;
+            L1.S = 1;
+            rc = launch_three(c, b, w, o, L1, st, 0u, 0xFFFFFFFFu);
+        }
+    } else {
+        rc = launch_three(c, b, w, o, p.L, st, 0u, 0xFFFFFFFFu);
+    }
+    c->timing = tm;
+    return rc;
 }
 
 static capart_status solve_host(capart_ctx *c, const capart_tasksets *in, const capart_options *opt,

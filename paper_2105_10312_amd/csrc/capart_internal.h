@@ -173,6 +173,8 @@ hipError_t launch_exh_dfs(const Batch &b, const Work &w, const Out &o, const Lau
 hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, int k, const int8_t *alloc,
                          uint8_t *feasible, int64_t *R, uint64_t *maxU, uint64_t *sumU, hipStream_t st);
 hipError_t configure_kernels();
+// Device address of this GPU's no-allocation workspace (current device).
+hipError_t scratch_address(void **ptr);
 // Full-rate 32-bit VALU lane-operations per second, measured.
 hipError_t measure_valu(hipStream_t st, double *lane_ops_per_s, double *best_ms);
 // counting variant of the heuristic evaluation (w.counters must be set)

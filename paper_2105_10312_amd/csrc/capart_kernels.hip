@@ -275,6 +275,19 @@ hipError_t launch_triple(const Batch &b, const Work &w, const int32_t *sizes, in
 }
 
 // ---------------------------------------------------------------------------
+// Workspace of the no-allocation entry point (capart_solve_async_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never names it in a launch: it takes the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) uint8_t scratch[CAPART_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_address(void **ptr)
+{
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
+// ---------------------------------------------------------------------------
 // Integer VALU throughput: every lane runs eight independent chains of
 // full-rate 32-bit adds (v_add_u32), 32 per loop step, written as inline asm
 // so that the compiler can neither fold the chains nor change the operation.
