@@ -152,6 +152,23 @@ def serving_leg(eng, capart, workload, rate, n_queries, seed=5):
             "evals_per_s": st["evals_per_s"], "mean_batch": st["mean_batch"], "rejected": st["rejected"]}
 
 
+def workload_bounds(ts):
+    """Per set, the total one-unit utilisation without any conflict (best) and
+    with every task in conflict (worst), as floats (exact ceil-Q32 terms summed
+    in integers first)."""
+    import numpy as np
+    off = ts["set_offset"]
+    T = ts["T"].astype(object)
+    cn = (ts["C_seq"] + ts["C_par"]).astype(object)
+    cc = (ts["k_permille"].astype(object) * cn + 999) // 1000
+    q = 1 << 32
+    un = -((-cn * q) // T)
+    uc = -((-cc * q) // T)
+    best = np.array([float(sum(un[off[s]:off[s + 1]])) / q for s in range(ts.n_sets)])
+    worst = np.array([float(sum(uc[off[s]:off[s + 1]])) / q for s in range(ts.n_sets)])
+    return best, worst
+
+
 def alg1_cpu_baseline(ts, mode, threads, policy="FP_DM"):
     """The oracle's Algorithm 1 over every set of the workload, on `threads` host threads."""
     from concurrent.futures import ThreadPoolExecutor
@@ -201,7 +218,19 @@ def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
     verdict = out["verdict"][:S].cpu().numpy()
     nparts = out["nparts"][:S].cpu().numpy()
     tried = out["tried"][:S].cpu().numpy()
+    wl = out["workload"][:S].cpu().numpy().astype(np.float64) / 2.0 ** 32
     rate = verdict.reshape(-1, per_point).mean(axis=1)
+    # the efficiency plot (Figs. 5 and 7): per point, over the schedulable sets,
+    # the mean scheduled workload against the no-interference (best) and the
+    # all-interference (worst) totals, one-unit utilisations
+    best, worst = workload_bounds(ts)
+    eff = {}
+    for i in range(len(rate)):
+        sl = slice(i * per_point, (i + 1) * per_point)
+        ok = verdict[sl] == 1
+        eff[str(2 * (i + 1))] = None if not ok.any() else {
+            "best": float(best[sl][ok].mean()), "worst": float(worst[sl][ok].mean()),
+            "scheduled": float(wl[sl][ok].mean())}
     wout = capart.device_alg1_results(S, N)
     work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, 50, 68, policy=pol)
     del wout
@@ -235,6 +264,7 @@ def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": desc, "n_sets": S, "alloc_mode": mode, "policy": pol, "sets_per_point": per_point},
            "schedulability_by_U": {str(2 * (i + 1)): float(r) for i, r in enumerate(rate)},
+           "efficiency_by_U": eff,
            "mean_partitions_when_schedulable": float(nparts[verdict == 1].mean()) if verdict.any() else None,
            "mean_merges_tried": float(tried.mean()),
            "roofline": roof, "cpu_baseline": cpu}
@@ -406,14 +436,12 @@ def main():
     eval_ms = ms_k["eval"] / max(1, n_k["eval"])
     log(f"[bench] kernels per step: {ms_k} over {n_k['eval']} steps")
 
-    work = None
-    if mode != "EXH":
-        # the algorithm's own work, counted exactly by the counting variant of
-        # the evaluation kernel (outside the timed region)
-        wout = capart.device_results(ts.n_sets, ts.n_tasks, K)
-        work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M, admissible=adm, policy=pol)
-        del wout
-        log(f"[bench] counted work per step: {work}")
+    # the algorithm's own work, counted exactly by the counting variants of
+    # the evaluation kernels (outside the timed region)
+    wout = capart.device_results(ts.n_sets, ts.n_tasks, K)
+    work = capart.capart_count_work(eng.ctx, dev, K, mode, wout, max_tasks, max_M, admissible=adm, policy=pol)
+    del wout
+    log(f"[bench] counted work per step: {work}")
 
     # end to end: host (pinned) inputs copied in, one step, results copied out;
     # reported beside `value`, which keeps the inputs resident
@@ -516,8 +544,12 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.4g} evals/s ({cpu['single_core']['value']:.4g} on one core)")
     roof = None
     if work is not None:
-        # the plan runs a persistent grid, or the direct schedule (blocks == 0)
-        kname = "eval_persistent_kernel" if plan is not None and plan_info["blocks"] > 0 else "eval_heur_kernel"
+        # the plan runs a persistent grid, or the direct schedule (blocks == 0);
+        # the exhaustive search fills subset tables and searches them
+        if mode == "EXH":
+            kname = "subset_table_kernel + exh_dfs_kernel"
+        else:
+            kname = "eval_persistent_kernel" if plan is not None and plan_info["blocks"] > 0 else "eval_heur_kernel"
         ops = work["terms"] * C_TERM + work["tests"] * C_TEST + work["lookups"] * C_LOOK
         achieved = ops / (eval_ms / 1000.0)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
@@ -531,16 +563,14 @@ def main():
                 "step_ms_with_kernel_events": ms_timed,
                 "peak_measured": valu_ops / 1e12, "frac_of_measured_peak": achieved / valu_ops}
         if pol == "EDF":
-            roof["note"] = ("EDF terms (members x density shortcut, busy-period steps and demand points) are priced "
-                            "at the fixed-priority term cost; each is a 64-bit division, so frac is a lower bound")
-        if cb is not None:
+            roof["note"] = ("EDF terms (members x utilisation and density sums, busy-period steps, demand points) "
+                            "are priced at the fixed-priority term cost")
+        if mode == "EXH":
+            roof["note"] = ("exhaustive search: terms and tests fill the subset tables, lookups are the table reads "
+                            "of the pruned depth-first search (6 operations each, as a frontier lookup)")
+        if cb is not None and mode != "EXH":
             roof["oracle_plain_order_terms_per_eval"] = cb["terms"] / cb["evals"]
             roof["oracle_plain_order_tests_per_eval"] = cb["tests"] / cb["evals"]
-    else:
-        roof = {"bound": "alu", "kernel": "exh_dfs_kernel + subset_table_kernel", "kernel_ms": eval_ms,
-                "achieved": None, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
-                "peak_measured": valu_ops / 1e12,
-                "note": "exhaustive search: work is data-dependent (pruned search); see DESIGN.md"}
     res = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int64", "data": "synthetic",

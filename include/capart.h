@@ -349,6 +349,13 @@ typedef struct capart_alg1_results {
     int64_t *R;
     int64_t *tried;
     int64_t *merged;
+    /* [n_sets], may be NULL: on success the scheduled workload of the result
+     * (Section "Results and discussions", the efficiency of Figs. 5 and 7):
+     * sum over the tasks of ceil(C_i(1) 2^32 / T_i) with C_i(1) the one-unit
+     * time in the conflict state the task's final partition gives it (Q32,
+     * modulo 2^64); 0 for an unschedulable set.  Between the same sum without
+     * any conflict and with every task in conflict. */
+    uint64_t *workload;
 } capart_alg1_results;
 
 /* Algorithm 1 over a batch in device memory; results in device memory. */
@@ -505,13 +512,16 @@ typedef struct capart_tuning {
 capart_status capart_set_tuning(capart_ctx *ctx, const capart_tuning *tuning);
 capart_status capart_get_tuning(const capart_ctx *ctx, capart_tuning *tuning);
 
-/* Algorithmic work of a heuristic solve, counted exactly by a counting
- * variant of the evaluation kernel (for roofline accounting; not for timing):
- * counts[0] = response-time terms (per fixed-point iteration, one plus one per
- * higher-priority term), counts[1] = exact partition tests, counts[2] =
- * candidate tests answered from a feasibility frontier.  Same arguments as
- * capart_solve_async (device pointers); results are written as by it.
- * Synchronous.  E_INVAL for exhaustive mode or per-set launches. */
+/* Algorithmic work of a solve, counted exactly (for roofline accounting; not
+ * for timing).  Heuristic modes, by a counting variant of the evaluation
+ * kernel: counts[0] = response-time terms (per fixed-point iteration, one plus
+ * one per higher-priority term), counts[1] = exact partition tests, counts[2]
+ * = candidate tests answered from a feasibility frontier.  Exhaustive mode,
+ * in its subset-table form (sets of at most 14 tasks, K <= 4): counts[0] and
+ * counts[1] = the terms and tests of filling the subset tables, counts[2] =
+ * table lookups of the pruned search.  Same arguments as capart_solve_async
+ * (device pointers); results are written as by it.  Synchronous.  E_INVAL
+ * for per-set launches and for exhaustive batches outside the table form. */
 capart_status capart_count_work(capart_ctx *ctx, const capart_tasksets *dev_in, const capart_options *opt,
                                 capart_results *dev_out, void *hip_stream, int64_t *counts);
 /* Algorithmic work of Algorithm 1 (capart_alg1_async), counted by a counting

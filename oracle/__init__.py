@@ -217,7 +217,9 @@ def alg1(task: dict, mode="BF_INA", flags: int = 0, policy: str = "FP_DM") -> di
     mode: BF_* = order ">" (Definition 5), SMS_* = order ">>" (Definition 4);
     *_ACT fills the forbidden list beforehand.  Returns verdict, the final
     partitions in par_list order (sizes), task -> partition (alloc), response
-    times R, and the numbers of merges tried and accepted."""
+    times R, the numbers of merges tried and accepted, and (on success) the
+    scheduled workload: the Q32 sum of every task's one-unit utilisation in the
+    conflict state its partition gives it (Figs. 5 and 7; 0 on failure)."""
     lib = _load()
     flags = int(flags) | POLICIES[policy]
     mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -228,7 +230,7 @@ def alg1(task: dict, mode="BF_INA", flags: int = 0, policy: str = "FP_DM") -> di
     sizes = np.zeros(n, np.int32)
     al = np.zeros(n, np.int8)
     R = np.zeros(n, np.int64)
-    st = np.zeros(2, np.int64)
+    st = np.zeros(3, np.int64)
     cn = np.ascontiguousarray(task["Cn_table"], np.int64) if task.get("Cn_table") is not None else None
     cc = np.ascontiguousarray(task["Cc_table"], np.int64) if cn is not None else None
     ok = lib.or_alg1_ex(*_one(task), cn.ctypes.data if cn is not None else None,
@@ -237,7 +239,7 @@ def alg1(task: dict, mode="BF_INA", flags: int = 0, policy: str = "FP_DM") -> di
     if ok < 0:
         raise ValueError("set outside the oracle's limits")
     return dict(verdict=int(ok), k=int(k.value), sizes=sizes[:k.value].copy(), alloc=al, R=R,
-                tried=int(st[0]), merged=int(st[1]))
+                tried=int(st[0]), merged=int(st[1]), workload=int(np.uint64(st[2].view(np.uint64))))
 
 
 def m_min(task: dict, i: int) -> int:

@@ -1065,7 +1065,7 @@ static int or_alg1(const or_set *s, int variant, int flags, int *nparts, int32_t
     int mm[OR_MAXN], okc[OR_MAXN], order[OR_MAXN];
     uint64_t key[OR_MAXN];
     int np = 0, i, j, c, Pi = 0, ok = 0;
-    stats[0] = stats[1] = 0;
+    stats[0] = stats[1] = stats[2] = 0;
     *nparts = 0;
     for (i = 0; i < n; i++) { alloc[i] = -1; R[i] = -1; }
     if (!(flags & OR_FLAG_NO_LEMMA1) && or_lemma1_reject(s)) goto done;
@@ -1167,6 +1167,18 @@ done:
             sizes[c] = parts[c].m;
             for (t = 0; t < parts[c].cnt; t++) alloc[parts[c].mem[t]] = (int8_t)c;
             or_eval_part(s, parts[c].mem, parts[c].cnt, parts[c].m, 0, R, NULL);
+        }
+        /* the scheduled workload (Figs. 5 and 7): every task's one-unit
+         * utilisation in the conflict state its partition gives it, Q32 ceil */
+        for (c = 0; c < np; c++) {
+            int t, u;
+            for (t = 0; t < parts[c].cnt; t++) {
+                int i = parts[c].mem[t], same = 0;
+                for (u = 0; u < parts[c].cnt; u++)
+                    if (s->type[parts[c].mem[u]] == s->type[i]) same++;
+                const int64_t C1 = same >= 2 ? or_cc(s, i, 1) : or_cn(s, i, 1);
+                stats[2] += (int64_t)(uint64_t)(((((u128)C1) << 32) + (u128)s->T[i] - 1) / (u128)s->T[i]);
+            }
         }
     }
     free(parts);

@@ -58,12 +58,12 @@ class capart_results(C.Structure):
 
 class capart_alg1_results(C.Structure):
     _fields_ = [("status", _vp), ("verdict", _vp), ("nparts", _vp), ("sizes", _vp), ("alloc", _vp), ("R", _vp),
-                ("tried", _vp), ("merged", _vp)]
+                ("tried", _vp), ("merged", _vp), ("workload", _vp)]
 
 
 ALG1_FIELDS = [("status", np.int32, "S"), ("verdict", np.uint8, "S"), ("nparts", np.int32, "S"),
                ("sizes", np.int32, "N"), ("alloc", np.int8, "N"), ("R", np.int64, "N"),
-               ("tried", np.int64, "S"), ("merged", np.int64, "S")]
+               ("tried", np.int64, "S"), ("merged", np.int64, "S"), ("workload", np.uint64, "S")]
 
 
 class capart_tuning(C.Structure):
@@ -441,7 +441,8 @@ def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, ma
 def device_alg1_results(S: int, N: int, device="cuda") -> dict:
     """Result tensors on the GPU for capart_alg1_async."""
     import torch
-    tmap = {np.int32: torch.int32, np.uint8: torch.uint8, np.int64: torch.int64, np.int8: torch.int8}
+    tmap = {np.int32: torch.int32, np.uint8: torch.uint8, np.int64: torch.int64, np.int8: torch.int8,
+            np.uint64: torch.uint64}
     return {name: torch.empty(max(S if shape == "S" else N, 1), dtype=tmap[dt], device=device)
             for name, dt, shape in ALG1_FIELDS}
 

@@ -902,7 +902,8 @@ static capart_status alg1_run(capart_ctx *c, const capart_tasksets *in, const ca
     give_tables(w, b);
     Out po{};
     po.status = out->status;
-    const A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged};
+    const A1Out a{out->status, out->verdict, out->nparts, out->sizes, out->alloc, out->R, out->tried, out->merged,
+                  out->workload};
     std::array<hipEvent_t, 4> ev{};
     const bool tm = c->timing && !counts;
     if (tm)
@@ -967,7 +968,7 @@ capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart
     auto add = [&](size_t bytes) { need = align256(need + std::max<size_t>(bytes, 1)); };
     add(8 * (S + 1)); add(4 * S);
     add(8 * N); add(8 * N); add(8 * N); add(8 * N); add(4 * N); add(N);
-    add(4 * S); add(S); add(4 * S); add(4 * N); add(N); add(8 * N); add(8 * S); add(8 * S);
+    add(4 * S); add(S); add(4 * S); add(4 * N); add(N); add(8 * N); add(8 * S); add(8 * S); add(8 * S);
     const int64_t TL = has_tables(in) ? in->table_len : 0;
     if (TL) { add(8 * S); add(8 * TL); add(8 * TL); }
     if ((rc = ensure_stage(c, need)) != CAPART_OK) return rc;
@@ -988,6 +989,7 @@ capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart
     r.R = bp.take<int64_t>(N);
     r.tried = bp.take<int64_t>(S);
     r.merged = bp.take<int64_t>(S);
+    r.workload = out->workload ? bp.take<uint64_t>(S) : nullptr;
     const hipStream_t st = c->stream;
     struct Cp { void *dst; const void *src; size_t n; } h2d[] = {
         {d_off, in->set_offset, 8 * (size_t)(S + 1)}, {d_M, in->M, 4 * (size_t)S},
@@ -1003,7 +1005,8 @@ capart_status capart_alg1(capart_ctx *c, const capart_tasksets *in, const capart
     Cp d2h[] = {{out->status, r.status, 4 * (size_t)S}, {out->verdict, r.verdict, (size_t)S},
                 {out->nparts, r.nparts, 4 * (size_t)S}, {out->sizes, r.sizes, 4 * (size_t)N},
                 {out->alloc, r.alloc, (size_t)N}, {out->R, r.R, 8 * (size_t)N},
-                {out->tried, r.tried, 8 * (size_t)S}, {out->merged, r.merged, 8 * (size_t)S}};
+                {out->tried, r.tried, 8 * (size_t)S}, {out->merged, r.merged, 8 * (size_t)S},
+                {out->workload, r.workload, out->workload ? 8 * (size_t)S : 0}};
     for (const auto &x : d2h)
         if (x.n && (e = hipMemcpyAsync(x.dst, x.src, x.n, hipMemcpyDeviceToHost, st)) != hipSuccess)
             return hip_fail(c, e, "hipMemcpyAsync D2H");
@@ -1154,14 +1157,16 @@ capart_status capart_count_work(capart_ctx *c, const capart_tasksets *in, const 
     capart_status rc;
     if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
     if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
-    if (opt->alloc_mode == CAPART_EXHAUSTIVE || (opt->flags & CAPART_FLAG_PER_SET_LAUNCH))
-        return fail(c, CAPART_E_INVAL, "work counting covers batched heuristic solves");
+    if (opt->flags & CAPART_FLAG_PER_SET_LAUNCH)
+        return fail(c, CAPART_E_INVAL, "work counting covers batched solves");
     if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
     counts[0] = counts[1] = counts[2] = 0;
     if (in->n_sets == 0) return CAPART_OK;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     const Plan p = make_plan(in, opt, c->tune);
+    if (p.L.mode == CAPART_EXHAUSTIVE && p.L.exh_form != 2)
+        return fail(c, CAPART_E_INVAL, "work counting of exhaustive solves covers the subset-table search");
     const WsLayout l = ws_layout(p.S, p.N, p.L.chunks);
     if ((rc = ensure_ws(c, l.total + 256)) != CAPART_OK) return rc;
     char *base = (char *)c->ws;
@@ -1181,9 +1186,19 @@ capart_status capart_count_work(capart_ctx *c, const capart_tasksets *in, const 
     const Out o = make_out(out);
     (void)hipGetLastError();
     if ((e = hipMemsetAsync(w.counters, 0, 24, st)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
-    if ((e = launch_prep(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
-    if ((e = launch_eval_count(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "counting eval launch");
-    if ((e = launch_final(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
+    if (p.L.mode == CAPART_EXHAUSTIVE) {
+        // subset tables (partition tests and their terms) and the pruned
+        // search (table lookups) count through w.counters
+        const bool tm = c->timing;
+        c->timing = false;
+        rc = launch_three(c, b, w, o, p.L, st, 0u, 0xFFFFFFFFu);
+        c->timing = tm;
+        if (rc != CAPART_OK) return rc;
+    } else {
+        if ((e = launch_prep(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+        if ((e = launch_eval_count(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "counting eval launch");
+        if ((e = launch_final(b, w, o, p.L, st)) != hipSuccess) return hip_fail(c, e, "final launch");
+    }
     uint64_t h[3] = {0, 0, 0};
     if ((e = hipMemcpyAsync(h, w.counters, 24, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
@@ -1876,10 +1891,13 @@ void launch_batch(capart_server *v, int i)
     int64_t *off = (int64_t *)(h + li.off);
     int32_t *M = (int32_t *)(h + li.M);
     int64_t acc = 0, wide_parts = 0;
+    int32_t nmax = 1, Mmax = 1;
     for (int64_t s = 0; s < S; s++) {
         SrvQuery &x = v->q[(first + s) % v->Qcap];
         off[s] = acc;
         M[s] = x.M;
+        nmax = std::max(nmax, x.n);
+        Mmax = std::max(Mmax, x.M);
         if (x.n > NARROW_MAX_TASKS) wide_parts += count_parts(x.M, v->cfg.K);
         std::memcpy(h + li.T + 8 * acc, &v->hT[x.t0], 8 * (size_t)x.n);
         std::memcpy(h + li.D + 8 * acc, &v->hD[x.t0], 8 * (size_t)x.n);
@@ -1910,8 +1928,8 @@ void launch_batch(capart_server *v, int i)
     b.k = (const int32_t *)(d + li.k);
     b.type = (const uint8_t *)(d + li.type);
     b.n_tasks_total = N;
-    b.max_tasks = v->cfg.max_tasks;
-    b.max_M = v->cfg.max_M;
+    b.max_tasks = nmax;  // the batch's own bounds: launches and LDS sized for its sets only
+    b.max_M = Mmax;
     Work w{};
     w.rec = v->rec + t_start;
     w.forbid = v->forbid + t_start;
@@ -1938,6 +1956,8 @@ void launch_batch(capart_server *v, int i)
     Launch L = v->L;
     L.s0 = 0;
     L.S = S;
+    L.table_words = (int)(table_lds_bytes(nmax, Mmax) / 4);
+    L.threads = eval_threads(nmax, Mmax);
     // the wave-per-partitioning launch only while the wide queries cannot fill the chip's lanes
     if (L.wchunk > 0 && v->ctx->tune.wide_chunk == 0 && wide_parts >= WIDE_LANE_FILL) L.wchunk = 0;
     hipError_t e;

@@ -73,6 +73,27 @@ CAPART_HD inline uint32_t util_q32_m1_magic(uint32_t C, uint32_t T, uint32_t clo
     return (uint32_t)(q - 1u);
 }
 
+// floor(x / X) for any 32-bit x and X >= 1 (X = 1 has no 2^64 reciprocal).
+CAPART_HD inline uint32_t udiv_magic(uint32_t x, uint32_t X, uint32_t lo, uint32_t hi)
+{
+    return X == 1u ? x : floordiv_magic(x, lo, hi);
+}
+
+// floor and ceil of C 2^32 / X for 1 <= C <= X < 2^31 without a 64-bit
+// division (the same correction as util_q32_m1_magic); both <= 2^32.
+CAPART_HD inline void q32_floor_ceil(uint32_t C, uint32_t X, uint32_t lo, uint32_t hi, uint64_t *fl, uint64_t *cl)
+{
+    const uint64_t num = (uint64_t)C << 32;
+    if (X == 1u) {
+        *fl = *cl = num;
+        return;
+    }
+    uint64_t y = (uint64_t)C * hi + (uint32_t)(((uint64_t)C * lo) >> 32);
+    if (y * X > num) y--;
+    *fl = y;
+    *cl = y + (y * X != num);
+}
+
 // Lemma 2 closed form: least m in [1, M] with C_seq + ceil(C_par/m) <= D.
 CAPART_HD inline uint16_t m_min(uint32_t Cs, uint32_t Cp, uint32_t D, uint32_t M)
 {

@@ -141,6 +141,7 @@ using Tally = TallyP<POL_ANY>;
 // Per-set data in LDS (ranks are deadline-monotonic priority positions).
 struct SetLDS {
     uint32_t T[MAXN], D[MAXN], clo[MAXN], chi[MAXN];
+    uint32_t dlo[MAXN], dhi[MAXN];  // 2^64 reciprocal of D (EDF density and demand)
     uint32_t Cs[MAXN], Cp[MAXN], k[MAXN];
     uint32_t mmin[MAXN];
     uint64_t forbid[MAXN];
@@ -150,6 +151,9 @@ struct SetLDS {
     uint8_t rank_of[MAXN];
     uint64_t memmask;
     uint32_t edf;  // 1: partitions are scheduled by EDF, 0: fixed-priority DM
+    // bit m of lbad[k-1]: no allocation schedules a k-part partitioning whose
+    // largest part has m units (stage_bounds)
+    uint64_t lbad[CAPART_MAX_K][4];
 };
 
 // Whether a test compiled with tally type TY uses EDF on the staged set.
@@ -194,6 +198,7 @@ __device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int6
         uint64_t f = 0ull;
         for (int j = 0; j < n; j++) f |= (uint64_t)(L.T[j] < L.D[r]) << j;
         L.intf[r] = f;
+        if (L.edf) magic_u32(L.D[r], &L.dlo[r], &L.dhi[r]);  // the EDF test divides by D
     }
 }
 
@@ -255,6 +260,65 @@ __device__ void stage_set_times(SetLDS &L, const Work &w, int64_t off, int n, in
     tb.C = tc;
     tb.U = nullptr;
     tb.n = n;
+}
+
+// ceil(C 2^32 / T) of rank r on m units where C <= T, else 2^32 + 1 (any
+// C > T has C 2^32 / T above 2^32): at least the exact Q32 utilisation minus 1.
+__device__ __forceinline__ uint64_t util_ceil_bound(const SetLDS &L, const Tables &tb, int r, int m, uint32_t conf)
+{
+    const int at = (m - 1) * 2 * tb.n + (int)conf * tb.n + r;
+    const uint32_t C = tb.C[at], T = L.T[r];
+    if (C > T) return (1ull << 32) + 1ull;
+    const uint32_t u = tb.U ? tb.U[at] : util_q32_m1_magic(C, T, L.clo[r], L.chi[r]);
+    return (uint64_t)u + 1ull;
+}
+
+// Partitionings that no allocation can schedule, from a necessary condition
+// (so skipping them changes no result): a schedulable partition has
+// utilisation at most 1, so the k parts together carry at most k; a task on a
+// part of m_p <= m_1 units needs at least its utilisation on m_1 units (times
+// never grow with more units); and at most one task of each type per part is
+// free of conflict (a conflict needs two of a type), so at most k of each
+// type take their time without conflict.  Hence a k-part partitioning whose
+// largest part has m_1 units is infeasible when
+//   sum_i uc_i(m_1) - (k largest uc_i - un_i of memory tasks)
+//                   - (k largest uc_i - un_i of compute tasks)  >  k,
+// with uc, un the utilisations in and out of conflict, taken as Q32 ceilings
+// (each at most 1 above 2^32 times the exact value, hence the n below).
+// One thread per m fills bit m of lbad[k-1] for k = 1..KMAX.
+template <int KMAX>
+__device__ void stage_bounds(SetLDS &L, const Tables &tb, int n, int M)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < KMAX * 4; i += nt) L.lbad[i >> 2][i & 3] = 0ull;
+    __syncthreads();
+    for (int m = tid + 1; m <= M; m += nt) {
+        uint64_t sum = 0, tm[KMAX], tcp[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; i++) { tm[i] = 0ull; tcp[i] = 0ull; }
+        for (int r = 0; r < n; r++) {
+            const uint64_t un = util_ceil_bound(L, tb, r, m, 0u), uc = util_ceil_bound(L, tb, r, m, 1u);
+            sum += uc;
+            uint64_t v = uc > un ? uc - un : 0ull;
+            if ((L.memmask >> r) & 1ull) {
+#pragma unroll
+                for (int i = 0; i < KMAX; i++)
+                    if (v > tm[i]) { const uint64_t t = tm[i]; tm[i] = v; v = t; }
+            } else {
+#pragma unroll
+                for (int i = 0; i < KMAX; i++)
+                    if (v > tcp[i]) { const uint64_t t = tcp[i]; tcp[i] = v; v = t; }
+            }
+        }
+        uint64_t cut = 0;
+#pragma unroll
+        for (int k = 1; k <= KMAX; k++) {
+            cut += tm[k - 1] + tcp[k - 1];
+            if (sum - cut >= (uint64_t)n + ((uint64_t)k << 32))
+                atomicOr((unsigned long long *)&L.lbad[k - 1][m >> 6], (unsigned long long)(1ull << (m & 63)));
+        }
+    }
+    __syncthreads();
 }
 
 // Q32 utilisation ceil(C 2^32 / T) of rank r on m units, exact modulo 2^64
@@ -359,6 +423,28 @@ struct EdfRes {
     bool ok;
 };
 
+// Member j's record as an EDF test reads it: C, T, D and the 2^64
+// reciprocals of T and D (magic_u32), which replace 64-bit divisions by
+// multiplies wherever the dividend fits 32 bits.
+struct EdfTask {
+    uint32_t C, T, D, tlo, thi, dlo, dhi;
+};
+
+// ceil(w / T) for w < 2^32 by the reciprocal, else by a 64-bit division.
+__device__ __forceinline__ uint64_t ceil_div_t(uint64_t w, const EdfTask &e)
+{
+    if (w == 0ull) return 0ull;
+    if (w <= 0xFFFFFFFFull) return (uint64_t)udiv_magic((uint32_t)(w - 1ull), e.T, e.tlo, e.thi) + 1ull;
+    return (w + e.T - 1ull) / e.T;
+}
+
+// floor(x / T) likewise.
+__device__ __forceinline__ uint64_t floor_div_t(uint64_t x, const EdfTask &e)
+{
+    if (x <= 0xFFFFFFFFull) return (uint64_t)udiv_magic((uint32_t)x, e.T, e.tlo, e.thi);
+    return x / e.T;
+}
+
 template <typename MT, typename GET>
 __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
 {
@@ -369,18 +455,24 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     bool dense = false;  // some C_j / D_j above 1
     uint32_t dmin = 0xFFFFFFFFu;
     for (MT h = S; h; h &= h - MT(1)) {
-        uint32_t C, T, D;
-        get(mctz(h), C, T, D);
-        const uint64_t num = (uint64_t)C << 32;
-        const uint64_t q = num / T;
-        uf += q;
+        const EdfTask e = get(mctz(h));
+        if (e.C > e.T) return res;  // C/T > 1: U > 1
+        uint64_t fl, cl;
+        q32_floor_ceil(e.C, e.T, e.tlo, e.thi, &fl, &cl);
+        uf += fl;
         if (uf > ONE) return res;
-        uc += q + (num != q * (uint64_t)T ? 1ull : 0ull);
-        const uint64_t qd = D == T ? q : num / D;
-        if (qd > ONE) dense = true;
-        else dc += qd + (num != qd * (uint64_t)D ? 1ull : 0ull);
-        sumC += C;
-        dmin = min(dmin, D);
+        uc += cl;
+        if (e.C > e.D) {
+            dense = true;
+        } else if (e.D == e.T) {
+            dc += cl;
+        } else {
+            uint64_t dfl, dcl;
+            q32_floor_ceil(e.C, e.D, e.dlo, e.dhi, &dfl, &dcl);
+            dc += dcl;
+        }
+        sumC += e.C;
+        dmin = min(dmin, e.D);
     }
     res.terms += cnt;
     const bool density_ok = !dense && dc <= ONE;
@@ -393,9 +485,8 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     for (int step = 0; step < EDF_BP_STEPS; step++) {
         uint64_t W = 0;
         for (MT h = S; h; h &= h - MT(1)) {
-            uint32_t C, T, D;
-            get(mctz(h), C, T, D);
-            W += ((w + T - 1ull) / T) * C;
+            const EdfTask e = get(mctz(h));
+            W += ceil_div_t(w, e) * e.C;
         }
         res.terms += cnt;
         if (W == w) { settled = true; break; }
@@ -416,32 +507,25 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     if (H != 0ull) {
         nd = 0;
         for (MT h = S; h; h &= h - MT(1)) {
-            uint32_t C, T, D;
-            get(mctz(h), C, T, D);
-            if (D < H) nd += (H - 1ull - D) / T + 1ull;
+            const EdfTask e = get(mctz(h));
+            if (e.D < H) nd += floor_div_t(H - 1ull - e.D, e) + 1ull;
         }
     }
     if (nd > EDF_ND_CAP) {
         // step 5: deadline-monotonic response times, members in rank order
         for (MT rem = S; rem; rem &= rem - MT(1)) {
             const int r = mctz(rem);
-            uint32_t Cr, Tr, Dr;
-            get(r, Cr, Tr, Dr);
+            const EdfTask er = get(r);
             const MT hp = S & below<MT>(r);
-            uint64_t R = Cr;
-            for (MT h = hp; h; h &= h - MT(1)) {
-                uint32_t C, T, D;
-                get(mctz(h), C, T, D);
-                R += C;
-            }
-            if (R > Dr) return res;
+            uint64_t R = er.C;
+            for (MT h = hp; h; h &= h - MT(1)) R += get(mctz(h)).C;
+            if (R > er.D) return res;
             for (;;) {
-                uint64_t W = Cr;
+                uint64_t W = er.C;
                 for (MT h = hp; h; h &= h - MT(1)) {
-                    uint32_t C, T, D;
-                    get(mctz(h), C, T, D);
-                    W += ((R + T - 1ull) / T) * C;
-                    if (W > Dr) return res;
+                    const EdfTask e = get(mctz(h));
+                    W += ceil_div_t(R, e) * e.C;  // R <= D < 2^31
+                    if (W > er.D) return res;
                 }
                 res.terms += 1u + (uint32_t)mpopc(hp);
                 if (W == R) break;
@@ -458,18 +542,16 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     auto demand = [&](uint64_t t) {
         uint64_t d = 0;
         for (MT h = S; h; h &= h - MT(1)) {
-            uint32_t C, T, D;
-            get(mctz(h), C, T, D);
-            if (D <= t) d += ((t - D) / T + 1ull) * C;
+            const EdfTask e = get(mctz(h));
+            if (e.D <= t) d += (floor_div_t(t - e.D, e) + 1ull) * e.C;
         }
         return d;
     };
     auto last_before = [&](uint64_t t) {  // largest absolute deadline < t (t > min D)
         uint64_t d = 0;
         for (MT h = S; h; h &= h - MT(1)) {
-            uint32_t C, T, D;
-            get(mctz(h), C, T, D);
-            if (D < t) d = max(d, (uint64_t)D + ((t - 1ull - D) / T) * T);
+            const EdfTask e = get(mctz(h));
+            if (e.D < t) d = max(d, (uint64_t)e.D + floor_div_t(t - 1ull - e.D, e) * e.T);
         }
         return d;
     };
@@ -495,10 +577,9 @@ __device__ __forceinline__ bool edf_part(const SetLDS &L, const Tables &tb, MT S
     const int n = tb.n;
     const uint32_t *row = tb.C + (m - 1) * 2 * n;
     const SetLDS *Ls = &L;
-    auto get = [=](int j, uint32_t &C, uint32_t &T, uint32_t &D) {
-        C = row[(int)mbit(cm, j) * n + j];
-        T = Ls->T[j];
-        D = Ls->D[j];
+    auto get = [=](int j) {
+        return EdfTask{row[(int)mbit(cm, j) * n + j], Ls->T[j], Ls->D[j], Ls->clo[j], Ls->chi[j], Ls->dlo[j],
+                       Ls->dhi[j]};
     };
     const EdfRes r = edf_demand<MT>(S, get, Hout != nullptr);
     ty.term(r.terms);
@@ -758,7 +839,20 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
 {
 #pragma unroll
     for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
+    // Capacity stop: every part of a schedulable partitioning has utilisation at
+    // most 1, a placed task never gets cheaper (members only gain conflicts),
+    // and an unplaced task needs at least its conflict-free utilisation on the
+    // largest part.  Once that need exceeds the room the parts can still have,
+    // no placement of the rest can succeed, so the heuristic, which only makes
+    // schedulable placements, must fail: it stops there (same outcome).
+    // Q32: table terms are ceil(u 2^32) - 1 <= u 2^32 for the need, and the
+    // parts' sums exceed the exact utilisation by less than one per member.
+    const uint32_t *urow1 = tb.U + (m[0] - 1) * 2 * n;
+    uint64_t need = 0;
+    for (int i = 0; i < n; i++) need += (uint64_t)urow1[i];
+    uint64_t room = (uint64_t)k << 32;  // k 2^32 - sum U + (members placed)
     for (int t = 0; t < n; t++) {
+        if (need > room) return false;
         const int r = L.sigma[t];
         const int mm = (int)L.mmin[r];
         const MT fb = ACT ? (MT)L.forbid[r] : MT(0);
@@ -796,9 +890,12 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
             if (better) { best = p; bestU = Un; bestReq = req; }
         }
         if (best < 0) return false;
+        uint64_t Uold = 0;
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
-            if (p == best) { S[p] |= MT(1) << r; U[p] = bestU; }
+            if (p == best) { Uold = U[p]; S[p] |= MT(1) << r; U[p] = bestU; }
+        need -= (uint64_t)urow1[r];
+        room = room + 1ull - (bestU - Uold);
     }
     return true;
 }
@@ -849,7 +946,16 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
     const uint64_t memm = L.memmask;
 #pragma unroll
     for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; }
+    // the capacity stop of heuristic(): lane i holds task i's conflict-free
+    // utilisation on the largest part, less one (a lower bound in Q32)
+    const int lane = threadIdx.x & 63;
+    const uint64_t li = lane < n ? util_term(L, tb, lane, m[0], 0u) - 1ull : 0ull;
+    uint64_t need = li;
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) need += __shfl_xor(need, o2, 64);
+    uint64_t room = (uint64_t)k << 32;
     for (int t = 0; t < n; t++) {
+        if (need > room) return false;
         const int r = L.sigma[t];
         const int mm = (int)L.mmin[r];
         const uint64_t fb = ACT ? L.forbid[r] : 0ull;
@@ -892,9 +998,12 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
             if (better) { best = p; bestU = Un; bestReq = req; }
         }
         if (best < 0) return false;
+        uint64_t Uold = 0;
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
-            if (p == best) { S[p] |= 1ull << r; U[p] = bestU; }
+            if (p == best) { Uold = U[p]; S[p] |= 1ull << r; U[p] = bestU; }
+        need -= __shfl(li, r, 64);
+        room = room + 1ull - (bestU - Uold);
     }
     return true;
 }
@@ -1150,6 +1259,17 @@ __device__ __forceinline__ int admit(const Adm &a, const int (&m)[KMAX], int k)
     return ok ? k : 0;
 }
 
+// k, or 0 for a partitioning (sizes m, non-increasing, k parts) that
+// stage_bounds found infeasible for every allocation: like an inadmissible
+// size, it then gets no parts and fails at its first task.
+template <int KMAX>
+__device__ __forceinline__ int bound_k(const SetLDS &L, const int (&m)[KMAX], int k)
+{
+    if (k <= 0) return k;
+    const int m1 = m[0];
+    return ((L.lbad[k - 1][m1 >> 6] >> (m1 & 63)) & 1ull) ? 0 : k;
+}
+
 #ifdef CAPART_MAIN_TU  // non-template kernels: compiled in the main translation unit only
 // ---------------------------------------------------------------------------
 // prep: one wave per set.
@@ -1265,6 +1385,45 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
         acc = (acc > cap || t > cap) ? cap + 1 : acc + t;
     }
     const bool reject = (acc > cap) && !(Lp.flags & CAPART_FLAG_NO_LEMMA1);
+    // the bound of stage_bounds at the largest part a k-part partitioning can
+    // have (M - k + 1 units; the bound only weakens as the largest part grows
+    // and as k grows): when it rules out every k <= K, no partitioning of the
+    // fixed-partitioning search can be schedulable and the set is not evaluated
+    bool nofit = true;
+    for (int k = 1; k <= min(Lp.K, M) && nofit; k++) {
+        const int m1 = M - k + 1;
+        uint64_t un = 0, uc = 0;
+        if (lane < n) {
+            uint64_t cn, cc;
+            if (tab) {
+                cn = (uint64_t)b.Cn[toff + (int64_t)lane * M + (m1 - 1)];
+                cc = (uint64_t)b.Cc[toff + (int64_t)lane * M + (m1 - 1)];
+            } else {
+                cn = (uint64_t)Cs + ((uint64_t)Cp + (uint64_t)m1 - 1ull) / (uint64_t)m1;
+                cc = ((uint64_t)kk * cn + 999ull) / 1000ull;
+            }
+            const uint64_t T64 = (uint64_t)T;
+            un = cn > T64 ? (1ull << 32) + 1ull : ((cn << 32) + T64 - 1ull) / T64;
+            uc = cc > T64 ? (1ull << 32) + 1ull : ((cc << 32) + T64 - 1ull) / T64;
+        }
+        uint64_t sum = uc;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) sum += __shfl_xor(sum, o2, 64);
+        // the k largest savings uc - un of each type, taken one by one
+        uint64_t sv = (lane < n && uc > un) ? uc - un : 0ull, cut = 0;
+        for (int t2 = 0; t2 < 2; t2++) {
+            uint64_t mine = (lane < n && ty == t2) ? sv : 0ull;
+            for (int j = 0; j < k; j++) {
+                uint64_t mx = mine;
+#pragma unroll
+                for (int o2 = 32; o2 >= 1; o2 >>= 1) mx = max(mx, (uint64_t)__shfl_xor(mx, o2, 64));
+                cut += mx;
+                const uint64_t who = __ballot(mine == mx && mx != 0ull);
+                if (who && lane == __ffsll((long long)who) - 1) mine = 0ull;
+            }
+        }
+        nofit = sum - cut >= (uint64_t)n + ((uint64_t)k << 32);
+    }
     // memory-intensive ranks
     uint64_t mm = (lane < n && ty == 1) ? (1ull << rank) : 0ull;
 #pragma unroll
@@ -1283,7 +1442,7 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
     }
     if (lane == 0) {
         w.memmask[s] = mm;
-        w.setflags[s] = SETF_VALID | (reject ? SETF_LEMMA1 : 0u) | (Lp.edf ? SETF_EDF : 0u);
+        w.setflags[s] = SETF_VALID | (reject ? SETF_LEMMA1 : 0u) | (nofit ? SETF_NOFIT : 0u) | (Lp.edf ? SETF_EDF : 0u);
     }
     const bool act = (Lp.mode == CAPART_HEUR_BF_ACT || Lp.mode == CAPART_HEUR_SMS_ACT);
     if (!act) return;
@@ -1314,12 +1473,11 @@ __global__ __launch_bounds__(64) void prep_kernel(Batch b, Work w, Out o, Launch
                 if (conf) { Ca = time_c(ta.k, Ca); Cb = time_c(tb.k, Cb); }
             }
             if (Lp.edf) {
-                const uint32_t Ta = ta.T, Tb = tb.T, Da = ta.D, Db = tb.D;
-                auto get = [=](int j, uint32_t &C, uint32_t &T, uint32_t &D) {
-                    C = j ? Cb : Ca;
-                    T = j ? Tb : Ta;
-                    D = j ? Db : Da;
-                };
+                uint32_t dla, dha, dlb, dhb;
+                magic_u32(ta.D, &dla, &dha);
+                magic_u32(tb.D, &dlb, &dhb);
+                const EdfTask ea{Ca, ta.T, ta.D, ta.clo, ta.chi, dla, dha}, eb{Cb, tb.T, tb.D, tb.clo, tb.chi, dlb, dhb};
+                auto get = [=](int j) { return j ? eb : ea; };
                 forb = !edf_demand<uint32_t>(3u, get, false).ok;
             } else if (Ca <= ta.D && Ca < ta.T) {
                 uint64_t R = (uint64_t)Cb + Ca;
@@ -1370,7 +1528,7 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
     MT *myS = lS + threadIdx.x;
     uint64_t *myU = lU + threadIdx.x;
     int m[KMAX];
-    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
+    int k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m)));
     uint64_t mpack = pack_sizes<KMAX>(m);
 #pragma unroll
     for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
@@ -1431,7 +1589,7 @@ __device__ void heur_run(const SetLDS &L, const Tables &tb, const uint32_t *np, 
                 d[2] = ok ? 0ull : ~0ull;
             }
             if (++q >= q1) break;
-            k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
+            k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, next_partition<KMAX>(m, K)));
             mpack = pack_sizes<KMAX>(m);
 #pragma unroll
             for (int i = 0; i < KMAX; i++) { myS[i * stride] = MT(0); myU[i * stride] = 0ull; }
@@ -1450,7 +1608,7 @@ __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_
                                 const Memo &mo)
 {
     int m[KMAX];
-    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
+    int k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m)));
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
@@ -1472,7 +1630,7 @@ __device__ void heur_run_nested(const SetLDS &L, const Tables &tb, const uint32_
             d[2] = ok ? 0ull : ~0ull;
         }
         if (++q >= q1) break;
-        k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
+        k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, next_partition<KMAX>(m, K)));
     }
 }
 
@@ -1481,7 +1639,7 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
                                int K, const Adm &adm, uint32_t q0, uint32_t q1, Key &best, uint64_t *dbg, TY &ty)
 {
     int m[KMAX];
-    int k = admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m));
+    int k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m)));
     for (uint32_t q = q0;;) {
         MT S[KMAX];
         uint64_t U[KMAX];
@@ -1503,7 +1661,7 @@ __device__ void heur_run_front(const SetLDS &L, const Tables &tb, const uint16_t
             d[2] = ok ? 0ull : ~0ull;
         }
         if (++q >= q1) break;
-        k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
+        k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, next_partition<KMAX>(m, K)));
     }
 }
 
@@ -1531,7 +1689,7 @@ __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t 
 #pragma unroll
     for (int i = 0; i < KMAX; i++) { m[i] = 0; S[i] = 0u; U[i] = 0ull; }
     bool active = q0 < q1;
-    int k = active ? admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m)) : 0;
+    int k = active ? bound_k<KMAX>(L, m, admit<KMAX>(adm, m, unrank<KMAX>(np, M, K, q0, m))) : 0;
     uint32_t q = q0;
     int t = 0;
     uint32_t known = 0u, passm = 0u;  // candidates of the current task settled / schedulable
@@ -1640,7 +1798,7 @@ __device__ void heur_run_memo(const SetLDS &L, const Tables &tb, const uint32_t 
                 if (++q >= q1) {
                     active = false;
                 } else {
-                    k = admit<KMAX>(adm, m, next_partition<KMAX>(m, K));
+                    k = bound_k<KMAX>(L, m, admit<KMAX>(adm, m, next_partition<KMAX>(m, K)));
 #pragma unroll
                     for (int i = 0; i < KMAX; i++) { S[i] = 0u; U[i] = 0ull; }
                     t = 0;
@@ -1736,9 +1894,10 @@ __global__ __launch_bounds__(512) void eval_heur_kernel(Batch b, Work w, Out o, 
     const uint32_t p1 = min(P, p0 + Lp.chunk);
     uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
     Key best = key_none();
-    if (!(f & SETF_LEMMA1)) {
+    if (!(f & (SETF_LEMMA1 | SETF_NOFIT))) {
         Tables tb;
         stage_set(L, w, off, n, M, s, ACT, tb);
+        stage_bounds<KMAX>(L, tb, n, M);
         memo_clear<MT, FORM>(Lp, n);
         eval_range<KMAX, ACT, SMS, MT, FORM>(L, tb, Lp, w.np, w.order, n, M, p0, p1, p_lo, p_hi, best, dbg, ty);
     } else if (dbg) {
@@ -1797,13 +1956,14 @@ __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, 
     uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     Key best = key_none();
-    if (!(f & SETF_LEMMA1)) {
+    if (!(f & (SETF_LEMMA1 | SETF_NOFIT))) {
         Tables tb;
         stage_set_times(L, w, off, n, M, s, ACT, tb);
+        stage_bounds<KMAX>(L, tb, n, M);
         const uint32_t q0 = p0 + (uint32_t)wv;
         if (q0 < p1) {
             int m[KMAX];
-            int k = admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q0, m));
+            int k = bound_k<KMAX>(L, m, admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q0, m)));
             for (uint32_t q = q0;;) {
                 if (q >= p_lo && q < p_hi) {
                     uint64_t S[KMAX], U[KMAX];
@@ -1828,7 +1988,7 @@ __global__ __launch_bounds__(512) void eval_wide_kernel(Batch b, Work w, Out o, 
                 q += (uint32_t)nw;
                 if (q >= p1) break;
                 for (int i = 0; i < nw; i++) k = next_partition<KMAX>(m, Lp.K);
-                k = admit<KMAX>(Lp.adm, m, k);
+                k = bound_k<KMAX>(L, m, admit<KMAX>(Lp.adm, m, k));
             }
         }
     } else if (dbg) {
@@ -1882,12 +2042,13 @@ __global__ __launch_bounds__(512) void eval_persistent_kernel(Batch b, Work w, O
         const uint32_t f = w.setflags[s];
         Key best = key_none();
         uint64_t *dbg = o.dbg_key ? o.dbg_key + 3 * o.dbg_offset[s] : nullptr;
-        if ((f & SETF_VALID) && !(f & SETF_LEMMA1)) {
+        if ((f & SETF_VALID) && !(f & (SETF_LEMMA1 | SETF_NOFIT))) {
             const int64_t off = b.off[s];
             const int n = (int)(b.off[s + 1] - off);
             const int M = b.M[s];
             if (s != staged) {
                 stage_set(L, w, off, n, M, s, ACT, tb);
+                stage_bounds<KMAX>(L, tb, n, M);
                 memo_clear<MT, FORM>(Lp, n);
                 staged = s;
             }
@@ -1926,11 +2087,12 @@ __global__ __launch_bounds__(256) void eval_exh_kernel(Batch b, Work w, Out o, L
     const uint32_t P = w.np[np_index(Lp.K, M, M)];
     if (q >= P) return;
     Key best = key_none();
-    if (!(f & SETF_LEMMA1) && q >= p_lo && q < p_hi) {
+    if (!(f & (SETF_LEMMA1 | SETF_NOFIT)) && q >= p_lo && q < p_hi) {
         Tables tb;
         stage_set(L, w, off, n, M, s, false, tb);
+        stage_bounds<KMAX>(L, tb, n, M);
         int m[KMAX];
-        const int k = admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q, m));
+        const int k = bound_k<KMAX>(L, m, admit<KMAX>(Lp.adm, m, unrank<KMAX>(w.np, M, Lp.K, q, m)));
         uint64_t A = k > 0 ? 1 : 0;  // an inadmissible partitioning has no allocation
         for (int i = 0; i < n; i++) A *= (uint64_t)k;
         for (uint64_t a = threadIdx.x; a < A; a += blockDim.x) {
@@ -2240,6 +2402,7 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
             o.nparts[s] = 0;
             o.tried[s] = tried;
             o.merged[s] = merged;
+            if (o.workload) o.workload[s] = 0ull;
         }
         if (off0 >= 0 && off1 >= off0 && off1 <= b.n_tasks_total)
             for (int64_t i = off0 + lane; i < off1; i += 64) { o.sizes[i] = 0; o.alloc[i] = -1; o.R[i] = -1; }
@@ -2391,12 +2554,18 @@ __global__ __launch_bounds__(64) void alg1_kernel(Batch b, Work w, A1Out o, Laun
         const int mm = readlane32(Pmu, p);
         if ((mk >> lane) & 1ull) { part = p; Sp = mk; mp = mm; }
     }
+    uint64_t wl = 0ull;  // the scheduled workload: one-unit utilisations in the final conflict states
     if (lane < n) {
-        const uint32_t R = resp_one<uint64_t, TY>(L, tb, mp, lane, Sp, conflict_mask<uint64_t>(Sp, memm));
+        const uint64_t cm = conflict_mask<uint64_t>(Sp, memm);
+        const uint32_t R = resp_one<uint64_t, TY>(L, tb, mp, lane, Sp, cm);
         const int64_t gi = off0 + L.orig[lane];
         o.alloc[gi] = (int8_t)part;
         o.R[gi] = R ? (int64_t)R : -1;
+        wl = util_term(L, tb, lane, 1, (uint32_t)((cm >> lane) & 1ull));
     }
+#pragma unroll
+    for (int o2 = 32; o2 >= 1; o2 >>= 1) wl += __shfl_xor(wl, o2, 64);
+    if (lane == 0 && o.workload) o.workload[s] = wl;
 }
 
 #ifdef CAPART_MAIN_TU
@@ -2414,7 +2583,7 @@ __global__ __launch_bounds__(256) void subset_table_kernel(Batch b, Work w, Laun
     if (s_local >= W) return;
     const int64_t s = s_begin + s_local;
     const uint32_t f = w.setflags[s];
-    if (!(f & SETF_VALID) || (f & SETF_LEMMA1)) return;
+    if (!(f & SETF_VALID) || (f & (SETF_LEMMA1 | SETF_NOFIT))) return;
     const int64_t off = b.off[s];
     const int n = (int)(b.off[s + 1] - off);
     const int M = b.M[s];
@@ -2423,12 +2592,29 @@ __global__ __launch_bounds__(256) void subset_table_kernel(Batch b, Work w, Laun
     stage_set(L, w, off, n, M, s, false, tb);
     uint64_t *dst = tab + (((size_t)s_local * Mtab + (size_t)(m - 1)) << ntab);
     const uint32_t NA = 1u << n;
+    Tally ty;  // kept only when the launch counts work (w.counters)
     for (uint32_t A = threadIdx.x; A < NA; A += blockDim.x) {
         uint32_t RA = 0;
         for (uint32_t a = A; a; a &= a - 1u) RA |= 1u << L.rank_of[__builtin_ctz(a)];
         uint64_t u = 0;
-        NoTally nt;
-        dst[A] = part_test<uint32_t>(L, tb, RA, m, &u, nt) ? u : ~0ull;
+        if (w.counters) {
+            dst[A] = part_test<uint32_t>(L, tb, RA, m, &u, ty) ? u : ~0ull;
+        } else {
+            NoTally nt;
+            dst[A] = part_test<uint32_t>(L, tb, RA, m, &u, nt) ? u : ~0ull;
+        }
+    }
+    if (w.counters) {
+        uint64_t a = ty.terms, bb = ty.tests;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) {
+            a += __shfl_xor(a, o2, 64);
+            bb += __shfl_xor(bb, o2, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd((unsigned long long *)&w.counters[0], (unsigned long long)a);
+            atomicAdd((unsigned long long *)&w.counters[1], (unsigned long long)bb);
+        }
     }
 }
 
@@ -2462,6 +2648,7 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
     const uint32_t P = w.np[np_index(Lp.K, M, M)];
     if (q >= P) return;
     Key best = key_none();
+    uint64_t combines = 0;  // subset-table lookups of candidate parts (counted when w.counters is set)
     int m[4];
     const int k = unrank<4>(w.np, M, Lp.K, q, m);
     if (threadIdx.x == 0) {
@@ -2476,7 +2663,7 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
     const uint64_t msz = (uint64_t)(uint32_t)m[0] | ((uint64_t)(uint32_t)m[1] << 8) | ((uint64_t)(uint32_t)m[2] << 16) |
                          ((uint64_t)(uint32_t)m[3] << 24);
     const bool admitted = admit<4>(Lp.adm, m, k) > 0;
-    if (!(f & SETF_LEMMA1) && admitted && threadIdx.x < npre && q >= p_lo && q < p_hi) {
+    if (!(f & (SETF_LEMMA1 | SETF_NOFIT)) && admitted && threadIdx.x < npre && q >= p_lo && q < p_hi) {
         const uint64_t *t = tab + (((size_t)s_local * Mtab) << ntab);
         // prefix digits: task Lpre-1 least significant
         uint64_t Apack = 0, aidx = 0;
@@ -2522,6 +2709,7 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
                             continue;
                         const uint32_t An = ((uint32_t)(Apack >> (16 * p)) & 0xFFFFu) | (1u << i);
                         const uint64_t u = t[((size_t)(mp - 1) << ntab) | An];
+                        combines++;
                         if (u == ~0ull) continue;
                         uint64_t nmx = 0, nsm = 0;
 #pragma unroll
@@ -2565,6 +2753,12 @@ __global__ __launch_bounds__(256) void exh_dfs_kernel(Batch b, Work w, Out o, La
                 }
             }
         }
+    }
+    if (w.counters) {
+        uint64_t c2 = combines;
+#pragma unroll
+        for (int o2 = 32; o2 >= 1; o2 >>= 1) c2 += __shfl_xor(c2, o2, 64);
+        if ((threadIdx.x & 63) == 0 && c2) atomicAdd((unsigned long long *)&w.counters[2], (unsigned long long)c2);
     }
     best = block_min(best, red);
     if (threadIdx.x == 0) {

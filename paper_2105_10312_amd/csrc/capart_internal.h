@@ -23,6 +23,7 @@ static_assert(sizeof(TaskRec) == 32, "TaskRec layout");
 constexpr uint32_t SETF_VALID = 1u;
 constexpr uint32_t SETF_LEMMA1 = 2u;  // Lemma 1 rejects the set
 constexpr uint32_t SETF_EDF = 4u;     // the set's partitions are scheduled by EDF (else fixed-priority DM)
+constexpr uint32_t SETF_NOFIT = 8u;   // no partitioning into at most K parts can be schedulable (prep's bound)
 
 // Partition-count table: NP(r, j, x) = number of partitions of r into at most
 // j parts, each part <= x (parts >= 1); r, x in [0, 255], j in [0, 8].
@@ -150,6 +151,7 @@ struct A1Out {
     int8_t *alloc;    // [N]
     int64_t *R;       // [N]
     int64_t *tried, *merged;
+    uint64_t *workload;  // [S] or nullptr
 };
 // count: the counting variant (adds response-time terms and exact tests to w.counters[0..1])
 hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st,

@@ -43,8 +43,8 @@ hipError_t launch_prep(const Batch &b, const Work &w, const Out &o, const Launch
 static int launch_max_n(const Launch &L, const Batch &b) { return L.n_hi > 0 ? min(L.n_hi, b.max_tasks) : b.max_tasks; }
 
 // Threads per block of a loop-form-1 launch whose LDS per block leaves room
-// for only one or two blocks on a compute unit (large per-set tables): wider
-// blocks keep about 8 waves per compute unit.  Frontier and form-2 launches
+// for only a few blocks on a compute unit (large per-set tables): wider
+// blocks keep 16 or more waves per compute unit.  Frontier and form-2 launches
 // keep their width (the frontier build and form 2's lane state assume at
 // most 256 threads).
 static Launch fit_block(const Launch &L, const Batch &b)
@@ -55,8 +55,8 @@ static Launch fit_block(const Launch &L, const Batch &b)
     const size_t dyn = (size_t)4 * L.table_words + (narrow && L.memo_log2 > 0 ? (size_t)8 << L.memo_log2 : 0);
     const size_t per_block = dyn + 8 * 1024;  // with the static per-set arrays
     const int fit = (int)((size_t)160 * 1024 / per_block);
-    if (fit <= 1) C.threads = 512;
-    else if (fit == 2) C.threads = max(C.threads, 256);
+    if (fit <= 2) C.threads = 512;
+    else if (fit <= 4) C.threads = max(C.threads, 256);
     return C;
 }
 

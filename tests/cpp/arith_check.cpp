@@ -101,6 +101,29 @@ int main()
             CHECK(util_q32_m1_magic(1 + d, T, lo, hi) == util_q32_m1(1 + d, T));
         }
     }
+    // floor and ceil of C 2^32 / X and floor(x / X) with X = 1 allowed: every
+    // C <= X for small X, random C over the full range for random X
+    auto q32_check = [&](uint32_t C, uint32_t X) {
+        uint32_t lo, hi;
+        magic_u32(X, &lo, &hi);
+        uint64_t fl, cl;
+        q32_floor_ceil(C, X, lo, hi, &fl, &cl);
+        const u128 num = (u128)C << 32;
+        CHECK((u128)fl == num / X);
+        CHECK((u128)cl == (num + X - 1) / X);
+    };
+    for (uint32_t X = 1; X < 1500; X++)
+        for (uint32_t C = 1; C <= X; C++) q32_check(C, X);
+    for (int t = 0; t < 2000000; t++) {
+        const uint32_t X = 1 + (uint32_t)(rng() % ((1u << 31) - 1));
+        q32_check(1 + (uint32_t)(rng() % X), X);
+        q32_check(X, X);
+        uint32_t lo, hi;
+        magic_u32(X, &lo, &hi);
+        const uint32_t x = (uint32_t)rng();
+        CHECK(udiv_magic(x, X, lo, hi) == x / X);
+    }
+    for (uint32_t x : edge_x) CHECK(udiv_magic(x, 1u, 0u, 0u) == x);
     std::printf("%s (%d failures)\n", fails ? "FAILED" : "OK", fails);
     return fails ? 1 : 0;
 }

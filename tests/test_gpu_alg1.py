@@ -3,7 +3,7 @@ with the CPU oracle's Algorithm 1.
 
 Integer method: every output is compared bit for bit (status, verdict,
 number of partitions, their sizes in par_list order, task -> partition,
-response times, merges tried and accepted)."""
+response times, merges tried and accepted, scheduled workload)."""
 import json
 import os
 import sys
@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 MODES = ("BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT")
-FIELDS = ("status", "verdict", "nparts", "sizes", "alloc", "R", "tried", "merged")
+FIELDS = ("status", "verdict", "nparts", "sizes", "alloc", "R", "tried", "merged", "workload")
 THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -54,12 +54,13 @@ def oracle_batch(ts, mode, no_lemma1=False):
         res = list(ex.map(lambda s: oracle.alg1(ts.set(s), mode, flags), range(S)))
     out = dict(status=np.zeros(S, np.int32), verdict=np.zeros(S, np.uint8), nparts=np.zeros(S, np.int32),
                sizes=np.zeros(N, np.int32), alloc=np.full(N, -1, np.int8), R=np.full(N, -1, np.int64),
-               tried=np.zeros(S, np.int64), merged=np.zeros(S, np.int64))
+               tried=np.zeros(S, np.int64), merged=np.zeros(S, np.int64), workload=np.zeros(S, np.uint64))
     for s, r in enumerate(res):
         a = int(off[s])
         out["verdict"][s] = r["verdict"]
         out["tried"][s] = r["tried"]
         out["merged"][s] = r["merged"]
+        out["workload"][s] = r["workload"]
         if r["verdict"]:
             out["nparts"][s] = r["k"]
             out["sizes"][a:a + r["k"]] = r["sizes"]

@@ -49,6 +49,44 @@ def test_orders_merge_different_partners():
             assert r["tried"] == want["tried"] and r["merged"] == want["merged"], order
 
 
+def test_scheduled_workload():
+    """The scheduled workload of Figs. 5 and 7 (hand-derived,
+    tests/golden/w7_alg1_workload.json): two compute tasks that must share
+    one unit are both in conflict (the worst load); on two units they stay
+    apart (the best load)."""
+    g = load("w7_alg1_workload.json")
+    for case in g["cases"]:
+        task = dict(g["set"], M=case["M"])
+        for mode in MODES:
+            r = oracle.alg1(task, mode)
+            assert r["verdict"] == 1 and list(r["sizes"]) == case["sizes"], (case["M"], mode)
+            assert r["workload"] == case["workload"], (case["M"], mode)
+    assert g["best"] == g["cases"][1]["workload"] and g["worst"] == g["cases"][0]["workload"]
+
+
+def test_workload_lies_between_the_bounds():
+    """On random sets: best (no task in conflict) <= workload <= worst (every
+    task in conflict), with equality to best exactly when no final partition
+    holds two tasks of one type."""
+    checked = 0
+    for task in random_sets(61, 300):
+        for mode in ("BF_INA", "SMS_ACT"):
+            r = oracle.alg1(task, mode)
+            if not r["verdict"]:
+                assert r["workload"] == 0
+                continue
+            n = len(task["T"])
+            ceil_q32 = lambda c, t: -((-c * (1 << 32)) // t)
+            best = sum(ceil_q32(oracle.exec_time(task, i, 1, False), int(task["T"][i])) for i in range(n))
+            worst = sum(ceil_q32(oracle.exec_time(task, i, 1, True), int(task["T"][i])) for i in range(n))
+            assert best <= r["workload"] <= worst
+            types = np.asarray(task["type"])
+            clash = any(np.bincount(types[r["alloc"] == p], minlength=2).max() >= 2 for p in range(r["k"]))
+            assert (r["workload"] == best) == (not clash or best == worst)
+            checked += 1
+    assert checked >= 100
+
+
 def test_worked_example_m7_m8():
     w1 = load("w1_worked_example.json")
     g = load("w4_alg1_merge_example.json")["w1_cases"]
