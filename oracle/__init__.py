@@ -208,6 +208,8 @@ def best_on_partitioning(task: dict, sizes, mode="EXH"):
     al = np.zeros(len(task["T"]), np.int8)
     mx, sm, ai = C.c_uint64(0), C.c_uint64(0), C.c_int64(-1)
     f = lib.or_best_on_partitioning(*_one(task), sz, len(sz), mode, al, C.byref(mx), C.byref(sm), C.byref(ai))
+    if f < 0:
+        raise ValueError("set outside the oracle's limits")
     return bool(f), al, int(mx.value), int(sm.value), int(ai.value)
 
 
@@ -247,7 +249,10 @@ def m_min(task: dict, i: int) -> int:
 
 
 def forbidden(task: dict, i: int, j: int) -> bool:
-    return bool(_load().or_forbidden_ex(*_one(task), i, j))
+    f = _load().or_forbidden_ex(*_one(task), i, j)
+    if f < 0:
+        raise ValueError("set or task index outside the oracle's limits")
+    return bool(f)
 
 
 def lemma1_reject(task: dict) -> bool:

@@ -67,7 +67,8 @@ enum { OR_OK = 0, OR_E_INVAL = -1, OR_E_RANGE = -2 };
  * gives way to the sufficient fixed-priority test */
 #define OR_EDF_BP_STEPS 4096
 #define OR_EDF_ND_CAP 65536
-#define OR_MAXN 64
+#define OR_MAXN 256       /* task capacity of the arrays (Algorithm 1 takes up to 256 tasks) */
+#define OR_MAXN_FIXED 64  /* largest set of the fixed-partitioning search */
 #define OR_MINF 1000000 /* "no such m" for Lemma 2 */
 
 typedef struct {
@@ -499,7 +500,7 @@ static int or_heuristic(const or_set *s, const int *sizes, int k, int variant, i
 static int or_validate(const or_set *s, int K, int mode)
 {
     int i;
-    if (s->n < 1 || s->n > OR_MAXN || s->M < 1 || s->M > 255) return OR_E_INVAL;
+    if (s->n < 1 || s->n > OR_MAXN_FIXED || s->M < 1 || s->M > 255) return OR_E_INVAL;
     if (s->n * s->M > 8192) return OR_E_INVAL; /* the boundary's per-set size limit */
     for (i = 0; i < s->n; i++) {
         int64_t T = s->T[i], D = s->D[i];
@@ -887,6 +888,7 @@ int or_best_on_partitioning(OR_SET_ARGS, const int32_t *sizes, int nparts, int m
     int sz[16], i, found = 0;
     int8_t cur[OR_MAXN];
     OR_SET_INIT(s);
+    if (n < 1 || n > OR_MAXN_FIXED) return -1;
     for (i = 0; i < nparts && i < 16; i++) sz[i] = sizes[i];
     if (mode == OR_EXH) {
         int64_t a, A = 1;
@@ -924,6 +926,7 @@ int or_forbidden_ex(OR_SET_ARGS, int i, int j)
     or_set s;
     int mm[OR_MAXN], t;
     OR_SET_INIT(s);
+    if (n < 1 || n > OR_MAXN || i < 0 || j < 0 || i >= n || j >= n) return -1;
     for (t = 0; t < n; t++) mm[t] = or_m_min(&s, t);
     return or_forbidden(&s, i, j, mm);
 }
@@ -1197,7 +1200,9 @@ int or_alg1_ex(OR_SET_ARGS, const int64_t *Cn_tab, const int64_t *Cc_tab, int va
     s.Cn_tab = Cn_tab;
     s.Cc_tab = Cn_tab ? Cc_tab : NULL;
     s.edf = (flags & OR_FLAG_EDF) != 0;
-    if (n < 1 || n > OR_MAXN || M < 1) return -1;
+    /* partition indices are int8: beyond 64 tasks the final partitions (at
+     * most M of them) must number at most 127 */
+    if (n < 1 || n > OR_MAXN || M < 1 || (n > OR_MAXN_FIXED && M > 127)) return -1;
     ok = or_alg1(&s, variant, flags, &np, sizes, alloc, R, stats);
     *nparts = np;
     return ok;

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from brute import partition_feasible
+from brute import partition_feasible, simulate_fp, task_time
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 MODES = ("BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT")
@@ -197,3 +197,57 @@ def test_success_implies_exhaustive_feasible(mode):
         assert want["verdict"][0] == 1, (task, r)
         checked += 1
     assert checked > 20
+
+
+def paper_sets_200(seed, points, per_point=1):
+    """The paper's 200-task sets (Figs. 6-8: n = 200, M = 68)."""
+    from paper_2105_10312_amd import workload
+    ts = workload.config_paper_fig4(seed=seed, n=200, sets_per_point=per_point, U_points=points)
+    return [ts.set(s) for s in range(ts.n_sets)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_soundness_at_200_tasks(mode):
+    """Lemma 3 on a 200-task set of the paper's generator: the sizes fit in M,
+    every task sits in one partition, each partition is at least its members'
+    Lemma 2 sizes, and a discrete-time simulation of every partition from a
+    synchronous release meets every deadline with the response times given;
+    with ACT no forbidden pair shares a partition.  A set at a higher
+    utilisation fails, and then no partition is reported."""
+    task = paper_sets_200(62, [36])[0]
+    n = len(task["T"])
+    r = oracle.alg1(task, mode)
+    assert r["verdict"] == 1
+    assert r["k"] == n - r["merged"] and r["sizes"].sum() <= task["M"]
+    assert sorted(set(r["alloc"].tolist())) == list(range(r["k"]))
+    for p in range(r["k"]):
+        members = [i for i in range(n) if r["alloc"][i] == p]
+        m = int(r["sizes"][p])
+        assert all(m >= oracle.m_min(task, i) for i in members)
+        C = [task_time(task, i, m, sum(1 for j in members if task["type"][j] == task["type"][i]) >= 2)
+             for i in members]
+        T = [int(task["T"][i]) for i in members]
+        D = [int(task["D"][i]) for i in members]
+        order = sorted(range(len(members)), key=lambda a: (D[a], T[a], members[a]))
+        prio = [order.index(a) for a in range(len(members))]
+        resp = simulate_fp(C, T, D, prio)
+        assert resp == [int(r["R"][i]) for i in members], (p, members)
+        if mode.endswith("ACT"):
+            for x in range(len(members)):
+                for y in range(x + 1, len(members)):
+                    assert not oracle.forbidden(task, members[x], members[y])
+    bad = oracle.alg1(paper_sets_200(62, [50])[0], mode)
+    assert bad["verdict"] == 0 and bad["k"] == 0 and (bad["alloc"] == -1).all() and (bad["R"] == -1).all()
+    assert bad["workload"] == 0
+
+
+def test_oracle_limits_at_200_tasks():
+    """Sets of more than 64 tasks take Algorithm 1 only, with M <= 127
+    (partition indices are int8)."""
+    task = paper_sets_200(63, [30])[0]
+    with pytest.raises(ValueError):
+        oracle.alg1(dict(task, M=128), "BF_INA")
+    with pytest.raises(ValueError):
+        oracle.best_on_partitioning(task, [34, 34], "BF_INA")
+    with pytest.raises(ValueError):
+        oracle.forbidden(task, 0, 200)
