@@ -20,8 +20,9 @@ admission latency and the saturation rate.
 
 Other workloads: c2 (100,000 sets, n = 10, M = 80), c4 (exhaustive stress,
 1,000 sets of 12 tasks on 48 units, every allocation), c5 (serving sweep),
-fig4 (the paper's Algorithm 1 with free partition sizes on its Fig. 4
-workload: 34,000 sets of 50 tasks on 68 units; value in task sets/s).
+fig4 and fig6 (the paper's Algorithm 1 with free partition sizes on its
+Fig. 4 and Figs. 6-8 workloads: 34,000 sets of 50 or of 200 tasks on 68
+units; value in task sets/s, with the analysis time per utilisation point).
 
 Prints one JSON line (metric, value in evals/s, ms_per_step, roofline of the
 dominant kernel from HIP events on its launch stream, and the CPU oracle timed
@@ -181,23 +182,28 @@ def alg1_cpu_baseline(ts, mode, threads, policy="FP_DM"):
 
 
 def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
-    """Algorithm 1 with free partition sizes on the paper's Fig. 4 workload:
-    n = 50 tasks, M = 68 units, U = 2..68 step 2, `--n-sets` sets per point
-    (default 1000); one step = the whole batch through capart_alg1_async."""
+    """Algorithm 1 with free partition sizes on the paper's workloads: fig4
+    (n = 50 tasks, Figs. 4-5) or fig6 (n = 200 tasks, Figs. 6-8), M = 68
+    units, U = 2..68 step 2, `--n-sets` sets per point (default 1000); one
+    step = the whole batch through capart_alg1_async.  Also the analysis time
+    per utilisation point (Fig. 8): each point's sets in a launch of their own."""
     import numpy as np
+    import torch
     mode = args.mode
     pol = args.policy
+    n = 50 if args.workload == "fig4" else 200
+    fig = "Fig. 4" if n == 50 else "Figs. 6-8"
     per_point = args.n_sets or 1000
-    ts = workload.config_paper_fig4(sets_per_point=per_point)
+    ts = workload.config_paper_fig4(sets_per_point=per_point, n=n)
     S, N = ts.n_sets, ts.n_tasks
-    desc = (f"paper Fig. 4: {S} task sets ({per_point} per point, U = 2..68 step 2), n=50, M=68, "
+    desc = (f"paper {fig}: {S} task sets ({per_point} per point, U = 2..68 step 2), n={n}, M=68, "
             f"D=0.75T, T log-uniform 50..4000 us, Algorithm 1 {mode}" + (f", {pol} per partition" if pol != "FP_DM" else ""))
-    log(f"[bench] workload fig4: {desc}")
+    log(f"[bench] workload {args.workload}: {desc}")
     dev = capart.device_tasksets(ts)
     out = capart.device_alg1_results(S, N)
 
     def step():
-        capart.capart_alg1_async(eng.ctx, dev, mode, out, max_tasks=50, max_M=68, policy=pol)
+        capart.capart_alg1_async(eng.ctx, dev, mode, out, max_tasks=n, max_M=68, policy=pol)
 
     for i in range(args.warmup):
         step()
@@ -231,16 +237,37 @@ def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
         eff[str(2 * (i + 1))] = None if not ok.any() else {
             "best": float(best[sl][ok].mean()), "worst": float(worst[sl][ok].mean()),
             "scheduled": float(wl[sl][ok].mean())}
+    # analysis time by utilisation (Fig. 8): one point's sets per launch, HIP
+    # events on the launch stream, the mean of three launches after a warmup
+    per_U = {}
+    s_launch = torch.cuda.current_stream()
+    for i in range(len(rate)):
+        sub = workload.subset(ts, np.arange(i * per_point, (i + 1) * per_point))
+        dsub = capart.device_tasksets(sub)
+        osub = capart.device_alg1_results(sub.n_sets, sub.n_tasks)
+        capart.capart_alg1_async(eng.ctx, dsub, mode, osub, max_tasks=n, max_M=68, policy=pol)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s_launch)
+        for _ in range(3):
+            capart.capart_alg1_async(eng.ctx, dsub, mode, osub, max_tasks=n, max_M=68, policy=pol)
+        e1.record(s_launch)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        per_U[str(2 * (i + 1))] = {"ms_per_launch": ms, "us_per_set": 1000.0 * ms / per_point}
+        del dsub, osub
+    log("[bench] analysis time by U (us per set): " +
+        ", ".join(f"{u}: {v['us_per_set']:.2f}" for u, v in per_U.items()))
     wout = capart.device_alg1_results(S, N)
-    work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, 50, 68, policy=pol)
+    work = capart.capart_alg1_count_work(eng.ctx, dev, mode, wout, n, 68, policy=pol)
     del wout
     log(f"[bench] Algorithm 1 kernel {k_ms:.3f} ms/launch, counted work {work}")
     ops = work["terms"] * C_TERM + work["tests"] * C_TEST
     achieved = ops / (k_ms / 1000.0)
-    kname = "alg1_kernel"
+    kname = "alg1_kernel" if n <= 64 else "alg1_big_kernel"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_LANE_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved / PEAK_INT_LANE_OPS,
-            "traffic": traffic_bytes(f"{kname}_fig4_{mode.lower()}{'_edf' if pol == 'EDF' else ''}_traffic.json"),
+            "traffic": traffic_bytes(f"{kname}_{args.workload}_{mode.lower()}{'_edf' if pol == 'EDF' else ''}"
+                                     f"_traffic.json"),
             "kernel": kname, "kernel_ms": k_ms, "ops_per_launch": ops, "work_per_launch": work,
             "ops_per_term": C_TERM, "ops_per_test": C_TEST,
             "other_kernels_ms": {"prep": ms_k["prep"] / max(1, n_k["prep"])},
@@ -248,13 +275,21 @@ def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
             "peak_measured": valu_ops / 1e12, "frac_of_measured_peak": achieved / valu_ops}
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] CPU oracle (Algorithm 1) on all {S} sets with {threads} threads")
-        cb = alg1_cpu_baseline(ts, mode, threads, pol)
-        if cb["schedulable"] != int(verdict.sum()):
+        # fig4: every set; fig6: every 10th set (about 20 ms of oracle work per
+        # 200-task set keeps the leg near 10-30 s)
+        stride = 1 if n <= 64 else 10
+        pick = np.arange(0, S, stride)
+        sample = ts if stride == 1 else workload.subset(ts, pick)
+        log(f"[bench] CPU oracle (Algorithm 1) on {sample.n_sets} sets with {threads} threads")
+        cb = alg1_cpu_baseline(sample, mode, threads, pol)
+        if cb["schedulable"] != int(verdict[pick].sum()):
             raise SystemExit("bench: the oracle's schedulable count differs from the GPU's")
-        one = alg1_cpu_baseline(workload.subset(ts, np.arange(0, S, max(1, S // 500))), mode, 1, pol)
+        one = alg1_cpu_baseline(workload.subset(ts, np.arange(0, S, max(1, S // (500 if n <= 64 else 100)))),
+                                mode, 1, pol)
+        what = f"all {cb['sets']} sets of the workload" if stride == 1 else \
+            f"{cb['sets']} sets (every {stride}th of the workload)"
         cpu = {"value": cb["sets"] / cb["seconds"], "unit": "sets/s", "cores": threads, "kind": "oracle",
-               "sample": f"all {cb['sets']} sets of the workload, {cb['seconds']:.2f} s wall",
+               "sample": f"{what}, {cb['seconds']:.2f} s wall",
                "single_core": {"value": one["sets"] / one["seconds"],
                                "sample": f"{one['sets']} sets spread over the workload, {one['seconds']:.2f} s"},
                "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
@@ -262,9 +297,11 @@ def alg1_main(args, eng, capart, workload, sync, threads, valu_ops):
     res = {"metric": "Algorithm 1 task sets/sec (free partition sizes)", "value": value, "unit": "sets/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": desc, "n_sets": S, "alloc_mode": mode, "policy": pol, "sets_per_point": per_point},
+           "config": {"workload": desc, "n_sets": S, "n_tasks": n, "alloc_mode": mode, "policy": pol,
+                      "sets_per_point": per_point},
            "schedulability_by_U": {str(2 * (i + 1)): float(r) for i, r in enumerate(rate)},
            "efficiency_by_U": eff,
+           "analysis_time_by_U": per_U,
            "mean_partitions_when_schedulable": float(nparts[verdict == 1].mean()) if verdict.any() else None,
            "mean_merges_tried": float(tried.mean()),
            "roofline": roof, "cpu_baseline": cpu}
@@ -277,8 +314,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fig4"],
-                    help="fig4: the paper's Algorithm 1 (free partition sizes) on its Fig. 4 workload")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fig4", "fig6"],
+                    help="fig4 / fig6: the paper's Algorithm 1 (free partition sizes) on its 50-task (Fig. 4) "
+                         "or 200-task (Figs. 6-8) workload")
     ap.add_argument("--mode", default="BF_INA", choices=["BF_INA", "BF_ACT", "SMS_INA", "SMS_ACT"])
     ap.add_argument("--n-sets", type=int, default=0, help="override the workload's number of sets")
     ap.add_argument("--cpu-sample", type=int, default=0, help="task sets timed on the CPU oracle (0 = default)")
@@ -353,7 +391,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
-    if args.workload == "fig4":
+    if args.workload in ("fig4", "fig6"):
         alg1_main(args, eng, capart, workload, sync, threads, valu_ops)
         return
 

@@ -122,6 +122,11 @@ typedef int32_t capart_status;
 #define CAPART_MAX_M       255  /* compute units per set                                  */
 #define CAPART_MAX_K       8    /* parts per partitioning                                  */
 #define CAPART_MAX_NM      8192 /* n * M per set (the per-set time table lives in LDS)    */
+/* Algorithm 1 (capart_alg1 calls) also takes sets of up to 256 tasks under
+ * fixed priority, with M <= 127 and n * M <= CAPART_ALG1_BIG_MAX_NM per set */
+#define CAPART_ALG1_MAX_TASKS  256
+#define CAPART_ALG1_BIG_MAX_M  127
+#define CAPART_ALG1_BIG_MAX_NM 14336
 
 /*
  * Task sets, structure of arrays.  Set s holds tasks set_offset[s] ..
@@ -151,7 +156,8 @@ typedef int32_t capart_status;
 typedef struct capart_tasksets {
     int64_t n_sets;
     int64_t n_tasks_total;       /* = set_offset[n_sets]                    */
-    int32_t max_tasks;           /* bound on tasks per set, 1..64           */
+    int32_t max_tasks;           /* bound on tasks per set, 1..64 (1..256
+                                    for the capart_alg1 calls)             */
     int32_t max_M;               /* bound on M, 1..255                      */
     const int64_t *set_offset;   /* [n_sets + 1], non-decreasing, from 0    */
     const int32_t *M;            /* [n_sets]                                */
@@ -326,6 +332,13 @@ capart_status capart_solve_async_noalloc(capart_ctx *ctx, const capart_tasksets 
  * Per-set validation as for capart_solve (status[s], the set's outputs then
  * hold the failure values).
  *
+ * Set sizes: a batch with max_tasks <= 64 runs one wave of 64 lanes per set
+ * under either policy.  A batch with max_tasks in 65..CAPART_ALG1_MAX_TASKS
+ * (the paper's 200-task experiments) runs one block of 256 threads per set:
+ * it takes CAPART_POLICY_FP_DM only and max_M <= CAPART_ALG1_BIG_MAX_M (else
+ * E_INVAL for the call), and a set with n * M > CAPART_ALG1_BIG_MAX_NM gets
+ * status E_INVAL.  Results are the same whichever path runs a set.
+ *
  * Results (caller-owned; device pointers for the async call, host pointers for
  * capart_alg1):
  *   status[S], verdict[S];
@@ -337,8 +350,8 @@ capart_status capart_solve_async_noalloc(capart_ctx *ctx, const capart_tasksets 
  *   R[N]        response time on its partition, -1 if none;
  *   tried[S], merged[S]  merges attempted (Algorithm 2 runs the algorithm
  *               asks for) and accepted; both 0 for sets rejected before any.
- * One wave of 64 lanes per set; every set of the batch runs in one launch
- * (after the prep kernel) ordered on hip_stream.
+ * Every set of the batch runs in one launch (after the prep kernel) ordered
+ * on hip_stream.
  */
 typedef struct capart_alg1_results {
     int32_t *status;

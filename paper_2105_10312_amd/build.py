@@ -40,6 +40,7 @@ def units():
     for pol in ("POL_FP", "POL_EDF"):
         u.append((f"wide_{pol[4:].lower()}", "capart_launch_wide.hip", [f"-DCAPART_I_POL={pol}"]))
         u.append((f"alg1_{pol[4:].lower()}", "capart_launch_alg1.hip", [f"-DCAPART_I_POL={pol}"]))
+    u.append(("alg1_big", "capart_launch_alg1big.hip", []))
     return u
 
 

@@ -24,6 +24,7 @@ CAPART_POLICY_FP_DM = 0
 CAPART_POLICY_EDF = 1
 POLICIES = {"FP_DM": CAPART_POLICY_FP_DM, "EDF": CAPART_POLICY_EDF}
 CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
+CAPART_ALG1_MAX_TASKS, CAPART_ALG1_BIG_MAX_M, CAPART_ALG1_BIG_MAX_NM = 256, 127, 14336
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
 EXPORTS = ["capart_create", "capart_destroy", "capart_last_error", "capart_build_hash", "capart_measure_valu",
@@ -205,13 +206,15 @@ def make_options(K: int, mode="BF_INA", flags: int = 0, admissible=None, policy=
                           (C.c_uint64 * 4)(*admissible_mask(admissible)))
 
 
-def make_tasksets(ts: dict, max_tasks: int | None = None, max_M: int | None = None) -> tuple:
-    """capart_tasksets over numpy (host) or torch (device) arrays; returns (struct, keep-alive)."""
+def make_tasksets(ts: dict, max_tasks: int | None = None, max_M: int | None = None, tasks_cap: int = 64) -> tuple:
+    """capart_tasksets over numpy (host) or torch (device) arrays; returns (struct, keep-alive).
+    Without max_tasks the bound is the largest set, capped at tasks_cap (256 for
+    the Algorithm 1 calls)."""
     off = ts["set_offset"]
     S = int(ts["M"].shape[0])
     if max_tasks is None:
         sizes = np.diff(np.asarray(off.cpu() if hasattr(off, "cpu") else off))
-        max_tasks = int(min(64, max(1, sizes.max() if S else 1)))
+        max_tasks = int(min(tasks_cap, max(1, sizes.max() if S else 1)))
     if max_M is None:
         Mh = ts["M"].cpu().numpy() if hasattr(ts["M"], "cpu") else ts["M"]
         max_M = int(min(255, max(1, Mh.max() if S else 1)))
@@ -429,7 +432,7 @@ def capart_alg1(ctx, ts: dict, mode="BF_INA", flags: int = 0, max_tasks=None, ma
     """Algorithm 1 (free partition sizes) over a host batch (synchronous); numpy results.
     sizes[set_offset[s] : set_offset[s] + nparts[s]] are set s's partitions in par_list order."""
     h = _host_ts(ts)
-    st, _keep = make_tasksets(h, max_tasks, max_M)
+    st, _keep = make_tasksets(h, max_tasks, max_M, tasks_cap=256)
     opt = make_options(1, mode, flags, policy=policy)
     S, N = st.n_sets, st.n_tasks_total
     out = {name: np.zeros(max(S if shape == "S" else N, 1), dt) for name, dt, shape in ALG1_FIELDS}

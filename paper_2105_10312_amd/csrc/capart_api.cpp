@@ -168,12 +168,14 @@ capart_status check_options(capart_ctx *c, const capart_options *opt)
     return CAPART_OK;
 }
 
-capart_status check_batch_shape(capart_ctx *c, const capart_tasksets *in)
+// tasks_bound: CAPART_MAX_TASKS, or CAPART_ALG1_MAX_TASKS for the Algorithm 1 calls
+capart_status check_batch_shape(capart_ctx *c, const capart_tasksets *in, int tasks_bound = CAPART_MAX_TASKS)
 {
     if (!in) return fail(c, CAPART_E_INVAL, "task sets is NULL");
     if (in->n_sets < 0 || in->n_tasks_total < 0) return fail(c, CAPART_E_INVAL, "negative size");
     if (in->n_sets > ((int64_t)1 << 31) - 1) return fail(c, CAPART_E_INVAL, "too many sets for one launch");
-    if (in->max_tasks < 1 || in->max_tasks > CAPART_MAX_TASKS) return fail(c, CAPART_E_INVAL, "max_tasks out of [1,64]");
+    if (in->max_tasks < 1 || in->max_tasks > tasks_bound)
+        return fail(c, CAPART_E_INVAL, tasks_bound == CAPART_MAX_TASKS ? "max_tasks out of [1,64]" : "max_tasks out of [1,256]");
     if (in->max_M < 1 || in->max_M > CAPART_MAX_M) return fail(c, CAPART_E_INVAL, "max_M out of [1,255]");
     if (in->n_sets > 0 && (!in->set_offset || !in->M))
         return fail(c, CAPART_E_INVAL, "NULL set arrays");
@@ -869,8 +871,14 @@ static capart_status alg1_check(capart_ctx *c, const capart_tasksets *in, const 
         return fail(c, CAPART_E_INVAL, "Algorithm 1 takes every partition size (admissible must be empty)");
     if (opt->flags & ~(CAPART_FLAG_SKIP_1G | CAPART_FLAG_NO_LEMMA1 | CAPART_FLAG_PER_SET_LAUNCH))
         return fail(c, CAPART_E_INVAL, "unknown flag");
-    capart_status rc = check_batch_shape(c, in);
+    capart_status rc = check_batch_shape(c, in, CAPART_ALG1_MAX_TASKS);
     if (rc != CAPART_OK) return rc;
+    if (in->max_tasks > CAPART_MAX_TASKS) {
+        if (opt->policy != CAPART_POLICY_FP_DM)
+            return fail(c, CAPART_E_INVAL, "sets of more than 64 tasks take the fixed-priority policy");
+        if (in->max_M > CAPART_ALG1_BIG_MAX_M)
+            return fail(c, CAPART_E_INVAL, "sets of more than 64 tasks take max_M <= 127");
+    }
     if (in->n_sets > 0 && (!out || !out->status || !out->verdict || !out->nparts || !out->tried || !out->merged))
         return fail(c, CAPART_E_INVAL, "NULL result array");
     if (in->n_tasks_total > 0 && (!out->sizes || !out->alloc || !out->R))
@@ -911,10 +919,14 @@ static capart_status alg1_run(capart_ctx *c, const capart_tasksets *in, const ca
             if (!(x = take_event(c))) return fail(c, CAPART_E_DEVICE, "hipEventCreate failed");
     (void)hipGetLastError();
     if (counts && (e = hipMemsetAsync(w.counters, 0, 16, st)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+    const bool big = in->max_tasks > CAPART_MAX_TASKS;  // one block of 256 threads per set
     if (tm) hipEventRecord(ev[0], st);
-    if ((e = launch_prep(b, w, po, L, st)) != hipSuccess) return hip_fail(c, e, "prep launch");
+    if ((e = big ? launch_prep_big(b, w, po, L, st) : launch_prep(b, w, po, L, st)) != hipSuccess)
+        return hip_fail(c, e, "prep launch");
     if (tm) hipEventRecord(ev[1], st);
-    if ((e = launch_alg1(b, w, a, L, st, counts != nullptr)) != hipSuccess) return hip_fail(c, e, "Algorithm 1 launch");
+    if ((e = big ? launch_alg1_big(b, w, a, L, st, counts != nullptr) : launch_alg1(b, w, a, L, st, counts != nullptr)) !=
+        hipSuccess)
+        return hip_fail(c, e, "Algorithm 1 launch");
     if (tm) {
         hipEventRecord(ev[2], st);
         hipEventRecord(ev[3], st);

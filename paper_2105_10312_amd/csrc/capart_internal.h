@@ -156,6 +156,12 @@ struct A1Out {
 // count: the counting variant (adds response-time terms and exact tests to w.counters[0..1])
 hipError_t launch_alg1(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st,
                        bool count = false);
+// Algorithm 1 for batches with sets of more than 64 tasks (fixed priority): its
+// own prep kernel, then one block of 256 threads per set.
+hipError_t launch_prep_big(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
+hipError_t launch_alg1_big(const Batch &b, const Work &w, const A1Out &o, const Launch &L, hipStream_t st,
+                           bool count);
+hipError_t allow_alg1_big();
 hipError_t launch_eval(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st);
 // evaluation restricted to partitioning indices [p_lo, p_hi)
 hipError_t launch_eval_range(const Batch &b, const Work &w, const Out &o, const Launch &L, hipStream_t st,

@@ -367,6 +367,7 @@ hipError_t configure_kernels()
     CAPART_ALLOW(WideLaunch<POL_EDF>::allow());
     CAPART_ALLOW(Alg1Launch<POL_FP>::allow());
     CAPART_ALLOW(Alg1Launch<POL_EDF>::allow());
+    CAPART_ALLOW(allow_alg1_big());
     CAPART_ALLOW(allow_lds(subset_table_kernel));
     CAPART_ALLOW(allow_lds(final_kernel<4>));
     CAPART_ALLOW(allow_lds(final_kernel<8>));
