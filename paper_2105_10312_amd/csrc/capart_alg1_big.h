@@ -174,6 +174,30 @@ __device__ __forceinline__ bool big_test(const BigLDS &L, const uint32_t *tc, in
     return true;
 }
 
+// The same test with the whole block (all threads call it): thread r tests
+// member r against the members above it, and the partition passes when every
+// member does.  okf[par] collects the result; okf[par ^ 1] is made ready for
+// the next call once every thread has read the previous call's result.
+template <typename TY>
+__device__ __forceinline__ bool coop_test(const BigLDS &L, const uint32_t *tc, int n, const M256 &S, int m,
+                                          const M256 &cm, int *okf, int &par, TY &ty)
+{
+    const int t = threadIdx.x;
+    __syncthreads();
+    if (t == 0) {
+        okf[par ^ 1] = 1;
+        ty.test();
+    }
+    if (t < n && m_has(S, t) && !big_rta(L, tc, n, t, m_and(S, m_prefix(t)), m, cm, ty)) okf[par] = 0;
+    __syncthreads();
+    const bool r = okf[par] != 0;
+    par ^= 1;
+    return r;
+}
+
+// Operands of at least this many members take the block-wide tests under ">".
+constexpr int LAZY_MIN = 32;
+
 // ---------------------------------------------------------------------------
 // prep for batches with sets of up to 256 tasks: validation, DM ranks, Lemma 1,
 // Lemma 2; one block of 256 threads per set (thread i reads task i), records
@@ -280,7 +304,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __shared__ BigLDS L;
     // block communication
     __shared__ M256 s_Sc, s_Xc, s_X3, s_S3, s_fail, s_Pm[BIGN];
-    __shared__ int s_c, s_bestl, s_cnt, s_mc, s_m3, s_mj, s_lead, s_ok, s_idj;
+    __shared__ int s_c, s_bestl, s_cnt, s_mc, s_m3, s_mj, s_lead, s_ok, s_idj, s_lo, s_hi;
+    __shared__ int s_okf[2];  // results of the block-wide tests, alternating
+    __shared__ M256 s_cm3;
     __shared__ unsigned long long s_besta, s_U3, s_wl, s_tried;
     __shared__ uint64_t s_PU[BIGN];
     __shared__ M256 s_PX[BIGN];
@@ -394,6 +420,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         Pm = s_Pm[t]; PX = s_PX[t]; PU = s_PU[t]; Pmu = s_Pmu[t]; Pl = s_Pl[t];
         __syncthreads();
     }
+    if (t == 0) s_okf[0] = 1;  // the first block-wide test's flag (others are set one test ahead)
+    int par = 0;
     M256 live = m_prefix(n);  // ids of the partitions
     int np = n;
     int64_t tried = 0, merged = 0;
@@ -416,42 +444,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         const int mc = s_mc;
         const int idc_i = m_low(Sc);
         const bool elig = t < np && t != c && !m_has(Xc, idb_i);
-        // every eligible partner's merge, one thread each; rank key (ka, t)
         bool mok = false;
         int m3 = 0;
         uint64_t U3 = 0, ka = ~0ull;
         M256 S3 = m_zero();
-        if (elig) {
-            S3 = m_or(Sc, Pm);
-            const M256 cm = big_conflicts(S3, memm);
-            const int mlo = max(mc, Pmu), mhi = min(mc + Pmu - 1, M);
-            if (!SMS) ka = big_group_util(L, tc, n, S3, mlo, cm);
-            if (mlo <= mhi && big_test(L, tc, n, S3, mhi, cm, ty)) {
-                int lo = mlo, hi = mhi;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (big_test(L, tc, n, S3, mid, cm, ty))
-                        hi = mid;
-                    else
-                        lo = mid + 1;
+        bool counted = false, forbid = false;
+        int best_l = BIGN;
+        if (SMS || m_popc(Sc) < LAZY_MIN) {
+            // every eligible partner's merge, one thread each; rank key (ka, t)
+            if (elig) {
+                S3 = m_or(Sc, Pm);
+                const M256 cm = big_conflicts(S3, memm);
+                const int mlo = max(mc, Pmu), mhi = min(mc + Pmu - 1, M);
+                if (!SMS) ka = big_group_util(L, tc, n, S3, mlo, cm);
+                if (mlo <= mhi && big_test(L, tc, n, S3, mhi, cm, ty)) {
+                    int lo = mlo, hi = mhi;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (big_test(L, tc, n, S3, mid, cm, ty))
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    mok = true;
+                    m3 = lo;
+                    U3 = big_group_util(L, tc, n, S3, lo, cm);
                 }
-                mok = true;
-                m3 = lo;
-                U3 = big_group_util(L, tc, n, S3, lo, cm);
+                if (SMS && mok) ka = ((uint64_t)m3 << 44) | U3;  // U3 <= 256 * 2^32: every member meets D <= T
             }
-            if (SMS && mok) ka = ((uint64_t)m3 << 44) | U3;  // U3 <= 256 * 2^32: every member meets D <= T
+            if (mok) atomicMin(&s_besta, (unsigned long long)ka);
+            __syncthreads();
+            const uint64_t best_a = s_besta;
+            if (mok && ka == best_a) atomicMin(&s_bestl, t);
+            __syncthreads();
+            best_l = s_bestl;
+            const bool before = ka < best_a || (ka == best_a && t < best_l);
+            // failed merges that forbid their pairs: for ">" those ranked before the
+            // merge taken (all of them if none is valid), for ">>" all of them
+            forbid = elig && !mok && (SMS || before);
+            counted = elig && (SMS || before || t == best_l);
+        } else {
+            // ">" with a large operand: the partners are ranked by (ka, t) as
+            // above, then tried in that order, each merge's tests spread over
+            // the union's members (a thread per member), until one is valid;
+            // the same merges are tried, taken and forbidden as above
+            M256 cm = m_zero();
+            int mlo = 0, mhi = 0;
+            if (elig) {
+                S3 = m_or(Sc, Pm);
+                cm = big_conflicts(S3, memm);
+                mlo = max(mc, Pmu);
+                mhi = min(mc + Pmu - 1, M);
+                ka = big_group_util(L, tc, n, S3, mlo, cm);
+            }
+            bool pend = elig;
+            for (;;) {
+                if (t == 0) { s_besta = ~0ull; s_bestl = BIGN; }
+                __syncthreads();
+                if (pend) atomicMin(&s_besta, (unsigned long long)ka);
+                __syncthreads();
+                if (pend && ka == s_besta) atomicMin(&s_bestl, t);
+                __syncthreads();
+                const int x = s_bestl;
+                if (x >= BIGN) break;  // every eligible merge failed
+                if (t == x) { s_S3 = S3; s_cm3 = cm; s_lo = mlo; s_hi = mhi; pend = false; counted = true; }
+                __syncthreads();
+                const M256 Sx = s_S3, cx = s_cm3;
+                int lo = s_lo, hi = s_hi;
+                const bool okx = lo <= hi && coop_test(L, tc, n, Sx, hi, cx, s_okf, par, ty);
+                if (okx) {
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (coop_test(L, tc, n, Sx, mid, cx, s_okf, par, ty))
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                }
+                if (t == x) {
+                    if (okx) {
+                        mok = true;
+                        m3 = lo;
+                        U3 = big_group_util(L, tc, n, S3, lo, cm);
+                    } else {
+                        forbid = true;
+                    }
+                }
+                if (okx) { best_l = x; break; }
+            }
         }
-        if (mok) atomicMin(&s_besta, (unsigned long long)ka);
-        __syncthreads();
-        const uint64_t best_a = s_besta;
-        if (mok && ka == best_a) atomicMin(&s_bestl, t);
-        __syncthreads();
-        const int best_l = s_bestl;
-        const bool before = ka < best_a || (ka == best_a && t < best_l);
-        // failed merges that forbid their pairs: for ">" those ranked before the
-        // merge taken (all of them if none is valid), for ">>" all of them
-        const bool forbid = elig && !mok && (SMS || before);
-        if (elig && (SMS || before || t == best_l)) atomicAdd(&s_tried, 1ull);
+        if (counted) atomicAdd(&s_tried, 1ull);
         if (forbid) {
             PX = m_or(PX, m_bit(idc_i));
             atomicOr((unsigned long long *)&s_fail.w[idb_i >> 6], (unsigned long long)(1ull << (idb_i & 63)));
