@@ -149,9 +149,10 @@ typedef int32_t capart_status;
  * [1, 2^31), non-increasing in m, Cc >= Cn at every m, and m * Cn(m) >= Cn(1)
  * (no super-linear speed-up, which Lemma 1 needs).  table_offset[s] >= 0 and
  * table_offset[s] + n * M[s] <= table_len (else E_INVAL).  Tables are taken by
- * capart_validate, capart_solve, capart_solve_async, capart_count_work and the
- * capart_alg1 calls; the batched plans, the server and the one-set calls
- * (capart_test_triple, capart_allocate) return E_INVAL for them.
+ * capart_validate, capart_solve, capart_solve_async,
+ * capart_solve_async_noalloc, capart_count_work, the batched plans and the
+ * capart_alg1 calls; the server and the one-set calls (capart_test_triple,
+ * capart_allocate) return E_INVAL for them.
  */
 typedef struct capart_tasksets {
     int64_t n_sets;

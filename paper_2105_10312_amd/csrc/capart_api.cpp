@@ -1435,9 +1435,11 @@ capart_status alloc_plan_buffers(capart_ctx *c, int64_t S, int64_t N, const std:
     return CAPART_OK;
 }
 
-capart_status launch_plan_kernels(capart_ctx *c, const Batch &b, const Work &w, const Out &o, const Launch &L,
+capart_status launch_plan_kernels(capart_ctx *c, const Batch &b, const Work &w0, const Out &o, const Launch &L,
                                   int blocks, hipStream_t st, bool timed)
 {
+    Work w = w0;
+    give_tables(w, b);  // explicit time tables, where the batch has them
     std::array<hipEvent_t, 4> ev{};
     if (timed)
         for (auto &e : ev)
@@ -1496,7 +1498,6 @@ capart_status capart_plan_batch(capart_ctx *c, const capart_tasksets *in, const 
     if ((rc = check_options(c, opt)) != CAPART_OK) return rc;
     if ((rc = check_batch_shape(c, in)) != CAPART_OK) return rc;
     if (opt->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "the batched form runs heuristic modes");
-    if (has_tables(in)) return fail(c, CAPART_E_INVAL, "explicit time tables are not taken by the batched form");
     if (in->n_sets < 1) return fail(c, CAPART_E_INVAL, "empty batch");
     if (!results_ok(out)) return fail(c, CAPART_E_INVAL, "NULL result array");
     const capart_plan_config def{1, 0, 0, 1};
@@ -2315,6 +2316,7 @@ capart_status capart_server_replay(capart_server *v, const capart_tasksets *qs, 
                                    capart_results *res, capart_server_stats *stats)
 {
     if (!v || !qs || !arrival_us || !stats || qs->n_sets < 0 || !qs->set_offset || !qs->M) return CAPART_E_INVAL;
+    if (has_tables(qs)) return srv_fail(v, CAPART_E_INVAL, "explicit time tables are not taken by the server");
     const int64_t nq = qs->n_sets;
     {
         std::lock_guard<std::mutex> lk(v->mu);

@@ -3,8 +3,8 @@
 Tables that restate the parametric model give the parametric results bit for
 bit; general tables (saturating memory-intensive profiles) give the oracle's
 results bit for bit in every allocation mode, for Algorithm 1, on the host and
-device entry points; tables outside the contract get the oracle's status; the
-paths that do not take tables refuse them."""
+device entry points and through the batched plans; tables outside the
+contract get the oracle's status; the server refuses them."""
 import os
 import sys
 
@@ -161,11 +161,42 @@ def test_tables_outside_the_contract(eng):
     assert got["status"][0] == capart.CAPART_E_RANGE and got["status"][2] == capart.CAPART_E_RANGE
 
 
-def test_paths_without_tables_refuse_them(eng):
+@pytest.mark.parametrize("mode", ["BF_INA", "SMS_ACT"])
+def test_batched_plans_with_tables(eng, mode):
+    """The batched form (autotuned plan, HIP graph, three replays with eager
+    work between them) on general tables: the plain path's results, which the
+    tests above check against the oracle, on every replay; a sample against
+    the oracle directly."""
     import torch
-    ts = tables_only(workload.with_time_tables(workload.config_c1(n_sets=4), seed=97))
+    c2 = workload.subset(workload.config_c2(n_sets=3000), np.arange(2000))
+    c3 = workload.subset(workload.config_c3(n_sets=3000), np.arange(1500))
+    ts = tables_only(workload.with_time_tables(workload.concat([c2, c3]), seed=98))
     dev = capart.device_tasksets(ts)
-    out = capart.device_results(ts.n_sets, ts.n_tasks, 3)
-    with pytest.raises(capart.CapartError):
-        capart.Plan(eng.ctx, dev, 3, "BF_INA", out, 5, 8)
-    torch.cuda.synchronize()
+    out = capart.device_results(ts.n_sets, ts.n_tasks, 4)
+    plan = capart.Plan(eng.ctx, dev, 4, mode, out, 32, 108)
+    want = eng.solve(ts, 4, mode)
+    for rep in range(3):
+        plan.run()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        for f in FIELDS:
+            n = np.asarray(want[f]).size
+            assert np.array_equal(got[f].ravel()[:n], np.asarray(want[f]).ravel()), (f, rep)
+        torch.zeros(1 << 20, device="cuda").sum().item()
+    pick = np.arange(0, ts.n_sets, 50)
+    sub = workload.subset(ts, pick)
+    ref = oracle.solve(sub, 4, mode, nthreads=THREADS)
+    mine = eng.solve(sub, 4, mode)
+    same(mine, ref, FIELDS, f"tables sample {mode}")
+    plan.close()
+    say(f"batched tables {mode}: {int(want['verdict'].sum())} of {ts.n_sets} schedulable")
+
+
+def test_paths_without_tables_refuse_them(eng):
+    ts = tables_only(workload.with_time_tables(workload.config_c1(n_sets=4), seed=97))
+    srv = capart.Server(eng.ctx, K=3, mode="BF_INA", max_tasks=5, max_M=8)
+    try:
+        with pytest.raises(capart.CapartError):
+            srv.replay(ts, np.zeros(ts.n_sets))
+    finally:
+        srv.close()
