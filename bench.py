@@ -398,11 +398,11 @@ def main():
     if args.workload == "c2":
         ts = workload.config_c2(n_sets=args.n_sets or 100_000)
         max_tasks, max_M, desc = 10, 80, "n=10, M=80"
-        cpu_sample, cpu_stride = args.cpu_sample or 30000, 1
+        cpu_sample, cpu_stride = args.cpu_sample or 100_000, 1  # the whole batch
     elif args.workload == "c3":
         ts = workload.config_c3(n_sets=args.n_sets or 1_000_000)
         max_tasks, max_M, desc = 32, 108, "n uniform 4..32, M in {16,48,80,108}, constrained deadlines"
-        cpu_sample, cpu_stride = args.cpu_sample or 6000, 100
+        cpu_sample, cpu_stride = args.cpu_sample or 10_000, 100
     else:
         ts = workload.config_c4(n_sets=args.n_sets or 1000)
         max_tasks, max_M, desc = 12, 48, "n=12, M=48, exhaustive allocation"
@@ -563,7 +563,7 @@ def main():
         # decodes every triple and would take hours per set)
         import oracle
         cflags = oracle.FLAG_EXH_FAST
-        cpu_sample = args.cpu_sample or 1
+        cpu_sample = args.cpu_sample or 10  # 10 sets x all 1,033 partitionings (about 45 s per set and thread)
         threads = min(threads, cpu_sample)
     if args.no_cpu:
         cb = None if mode == "EXH" else cpu_baseline(ts, K, mode, 200, threads, cpu_stride, adm, pol)
