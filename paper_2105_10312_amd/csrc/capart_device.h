@@ -837,8 +837,9 @@ template <int KMAX, bool ACT, bool SMS, typename MT, typename TY>
 __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int n, const int (&m)[KMAX], int k,
                                           MT (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty, const Memo &mo = Memo{nullptr, 0u})
 {
+    int lbm[KMAX];  // per part, the largest Lemma 2 size of its members (SMS: a floor on the fewest units)
 #pragma unroll
-    for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; }
+    for (int p = 0; p < KMAX; p++) { S[p] = MT(0); U[p] = 0ull; lbm[p] = 0; }
     // Capacity stop: every part of a schedulable partitioning has utilisation at
     // most 1, a placed task never gets cheaper (members only gain conflicts),
     // and an unplaced task needs at least its conflict-free utilisation on the
@@ -865,6 +866,18 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
             const MT Sp = S[p];
             if (p >= k || mm > mp) continue;
             if (ACT && (fb & Sp)) continue;
+            // a part that cannot beat the best so far whatever its test says is not
+            // tested: under ">" when its utilisation with the task is not below the
+            // best's; under ">>" when the fewest units it could need (the largest
+            // Lemma 2 size of its members) already exceed the best's, or equal them
+            // with a utilisation not below the best's
+            if (best >= 0) {
+                if (!SMS && util_add<MT>(L, tb, Sp, r, mp, U[p]) >= bestU) continue;
+                if (SMS) {
+                    const int lb = max(lbm[p], mm);
+                    if (lb > bestReq || (lb == bestReq && util_add<MT>(L, tb, Sp, r, mp, U[p]) >= bestU)) continue;
+                }
+            }
             uint64_t Un;
             int req = 0;
             if (sizeof(MT) == 4 && mo.mask) {
@@ -893,7 +906,7 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
         uint64_t Uold = 0;
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
-            if (p == best) { Uold = U[p]; S[p] |= MT(1) << r; U[p] = bestU; }
+            if (p == best) { Uold = U[p]; S[p] |= MT(1) << r; U[p] = bestU; lbm[p] = max(lbm[p], mm); }
         need -= (uint64_t)urow1[r];
         room = room + 1ull - (bestU - Uold);
     }
@@ -944,8 +957,9 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
                                uint64_t (&S)[KMAX], uint64_t (&U)[KMAX], TY &ty)
 {
     const uint64_t memm = L.memmask;
+    int lbm[KMAX];  // per part, the largest Lemma 2 size of its members
 #pragma unroll
-    for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; }
+    for (int p = 0; p < KMAX; p++) { S[p] = 0ull; U[p] = 0ull; lbm[p] = 0; }
     // the capacity stop of heuristic(): lane i holds task i's conflict-free
     // utilisation on the largest part, less one (a lower bound in Q32)
     const int lane = threadIdx.x & 63;
@@ -977,9 +991,17 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
                 flip = __builtin_ctzll(same);
                 first = min(first, flip);
             }
-            if (!wave_test_from(L, tb, Sn, first, mp, cm, ty)) continue;
             uint64_t Un = U[p] + util_term(L, tb, r, mp, ns >= 1 ? 1u : 0u);
             if (flip >= 0) Un += util_term(L, tb, flip, mp, 1u) - util_term(L, tb, flip, mp, 0u);
+            // cannot beat the best so far whatever its test says (as in heuristic()): no test
+            if (best >= 0) {
+                if (!SMS && Un >= bestU) continue;
+                if (SMS) {
+                    const int lb = max(lbm[p], mm);
+                    if (lb > bestReq || (lb == bestReq && Un >= bestU)) continue;
+                }
+            }
+            if (!wave_test_from(L, tb, Sn, first, mp, cm, ty)) continue;
             int req = 0;
             if (SMS) {  // fewest units for Sn (binary search, as min_units)
                 int lo = 1;
@@ -1001,7 +1023,7 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
         uint64_t Uold = 0;
 #pragma unroll
         for (int p = 0; p < KMAX; p++)
-            if (p == best) { Uold = U[p]; S[p] |= 1ull << r; U[p] = bestU; }
+            if (p == best) { Uold = U[p]; S[p] |= 1ull << r; U[p] = bestU; lbm[p] = max(lbm[p], mm); }
         need -= __shfl(li, r, 64);
         room = room + 1ull - (bestU - Uold);
     }
