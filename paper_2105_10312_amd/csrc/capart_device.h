@@ -859,48 +859,75 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
         const MT fb = ACT ? (MT)L.forbid[r] : MT(0);
         int best = -1, bestReq = 0;
         uint64_t bestU = 0;
-        // parts are visited with compile-time indices so that S, U and m stay in registers
-#pragma unroll
-        for (int p = 0; p < KMAX; p++) {
-            const int mp = m[p];
-            const MT Sp = S[p];
-            if (p >= k || mm > mp) continue;
-            if (ACT && (fb & Sp)) continue;
-            // a part that cannot beat the best so far whatever its test says is not
-            // tested: under ">" when its utilisation with the task is not below the
-            // best's; under ">>" when the fewest units it could need (the largest
-            // Lemma 2 size of its members) already exceed the best's, or equal them
-            // with a utilisation not below the best's
-            if (best >= 0) {
-                if (!SMS && util_add<MT>(L, tb, Sp, r, mp, U[p]) >= bestU) continue;
-                if (SMS) {
-                    const int lb = max(lbm[p], mm);
-                    if (lb > bestReq || (lb == bestReq && util_add<MT>(L, tb, Sp, r, mp, U[p]) >= bestU)) continue;
-                }
-            }
+        // the candidate test of part (Sp, mp): through the memo where the set has
+        // one (a recorded fact, else the incremental test, recorded), else direct
+        auto passes = [&](MT Sp, int mp, uint64_t Up, int &f, int &pz) -> bool {
             uint64_t Un;
-            int req = 0;
+            f = 0;
+            pz = 256;
             if (sizeof(MT) == 4 && mo.mask) {
-                // through the memo: a recorded fact, else the incremental test (recorded)
                 const MT Sn = Sp | (MT(1) << r);
-                int f, pz;
                 ty.look();
                 memo_get(mo, (uint32_t)Sn, f, pz);
                 bool ok = mp >= pz;
                 if (!ok && mp > f) {
-                    ok = part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty);
+                    ok = part_test_add<MT>(L, tb, Sp, r, mp, Up, &Un, ty);
                     memo_put(mo, (uint32_t)Sn, mp, ok);
                     if (ok) pz = mp;
                 }
-                if (!ok) continue;
-                Un = util_add<MT>(L, tb, Sp, r, mp, U[p]);
-                if (SMS) req = min_units_memo<MT>(L, tb, Sn, f, min(pz, mp), mo, ty);
-            } else {
-                if (!part_test_add<MT>(L, tb, Sp, r, mp, U[p], &Un, ty)) continue;
-                if (SMS) req = min_units<MT>(L, tb, Sp | (MT(1) << r), mp, ty);
+                return ok;
             }
-            const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
-            if (better) { best = p; bestU = Un; bestReq = req; }
+            return part_test_add<MT>(L, tb, Sp, r, mp, Up, &Un, ty);
+        };
+        if (!SMS) {
+            // ">": the part taken is the passing one of least (utilisation with the
+            // task, index).  The utilisations are known from the tables before any
+            // test, so the candidates are tested in that order and the first that
+            // passes is taken; the others need no test.  (Parts are selected with
+            // compile-time indices so that S, U and m stay in registers.)
+            uint64_t un[KMAX];
+            uint32_t cand = 0u;
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                un[p] = 0ull;
+                if (p >= k || mm > m[p] || (ACT && (fb & S[p]))) continue;
+                un[p] = util_add<MT>(L, tb, S[p], r, m[p], U[p]);
+                cand |= 1u << p;
+            }
+            while (cand) {
+                int q = -1, mq = 0;
+                uint64_t uq = 0ull, Uq = 0ull;
+                MT Sq = MT(0);
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (((cand >> p) & 1u) && (q < 0 || un[p] < uq)) { q = p; uq = un[p]; Sq = S[p]; mq = m[p]; Uq = U[p]; }
+                cand &= ~(1u << q);
+                int f, pz;
+                if (passes(Sq, mq, Uq, f, pz)) { best = q; bestU = uq; break; }
+            }
+        } else {
+            // ">>": parts in index order; a part whose fewest units are known to
+            // exceed the best's (they are at least the largest Lemma 2 size of its
+            // members and the task), or to equal them with a utilisation not below
+            // the best's, cannot be taken and needs no test
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                const int mp = m[p];
+                const MT Sp = S[p];
+                if (p >= k || mm > mp) continue;
+                if (ACT && (fb & Sp)) continue;
+                const uint64_t Un = util_add<MT>(L, tb, Sp, r, mp, U[p]);
+                if (best >= 0) {
+                    const int lb = max(lbm[p], mm);
+                    if (lb > bestReq || (lb == bestReq && Un >= bestU)) continue;
+                }
+                int f, pz;
+                if (!passes(Sp, mp, U[p], f, pz)) continue;
+                const MT Sn = Sp | (MT(1) << r);
+                const int req = (sizeof(MT) == 4 && mo.mask) ? min_units_memo<MT>(L, tb, Sn, f, min(pz, mp), mo, ty)
+                                                            : min_units<MT>(L, tb, Sn, mp, ty);
+                if (best < 0 || req < bestReq || (req == bestReq && Un < bestU)) { best = p; bestU = Un; bestReq = req; }
+            }
         }
         if (best < 0) return false;
         uint64_t Uold = 0;
@@ -976,34 +1003,64 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
         const uint64_t typ = ((memm >> r) & 1ull) ? memm : ~memm;
         int best = -1, bestReq = 0;
         uint64_t bestU = 0;
-#pragma unroll
-        for (int p = 0; p < KMAX; p++) {
-            const int mp = m[p];
-            const uint64_t Sp = S[p];
-            if (p >= k || mm > mp) continue;
-            if (ACT && (fb & Sp)) continue;
-            const uint64_t Sn = Sp | (1ull << r);
+        // part p's union with the task: its mask, conflict mask, first member
+        // whose response time can change, and utilisation
+        auto cand_of = [&](uint64_t Sp, int mp, uint64_t Up, uint64_t &Sn, uint64_t &cm, int &first) -> uint64_t {
+            Sn = Sp | (1ull << r);
             const uint64_t same = Sp & typ;
             const int ns = __popcll(same);
-            const uint64_t cm = conflict_mask<uint64_t>(Sn, memm);
-            int first = r, flip = -1;
+            cm = conflict_mask<uint64_t>(Sn, memm);
+            first = r;
+            uint64_t Un = Up + util_term(L, tb, r, mp, ns >= 1 ? 1u : 0u);
             if (ns == 1) {
-                flip = __builtin_ctzll(same);
+                const int flip = __builtin_ctzll(same);
                 first = min(first, flip);
+                Un += util_term(L, tb, flip, mp, 1u) - util_term(L, tb, flip, mp, 0u);
             }
-            uint64_t Un = U[p] + util_term(L, tb, r, mp, ns >= 1 ? 1u : 0u);
-            if (flip >= 0) Un += util_term(L, tb, flip, mp, 1u) - util_term(L, tb, flip, mp, 0u);
-            // cannot beat the best so far whatever its test says (as in heuristic()): no test
-            if (best >= 0) {
-                if (!SMS && Un >= bestU) continue;
-                if (SMS) {
+            return Un;
+        };
+        if (!SMS) {
+            // ">": candidates tested in order of (utilisation with the task,
+            // index), the first that passes taken (as in heuristic())
+            uint64_t un[KMAX];
+            uint32_t cand = 0u;
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                un[p] = 0ull;
+                if (p >= k || mm > m[p] || (ACT && (fb & S[p]))) continue;
+                uint64_t Sn, cm;
+                int first;
+                un[p] = cand_of(S[p], m[p], U[p], Sn, cm, first);
+                cand |= 1u << p;
+            }
+            while (cand) {
+                int q = -1, mq = 0;
+                uint64_t uq = 0ull, Sq = 0ull, Uq = 0ull;
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (((cand >> p) & 1u) && (q < 0 || un[p] < uq)) { q = p; uq = un[p]; Sq = S[p]; mq = m[p]; Uq = U[p]; }
+                cand &= ~(1u << q);
+                uint64_t Sn, cm;
+                int first;
+                cand_of(Sq, mq, Uq, Sn, cm, first);
+                if (wave_test_from(L, tb, Sn, first, mq, cm, ty)) { best = q; bestU = uq; break; }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < KMAX; p++) {
+                const int mp = m[p];
+                if (p >= k || mm > mp) continue;
+                if (ACT && (fb & S[p])) continue;
+                uint64_t Sn, cm;
+                int first;
+                const uint64_t Un = cand_of(S[p], mp, U[p], Sn, cm, first);
+                // cannot be taken whatever its test says (as in heuristic()): no test
+                if (best >= 0) {
                     const int lb = max(lbm[p], mm);
                     if (lb > bestReq || (lb == bestReq && Un >= bestU)) continue;
                 }
-            }
-            if (!wave_test_from(L, tb, Sn, first, mp, cm, ty)) continue;
-            int req = 0;
-            if (SMS) {  // fewest units for Sn (binary search, as min_units)
+                if (!wave_test_from(L, tb, Sn, first, mp, cm, ty)) continue;
+                // fewest units for Sn (binary search, as min_units)
                 int lo = 1;
                 for (uint64_t h = Sn; h; h &= h - 1ull) lo = max(lo, (int)L.mmin[__builtin_ctzll(h)]);
                 int hi = mp;
@@ -1014,10 +1071,9 @@ __device__ bool wave_heuristic(const SetLDS &L, const Tables &tb, int n, const i
                     else
                         lo = mid + 1;
                 }
-                req = lo;
+                const int req = lo;
+                if (best < 0 || req < bestReq || (req == bestReq && Un < bestU)) { best = p; bestU = Un; bestReq = req; }
             }
-            const bool better = (best < 0) || (SMS ? (req < bestReq || (req == bestReq && Un < bestU)) : (Un < bestU));
-            if (better) { best = p; bestU = Un; bestReq = req; }
         }
         if (best < 0) return false;
         uint64_t Uold = 0;
