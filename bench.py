@@ -336,6 +336,8 @@ def main():
                     help="per-partition scheduling: fixed-priority DM (default) or EDF")
     ap.add_argument("--admissible", default="",
                     help="comma-separated admissible partition sizes (MIG-like restriction; default: every size)")
+    ap.add_argument("--rates", default="",
+                    help="c5: comma-separated offered rates in queries/s (default 1e3, 3e3, .., 1e6)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form without HIP graph capture (same kernels and arguments; for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -371,8 +373,8 @@ def main():
     valu_ops, valu_ms = capart.capart_measure_valu(eng.ctx)
     log(f"[bench] measured full-rate int32 VALU: {valu_ops / 1e12:.2f} T lane-ops/s (kernel {valu_ms:.2f} ms)")
     if args.workload == "c5":
-        # below and above the capacity of this query mix (about 1.4e4 queries/s)
-        rates = [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6]
+        # below and above the capacity of this query mix (about 2.7e4 queries/s)
+        rates = [float(x) for x in args.rates.split(",")] if args.rates else [1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6]
         legs = []
         for r in rates:
             n_q = int(min(200000, max(2000, r * 2.0)))
