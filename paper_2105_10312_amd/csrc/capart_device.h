@@ -906,27 +906,82 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
                 if (passes(Sq, mq, Uq, f, pz)) { best = q; bestU = uq; break; }
             }
         } else {
-            // ">>": parts in index order; a part whose fewest units are known to
-            // exceed the best's (they are at least the largest Lemma 2 size of its
-            // members and the task), or to equal them with a utilisation not below
-            // the best's, cannot be taken and needs no test
+            // ">>": the part taken is the passing one of least (fewest units,
+            // utilisation with the task, index).  The fewest units are at least
+            // lb, the largest Lemma 2 size of the part's members and the task, so
+            // the candidates are visited in order of (lb, utilisation, index) and
+            // the visit stops at the first that cannot beat the best found; once
+            // there is a best, a candidate's fewest units only matter up to the
+            // best's, so its test is at that size and its search below it.
+            uint64_t un[KMAX];
+            int lbp[KMAX];
+            uint32_t cand = 0u;
 #pragma unroll
             for (int p = 0; p < KMAX; p++) {
-                const int mp = m[p];
-                const MT Sp = S[p];
-                if (p >= k || mm > mp) continue;
-                if (ACT && (fb & Sp)) continue;
-                const uint64_t Un = util_add<MT>(L, tb, Sp, r, mp, U[p]);
-                if (best >= 0) {
-                    const int lb = max(lbm[p], mm);
-                    if (lb > bestReq || (lb == bestReq && Un >= bestU)) continue;
+                un[p] = 0ull;
+                lbp[p] = 0;
+                if (p >= k || mm > m[p] || (ACT && (fb & S[p]))) continue;
+                un[p] = util_add<MT>(L, tb, S[p], r, m[p], U[p]);
+                lbp[p] = max(lbm[p], mm);
+                cand |= 1u << p;
+            }
+            while (cand) {
+                int q = -1, mq = 0, lq = 0;
+                uint64_t uq = 0ull, Uq = 0ull;
+                MT Sq = MT(0);
+#pragma unroll
+                for (int p = 0; p < KMAX; p++)
+                    if (((cand >> p) & 1u) && (q < 0 || lbp[p] < lq || (lbp[p] == lq && un[p] < uq))) {
+                        q = p; lq = lbp[p]; uq = un[p]; Sq = S[p]; mq = m[p]; Uq = U[p];
+                    }
+                cand &= ~(1u << q);
+                if (best >= 0 && (lq > bestReq || (lq == bestReq && (uq > bestU || (uq == bestU && q > best))))) break;
+                const MT Sn = Sq | (MT(1) << r);
+                const MT cm = conflict_mask<MT>(Sn, (MT)L.memmask);
+                int f = 0, pz = 256;  // largest size known to fail, smallest known to pass
+                if (sizeof(MT) == 4 && mo.mask) {
+                    ty.look();
+                    memo_get(mo, (uint32_t)Sn, f, pz);
                 }
-                int f, pz;
-                if (!passes(Sp, mp, U[p], f, pz)) continue;
-                const MT Sn = Sp | (MT(1) << r);
-                const int req = (sizeof(MT) == 4 && mo.mask) ? min_units_memo<MT>(L, tb, Sn, f, min(pz, mp), mo, ty)
-                                                            : min_units<MT>(L, tb, Sn, mp, ty);
-                if (best < 0 || req < bestReq || (req == bestReq && Un < bestU)) { best = p; bestU = Un; bestReq = req; }
+                auto test_at = [&](int msz) -> bool {  // the whole union at msz units
+                    if (msz <= f) return false;
+                    if (msz >= pz) return true;
+                    const bool ok = test_from<MT>(L, tb, Sn, 0, msz, cm, ty);
+                    if (sizeof(MT) == 4 && mo.mask) memo_put(mo, (uint32_t)Sn, msz, ok);
+                    if (ok) pz = msz; else f = msz;
+                    return ok;
+                };
+                int hi = mq;
+                if (best >= 0 && bestReq < mq) {
+                    if (!test_at(bestReq)) continue;  // needs more units than the best (or does not fit)
+                    hi = bestReq;
+                } else {
+                    // the part's own test at its size: the incremental test
+                    bool ok = mq >= pz;
+                    if (!ok && mq > f) {
+                        uint64_t Un2;
+                        ok = part_test_add<MT>(L, tb, Sq, r, mq, Uq, &Un2, ty);
+                        if (sizeof(MT) == 4 && mo.mask) memo_put(mo, (uint32_t)Sn, mq, ok);
+                        if (ok) pz = mq; else f = mq;
+                    }
+                    if (!ok) continue;
+                }
+                // the fewest units: the least passing size in [max(lb, f + 1), hi]
+                int lo = max(lq, f + 1);
+                hi = min(hi, pz);
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (test_at(mid))
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                const int req = lo;
+                if (best < 0 || req < bestReq || (req == bestReq && (uq < bestU || (uq == bestU && q < best)))) {
+                    best = q;
+                    bestU = uq;
+                    bestReq = req;
+                }
             }
         }
         if (best < 0) return false;
