@@ -116,6 +116,9 @@ typedef int32_t capart_status;
 #define CAPART_FLAG_SKIP_1G         1u /* do not evaluate the whole-GPU baseline (R_1g = -1)    */
 #define CAPART_FLAG_NO_LEMMA1       2u /* disable the Lemma 1 pre-filter (results identical)     */
 #define CAPART_FLAG_PER_SET_LAUNCH  4u /* plain path: one launch sequence per task set           */
+/* capart_server_config.flags only: reserve room for explicit time tables
+ * (max_M entries of each kind per task) so that queries may carry them. */
+#define CAPART_SERVER_TABLES        8u
 
 /* limits */
 #define CAPART_MAX_TASKS   64   /* tasks per set                                          */
@@ -150,9 +153,10 @@ typedef int32_t capart_status;
  * (no super-linear speed-up, which Lemma 1 needs).  table_offset[s] >= 0 and
  * table_offset[s] + n * M[s] <= table_len (else E_INVAL).  Tables are taken by
  * capart_validate, capart_solve, capart_solve_async,
- * capart_solve_async_noalloc, capart_count_work, the batched plans and the
- * capart_alg1 calls; the server and the one-set calls (capart_test_triple,
- * capart_allocate) return E_INVAL for them.
+ * capart_solve_async_noalloc, capart_count_work, the batched plans, the
+ * capart_alg1 calls and a server created with CAPART_SERVER_TABLES; other
+ * servers and the one-set calls (capart_test_triple, capart_allocate) return
+ * E_INVAL for them.
  */
 typedef struct capart_tasksets {
     int64_t n_sets;
@@ -439,6 +443,12 @@ capart_status capart_plan_destroy(capart_plan *plan);
  * (continuous batching).  capart_server_poll returns a query's results once
  * its batch has completed and frees its ring space.  A query's results do not
  * depend on the other queries of its batch.  submit and poll are thread-safe.
+ * With CAPART_SERVER_TABLES in cfg.flags a query may bring explicit time
+ * tables (its table_offset[0] .. + n * M entries of Cn_table and Cc_table are
+ * copied at submit; their domain is checked on the device, as for
+ * capart_solve, giving the query status E_RANGE); a batch then holds queries
+ * of one kind only, with tables or without.  The device budget counts
+ * 16 * max_M more bytes per task for them.
  * Latency is measured from submit (or the replayed arrival time) to the moment
  * the dispatcher sees the batch complete.
  */
@@ -446,7 +456,7 @@ typedef struct capart_server capart_server;
 
 typedef struct capart_server_config {
     int32_t K, alloc_mode;  /* options applied to every query (heuristic modes) */
-    uint32_t flags;
+    uint32_t flags;         /* CAPART_FLAG_SKIP_1G, _NO_LEMMA1, CAPART_SERVER_TABLES */
     int32_t max_tasks;      /* bound on tasks per query, 1..64        */
     int32_t max_M;          /* bound on M per query, 1..255           */
     int32_t max_queries;    /* query slots (0 = 4096)                 */

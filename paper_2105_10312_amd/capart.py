@@ -24,6 +24,7 @@ CAPART_POLICY_FP_DM = 0
 CAPART_POLICY_EDF = 1
 POLICIES = {"FP_DM": CAPART_POLICY_FP_DM, "EDF": CAPART_POLICY_EDF}
 CAPART_FLAG_SKIP_1G, CAPART_FLAG_NO_LEMMA1, CAPART_FLAG_PER_SET_LAUNCH = 1, 2, 4
+CAPART_SERVER_TABLES = 8
 CAPART_ALG1_MAX_TASKS, CAPART_ALG1_BIG_MAX_M, CAPART_ALG1_BIG_MAX_NM = 256, 127, 14336
 MODES = {"EXH": CAPART_EXHAUSTIVE, "BF_INA": CAPART_HEUR_BF_INA, "BF_ACT": CAPART_HEUR_BF_ACT,
          "SMS_INA": CAPART_HEUR_SMS_INA, "SMS_ACT": CAPART_HEUR_SMS_ACT}
@@ -286,10 +287,17 @@ def capart_validate(ts: dict, K: int, mode="BF_INA", flags: int = 0, max_tasks=N
 
 
 def _one_set(task: dict) -> dict:
+    """One set as a host batch; a task dict with "Cn_table" and "Cc_table"
+    (n * M entries each, task-major) brings explicit time tables."""
     n = len(task["T"])
-    return _host_ts({"set_offset": np.array([0, n]), "M": np.array([int(task["M"])]), "T": task["T"],
-                     "D": task["D"], "C_seq": task["C_seq"], "C_par": task["C_par"],
-                     "k_permille": task["k_permille"], "type": task["type"]})
+    one = {"set_offset": np.array([0, n]), "M": np.array([int(task["M"])]), "T": task["T"], "D": task["D"],
+           "type": task["type"]}
+    for key in ("C_seq", "C_par", "k_permille"):
+        if task.get(key) is not None:
+            one[key] = task[key]
+    if task.get("Cn_table") is not None:
+        one.update(table_offset=np.zeros(1, np.int64), Cn_table=task["Cn_table"], Cc_table=task["Cc_table"])
+    return _host_ts(one)
 
 
 def capart_test_triple(ctx, task: dict, sizes, alloc):
@@ -582,10 +590,12 @@ class Server:
 
     def __init__(self, ctx, K: int = 4, mode="BF_INA", flags: int = 0, max_tasks: int = 64, max_M: int = 108,
                  max_queries: int = 0, device_bytes: int = 0, streams: int = 0, max_batch: int = 0,
-                 policy="FP_DM"):
+                 policy="FP_DM", tables: bool = False):
         self.ctx = ctx
         self.K = int(K)
         pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+        if tables:
+            flags = int(flags) | CAPART_SERVER_TABLES
         cfg = capart_server_config(int(K), _mode(mode), int(flags), int(max_tasks), int(max_M), int(max_queries),
                                    int(device_bytes), int(streams), int(max_batch), pol)
         h = _vp()

@@ -1749,6 +1749,7 @@ struct SrvQuery {
     uint64_t ticket = 0;
     int64_t t0 = 0;        // first task in the task ring
     int32_t n = 0, M = 0;
+    bool tab = false;      // brings explicit time tables
     int state = Q_FREE;
     double t_arrival = 0;  // microseconds since the server's origin
     double t_done = 0;
@@ -1756,13 +1757,14 @@ struct SrvQuery {
 
 // Packed per-batch layout (offsets in bytes, 256-aligned segments).
 struct PackIn {
-    size_t off, M, T, D, Cs, Cp, k, type, total;
+    size_t off, M, T, D, Cs, Cp, k, type, toff, Cn, Cc, total;
 };
 struct PackOut {
     size_t status, verdict, v1g, pidx, sizes, aidx, maxU, sumU, nev, alloc, R, R1g, total;
 };
 
-PackIn pack_in_layout(int64_t S, int64_t N)
+// NT: explicit time-table entries of each kind in the batch (0 without tables)
+PackIn pack_in_layout(int64_t S, int64_t N, int64_t NT)
 {
     PackIn l;
     size_t o = 0;
@@ -1775,6 +1777,9 @@ PackIn pack_in_layout(int64_t S, int64_t N)
     l.Cp = take(8 * (size_t)N);
     l.k = take(4 * (size_t)N);
     l.type = take((size_t)N);
+    l.toff = take(NT ? 8 * (size_t)S : 0);
+    l.Cn = take(8 * (size_t)NT);
+    l.Cc = take(8 * (size_t)NT);
     l.total = o;
     return l;
 }
@@ -1824,6 +1829,7 @@ struct capart_server {
     int64_t Tcap = 0;
     int64_t Sb = 0, Tb = 0;  // batch capacity (sets, tasks)
     Launch L{};
+    bool tabs = false;       // queries may bring explicit time tables
     // device rings
     void *dev = nullptr;
     TaskRec *rec = nullptr;
@@ -1835,6 +1841,7 @@ struct capart_server {
     // host rings: inputs and results of every live query
     std::vector<SrvQuery> q;
     std::vector<int64_t> hT, hD, hCs, hCp, hR, hR1g;
+    std::vector<int64_t> hCn, hCc;  // with tabs: task ring index t holds its table at [t * max_M, + M)
     std::vector<int32_t> hk;
     std::vector<uint8_t> htype;
     std::vector<int8_t> halloc;
@@ -1887,23 +1894,25 @@ void launch_batch(capart_server *v, int i)
 {
     SrvStream &ss = v->streams[i];
     const uint64_t first = v->launch_ticket;
-    int64_t S = 0, N = 0;
+    int64_t S = 0, N = 0, NT = 0;
     int64_t t_start = v->q[first % v->Qcap].t0;
+    const bool tab = v->q[first % v->Qcap].tab;  // a batch holds queries of one kind
     while (first + S < v->next_ticket && S < v->Sb) {
         const SrvQuery &x = v->q[(first + S) % v->Qcap];
-        if (x.state != Q_PENDING) break;
+        if (x.state != Q_PENDING || x.tab != tab) break;
         if (S > 0 && ((first + S) % v->Qcap == 0 || x.t0 != t_start + N)) break;  // ring wraps end a batch
         if (N + x.n > v->Tb) break;
         N += x.n;
+        if (tab) NT += (int64_t)x.n * x.M;
         S++;
     }
     if (S == 0) return;
-    const PackIn li = pack_in_layout(S, N);
+    const PackIn li = pack_in_layout(S, N, NT);
     const PackOut lo = pack_out_layout(S, N, v->cfg.K);
     char *h = ss.in_host;
     int64_t *off = (int64_t *)(h + li.off);
     int32_t *M = (int32_t *)(h + li.M);
-    int64_t acc = 0, wide_parts = 0;
+    int64_t acc = 0, tacc = 0, wide_parts = 0;
     int32_t nmax = 1, Mmax = 1;
     for (int64_t s = 0; s < S; s++) {
         SrvQuery &x = v->q[(first + s) % v->Qcap];
@@ -1918,6 +1927,13 @@ void launch_batch(capart_server *v, int i)
         std::memcpy(h + li.Cp + 8 * acc, &v->hCp[x.t0], 8 * (size_t)x.n);
         std::memcpy(h + li.k + 4 * acc, &v->hk[x.t0], 4 * (size_t)x.n);
         std::memcpy(h + li.type + acc, &v->htype[x.t0], (size_t)x.n);
+        if (tab) {
+            const size_t e = (size_t)x.n * x.M, at = (size_t)x.t0 * v->cfg.max_M;
+            ((int64_t *)(h + li.toff))[s] = tacc;
+            std::memcpy(h + li.Cn + 8 * tacc, &v->hCn[at], 8 * e);
+            std::memcpy(h + li.Cc + 8 * tacc, &v->hCc[at], 8 * e);
+            tacc += (int64_t)e;
+        }
         acc += x.n;
         x.state = Q_LAUNCHED;
     }
@@ -1943,6 +1959,12 @@ void launch_batch(capart_server *v, int i)
     b.n_tasks_total = N;
     b.max_tasks = nmax;  // the batch's own bounds: launches and LDS sized for its sets only
     b.max_M = Mmax;
+    if (tab) {
+        b.toff = (const int64_t *)(d + li.toff);
+        b.Cn = (const int64_t *)(d + li.Cn);
+        b.Cc = (const int64_t *)(d + li.Cc);
+        b.tlen = NT;
+    }
     Work w{};
     w.rec = v->rec + t_start;
     w.forbid = v->forbid + t_start;
@@ -1952,6 +1974,7 @@ void launch_batch(capart_server *v, int i)
     w.partial = v->partial + 4 * (size_t)slot0 * v->L.chunks;
     w.np = v->ctx->np_dev;
     w.order = v->ctx->order_dev;
+    give_tables(w, b);
     Out o{};
     char *od = ss.out_dev;
     o.status = (int32_t *)(od + lo.status);
@@ -2069,13 +2092,24 @@ capart_status srv_submit(capart_server *v, const capart_tasksets *one, uint64_t 
     if (one->n_sets != 1 || !one->set_offset || !one->M || one->set_offset[0] != 0 ||
         one->set_offset[1] != one->n_tasks_total)
         return srv_fail(v, CAPART_E_INVAL, "submit takes one set with offsets {0, n}");
-    if (has_tables(one)) return srv_fail(v, CAPART_E_INVAL, "explicit time tables are not taken by the server");
+    const bool tab = has_tables(one);
+    if (tab && !v->tabs)
+        return srv_fail(v, CAPART_E_INVAL, "explicit time tables need a server created with CAPART_SERVER_TABLES");
     const int64_t n = one->n_tasks_total;
     const int32_t M = one->M[0];
     if (n < 1 || n > v->cfg.max_tasks || M < 1 || M > v->cfg.max_M || n * M > CAPART_MAX_NM)
         return srv_fail(v, CAPART_E_INVAL, "query exceeds the server's size bounds");
-    if (!one->T || !one->D || !one->C_seq || !one->C_par || !one->k_permille || !one->type)
+    if (!one->T || !one->D || !one->type || (!tab && (!one->C_seq || !one->C_par || !one->k_permille)))
         return srv_fail(v, CAPART_E_INVAL, "NULL task arrays");
+    int64_t tab0 = 0;
+    if (tab) {
+        if (!one->table_offset || !one->Cn_table || !one->Cc_table || one->table_len < 0)
+            return srv_fail(v, CAPART_E_INVAL,
+                            "explicit time tables need table_offset, Cn_table, Cc_table and table_len");
+        tab0 = one->table_offset[0];
+        if (tab0 < 0 || tab0 > one->table_len - n * M)
+            return srv_fail(v, CAPART_E_INVAL, "table_offset[0] + n * M exceeds table_len");
+    }
     std::unique_lock<std::mutex> lk(v->mu);
     if (v->next_ticket - v->tail_ticket >= (uint64_t)v->Qcap) {
         v->st_rejected++;
@@ -2092,13 +2126,24 @@ capart_status srv_submit(capart_server *v, const capart_tasksets *one, uint64_t 
     x.t0 = t0;
     x.n = (int32_t)n;
     x.M = M;
+    x.tab = tab;
     x.t_arrival = use_arrival ? t_arrival : now_us(v->origin);
     std::memcpy(&v->hT[t0], one->T, 8 * (size_t)n);
     std::memcpy(&v->hD[t0], one->D, 8 * (size_t)n);
-    std::memcpy(&v->hCs[t0], one->C_seq, 8 * (size_t)n);
-    std::memcpy(&v->hCp[t0], one->C_par, 8 * (size_t)n);
-    std::memcpy(&v->hk[t0], one->k_permille, 4 * (size_t)n);
     std::memcpy(&v->htype[t0], one->type, (size_t)n);
+    if (tab) {
+        // the parametric fields are not read with tables
+        std::fill(&v->hCs[t0], &v->hCs[t0] + n, 0);
+        std::fill(&v->hCp[t0], &v->hCp[t0] + n, 0);
+        std::fill(&v->hk[t0], &v->hk[t0] + n, 1000);
+        const size_t at = (size_t)t0 * v->cfg.max_M;
+        std::memcpy(&v->hCn[at], one->Cn_table + tab0, 8 * (size_t)(n * M));
+        std::memcpy(&v->hCc[at], one->Cc_table + tab0, 8 * (size_t)(n * M));
+    } else {
+        std::memcpy(&v->hCs[t0], one->C_seq, 8 * (size_t)n);
+        std::memcpy(&v->hCp[t0], one->C_par, 8 * (size_t)n);
+        std::memcpy(&v->hk[t0], one->k_permille, 4 * (size_t)n);
+    }
     x.state = Q_PENDING;
     v->task_head = t0 + n;
     v->st_submitted++;
@@ -2144,7 +2189,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
 {
     if (!c || !cfg || !out) return CAPART_E_INVAL;
     *out = nullptr;
-    capart_options opt{cfg->K, cfg->policy, cfg->alloc_mode, cfg->flags};
+    const bool tabs = (cfg->flags & CAPART_SERVER_TABLES) != 0u;
+    capart_options opt{cfg->K, cfg->policy, cfg->alloc_mode, cfg->flags & ~CAPART_SERVER_TABLES};
     capart_status rc = check_options(c, &opt);
     if (rc != CAPART_OK) return rc;
     if (cfg->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "serving runs heuristic modes");
@@ -2157,6 +2203,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     if (!v) return fail(c, CAPART_E_NOMEM, "server allocation failed");
     v->ctx = c;
     v->cfg = *cfg;
+    v->tabs = tabs;
     if (v->cfg.streams == 0) v->cfg.streams = 4;
     if (v->cfg.max_queries == 0) v->cfg.max_queries = 4096;
     if (v->cfg.device_bytes == 0) v->cfg.device_bytes = (int64_t)256 << 20;
@@ -2170,7 +2217,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     Launch &L = v->L;
     L.K = cfg->K;
     L.mode = cfg->alloc_mode;
-    L.flags = cfg->flags;
+    L.flags = opt.flags;
     L.edf = cfg->policy == CAPART_POLICY_EDF;
     L.threads = eval_threads(cfg->max_tasks, cfg->max_M);
     L.table_words = (int)(table_lds_bytes(cfg->max_tasks, cfg->max_M) / 4);
@@ -2188,7 +2235,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     const int64_t per_task_ring = (int64_t)sizeof(TaskRec) + 8 + 1;
     const int64_t avail = v->cfg.device_bytes - per_slot * v->Qcap;
     // each task needs ring space and, while in a batch, packed input/output space
-    const int64_t per_task_total = per_task_ring + (37 + 17) * 1;
+    // (with tables, max_M entries of each kind per task, packed per batch)
+    const int64_t per_task_total = per_task_ring + (37 + 17) * 1 + (tabs ? 16 * (int64_t)cfg->max_M : 0);
     v->Tcap = avail > 0 ? avail / per_task_total : 0;
     v->Tb = std::min<int64_t>(v->Tcap / std::max(1, v->cfg.streams), v->Sb * cfg->max_tasks);
     if (v->Tcap < cfg->max_tasks || v->Tb < cfg->max_tasks) {
@@ -2202,7 +2250,7 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     const size_t r_rec = take(sizeof(TaskRec) * (size_t)v->Tcap), r_forbid = take(8 * (size_t)v->Tcap),
                  r_sigma = take((size_t)v->Tcap), r_flags = take(4 * (size_t)v->Qcap),
                  r_mm = take(8 * (size_t)v->Qcap), r_part = take(32 * (size_t)v->Qcap * L.chunks);
-    const PackIn li = pack_in_layout(v->Sb, v->Tb);
+    const PackIn li = pack_in_layout(v->Sb, v->Tb, tabs ? v->Tb * cfg->max_M : 0);
     const PackOut lo = pack_out_layout(v->Sb, v->Tb, cfg->K);
     std::vector<size_t> s_in, s_out;
     for (int i = 0; i < v->cfg.streams; i++) {
@@ -2235,7 +2283,11 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     v->q.assign(v->Qcap, SrvQuery{});
     const size_t T = (size_t)v->Tcap, Q = (size_t)v->Qcap;
     v->hT.assign(T, 0); v->hD.assign(T, 0); v->hCs.assign(T, 0); v->hCp.assign(T, 0);
-    v->hk.assign(T, 0); v->htype.assign(T, 0); v->halloc.assign(T, 0); v->hR.assign(T, 0); v->hR1g.assign(T, 0);
+    v->hk.assign(T, 0); v->htype.assign(T, 0);
+    if (tabs) {
+        v->hCn.assign(T * (size_t)cfg->max_M, 0);
+        v->hCc.assign(T * (size_t)cfg->max_M, 0);
+    } v->halloc.assign(T, 0); v->hR.assign(T, 0); v->hR1g.assign(T, 0);
     v->hstatus.assign(Q, 0); v->hpidx.assign(Q, 0); v->hsizes.assign(Q * cfg->K, 0); v->hverdict.assign(Q, 0);
     v->hv1g.assign(Q, 0); v->haidx.assign(Q, 0); v->hnev.assign(Q, 0); v->hmaxU.assign(Q, 0); v->hsumU.assign(Q, 0);
     v->origin = std::chrono::steady_clock::now();
@@ -2316,7 +2368,6 @@ capart_status capart_server_replay(capart_server *v, const capart_tasksets *qs, 
                                    capart_results *res, capart_server_stats *stats)
 {
     if (!v || !qs || !arrival_us || !stats || qs->n_sets < 0 || !qs->set_offset || !qs->M) return CAPART_E_INVAL;
-    if (has_tables(qs)) return srv_fail(v, CAPART_E_INVAL, "explicit time tables are not taken by the server");
     const int64_t nq = qs->n_sets;
     {
         std::lock_guard<std::mutex> lk(v->mu);
@@ -2342,8 +2393,11 @@ capart_status capart_server_replay(capart_server *v, const capart_tasksets *qs, 
             one.n_tasks_total = n;
             one.set_offset = offs;
             one.M = qs->M + next;
-            one.T = qs->T + o0; one.D = qs->D + o0; one.C_seq = qs->C_seq + o0; one.C_par = qs->C_par + o0;
-            one.k_permille = qs->k_permille + o0; one.type = qs->type + o0;
+            one.T = qs->T + o0; one.D = qs->D + o0; one.type = qs->type + o0;
+            one.C_seq = qs->C_seq ? qs->C_seq + o0 : nullptr;
+            one.C_par = qs->C_par ? qs->C_par + o0 : nullptr;
+            one.k_permille = qs->k_permille ? qs->k_permille + o0 : nullptr;
+            if (qs->table_offset) one.table_offset = qs->table_offset + next;  // the tables stay whole
             uint64_t tk;
             const capart_status rc = srv_submit(v, &one, &tk, t0 + arrival_us[next], true);
             if (rc == CAPART_E_AGAIN) break;

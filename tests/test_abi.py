@@ -144,7 +144,8 @@ def test_header_constants_match_the_binding():
     for name, value in defs.items():
         if hasattr(capart, name):
             assert getattr(capart, name) == value, name
-    for name in ("CAPART_POLICY_EDF", "CAPART_POLICY_FP_DM", "CAPART_E_AGAIN", "CAPART_FLAG_PER_SET_LAUNCH"):
+    for name in ("CAPART_POLICY_EDF", "CAPART_POLICY_FP_DM", "CAPART_E_AGAIN", "CAPART_FLAG_PER_SET_LAUNCH",
+                 "CAPART_SERVER_TABLES"):
         assert name in defs and hasattr(capart, name), name
 
 

@@ -4,9 +4,11 @@ Tables that restate the parametric model give the parametric results bit for
 bit; general tables (saturating memory-intensive profiles) give the oracle's
 results bit for bit in every allocation mode, for Algorithm 1, on the host and
 device entry points and through the batched plans; tables outside the
-contract get the oracle's status; the server refuses them."""
+contract get the oracle's status; a server created with room for tables
+takes them, others and the one-set calls refuse them."""
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -192,11 +194,83 @@ def test_batched_plans_with_tables(eng, mode):
     say(f"batched tables {mode}: {int(want['verdict'].sum())} of {ts.n_sets} schedulable")
 
 
+def query_fields(r, q, off, K):
+    """Query q's results out of a batch result dict."""
+    a, b = int(off[q]), int(off[q + 1])
+    return {f: (np.asarray(r[f]).reshape(-1, K)[q] if f == "sizes" else
+                (np.asarray(r[f])[a:b] if f in ("alloc", "R", "R_1g") else np.asarray(r[f])[q:q + 1]))
+            for f in FIELDS}
+
+
+@pytest.mark.parametrize("mode,policy", [("BF_INA", "FP_DM"), ("SMS_ACT", "FP_DM"), ("BF_ACT", "EDF")])
+def test_server_with_tables(eng, mode, policy):
+    """A server created with room for tables: queries with general tables and
+    parametric queries submitted in alternating runs of each kind (a batch
+    holds one kind), then the tables batch replayed at 20k q/s; every query
+    gets the oracle's results, and a query whose table leaves the contract
+    gets E_RANGE without disturbing the others."""
+    c5 = workload.config_c5(seed=71, n_queries=700)
+    pick = [i for i in range(c5.n_sets) if c5.sizes()[i] <= 24 and c5["M"][i] >= 2][:150]
+    ts = workload.subset(c5, pick)
+    tt = tables_only(workload.with_time_tables(ts, seed=72))
+    bad = 7
+    a = int(tt["table_offset"][bad])
+    tt["Cn_table"][a + 1] = tt["Cn_table"][a] + 1  # increasing in m
+    off, K = ts["set_offset"], 4
+    say(f"server tables {mode} {policy}: oracle on {ts.n_sets} queries, both kinds")
+    want_t = oracle.solve(tt, K, mode, nthreads=THREADS, policy=policy)
+    want_p = oracle.solve(ts, K, mode, nthreads=THREADS, policy=policy)
+    assert want_t["status"][bad] == capart.CAPART_E_RANGE
+    assert (np.delete(want_t["status"], bad) == oracle.OK).all()
+    srv = capart.Server(eng.ctx, K=K, mode=mode, max_tasks=24, max_M=108, policy=policy, tables=True)
+    try:
+        rng = np.random.default_rng(73)
+        kind, left, tickets = True, 0, []
+        for q in range(ts.n_sets):
+            if left == 0:
+                kind, left = not kind, int(rng.integers(1, 8))
+            left -= 1
+            tk = srv.submit(tt.set(q) if kind else ts.set(q))
+            assert tk is not None
+            tickets.append((q, kind, tk))
+        say(f"server tables: {len(tickets)} queries submitted, {srv.stats()['batches']} batches so far")
+        for q, kind, tk in tickets:
+            got = wait(srv, tk, int(off[q + 1] - off[q]))
+            want = query_fields(want_t if kind else want_p, q, off, K)
+            same(got, want, FIELDS, f"query {q} ({'tables' if kind else 'parametric'})")
+        arrival = np.cumsum(rng.exponential(1e6 / 20000.0, tt.n_sets))
+        mix, stats = srv.replay(tt, arrival)
+        say("server tables replay", stats)
+        same(mix, want_t, FIELDS, f"replay {mode} {policy}")
+    finally:
+        srv.close()
+
+
+def wait(srv, ticket, n, timeout=30.0):
+    t0 = time.time()
+    while True:
+        r = srv.poll(ticket, n)
+        if r is not None:
+            return r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"ticket {ticket} not complete")
+        time.sleep(0.0002)
+
+
 def test_paths_without_tables_refuse_them(eng):
+    """A server created without room for tables, and the one-set calls."""
     ts = tables_only(workload.with_time_tables(workload.config_c1(n_sets=4), seed=97))
     srv = capart.Server(eng.ctx, K=3, mode="BF_INA", max_tasks=5, max_M=8)
     try:
         with pytest.raises(capart.CapartError):
             srv.replay(ts, np.zeros(ts.n_sets))
+        with pytest.raises(capart.CapartError):
+            srv.submit(ts.set(0))
     finally:
         srv.close()
+    task = ts.set(1)
+    n, M = len(task["T"]), int(task["M"])
+    with pytest.raises(capart.CapartError):
+        eng.test_triple(task, [M], np.zeros(n, np.int8))
+    with pytest.raises(capart.CapartError):
+        eng.allocate(task, [M], 3, "BF_INA")
