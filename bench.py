@@ -46,7 +46,7 @@ METRIC = "schedulability evals/sec (taskset×partitioning); p99 admission latenc
 # an exact partition test sets up its conflict mask and sums (8); a candidate
 # answered from the feasibility frontier is a mask OR, a compare and the
 # utilisation update (6).
-C_TERM = 12
+C_TERM = 9
 C_TEST = 8
 C_LOOK = 6
 # 256 CUs x 128 full-rate 32-bit VALU lane-operations per clock x 2.4 GHz: the

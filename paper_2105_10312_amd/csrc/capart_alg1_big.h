@@ -89,6 +89,7 @@ __device__ __forceinline__ int m_first(const M256 &a) { return m_any(a) ? m_low(
 // Per-set records (by deadline-monotonic rank) of a set of up to 256 tasks.
 struct BigLDS {
     uint32_t T[BIGN], D[BIGN], clo[BIGN], chi[BIGN];
+    uint32_t rm[BIGN], rs[BIGN];  // 32-bit multiplier and shift of T (floordiv31, response times)
     uint32_t Cs[BIGN], Cp[BIGN], k[BIGN];
     uint16_t mmin[BIGN];
     uint8_t orig[BIGN];
@@ -149,9 +150,10 @@ __device__ __forceinline__ uint32_t big_rta(const BigLDS &L, const uint32_t *tc,
     for (;;) {
         uint64_t W = Cr;
         uint32_t terms = 1u;
+        const uint32_t x2 = ((uint32_t)R - 1u) << 1;  // R <= D < 2^31
         for (int j = m_first(hp); j < BIGN; j = m_next(hp, j)) {
             const uint32_t Cj = big_time(tc, n, j, m, m_has(cm, j) ? 1 : 0);
-            W += ((uint64_t)udiv_magic((uint32_t)R - 1u, L.T[j], L.clo[j], L.chi[j]) + 1ull) * Cj;
+            W += ((uint64_t)floordiv31(x2, L.rm[j], L.rs[j]) + 1ull) * Cj;
             terms++;
         }
         ty.term(terms);
@@ -336,6 +338,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (t < n) {
         const TaskRec r = w.rec[off0 + t];
         L.T[t] = r.T; L.D[t] = r.D; L.clo[t] = r.clo; L.chi[t] = r.chi;
+        uint32_t rm, rs;
+        magic31(r.T, &rm, &rs);
+        L.rm[t] = rm; L.rs[t] = rs;
         L.Cs[t] = r.Cs; L.Cp[t] = r.Cp; L.k[t] = r.k;
         L.mmin[t] = r.mmin;
         L.orig[t] = r.orig;

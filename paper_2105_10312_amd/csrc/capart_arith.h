@@ -33,6 +33,25 @@ CAPART_HD inline uint32_t floordiv_magic(uint32_t x, uint32_t clo, uint32_t chi)
     return (uint32_t)(((uint64_t)chi * x + lo_hi) >> 32);
 }
 
+// floor(x / T) for 0 <= x < 2^31 with a single 32-bit multiplier
+// (Granlund and Montgomery 1994, Theorem 4.2, with N = 31 dividend bits):
+// l = ceil(log2 T) and m = ceil(2^(31+l) / T) give m T - 2^(31+l) < T <= 2^l,
+// so floor(x/T) = floor(m x / 2^(31+l)) = mul_hi(m, 2x) >> l; m < 2^32 (2^31
+// when T is a power of two, T = 1 included).  One mul_hi and one shift.
+CAPART_HD inline void magic31(uint32_t T, uint32_t *m, uint32_t *l)
+{
+    uint32_t s = 0;
+    while (s < 31u && (1u << s) < T) s++;
+    *m = (uint32_t)((((uint64_t)1 << (31u + s)) + T - 1u) / T);
+    *l = s;
+}
+
+// x2 = 2x for the x above.
+CAPART_HD inline uint32_t floordiv31(uint32_t x2, uint32_t m, uint32_t l)
+{
+    return (uint32_t)(((uint64_t)m * x2) >> 32) >> l;
+}
+
 // Execution time on m units without conflict: C_seq + ceil(C_par / m).
 // With C_seq + C_par < 2^31 the result is < 2^31.
 CAPART_HD inline uint32_t time_n(uint32_t Cs, uint32_t Cp, uint32_t m)

@@ -141,6 +141,7 @@ using Tally = TallyP<POL_ANY>;
 // Per-set data in LDS (ranks are deadline-monotonic priority positions).
 struct SetLDS {
     uint32_t T[MAXN], D[MAXN], clo[MAXN], chi[MAXN];
+    uint32_t rm[MAXN], rs[MAXN];    // 32-bit multiplier and shift of T (floordiv31, response times)
     uint32_t dlo[MAXN], dhi[MAXN];  // 2^64 reciprocal of D (EDF density and demand)
     uint32_t Cs[MAXN], Cp[MAXN], k[MAXN];
     uint32_t mmin[MAXN];
@@ -182,6 +183,9 @@ __device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int6
     for (int i = tid; i < n; i += nt) {
         TaskRec t = w.rec[off + i];
         L.T[i] = t.T; L.D[i] = t.D; L.clo[i] = t.clo; L.chi[i] = t.chi;
+        uint32_t rm, rs;
+        magic31(t.T, &rm, &rs);
+        L.rm[i] = rm; L.rs[i] = rs;
         L.Cs[i] = t.Cs; L.Cp[i] = t.Cp; L.k[i] = t.k;
         L.mmin[i] = t.mmin;
         L.orig[i] = t.orig;
@@ -368,14 +372,20 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
 {
     if (base > D) return 0u;
     uint64_t R = base;
+    // members out of conflict read the first row, the others the second
+    const MT hpn = hp & ~cm, hpc = hp & cm;
+    const uint32_t *rowc = row + n;
     while (hp) {
         ty.term(1u + (uint32_t)mpopc(hp));
-        const uint32_t x = (uint32_t)R - 1u;
+        const uint32_t x2 = ((uint32_t)R - 1u) << 1;  // R <= D < 2^31
         uint64_t W = base;
-        for (MT h = hp; h; h &= h - MT(1)) {
+        for (MT h = hpn; h; h &= h - MT(1)) {
             const int j = mctz(h);
-            const uint32_t Cj = row[(int)mbit(cm, j) * n + j];
-            W += (uint64_t)floordiv_magic(x, L.clo[j], L.chi[j]) * Cj;
+            W += (uint64_t)floordiv31(x2, L.rm[j], L.rs[j]) * row[j];
+        }
+        for (MT h = hpc; h; h &= h - MT(1)) {
+            const int j = mctz(h);
+            W += (uint64_t)floordiv31(x2, L.rm[j], L.rs[j]) * rowc[j];
         }
         if (W > D) return 0u;
         if (W == R) break;

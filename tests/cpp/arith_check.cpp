@@ -48,6 +48,45 @@ int main()
         uint32_t x = (uint32_t)rng();
         CHECK(floordiv_magic(x, lo, hi) == x / T);
     }
+    // floor division of x < 2^31 by the 32-bit multiplier: all x below 40000
+    // and every x near a multiple for small T, the edge divisors, T = 1 and
+    // powers of two, random pairs over the full range
+    auto d31 = [&](uint32_t x, uint32_t T) {
+        uint32_t m, l;
+        magic31(T, &m, &l);
+        CHECK(floordiv31(x << 1, m, l) == x / T);
+    };
+    for (uint32_t T = 1; T < 3000; T++) {
+        for (uint32_t x = 0; x < 40000; x += 3) d31(x, T);
+        for (uint32_t q = 1; q < 2000; q++) {
+            const uint64_t z = (uint64_t)q * T * 997u % 0x80000000ull;
+            if (z) d31((uint32_t)z - 1, T);
+            d31((uint32_t)z, T);
+        }
+        d31(0x7FFFFFFFu, T);
+        d31(0x7FFFFFFEu, T);
+    }
+    for (uint32_t k = 0; k < 31; k++) {
+        const uint32_t T = 1u << k;
+        for (uint32_t x : {0u, 1u, T - 1u, T, T + 1u, 0x7FFFFFFFu, 0x7FFFFFFEu}) if (x < 0x80000000u) d31(x, T);
+        for (int t = 0; t < 20000; t++) d31((uint32_t)rng() & 0x7FFFFFFFu, T);
+        if (T > 2) for (int t = 0; t < 20000; t++) d31((uint32_t)rng() & 0x7FFFFFFFu, T - 1), d31((uint32_t)rng() & 0x7FFFFFFFu, T + 1);
+    }
+    for (uint32_t T : edge_T) {
+        for (uint32_t x : edge_x) if (x < 0x80000000u) d31(x, T);
+        for (int t = 0; t < 200000; t++) {
+            d31((uint32_t)rng() & 0x7FFFFFFFu, T);
+            const uint64_t z = (rng() % 1000) * (uint64_t)T % 0x80000000ull;
+            if (z) d31((uint32_t)z - 1, T);
+            d31((uint32_t)z, T);
+        }
+    }
+    for (int t = 0; t < 4000000; t++) {
+        const uint32_t T = 1 + (uint32_t)(rng() % ((1u << 31) - 1));
+        d31((uint32_t)rng() & 0x7FFFFFFFu, T);
+        const uint64_t z = (rng() % 64) * (uint64_t)T;
+        if (z && z < 0x80000000ull) d31((uint32_t)z - 1, T), d31((uint32_t)z, T);
+    }
     // execution times, utilisation, Lemma 2
     for (int t = 0; t < 2000000; t++) {
         uint32_t Cs = (uint32_t)(rng() % (1u << 30)), Cp = (uint32_t)(rng() % (1u << 30));
