@@ -134,10 +134,12 @@ __device__ __forceinline__ uint64_t big_group_util(const BigLDS &L, const uint32
 }
 
 // Response time of rank r on m units under the members hp (all of higher DM
-// priority), exact fixed point, 0 on a miss.
+// priority), exact fixed point, 0 on a miss.  start: a lower bound of the
+// fixed point (0, or the response time of the next higher-priority member
+// plus C_r, below which the level-r demand exceeds the time).
 template <typename TY>
 __device__ __forceinline__ uint32_t big_rta(const BigLDS &L, const uint32_t *tc, int n, int r, const M256 &hp, int m, const M256 &cm,
-                            TY &ty)
+                            TY &ty, uint64_t start = 0)
 {
     const uint32_t Cr = big_time(tc, n, r, m, m_has(cm, r) ? 1 : 0), D = L.D[r];
     uint64_t R = Cr;
@@ -146,6 +148,9 @@ __device__ __forceinline__ uint32_t big_rta(const BigLDS &L, const uint32_t *tc,
         if (Cj >= L.T[j]) return 0u;  // a higher-priority utilisation of 1 or more leaves no time
         R += Cj;
     }
+    if (R > D) return 0u;
+    if (!m_any(hp)) return (uint32_t)R;
+    if (start > R) R = start;
     if (R > D) return 0u;
     for (;;) {
         uint64_t W = Cr;
@@ -169,8 +174,12 @@ __device__ __forceinline__ bool big_test(const BigLDS &L, const uint32_t *tc, in
 {
     ty.test();
     M256 hp = m_zero();
+    uint64_t Rprev = 0;  // response time of the member before (0: none yet)
     for (int r = m_first(S); r < BIGN; r = m_next(S, r)) {
-        if (!big_rta(L, tc, n, r, hp, m, cm, ty)) return false;
+        const uint32_t R = big_rta(L, tc, n, r, hp, m, cm, ty,
+                                   Rprev ? Rprev + big_time(tc, n, r, m, m_has(cm, r) ? 1 : 0) : 0);
+        if (!R) return false;
+        Rprev = R;
         hp = m_or(hp, m_bit(r));
     }
     return true;

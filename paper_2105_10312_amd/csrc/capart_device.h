@@ -361,17 +361,23 @@ __device__ __forceinline__ MT conflict_mask(MT S, MT memmask)
     return (mpopc(mem) >= 2 ? memmask : MT(0)) | (mpopc(cmp) >= 2 ? ~memmask : MT(0));
 }
 
-// Fixed point of R = base + sum_{j in hp} floor((R-1)/T_j) C_j from R = base,
-// where base = C_r + sum_{j in hp} C_j is the demand with one job of every
-// higher-priority task (so the sum equals C_r + sum ceil(R/T_j) C_j), and hp
-// holds only tasks with T_j < D_r (the others never release a second job
-// before D_r).  Returns R, or 0 once R exceeds D.
+// Least fixed point of R = base + sum_{j in hp} floor((R-1)/T_j) C_j, where
+// base = C_r + sum C_j over every higher-priority member is the demand with
+// one job of each (so the sum equals C_r + sum ceil(R/T_j) C_j), and hp holds
+// only members with T_j < D_r (the others never release a second job before
+// D_r).  The iteration starts at `start`, a lower bound of the fixed point
+// that is at least base (base itself, or the response time of the next
+// higher-priority member plus C_r: the level-r demand exceeds every t below
+// that bound, since the higher level's demand exceeds every t below its own
+// response time).  Returns R, or 0 once R exceeds D.
 template <typename MT, typename TY>
-__device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row, int n, uint64_t base, uint32_t D,
-                                           MT hp, MT cm, TY &ty)
+__device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row, int n, uint64_t base,
+                                           uint64_t start, uint32_t D, MT hp, MT cm, TY &ty)
 {
     if (base > D) return 0u;
-    uint64_t R = base;
+    if (!hp) return (uint32_t)base;
+    if (start > D) return 0u;
+    uint64_t R = start;
     // members out of conflict read the first row, the others the second
     const MT hpn = hp & ~cm, hpc = hp & cm;
     const uint32_t *rowc = row + n;
@@ -615,12 +621,16 @@ __device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, in
         sumC += Cj;
         sat |= (Cj >= L.T[j]);
     }
+    uint64_t Rprev = 0;  // response time of the member tested before (0: none yet)
     for (MT rem = S & ~below<MT>(first); rem; rem &= rem - MT(1)) {
         const int r = mctz(rem);
         const uint32_t Cr = row[(int)mbit(cm, r) * n + r];
         if (sat) return false;
         const MT hp = S & below<MT>(r) & (MT)L.intf[r];
-        if (!rta_fp<MT>(L, row, n, sumC + Cr, L.D[r], hp, cm, ty)) return false;
+        const uint64_t base = sumC + Cr;
+        const uint32_t R = rta_fp<MT>(L, row, n, base, max(base, Rprev + Cr), L.D[r], hp, cm, ty);
+        if (!R) return false;
+        Rprev = R;
         sumC += Cr;
         sat |= (Cr >= L.T[r]);
     }
@@ -707,7 +717,7 @@ __device__ uint32_t rta_one(const SetLDS &L, const Tables &tb, int m, int r, MT 
     }
     if (sat) return 0u;
     NoTally nt;
-    return rta_fp<MT>(L, row, n, base, L.D[r], hp & (MT)L.intf[r], cm, nt);
+    return rta_fp<MT>(L, row, n, base, base, L.D[r], hp & (MT)L.intf[r], cm, nt);
 }
 
 // Reported response time of rank r in partition Sp (m units, conflict mask
@@ -1034,7 +1044,7 @@ __device__ bool wave_test_from(const SetLDS &L, const Tables &tb, uint64_t S, in
             base += Cj;
             sat |= (Cj >= L.T[j]);
         }
-        fail = sat || rta_fp<uint64_t>(L, row, n, base, L.D[lane], hp & L.intf[lane], cm, ty) == 0u;
+        fail = sat || rta_fp<uint64_t>(L, row, n, base, base, L.D[lane], hp & L.intf[lane], cm, ty) == 0u;
     }
     if (lane == 0) ty.test();
     return !__any(fail);
