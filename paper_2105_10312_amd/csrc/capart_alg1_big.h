@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         const TaskRec r = w.rec[off0 + t];
         L.T[t] = r.T; L.D[t] = r.D; L.clo[t] = r.clo; L.chi[t] = r.chi;
         uint32_t rm, rs;
-        magic31(r.T, &rm, &rs);
+        magic31_of(r.T, r.clo, r.chi, &rm, &rs);
         L.rm[t] = rm; L.rs[t] = rs;
         L.Cs[t] = r.Cs; L.Cp[t] = r.Cp; L.k[t] = r.k;
         L.mmin[t] = r.mmin;

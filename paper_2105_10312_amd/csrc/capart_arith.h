@@ -46,6 +46,22 @@ CAPART_HD inline void magic31(uint32_t T, uint32_t *m, uint32_t *l)
     *l = s;
 }
 
+// The same m and l from c = ceil(2^64 / T) (magic_u32) without a division:
+// ceil(c / 2^(33-l)) = ceil(2^(31+l) / T), since nested ceilings of
+// divisions by positive integers compose; T = 1 (no c) gives 2^31 and 0.
+CAPART_HD inline void magic31_of(uint32_t T, uint32_t clo, uint32_t chi, uint32_t *m, uint32_t *l)
+{
+    if (T < 2u) {
+        *m = 0x80000000u;
+        *l = 0u;
+        return;
+    }
+    const uint32_t s = 32u - (uint32_t)__builtin_clz(T - 1u);  // ceil(log2 T), 1..31
+    const uint64_t c = ((uint64_t)chi << 32) | clo;
+    *m = (uint32_t)((c + (((uint64_t)1 << (33u - s)) - 1u)) >> (33u - s));
+    *l = s;
+}
+
 // x2 = 2x for the x above.
 CAPART_HD inline uint32_t floordiv31(uint32_t x2, uint32_t m, uint32_t l)
 {

@@ -184,7 +184,7 @@ __device__ void stage_records(SetLDS &L, const Work &w, int64_t off, int n, int6
         TaskRec t = w.rec[off + i];
         L.T[i] = t.T; L.D[i] = t.D; L.clo[i] = t.clo; L.chi[i] = t.chi;
         uint32_t rm, rs;
-        magic31(t.T, &rm, &rs);
+        magic31_of(t.T, t.clo, t.chi, &rm, &rs);
         L.rm[i] = rm; L.rs[i] = rs;
         L.Cs[i] = t.Cs; L.Cp[i] = t.Cp; L.k[i] = t.k;
         L.mmin[i] = t.mmin;
@@ -615,9 +615,16 @@ __device__ bool test_from(const SetLDS &L, const Tables &tb, MT S, int first, in
     const uint32_t *row = tb.C + (m - 1) * 2 * n;
     uint64_t sumC = 0;
     bool sat = false;  // some higher-priority task has utilisation >= 1
-    for (MT h = S & below<MT>(first); h; h &= h - MT(1)) {
+    const MT above = S & below<MT>(first);
+    for (MT h = above & ~cm; h; h &= h - MT(1)) {  // out of conflict: first row
         const int j = mctz(h);
-        const uint32_t Cj = row[(int)mbit(cm, j) * n + j];
+        const uint32_t Cj = row[j];
+        sumC += Cj;
+        sat |= (Cj >= L.T[j]);
+    }
+    for (MT h = above & cm; h; h &= h - MT(1)) {  // in conflict: second row
+        const int j = mctz(h);
+        const uint32_t Cj = row[n + j];
         sumC += Cj;
         sat |= (Cj >= L.T[j]);
     }

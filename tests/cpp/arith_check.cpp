@@ -52,9 +52,12 @@ int main()
     // and every x near a multiple for small T, the edge divisors, T = 1 and
     // powers of two, random pairs over the full range
     auto d31 = [&](uint32_t x, uint32_t T) {
-        uint32_t m, l;
+        uint32_t m, l, m2, l2, lo, hi;
         magic31(T, &m, &l);
         CHECK(floordiv31(x << 1, m, l) == x / T);
+        magic_u32(T, &lo, &hi);
+        magic31_of(T, lo, hi, &m2, &l2);  // the division-free form gives the same pair
+        CHECK(m2 == m && l2 == l);
     };
     for (uint32_t T = 1; T < 3000; T++) {
         for (uint32_t x = 0; x < 40000; x += 3) d31(x, T);
