@@ -1216,6 +1216,10 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
     __shared__ uint32_t cnt[2][2];         // queue lengths; chunks alternate rows (one is cleared while the other is read)
     const uint16_t *ord = order + ((1u << n) - 2u);
     const MT memm = (MT)L.memmask;
+    // the utilisation screen below pays where utilisation is what limits a
+    // partition, i.e. with implicit deadlines; with shorter deadlines it
+    // rarely moves a bound and only costs its reads (the block has >= n threads)
+    const bool screen = __syncthreads_and((int)threadIdx.x >= n || L.D[threadIdx.x] == L.T[threadIdx.x]) != 0;
     if (threadIdx.x == 0) { ms[0] = 0; cnt[0][0] = cnt[0][1] = cnt[1][0] = cnt[1][1] = 0u; }
     uint32_t cur = 0;
     uint32_t lvl_off = 1, lvl_cnt = (uint32_t)n;  // level 1 follows the empty set
@@ -1234,6 +1238,25 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
                     const uint16_t v = ms[S & ~(h & (0u - h))];
                     none |= (v == FRONT_NONE);
                     lo = max(lo, (int)v);
+                }
+                if (!none && screen) {
+                    // utilisation screen: a partition whose utilisation exceeds 1
+                    // on m units is unschedulable there, and utilisations never
+                    // grow with m, so ms[S] lies above every m where the Q32 lower
+                    // bound of the sum (table terms ceil(u 2^32) - 1 <= u 2^32)
+                    // exceeds 2^32; no test is spent on those sizes
+                    const MT cmS = conflict_mask<MT>((MT)S, memm);
+                    while (lo <= M) {
+                        const uint32_t *urow = tb.U + (lo - 1) * 2 * n;
+                        uint64_t u = 0;
+                        for (uint32_t h = S; h; h &= h - 1u) {
+                            const int j = __ffs(h) - 1;
+                            u += urow[(int)mbit(cmS, j) * n + j];
+                        }
+                        if (u <= (1ull << 32)) break;
+                        lo++;
+                    }
+                    none = lo > M;
                 }
                 if (none) {
                     ms[S] = FRONT_NONE;
