@@ -929,6 +929,9 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
                 for (int p = 0; p < KMAX; p++)
                     if (((cand >> p) & 1u) && (q < 0 || un[p] < uq)) { q = p; uq = un[p]; Sq = S[p]; mq = m[p]; Uq = U[p]; }
                 cand &= ~(1u << q);
+                // utilisation above 1 (the Q32 terms less one each bound it from
+                // below) cannot be scheduled: no test
+                if (uq - (uint64_t)(mpopc(Sq) + 1) > (1ull << 32)) continue;
                 int f, pz;
                 if (passes(Sq, mq, Uq, f, pz)) { best = q; bestU = uq; break; }
             }
@@ -963,6 +966,7 @@ __device__ __forceinline__ bool heuristic(const SetLDS &L, const Tables &tb, int
                     }
                 cand &= ~(1u << q);
                 if (best >= 0 && (lq > bestReq || (lq == bestReq && (uq > bestU || (uq == bestU && q > best))))) break;
+                if (uq - (uint64_t)(mpopc(Sq) + 1) > (1ull << 32)) continue;  // utilisation above 1 on m[q]
                 const MT Sn = Sq | (MT(1) << r);
                 const MT cm = conflict_mask<MT>(Sn, (MT)L.memmask);
                 int f = 0, pz = 256;  // largest size known to fail, smallest known to pass
