@@ -1221,9 +1221,12 @@ __device__ void build_frontier(const SetLDS &L, const Tables &tb, int n, int M, 
     const uint16_t *ord = order + ((1u << n) - 2u);
     const MT memm = (MT)L.memmask;
     // the utilisation screen below pays where utilisation is what limits a
-    // partition, i.e. with implicit deadlines; with shorter deadlines it
-    // rarely moves a bound and only costs its reads (the block has >= n threads)
-    const bool screen = __syncthreads_and((int)threadIdx.x >= n || L.D[threadIdx.x] == L.T[threadIdx.x]) != 0;
+    // fixed-priority partition, i.e. with implicit deadlines; with shorter
+    // deadlines it rarely moves a bound, and under EDF the test itself starts
+    // with the same utilisation check, so there it only costs its reads (the
+    // block has >= n threads)
+    const bool screen = __syncthreads_and((int)threadIdx.x >= n || L.D[threadIdx.x] == L.T[threadIdx.x]) != 0 &&
+                        !use_edf<TY>(L);
     if (threadIdx.x == 0) { ms[0] = 0; cnt[0][0] = cnt[0][1] = cnt[1][0] = cnt[1][1] = 0u; }
     uint32_t cur = 0;
     uint32_t lvl_off = 1, lvl_cnt = (uint32_t)n;  // level 1 follows the empty set
