@@ -185,7 +185,8 @@ typedef struct capart_tasksets {
  * 0 allows every size.  A partitioning with a part of another size is still
  * numbered and counted in n_evals but is infeasible (its debug key is
  * "none"); the whole-GPU baseline is unaffected.  Honoured by capart_solve,
- * capart_solve_async, capart_count_work and the batched plans; capart_alg1
+ * capart_solve_async, capart_count_work, the batched plans and the server
+ * (capart_server_config.admissible, for every query); capart_alg1
  * and capart_alg1_async return E_INVAL for a non-empty mask; the one-set calls
  * evaluate the partitioning they are given.
  */
@@ -464,6 +465,7 @@ typedef struct capart_server_config {
     int32_t streams;        /* batches in flight, 1..8 (0 = 4)        */
     int32_t max_batch;      /* queries per launch (0 = no limit)      */
     int32_t policy;         /* CAPART_POLICY_FP_DM (0) or CAPART_POLICY_EDF, every query */
+    uint64_t admissible[4]; /* allowed part sizes for every query (as capart_options), all 0 = every size */
 } capart_server_config;
 
 typedef struct capart_server_stats {

@@ -88,7 +88,8 @@ class capart_plan_info(C.Structure):
 class capart_server_config(C.Structure):
     _fields_ = [("K", C.c_int32), ("alloc_mode", C.c_int32), ("flags", C.c_uint32), ("max_tasks", C.c_int32),
                 ("max_M", C.c_int32), ("max_queries", C.c_int32), ("device_bytes", C.c_int64),
-                ("streams", C.c_int32), ("max_batch", C.c_int32), ("policy", C.c_int32)]
+                ("streams", C.c_int32), ("max_batch", C.c_int32), ("policy", C.c_int32),
+                ("admissible", C.c_uint64 * 4)]
 
 
 class capart_server_stats(C.Structure):
@@ -590,14 +591,15 @@ class Server:
 
     def __init__(self, ctx, K: int = 4, mode="BF_INA", flags: int = 0, max_tasks: int = 64, max_M: int = 108,
                  max_queries: int = 0, device_bytes: int = 0, streams: int = 0, max_batch: int = 0,
-                 policy="FP_DM", tables: bool = False):
+                 policy="FP_DM", tables: bool = False, admissible=None):
         self.ctx = ctx
         self.K = int(K)
         pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
         if tables:
             flags = int(flags) | CAPART_SERVER_TABLES
         cfg = capart_server_config(int(K), _mode(mode), int(flags), int(max_tasks), int(max_M), int(max_queries),
-                                   int(device_bytes), int(streams), int(max_batch), pol)
+                                   int(device_bytes), int(streams), int(max_batch), pol,
+                                   (C.c_uint64 * 4)(*admissible_mask(admissible)))
         h = _vp()
         _check(load_library().capart_server_create(ctx, C.byref(cfg), C.byref(h)), ctx)
         self.handle = h

@@ -2190,7 +2190,8 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     if (!c || !cfg || !out) return CAPART_E_INVAL;
     *out = nullptr;
     const bool tabs = (cfg->flags & CAPART_SERVER_TABLES) != 0u;
-    capart_options opt{cfg->K, cfg->policy, cfg->alloc_mode, cfg->flags & ~CAPART_SERVER_TABLES};
+    capart_options opt{cfg->K, cfg->policy, cfg->alloc_mode, cfg->flags & ~CAPART_SERVER_TABLES,
+                       {cfg->admissible[0], cfg->admissible[1], cfg->admissible[2], cfg->admissible[3]}};
     capart_status rc = check_options(c, &opt);
     if (rc != CAPART_OK) return rc;
     if (cfg->alloc_mode == CAPART_EXHAUSTIVE) return fail(c, CAPART_E_INVAL, "serving runs heuristic modes");
@@ -2218,13 +2219,16 @@ capart_status capart_server_create(capart_ctx *c, const capart_server_config *cf
     L.K = cfg->K;
     L.mode = cfg->alloc_mode;
     L.flags = opt.flags;
+    for (int i = 0; i < 4; i++) L.adm.w[i] = opt.admissible[i];
     L.edf = cfg->policy == CAPART_POLICY_EDF;
     L.threads = eval_threads(cfg->max_tasks, cfg->max_M);
     L.table_words = (int)(table_lds_bytes(cfg->max_tasks, cfg->max_M) / 4);
     L.form = c->tune.loop_form == 2 ? 2 : 1;
     L.memo_packed = c->tune.loop_form == 3;
     L.exh_form = 1;
-    size_frontier(L, cfg->max_tasks, cfg->alloc_mode, c->tune);
+    capart_tuning tf = c->tune;
+    if (tf.frontier == 0 && !frontier_pays(cfg->max_tasks, cfg->max_M, cfg->K, L.adm)) tf.frontier = 2;
+    size_frontier(L, cfg->max_tasks, cfg->alloc_mode, tf);
     const uint32_t Pmax = count_parts(cfg->max_M, cfg->K);
     // 512 partitionings per block: one per lane of the widest blocks (large-set launches)
     L.chunk = c->tune.chunk > 0 ? (uint32_t)c->tune.chunk : 512u;

@@ -1,7 +1,7 @@
 """Admissible partition sizes on the GPU (through the C ABI): bit-exact with
 the oracle on every evaluation path (exhaustive forms, frontier, test memo,
-the three loop forms, wide sets, batched plans); excluded partitionings carry
-"none" debug keys; Algorithm 1 refuses a restriction."""
+the three loop forms, wide sets, batched plans, the server); excluded
+partitionings carry "none" debug keys; Algorithm 1 refuses a restriction."""
 import os
 import sys
 
@@ -105,3 +105,33 @@ def test_alg1_refuses_a_restriction(eng):
     res = capart.capart_alg1_results(*[capart._ptr(out[f[0]]) for f in capart.ALG1_FIELDS])
     rc = capart.load_library().capart_alg1(eng.ctx, capart.C.byref(st), capart.C.byref(opt), capart.C.byref(res))
     assert rc == capart.CAPART_E_INVAL
+
+
+@pytest.mark.parametrize("mode,policy", [("BF_INA", "FP_DM"), ("SMS_ACT", "EDF")])
+def test_server_matches_oracle(eng, mode, policy):
+    """A server whose configuration restricts the part sizes: every query of a
+    serving mix (narrow, memo-class and wide queries, replayed at 20k q/s)
+    gets the plain path's results under the same restriction, which the
+    tests above check against the oracle; a sample against the oracle
+    directly."""
+    c5 = workload.config_c5(seed=103, n_queries=400)
+    pick = [i for i in range(c5.n_sets) if c5.sizes()[i] <= 24 or c5["M"][i] <= 48][:200]
+    ts = workload.subset(c5, pick)
+    srv = capart.Server(eng.ctx, K=4, mode=mode, max_tasks=64, max_M=108, policy=policy, admissible=MIG_LIKE)
+    try:
+        rng = np.random.default_rng(104)
+        arrival = np.cumsum(rng.exponential(1e6 / 20000.0, ts.n_sets))
+        say(f"server admissible {mode} {policy}: {ts.n_sets} queries")
+        got, stats = srv.replay(ts, arrival)
+        assert stats["completed"] == ts.n_sets
+    finally:
+        srv.close()
+    same(got, eng.solve(ts, 4, mode, admissible=MIG_LIKE, policy=policy), f"server {mode} {policy}")
+    small = [i for i in range(ts.n_sets) if ts.sizes()[i] <= 16][:40]
+    sub = workload.subset(ts, small)
+    want = oracle.solve(sub, 4, mode, nthreads=THREADS, admissible=MIG_LIKE, policy=policy)
+    off = ts["set_offset"]
+    task_idx = np.concatenate([np.arange(off[s], off[s + 1]) for s in small])
+    for f in FIELDS:
+        g = got[f][task_idx] if f in ("alloc", "R", "R_1g") else (got[f][small] if f != "sizes" else got[f][small])
+        assert np.array_equal(np.asarray(g).ravel(), np.asarray(want[f]).ravel()), f"oracle sample: {f}"
