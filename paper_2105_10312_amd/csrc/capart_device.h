@@ -423,7 +423,9 @@ __device__ __forceinline__ uint32_t rta_fp(const SetLDS &L, const uint32_t *row,
 // deadlines, so every skipped deadline d has h(d) <= d, and the walk moves
 // below at least one deadline every two points: at most 2 ND + 1 points.
 // get(j, C, T, D) reads member j.  Returns ok, H (0 where undetermined or not
-// wanted; when ok every job of the partition completes by min(D_i, H)) and
+// wanted; when ok every job of the partition completes by min(D_i, H); where
+// step 2 decided, a value at or above the largest D stands for any H that
+// large, since only min(D_i, H) is reported) and
 // the terms evaluated (members x busy-period steps, demand points and DM
 // fixed-point steps).  64-bit bounds: C < 2^31 and T, D < 2^31; w < 2^50 over
 // the busy-period steps (U < 1 + 2^-26); H < 2^57 (a larger bound puts more
@@ -469,7 +471,7 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     EdfRes res{0ull, 0u, false};
     uint64_t uf = 0, uc = 0, dc = 0, sumC = 0;
     bool dense = false;  // some C_j / D_j above 1
-    uint32_t dmin = 0xFFFFFFFFu;
+    uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
     for (MT h = S; h; h &= h - MT(1)) {
         const EdfTask e = get(mctz(h));
         if (e.C > e.T) return res;  // C/T > 1: U > 1
@@ -489,6 +491,7 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
         }
         sumC += e.C;
         dmin = min(dmin, e.D);
+        dmax = max(dmax, e.D);
     }
     res.terms += cnt;
     const bool density_ok = !dense && dc <= ONE;
@@ -498,7 +501,12 @@ __device__ __noinline__ EdfRes edf_demand(MT S, GET get, bool need_h)
     }
     uint64_t w = sumC, H = 0;
     bool settled = false;
+    // with the verdict decided by the density bound, H is wanted only for the
+    // members' min(D_i, H): the iterates rise to H, so once one reaches the
+    // largest D it stands in for H (every min is then D_i)
+    const uint64_t wcap = density_ok ? (uint64_t)dmax : ~0ull;
     for (int step = 0; step < EDF_BP_STEPS; step++) {
+        if (w >= wcap) { settled = true; break; }
         uint64_t W = 0;
         for (MT h = S; h; h &= h - MT(1)) {
             const EdfTask e = get(mctz(h));
