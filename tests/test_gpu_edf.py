@@ -210,3 +210,35 @@ def test_tables_and_admissible_sizes_under_edf(eng):
         if w["verdict"]:
             assert np.array_equal(got["sizes"][a:a + w["k"]], w["sizes"]), s
             assert np.array_equal(got["alloc"][a:b], w["alloc"]) and np.array_equal(got["R"][a:b], w["R"]), s
+
+
+def test_response_report_around_the_largest_deadline(eng):
+    """Where the density bound decides, the reported response time is
+    min(D_i, H) with H the busy period, and the kernels stop iterating H at
+    the partition's largest deadline: sets whose busy period ends well
+    before, just before, at and after the largest deadline (chosen triple
+    and whole GPU) give the oracle's R and R_1g."""
+    from test_gpu_alg1 import as_batch
+    tasks = []
+    # light: busy period far below every deadline
+    tasks.append(dict(M=4, T=[1000, 2000, 4000], D=[1000, 2000, 4000], C_seq=[5, 5, 5], C_par=[20, 40, 80],
+                      k_permille=[1000, 1000, 1000], type=[0, 0, 1]))
+    # heavy: utilisation near 1 on the chosen part, busy period past the largest deadline
+    tasks.append(dict(M=2, T=[10, 15, 35], D=[10, 15, 35], C_seq=[2, 3, 4], C_par=[4, 6, 12],
+                      k_permille=[1000, 1000, 1000], type=[0, 0, 0]))
+    rng = np.random.default_rng(55)
+    for _ in range(120):
+        n = int(rng.integers(2, 9))
+        T = rng.integers(20, 400, n)
+        u = rng.dirichlet(np.ones(n)) * float(rng.uniform(0.3, 1.8))
+        Cp = np.maximum(1, (u * T * rng.uniform(0.5, 1.0, n)).astype(np.int64))
+        Cs = np.maximum(0, (u * T).astype(np.int64) - Cp)
+        tasks.append(dict(M=int(rng.integers(1, 7)), T=T, D=T, C_seq=Cs, C_par=Cp,
+                          k_permille=rng.choice([1000, 1200, 2300], n), type=rng.integers(0, 2, n)))
+    ts = as_batch(tasks)
+    for K, mode in ((1, "BF_INA"), (3, "BF_INA"), (3, "SMS_ACT"), (2, "EXH")):
+        want = oracle.solve(ts, K, mode, policy="EDF")
+        got = eng.solve(ts, K, mode, policy="EDF")
+        same(got, want, FIELDS, f"EDF report K={K} {mode}")
+        say(f"EDF report K={K} {mode}: {int(got['verdict'].sum())} of {ts.n_sets} schedulable, "
+            f"{int((got['R'] > 0).sum())} response times")
